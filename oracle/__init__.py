@@ -1,0 +1,299 @@
+"""FP64 CPU oracle of the GSta training path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The GPU library never loads it and shares no code with
+it.  The rasterizer (projection, binning, compositing, backward) lives in
+``gsta_oracle.cpp`` (plain double-precision C++); the element-wise steps
+(loss, Adam, gradient-norm scores, freezing, threshold schedule, early stop,
+plateau learning rate) are written here in numpy float64.
+
+Paper: "GSta: Efficient Training Scheme with Siestaed Gaussians for Monocular
+3D Scene Reconstruction" (arXiv 2504.06716).  Each function names the
+section or equation it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsta_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NREC = 40
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C++ oracle (g++, FP64, no floating-point contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC",
+               "-o", _LIB, _SRC]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        L.oracle_project.argtypes = [P, i64, i64, i32, P, i32, i32, P]
+        L.oracle_bin.argtypes = [P, i64, i64, i32, P, i32, i32, P, P, P, P]
+        L.oracle_bin.restype = i64
+        L.oracle_render.argtypes = [P, i64, i64, i32, P, i32, i32, P, i32] + [P] * 8
+        L.oracle_render_backward.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P, P, P, P, P]
+        L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _as_f64(params: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(params, dtype=np.float64)
+
+
+def cam_vec(cam) -> np.ndarray:
+    """Camera as the 22 doubles the C oracle reads."""
+    v = np.zeros(22, dtype=np.float64)
+    v[0], v[1] = cam.width, cam.height
+    v[2:6] = [cam.fx, cam.fy, cam.cx, cam.cy]
+    v[6:18] = np.concatenate([np.asarray(cam.R, np.float64), np.asarray(cam.t, np.float64)[:, None]],
+                             axis=1).reshape(-1)
+    v[18:21] = cam.campos
+    v[21] = cam.near
+    return v
+
+
+def n_rows(degree: int) -> int:
+    return 11 + 3 * (degree + 1) ** 2
+
+
+# ---------------------------------------------------------------------------
+# Rasterizer (Section 3.1, eqs. 1-2; Section 3.2.4)
+# ---------------------------------------------------------------------------
+
+def project(params, degree, cam, tile=16):
+    """Per-Gaussian projected records (see oracle_project for the layout)."""
+    P = _as_f64(params)
+    n = P.shape[1]
+    rec = np.zeros((n, NREC), dtype=np.float64)
+    lib().oracle_project(_ptr(P), n, n, degree, _ptr(cam_vec(cam)), tile, tile, _ptr(rec))
+    return rec
+
+
+def bin_tiles(params, degree, cam, tile=16):
+    """Per-tile depth-ordered id lists: (counts [T], ids [I], depth order)."""
+    P = _as_f64(params)
+    n = P.shape[1]
+    cv = cam_vec(cam)
+    ntiles = ((cam.width + tile - 1) // tile) * ((cam.height + tile - 1) // tile)
+    counts = np.zeros(ntiles, dtype=np.int64)
+    nvis = np.zeros(1, dtype=np.int64)
+    order = np.zeros(n, dtype=np.int64)
+    total = lib().oracle_bin(_ptr(P), n, n, degree, _ptr(cv), tile, tile, _ptr(counts), None,
+                             _ptr(order), _ptr(nvis))
+    ids = np.zeros(max(total, 1), dtype=np.int64)
+    lib().oracle_bin(_ptr(P), n, n, degree, _ptr(cv), tile, tile, _ptr(counts), _ptr(ids), None, None)
+    return counts, ids[:total], order[: int(nvis[0])]
+
+
+def render(params, degree, cam, tile=16, bg=(0.0, 0.0, 0.0), brute=False):
+    """Forward render of one view (eq. 2) with per-pixel decision margins."""
+    P = _as_f64(params)
+    n = P.shape[1]
+    H, W = cam.height, cam.width
+    out = dict(
+        image=np.zeros((3, H, W)), T_final=np.zeros((H, W)),
+        last=np.zeros((H, W), np.int64), n_members=np.zeros((H, W), np.int64),
+        m_value=np.zeros((H, W)), m_grad=np.zeros((H, W)), ztie=np.zeros((H, W)),
+        hash=np.zeros((H, W), np.uint64))
+    bgv = np.asarray(bg, dtype=np.float64)
+    lib().oracle_render(_ptr(P), n, n, degree, _ptr(cam_vec(cam)), tile, tile, _ptr(bgv), int(brute),
+                        _ptr(out["image"]), _ptr(out["T_final"]), _ptr(out["last"]),
+                        _ptr(out["n_members"]), _ptr(out["m_value"]), _ptr(out["m_grad"]),
+                        _ptr(out["ztie"]), _ptr(out["hash"]))
+    return out
+
+
+def render_backward(params, degree, cams, dL_dimage, frozen=None, tile=16, bg=(0.0, 0.0, 0.0),
+                    grads_init=None):
+    """Parameter gradients summed over views (Section 3.2.4).
+
+    Frozen columns keep ``grads_init`` (zeros by default).  Returns
+    (grads [R, n], grad2d [V, 9, n], visible [V, n]).
+    """
+    P = _as_f64(params)
+    R, n = P.shape
+    V = len(cams)
+    cv = np.concatenate([cam_vec(c) for c in cams])
+    dL = np.ascontiguousarray(dL_dimage, dtype=np.float64)
+    grads = np.zeros((R, n)) if grads_init is None else np.array(grads_init, dtype=np.float64)
+    g2 = np.zeros((V, 9, n))
+    vis = np.zeros((V, n), np.uint8)
+    fz = None if frozen is None else np.ascontiguousarray(frozen, dtype=np.uint8)
+    bgv = np.asarray(bg, dtype=np.float64)
+    lib().oracle_render_backward(_ptr(P), n, n, degree, _ptr(cv), V, tile, tile, _ptr(bgv), _ptr(dL),
+                                 None if fz is None else _ptr(fz), _ptr(grads), _ptr(g2), _ptr(vis))
+    return grads, g2, vis
+
+
+def sh_basis(degree, dirs, with_grad=False):
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    m = d.shape[0]
+    K = (degree + 1) ** 2
+    out = np.zeros((m, K))
+    g = np.zeros((m, K, 3)) if with_grad else None
+    lib().oracle_sh_basis(degree, _ptr(d), m, _ptr(out), None if g is None else _ptr(g))
+    return (out, g) if with_grad else out
+
+
+# ---------------------------------------------------------------------------
+# Loss (eq. 3, L1 part) and PSNR
+# ---------------------------------------------------------------------------
+
+def l1_loss(image, target):
+    """L = mean |C - C*| (eq. 3 with lambda_SSIM = 0); dL/dC = sign(C - C*) / count.
+
+    PSNR = 10 log10(1 / MSE) with C clamped to [0, 1].
+    """
+    C = np.asarray(image, np.float64)
+    Ct = np.asarray(target, np.float64)
+    d = C - Ct
+    count = d.size
+    loss = np.abs(d).sum() / count
+    dL = np.sign(d) / count
+    mse = ((np.clip(C, 0.0, 1.0) - Ct) ** 2).sum() / count
+    return loss, dL, mse
+
+
+def psnr(mse):
+    return 10.0 * np.log10(1.0 / mse)
+
+
+# ---------------------------------------------------------------------------
+# Masked Adam (Section 3.2.4: frozen Gaussians are not updated)
+# ---------------------------------------------------------------------------
+
+def adam_masked(p, g, m, v, lr_rows, beta1, beta2, eps, step, frozen=None):
+    """One Adam step (Kingma & Ba, bias-corrected, global step ``step``)
+    on an [R, n] block; columns with frozen != 0 are left untouched."""
+    p = np.array(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = np.array(m, np.float64)
+    v = np.array(v, np.float64)
+    lr = np.asarray(lr_rows, np.float64)[:, None]
+    act = np.ones(p.shape[1], bool) if frozen is None else (np.asarray(frozen) == 0)
+    m_new = beta1 * m + (1.0 - beta1) * g
+    v_new = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m_new / (1.0 - beta1 ** step)
+    vhat = v_new / (1.0 - beta2 ** step)
+    p_new = p - lr * mhat / (np.sqrt(vhat) + eps)
+    p[:, act] = p_new[:, act]
+    m[:, act] = m_new[:, act]
+    v[:, act] = v_new[:, act]
+    return p, m, v
+
+
+# ---------------------------------------------------------------------------
+# Gradient-norm scores and freezing (Section 3.2.1, eqs. 4-6)
+# ---------------------------------------------------------------------------
+
+def scores(grads):
+    """(g_xyz, g_rgb, g_op, g_sc): |dL/dmu|, |dL/df_dc|, |dL/dlogit|, |dL/dlog_s|."""
+    g = np.asarray(grads, np.float64)
+    return (np.sqrt((g[0:3] ** 2).sum(0)), np.sqrt((g[11:14] ** 2).sum(0)),
+            np.abs(g[10]), np.sqrt((g[3:6] ** 2).sum(0)))
+
+
+FLT_MAX = float(np.finfo(np.float32).max)
+
+
+def ema_update(ema, g, visible_any, frozen, beta):
+    """Exponential moving average of a score, only for active Gaussians seen
+    in at least one view; an entry at FLT_MAX (never seen) takes g directly."""
+    ema = np.array(ema, np.float64)
+    upd = np.asarray(visible_any, bool) & (np.asarray(frozen) == 0)
+    first = upd & (ema >= FLT_MAX)
+    rest = upd & ~(ema >= FLT_MAX)
+    ema[first] = g[first]
+    ema[rest] = beta * ema[rest] + (1.0 - beta) * g[rest]
+    return ema
+
+
+def freeze_update(frozen, s_xyz, s_rgb, eps_xyz, eps_rgb, mode, proposal=None):
+    """Eq. 4 per parameter group (|grad| < eps, strict), eq. 6 (both groups),
+    accumulated into the previous map (mode 0), reset (mode 1) or overwrite
+    (mode 2).  Inputs are compared in float32, as the GPU receives them."""
+    sx = np.asarray(s_xyz, np.float32)
+    sr = np.asarray(s_rgb, np.float32)
+    cond = (sx < np.float32(eps_xyz)) & (sr < np.float32(eps_rgb))
+    if proposal is not None:
+        cond = cond | (np.asarray(proposal) != 0)
+    old = np.asarray(frozen) != 0
+    if mode == 0:
+        new = old | cond
+    elif mode == 1:
+        new = np.zeros_like(old)
+    else:
+        new = cond
+    return new.astype(np.uint8)
+
+
+# ---------------------------------------------------------------------------
+# Host schedule (Section 3.2.1 eq. 5, Section 3.2.2 eq. 7, Section 3.2.3)
+# ---------------------------------------------------------------------------
+
+def freeze_threshold(k, K, eps0, k_stop=None, lam1=0.5, lam2=1.5, linear=False):
+    """Threshold at iteration k.  The recursion of eq. 5 is read with the
+    previous threshold replaced by the initial one and the factor bounded to
+    [lam1, lam2] (the text fixes the range [0.5, 1.5] of the initial value):
+    eps0 * clamp(lam1 + lam2 * k'/K, lam1, lam2), k' = min(k, k_stop).  The
+    ``linear`` reading is eps0 * (lam1 + (lam2 - lam1) * k'/K)."""
+    kk = k if k_stop is None else min(k, k_stop)
+    if linear:
+        f = lam1 + (lam2 - lam1) * kk / K
+    else:
+        f = min(max(lam1 + lam2 * kk / K, lam1), lam2)
+    return eps0 * f
+
+
+def early_stop(psnrs, eps=0.2):
+    """Eq. 7: stop when the last two PSNR gains are both below eps."""
+    if len(psnrs) < 3:
+        return False
+    d1 = psnrs[-1] - psnrs[-2]
+    d0 = psnrs[-2] - psnrs[-3]
+    return (d1 < eps) and (d0 < eps)
+
+
+class PlateauLR:
+    """Section 3.2.3: a plateau scheduler on the position learning rate.  An
+    evaluation improves iff its PSNR exceeds the best so far by more than
+    ``eps``; after more than ``patience`` evaluations in a row without
+    improvement the scale is multiplied by ``factor``."""
+
+    def __init__(self, factor=0.75, patience=1, eps=1.0):
+        self.factor, self.patience, self.eps = factor, patience, eps
+        self.scale = 1.0
+        self.bad = 0
+        self.best = None
+
+    def step(self, psnr_value):
+        if self.best is None or psnr_value > self.best + self.eps:
+            self.best = psnr_value
+            self.bad = 0
+        else:
+            self.bad += 1
+        if self.bad > self.patience:
+            self.scale *= self.factor
+            self.bad = 0
+        return self.scale

@@ -1,0 +1,452 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+closed forms, quadrature, symmetry, brute force, finite differences, an
+independent torch-autograd route and torch's Adam.  All CPU."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from tests.dense_torch import render_dense
+
+Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+
+
+def tiny_scene(n=64, degree=3, seed=0, log_s_shift=0.0, size=32, n_cams=2):
+    p = S.make_scene(n, degree, seed=seed).astype(np.float64)
+    p[3:6] += log_s_shift
+    cams = [S.look_at(10.0 + 35.0 * k, 20.0 + 70.0 * k, size, size) for k in range(n_cams)]
+    return p, cams
+
+
+# ---------------------------------------------------------------------------
+# Spherical harmonics (Section 3.1: SH colour up to 3 bands)
+# ---------------------------------------------------------------------------
+
+def test_sh_constants_textbook():
+    # textbook normalisation constants of the real SH basis (positive sign)
+    d = np.array([[0.0, 0.0, 1.0]])
+    B = O.sh_basis(3, d)[0]
+    assert B[0] == pytest.approx(0.2820948, abs=1e-7)
+    assert B[2] == pytest.approx(0.4886025, abs=1e-7)              # z
+    assert B[6] == pytest.approx(2 * 0.3153916, abs=1e-7)          # 2z^2 - x^2 - y^2 at z=1
+    assert B[12] == pytest.approx(2 * 0.3731763, abs=1e-7)         # z(2z^2 - ...) at z=1
+    s = 1 / math.sqrt(3)
+    B = O.sh_basis(3, np.array([[s, s, s]]))[0]
+    assert B[4] == pytest.approx(1.0925484 * s * s, abs=1e-7)      # xy
+    assert B[10] == pytest.approx(2.8906114 * s ** 3, abs=1e-7)    # xyz
+    d = np.array([[1.0, 0.0, 0.0]])
+    B = O.sh_basis(3, d)[0]
+    assert B[8] == pytest.approx(0.5462742, abs=1e-7)              # x^2 - y^2
+    assert B[15] == pytest.approx(0.5900436, abs=1e-7)             # x(x^2 - 3y^2)
+    assert B[13] == pytest.approx(-0.4570458, abs=1e-7)            # x(4z^2 - x^2 - y^2)
+    d = np.array([[math.sqrt(0.5), 0.0, math.sqrt(0.5)]])
+    B = O.sh_basis(3, d)[0]
+    assert B[14] == pytest.approx(1.4453057 * math.sqrt(0.5) * 0.5, abs=1e-7)  # z(x^2 - y^2)
+
+
+def _sphere_quadrature(n_theta=12, n_phi=24):
+    # Gauss-Legendre in cos(theta) x uniform phi: exact for polynomials of degree <= 6
+    xg, wg = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2 * np.pi * np.arange(n_phi) / n_phi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (np.repeat(wg[:, None], n_phi, 1) * (2 * np.pi / n_phi)).reshape(-1)
+    return dirs, w
+
+
+def test_sh_orthonormal_quadrature():
+    dirs, w = _sphere_quadrature()
+    B = O.sh_basis(3, dirs)
+    G = (B * w[:, None]).T @ B
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_parity():
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    B1, B2 = O.sh_basis(3, d), O.sh_basis(3, -d)
+    band = np.array([0] + [1] * 3 + [2] * 5 + [3] * 7)
+    np.testing.assert_allclose(B2, B1 * (-1.0) ** band, atol=1e-15)
+
+
+def test_sh_gradient_fd():
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((20, 3))
+    _, g = O.sh_basis(3, d, with_grad=True)
+    h = 1e-6
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (O.sh_basis(3, d + e) - O.sh_basis(3, d - e)) / (2 * h)
+        np.testing.assert_allclose(g[:, :, a], fd, atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Projection (eq. 1, EWA) closed forms
+# ---------------------------------------------------------------------------
+
+def _single(mu, log_s, q=(1.0, 0, 0, 0), logit=0.0, rgb=(0.2, 0.5, 0.9)):
+    p = np.zeros((14, 1))
+    p[0:3, 0] = mu
+    p[3:6, 0] = log_s
+    p[6:10, 0] = q
+    p[10, 0] = logit
+    p[11:14, 0] = (np.asarray(rgb) - 0.5) / Y00
+    return p
+
+
+def test_isotropic_on_axis_closed_form():
+    cam = S.config_cameras("c1")[0]               # at (3, 0, 0) looking at the origin
+    s = 0.05
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        q = rng.standard_normal(4)
+        p = _single([0.0, 0.0, 0.0], [math.log(s)] * 3, q)
+        r = O.project(p, 0, cam)[0]
+        z = 3.0
+        sig2 = (cam.fx * s / z) ** 2 + 0.3
+        assert r[0] == 1
+        assert r[3] == pytest.approx(z, abs=1e-12)
+        assert r[1] == pytest.approx(cam.cx, abs=1e-9) and r[2] == pytest.approx(cam.cy, abs=1e-9)
+        assert r[5] == pytest.approx(sig2, rel=1e-12)
+        assert r[7] == pytest.approx(sig2, rel=1e-12)
+        assert abs(r[6]) < 1e-12
+        np.testing.assert_allclose(r[9:12], [1 / sig2, 0.0, 1 / sig2], atol=1e-12)
+
+
+def test_near_plane_cull():
+    cam = S.config_cameras("c1")[0]
+    # camera at (3,0,0), forward -x: world x = 3 - z_cam
+    p = np.concatenate([_single([3.0 - 0.19, 0, 0], [-3] * 3), _single([3.0 - 0.21, 0, 0], [-3] * 3)], 1)
+    r = O.project(p, 0, cam)
+    assert r[0, 0] == 0 and r[1, 0] == 1
+
+
+def test_single_gaussian_image_closed_form():
+    cam = S.config_cameras("c1")[0]
+    s, logit, rgb = 0.08, 0.7, np.array([0.2, 0.5, 0.9])
+    p = _single([0.0, 0.0, 0.0], [math.log(s)] * 3, logit=logit, rgb=rgb)
+    out = O.render(p, 0, cam)
+    sig2 = (cam.fx * s / 3.0) ** 2 + 0.3
+    o = 1 / (1 + math.exp(-logit))
+    py, px = np.mgrid[0:cam.height, 0:cam.width].astype(np.float64)
+    qf = ((px - cam.cx) ** 2 + (py - cam.cy) ** 2) / sig2
+    power = -0.5 * qf
+    alpha = np.minimum(0.99, o * np.exp(power))
+    mem = (power >= -4.5) & (alpha >= 1 / 255)
+    exp_img = rgb[:, None, None] * np.where(mem, alpha, 0.0)[None]
+    np.testing.assert_allclose(out["image"], exp_img, atol=1e-13)
+    np.testing.assert_allclose(out["T_final"], np.where(mem, 1 - alpha, 1.0), atol=1e-13)
+    assert mem.sum() > 20 and (~mem).sum() > 20
+
+
+def test_two_gaussian_blend_closed_form():
+    cam = S.config_cameras("c1")[0]
+    c1, c2 = np.array([0.9, 0.1, 0.3]), np.array([0.2, 0.8, 0.6])
+    p = np.concatenate([_single([0.5, 0, 0], [math.log(0.06)] * 3, logit=0.3, rgb=c1),     # z = 2.5
+                        _single([-0.5, 0, 0], [math.log(0.09)] * 3, logit=1.2, rgb=c2)], 1)  # z = 3.5
+    out = O.render(p, 0, cam)
+    py, px = np.mgrid[0:cam.height, 0:cam.width].astype(np.float64)
+    r2 = (px - cam.cx) ** 2 + (py - cam.cy) ** 2
+
+    def alpha(s, z, logit):
+        sig2 = (cam.fx * s / z) ** 2 + 0.3
+        power = -0.5 * r2 / sig2
+        a = np.minimum(0.99, np.exp(power) / (1 + math.exp(-logit)))
+        return np.where((power >= -4.5) & (a >= 1 / 255), a, 0.0)
+
+    a1, a2 = alpha(0.06, 2.5, 0.3), alpha(0.09, 3.5, 1.2)
+    exp_img = c1[:, None, None] * a1 + c2[:, None, None] * (a2 * (1 - a1))
+    np.testing.assert_allclose(out["image"], exp_img, atol=1e-13)
+
+
+def test_tangent_clamp_and_rect_definition():
+    # Gaussians far off-axis exercise the tangent clamp; the rect must equal
+    # the per-tile interval test written out directly.
+    cam = S.look_at(0.0, 0.0, 64, 48)
+    rng = np.random.default_rng(7)
+    n = 300
+    p = np.zeros((14, n))
+    p[0] = rng.uniform(-1, 1.5, n)
+    p[1] = rng.uniform(-4, 4, n)
+    p[2] = rng.uniform(-3, 3, n)
+    p[3:6] = rng.normal(-2.5, 0.5, (3, n))
+    p[6:10] = rng.standard_normal((4, n))
+    rec = O.project(p, 0, cam, tile=16)
+    assert rec[:, 30].sum() > 10                       # some tangent clamps fired
+    ntx, nty = 4, 3
+    for g in range(n):
+        r = rec[g]
+        if r[3] <= 0.2 or r[8] <= 0:
+            assert r[0] == 0
+            continue
+        u, v, ex, ey = r[1], r[2], r[12], r[13]
+        tx = [t for t in range(ntx) if 16 * t <= u + ex and 16 * t + 15 >= u - ex]
+        ty = [t for t in range(nty) if 16 * t <= v + ey and 16 * t + 15 >= v - ey]
+        if tx and ty:
+            assert (r[14], r[15]) == (tx[0], tx[-1] + 1)
+            assert (r[16], r[17]) == (ty[0], ty[-1] + 1)
+            assert r[0] == 1
+        else:
+            assert r[0] == 0
+
+
+def test_ellipse_bounding_box_is_tight():
+    # ex = 3 sqrt(Sigma'_xx) is the exact half-width of the ellipse d^T K d = 9
+    p, cams = tiny_scene(n=30, degree=0, log_s_shift=1.0)
+    rec = O.project(p, 0, cams[0])
+    th = np.linspace(0, 2 * np.pi, 20001)
+    for r in rec[rec[:, 0] == 1]:
+        A = np.array([[r[5], r[6]], [r[6], r[7]]])
+        L = np.linalg.cholesky(A)
+        d = 3.0 * (L @ np.stack([np.cos(th), np.sin(th)]))
+        assert np.abs(d[0]).max() == pytest.approx(r[12], rel=1e-6)
+        assert np.abs(d[1]).max() == pytest.approx(r[13], rel=1e-6)
+        K = np.array([[r[9], r[10]], [r[10], r[11]]])
+        np.testing.assert_allclose(np.einsum("ij,ik,kj->j", d, K, d), 9.0, rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Binning, order, brute force, invariants (eq. 2, "sorted order")
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("degree,n,size", [(0, 400, 48), (3, 300, 40)])
+def test_bin_lists_match_direct_filter(degree, n, size):
+    p, cams = tiny_scene(n=n, degree=degree, size=size, log_s_shift=0.7)
+    cam = cams[0]
+    rec = O.project(p, degree, cam)
+    counts, ids, order = O.bin_tiles(p, degree, cam)
+    ntx = (cam.width + 15) // 16
+    pos = 0
+    for t in range(len(counts)):
+        tx, ty = t % ntx, t // ntx
+        exp = [g for g in range(n) if rec[g, 0] == 1 and rec[g, 14] <= tx < rec[g, 15]
+               and rec[g, 16] <= ty < rec[g, 17]]
+        exp.sort(key=lambda g: (np.float32(rec[g, 3]), g))
+        got = list(ids[pos:pos + counts[t]])
+        pos += counts[t]
+        assert got == exp
+
+
+@pytest.mark.parametrize("degree,seed", [(0, 0), (3, 1), (3, 2)])
+def test_tiled_equals_brute_force(degree, seed):
+    p, cams = tiny_scene(n=500, degree=degree, seed=seed, size=48, log_s_shift=0.8)
+    for cam in cams:
+        a = O.render(p, degree, cam)
+        b = O.render(p, degree, cam, brute=True)
+        for k in ("image", "T_final", "n_members", "hash"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["n_members"].max() > 5
+
+
+def test_tile_size_invariance():
+    p, cams = tiny_scene(n=500, degree=3, size=48, log_s_shift=0.8)
+    ref = O.render(p, 3, cams[0], tile=16)
+    for tile in (8, 32, 48):
+        o = O.render(p, 3, cams[0], tile=tile)
+        assert np.array_equal(o["image"], ref["image"])
+        assert np.array_equal(o["T_final"], ref["T_final"])
+
+
+def test_weights_plus_transmittance_is_one():
+    p, cams = tiny_scene(n=500, degree=0, size=48, log_s_shift=0.8)
+    p[11:14] = 0.5 / Y00                    # colour exactly 1 in every channel
+    o = O.render(p, 0, cams[0])
+    np.testing.assert_allclose(o["image"] + o["T_final"][None], 1.0, atol=1e-12)
+    assert o["T_final"].min() < 0.01 and o["n_members"].max() > 10
+
+
+def test_relabel_invariance():
+    p, cams = tiny_scene(n=400, degree=3, size=40, log_s_shift=0.8)
+    perm = np.random.default_rng(9).permutation(p.shape[1])
+    a = O.render(p, 3, cams[0])
+    b = O.render(p[:, perm], 3, cams[0])
+    assert (a["ztie"] > 0).all()            # no exact depth ties
+    np.testing.assert_allclose(a["image"], b["image"], atol=1e-15)
+
+
+def test_termination_floor():
+    # a stack of opaque Gaussians on the axis: the walk must stop before
+    # transmittance drops below 1e-4 (0.01^2 = 1e-4 is not below, 0.01^3 is)
+    cam = S.config_cameras("c1")[0]
+    gs = [_single([0.5 - 0.1 * k, 0, 0], [math.log(0.5)] * 3, logit=12.0, rgb=(1, 1, 1)) for k in range(5)]
+    p = np.concatenate(gs, 1)
+    o = O.render(p, 0, cam)
+    c = (cam.height // 2, cam.width // 2)
+    assert o["n_members"][c] == 2
+    assert o["T_final"][c] == pytest.approx(1e-4, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Backward (Section 3.2.4): finite differences and torch autograd
+# ---------------------------------------------------------------------------
+
+def _decisions(p, degree, cams):
+    sig = []
+    for cam in cams:
+        r = O.render(p, degree, cam)
+        rec = O.project(p, degree, cam)
+        sig.append((r["hash"].copy(), rec[:, [0, 14, 15, 16, 17, 21, 22, 23, 30, 31]].copy()))
+    return sig
+
+
+def _same(a, b):
+    return all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("degree,shift", [(3, 0.9), (0, 1.2)])
+def test_backward_matches_finite_differences(degree, shift):
+    p, cams = tiny_scene(n=64, degree=degree, size=32, log_s_shift=shift)
+    rng = np.random.default_rng(11)
+    wimg = rng.standard_normal((len(cams), 3, 32, 32))
+
+    def loss(pp):
+        return sum((O.render(pp, degree, c)["image"] * wimg[v]).sum() for v, c in enumerate(cams))
+
+    grads, _, _ = O.render_backward(p, degree, cams, wimg)
+    base = _decisions(p, degree, cams)
+    R, n = p.shape
+    checked = skipped = 0
+    gmax = np.abs(grads).max()
+    for g in range(0, n, 3):
+        for row in range(R):
+            h = 1e-6 * max(abs(p[row, g]), 0.1)
+            pp, pm = p.copy(), p.copy()
+            pp[row, g] += h
+            pm[row, g] -= h
+            if not (_same(_decisions(pp, degree, cams), base) and _same(_decisions(pm, degree, cams), base)):
+                skipped += 1
+                continue
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            assert abs(fd - grads[row, g]) <= 1e-6 * gmax + 1e-5 * abs(grads[row, g]), (row, g, fd, grads[row, g])
+            checked += 1
+    assert checked > 0.95 * (checked + skipped)
+
+
+@pytest.mark.parametrize("degree,shift,bg", [(3, 0.9, (0.0, 0.0, 0.0)), (3, 1.3, (0.3, 0.6, 0.1)),
+                                             (0, 1.0, (0.0, 0.0, 0.0))])
+def test_backward_matches_torch_autograd(degree, shift, bg):
+    p, cams = tiny_scene(n=64, degree=degree, size=32, log_s_shift=shift, n_cams=2)
+    rng = np.random.default_rng(12)
+    wimg = rng.standard_normal((len(cams), 3, 32, 32))
+    pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    L = sum((render_dense(pt, degree, c, bg) * torch.tensor(wimg[v])).sum() for v, c in enumerate(cams))
+    L.backward()
+    ref = pt.grad.numpy()
+    # the forward of the dense route equals the oracle image
+    for v, c in enumerate(cams):
+        np.testing.assert_allclose(render_dense(pt.detach(), degree, c, bg).numpy(),
+                                   O.render(p, degree, c, bg=bg)["image"], atol=1e-12)
+    grads, _, _ = O.render_backward(p, degree, cams, wimg, bg=bg)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(grads, ref, atol=1e-9 * scale, rtol=1e-9)
+
+
+def test_backward_frozen_rows_untouched_and_active_unchanged():
+    p, cams = tiny_scene(n=64, degree=3, size=32, log_s_shift=0.9)
+    wimg = np.random.default_rng(13).standard_normal((2, 3, 32, 32))
+    frozen = (np.arange(64) % 3 == 0).astype(np.uint8)
+    init = np.full((p.shape[0], 64), 7.0)
+    g_all, _, _ = O.render_backward(p, 3, cams, wimg)
+    g_fz, _, _ = O.render_backward(p, 3, cams, wimg, frozen=frozen, grads_init=init)
+    assert (g_fz[:, frozen == 1] == 7.0).all()
+    np.testing.assert_array_equal(g_fz[:, frozen == 0], g_all[:, frozen == 0])
+
+
+# ---------------------------------------------------------------------------
+# Adam (Section 3.2.4 optimizer restricted to non-frozen Gaussians)
+# ---------------------------------------------------------------------------
+
+def test_adam_matches_torch_optim():
+    rng = np.random.default_rng(14)
+    R, n = 14, 50
+    p0 = rng.standard_normal((R, n))
+    lrs = np.linspace(1e-3, 2e-2, R)
+    pt = [torch.tensor(p0[r].copy(), requires_grad=True) for r in range(R)]
+    opt = torch.optim.Adam([{"params": [pt[r]], "lr": float(lrs[r])} for r in range(R)],
+                           betas=(0.9, 0.999), eps=1e-15)
+    p, m, v = p0.copy(), np.zeros((R, n)), np.zeros((R, n))
+    for step in range(1, 6):
+        g = rng.standard_normal((R, n))
+        for r in range(R):
+            pt[r].grad = torch.tensor(g[r].copy())
+        opt.step()
+        p, m, v = O.adam_masked(p, g, m, v, lrs, 0.9, 0.999, 1e-15, step)
+        np.testing.assert_allclose(p, np.stack([x.detach().numpy() for x in pt]), rtol=1e-12, atol=1e-14)
+
+
+def test_adam_first_step_closed_form_and_frozen():
+    rng = np.random.default_rng(15)
+    R, n = 59, 40
+    p0, g = rng.standard_normal((R, n)), rng.standard_normal((R, n))
+    lrs = np.full(R, 0.01)
+    p1, m1, v1 = O.adam_masked(p0, g, np.zeros((R, n)), np.zeros((R, n)), lrs, 0.9, 0.999, 1e-15, 1)
+    np.testing.assert_allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-15), rtol=1e-12)
+    frozen = np.ones(n, np.uint8)
+    m0, v0 = rng.random((R, n)), rng.random((R, n))
+    p2, m2, v2 = O.adam_masked(p0, g, m0, v0, lrs, 0.9, 0.999, 1e-15, 3, frozen)
+    assert np.array_equal(p2, p0) and np.array_equal(m2, m0) and np.array_equal(v2, v0)
+
+
+# ---------------------------------------------------------------------------
+# Scores and freezing (eqs. 4-6) and the host schedule (eqs. 5, 7; Section 3.2.3)
+# ---------------------------------------------------------------------------
+
+def test_freeze_rule_hand_cases():
+    sx = np.array([1e-5, 1e-5, 5e-5, 2e-5, 3e-5, np.finfo(np.float32).max], np.float32)
+    sr = np.array([1e-5, 2e-4, 1e-5, 9e-5, 1e-5, 0.0], np.float32)
+    old = np.array([0, 1, 0, 0, 0, 0], np.uint8)
+    # eq. 4 strict: 3e-5 is not < 3e-5; eq. 6: both groups must pass
+    assert list(O.freeze_update(old, sx, sr, 3e-5, 1e-4, 0)) == [1, 1, 0, 1, 0, 0]
+    assert list(O.freeze_update(old, sx, sr, 3e-5, 1e-4, 2)) == [1, 0, 0, 1, 0, 0]
+    assert list(O.freeze_update(old, sx, sr, 3e-5, 1e-4, 1)) == [0] * 6
+    prop = np.array([0, 0, 1, 0, 0, 0], np.uint8)
+    assert list(O.freeze_update(old, sx, sr, 3e-5, 1e-4, 0, prop)) == [1, 1, 1, 1, 0, 0]
+
+
+def test_ema_hand_cases():
+    big = np.finfo(np.float32).max
+    ema = np.array([big, 2.0, 2.0, 2.0])
+    g = np.array([0.5, 1.0, 1.0, 1.0])
+    vis = np.array([1, 1, 0, 1])
+    fz = np.array([0, 0, 0, 1])
+    out = O.ema_update(ema, g, vis, fz, 0.9)
+    np.testing.assert_allclose(out, [0.5, 1.9, 2.0, 2.0])
+
+
+def test_scores_definition():
+    g = np.zeros((59, 2))
+    g[0:3, 0] = [3, 4, 0]
+    g[11:14, 0] = [0, 0, 2]
+    g[10, 1] = -0.5
+    g[3:6, 1] = [1, 2, 2]
+    gx, gr, go, gs = O.scores(g)
+    assert list(gx) == [5, 0] and list(gr) == [2, 0] and list(go) == [0, 0.5] and list(gs) == [0, 3]
+
+
+def test_threshold_schedule_hand_values():
+    e0, K = 3e-5, 2000
+    assert O.freeze_threshold(0, K, e0) == pytest.approx(1.5e-5)
+    assert O.freeze_threshold(1000, K, e0) == pytest.approx(3.75e-5)
+    assert O.freeze_threshold(2000, K, e0) == pytest.approx(4.5e-5)
+    assert O.freeze_threshold(1500, K, e0, k_stop=1000) == pytest.approx(3.75e-5)
+    assert O.freeze_threshold(1000, K, e0, linear=True) == pytest.approx(3e-5)
+
+
+def test_early_stop_hand_sequences():
+    assert not O.early_stop([20.0, 25.0])
+    assert not O.early_stop([20.0, 25.0, 25.1])          # earlier gain 5 dB
+    assert O.early_stop([20.0, 25.0, 25.1, 25.15])        # gains 0.1, 0.05
+    assert not O.early_stop([25.0, 25.1, 25.5])           # latest gain 0.4
+
+
+def test_plateau_lr_hand_sequence():
+    s = O.PlateauLR(factor=0.75, patience=1, eps=1.0)
+    seq = [20.0, 20.5, 20.8, 22.0, 22.3, 22.4, 22.5, 22.6]
+    scales = [s.step(x) for x in seq]
+    assert scales == [1, 1, 0.75, 0.75, 0.75, 0.5625, 0.5625, 0.421875]

@@ -1,0 +1,204 @@
+/*
+ * gsta.h -- C ABI of libgsta, the MI355X (gfx950) training hot path of GSta
+ * ("GSta: Efficient Training Scheme with Siestaed Gaussians for Monocular 3D
+ * Scene Reconstruction", arXiv 2504.06716).
+ *
+ * One training iteration of the paper's Algorithm 1 maps to:
+ *   rasterize(G, freeze_map, cam_pose)           -> gsta_render_forward + gsta_render_backward
+ *   loss_fcn(gt_image, render_image)             -> gsta_l1_loss
+ *   optimizer_step(G, lr, loss, freeze_map)      -> gsta_adam_masked
+ *   update_freeze_map / reset_freeze_map         -> gsta_update_freeze_mask
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked (host).  The caller owns
+ *     every argument buffer; the library owns only the scratch held in the
+ *     context, allocated by gsta_create / gsta_reserve.  No other call
+ *     allocates device memory.
+ *   - Work is enqueued on `stream` and the call returns without
+ *     synchronising, except gsta_create, gsta_reserve, gsta_destroy and
+ *     gsta_check.
+ *   - Arguments are validated on the host before anything is enqueued; an
+ *     invalid call returns GSTA_ERR_INVALID, enqueues nothing and leaves a
+ *     message for gsta_last_error.  Conditions only the device can see (tile
+ *     instance overflow, non-finite values) raise flags that gsta_check
+ *     reports.
+ *   - A context is not thread-safe.  Calls that share a context must be
+ *     issued on one stream (or ordered by the caller).
+ *
+ * Parameter block (Section 3.1: a Gaussian is a mean, a scale, a rotation
+ * quaternion, an opacity and SH colour coefficients up to 3 bands, 59
+ * numbers at degree 3).  Structure of arrays, float32, R rows of stride ld:
+ *   rows 0-2   mean (world x, y, z)
+ *   rows 3-5   log-scale per local axis (scale = exp)
+ *   rows 6-9   quaternion (w, x, y, z), normalised inside the library
+ *   row  10    opacity logit (opacity = sigmoid)
+ *   rows 11..  SH coefficients, row 11 + 3*k + channel, k < (D+1)^2
+ * R = 11 + 3*(D+1)^2, D = sh_degree in 0..3.  Element (r, i) is at
+ * block[r * ld + i]; ld >= n.
+ */
+#ifndef GSTA_H
+#define GSTA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSTA_OK = 0,
+    GSTA_ERR_INVALID = 1,    /* bad argument; nothing was enqueued */
+    GSTA_ERR_CAPACITY = 2,   /* (gsta_check) tile instances exceeded the reserved capacity */
+    GSTA_ERR_HIP = 3,        /* a HIP runtime call failed; see gsta_last_error */
+    GSTA_ERR_OOM = 4,        /* scratch allocation failed in create/reserve */
+    GSTA_ERR_NONFINITE = 5   /* (gsta_check) a non-finite gradient reached the optimizer */
+} gsta_status;
+
+typedef struct gsta_ctx gsta_ctx;  /* opaque; owns all scratch */
+
+/* Sizes the scratch is reserved for (host struct). */
+typedef struct {
+    int64_t max_gaussians;      /* N */
+    int32_t max_views;          /* views per render call */
+    int32_t max_height, max_width;
+    int64_t instance_capacity;  /* (view, tile, Gaussian) pairs per render call; <= 2^32-1 */
+    int32_t tile_w, tile_h;     /* must be 16 x 16 */
+    int32_t n_slots;            /* forward states kept for a later backward (>= 1) */
+} gsta_limits;
+
+/* Pinhole camera (host struct).  Camera frame: x right, y down, z forward.
+ * Pixel (px, py) has its centre at integer coordinates; a camera-space point
+ * (x, y, z) lands at u = fx*x/z + cx, v = fy*y/z + cy. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float world_to_cam[12];     /* row-major [R | t]: x_cam = R x_world + t */
+    float cam_pos[3];           /* camera centre in world coordinates (SH view direction) */
+    float near_z;               /* Gaussians with camera depth <= near_z are culled */
+} gsta_camera;
+
+/* A parameter-shaped block (host struct holding a device pointer). */
+typedef struct {
+    int64_t n;                  /* Gaussians */
+    int64_t ld;                 /* row stride in elements, >= n */
+    int32_t sh_degree;          /* 0..3 */
+    float* block;               /* device, [R][ld] float32 */
+} gsta_params;
+
+/* Fields readable with gsta_get_state (after gsta_render_forward). */
+typedef enum {
+    GSTA_STATE_REC_GEO = 0,     /* float4 [V][N]: u, v, conic_a, conic_b           */
+    GSTA_STATE_REC_COL = 1,     /* float4 [V][N]: conic_c, opacity, depth z, 0      */
+    GSTA_STATE_REC_RGB = 2,     /* float4 [V][N]: r, g, b (clamped colour), 0      */
+    GSTA_STATE_RECT = 3,        /* uint16x4 [V][N]: tile x0, x1, y0, y1 (exclusive ends); all 0 if culled */
+    GSTA_STATE_DEPTH_ORDER = 4, /* uint32 [V][N]: gid in ascending (float32 depth, gid) order, culled last */
+    GSTA_STATE_INST_KEYS = 5,   /* uint32 [I]: view * T + tile of each instance, sorted */
+    GSTA_STATE_INST_IDS = 6,    /* uint32 [I]: gid of each instance (depth order within a tile) */
+    GSTA_STATE_RANGES = 7,      /* uint32x2 [V*T]: [start, end) of each (view, tile) in the instance list */
+    GSTA_STATE_T_FINAL = 8,     /* float [V][H][W]: transmittance left after the last member */
+    GSTA_STATE_LAST = 9,        /* uint32 [V][H][W]: tile-list index + 1 of the last member (0 if none) */
+    GSTA_STATE_N_INSTANCES = 10 /* uint64 [1]: instances generated (may exceed capacity) */
+} gsta_state_field;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Allocates the scratch for `lim` on the current HIP device. */
+gsta_status gsta_create(const gsta_limits* lim, gsta_ctx** out);
+/* Grows (never shrinks) the scratch; synchronises the device first. */
+gsta_status gsta_reserve(gsta_ctx* ctx, const gsta_limits* lim);
+void gsta_destroy(gsta_ctx* ctx);
+/* Message for the last non-OK status returned on this context ("" if none). */
+const char* gsta_last_error(const gsta_ctx* ctx);
+/* Synchronises `stream`, then reports and clears the device flags:
+ * GSTA_ERR_CAPACITY if a render overflowed the instance capacity,
+ * GSTA_ERR_NONFINITE if the optimizer met a non-finite gradient.  The
+ * largest instance count any render needed since the last check is written
+ * to *max_instances (host, may be NULL). */
+gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances);
+/* Copies `bytes` of an internal field of forward state `slot` into device
+ * memory `dst` (stream-ordered).  For tests and tools. */
+gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst, int64_t bytes,
+                           hipStream_t stream);
+
+/* ---- the hot path ------------------------------------------------------- */
+
+/* Section 3.1, eqs. 1-2.  Renders n_views views of the Gaussians `g`:
+ * per Gaussian, the EWA projection (covariance R S S^T R^T, Jacobian of the
+ * perspective map with tangent ratios clamped to 1.3x the half field of view,
+ * 2-D covariance + 0.3 I, conic = its inverse), SH colour + 0.5 clamped at 0,
+ * opacity = sigmoid(logit); Gaussians with depth <= near_z are culled.  Each
+ * Gaussian is binned to every 16x16 tile that meets the bounding box of its
+ * 3-sigma ellipse; per tile the list is in ascending (float32 depth, gid)
+ * order.  Each pixel composites front to back the Gaussians with
+ * power = -0.5 d^T conic d >= -4.5 and alpha = min(0.99, o exp(power)) >=
+ * 1/255, stopping before the one that would take the transmittance below
+ * 1e-4:  C = sum c_i alpha_i T_i + T_final * bg.
+ *   cams  (host) [n_views]; every view must have the same width and height.
+ *   bg    (host) [3] background colour.
+ *   image [n_views][3][H][W] float32 output.
+ *   state_slot in [0, n_slots): the forward state (binning, T_final, last
+ *   member) is kept there for gsta_render_backward.
+ * Returns GSTA_ERR_INVALID for sizes beyond the reserved limits. */
+gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                int32_t n_views, const float* bg, float* image, int32_t state_slot,
+                                hipStream_t stream);
+
+/* Section 3.2.4.  Backward of gsta_render_forward for the same g, cams,
+ * n_views, bg and state_slot (checked).  dL_dimage [n_views][3][H][W].
+ * Per pixel the transmittance is recomputed front to back (nothing per
+ * (pixel, Gaussian) is stored).  Gaussians with frozen[i] != 0 still
+ * attenuate the pixels behind them, but get no gradient work: their rows of
+ * `grad` are not written.  Rows of active Gaussians are overwritten with the
+ * gradient summed over the views.  frozen [n] uint8 or NULL (none frozen).
+ *   grad2d  optional [n_views][9][n] float32 output: dL/d(u, v, conic_a,
+ *           conic_b, conic_c, opacity, r, g, b) per view (0 where frozen or
+ *           untouched); NULL to skip.
+ *   ema     optional [4][n] float32 in/out: exponential moving averages of
+ *           |dL/dmean|, |dL/d(DC colour)|, |dL/dlogit|, |dL/dlog-scale| for
+ *           active Gaussians visible in >= 1 view: s <- b*s + (1-b)*g, and
+ *           s <- g where s is FLT_MAX (never seen).  NULL to skip.
+ *   ema_beta in [0, 1). */
+gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                 int32_t n_views, const float* bg, int32_t state_slot,
+                                 const float* dL_dimage, const uint8_t* frozen, gsta_params* grad,
+                                 float* grad2d, float* ema, float ema_beta, hipStream_t stream);
+
+/* Section 3.2.4 (optimizer that updates only non-frozen Gaussians).  Adam
+ * with bias correction on every row of the block:
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   p <- p - lr[row] * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * Columns with frozen[i] != 0 keep p, m and v bit-unchanged.
+ * p, grad, m, v share n and sh_degree (their ld may differ).
+ *   lr_per_row (host) [R];  step >= 1 is the global step;  frozen [n] or NULL.
+ * A non-finite gradient in an active column raises the NONFINITE flag (the
+ * update is still applied). */
+gsta_status gsta_adam_masked(gsta_ctx* ctx, gsta_params* p, const gsta_params* grad, gsta_params* m,
+                             gsta_params* v, const float* lr_per_row, float beta1, float beta2,
+                             float eps, int32_t step, const uint8_t* frozen, hipStream_t stream);
+
+/* Section 3.2.1, eqs. 4 and 6, with the accumulation and reset of the freeze
+ * map.  cond_i = (score_xyz[i] < eps_xyz) && (score_rgb[i] < eps_rgb)
+ * (strict, float32), or proposal[i] != 0 when `proposal` is given.
+ *   mode 0: frozen[i] |= cond_i  (frozen Gaussians stay frozen)
+ *   mode 1: frozen[i] = 0        (reset; scores unused, may be NULL)
+ *   mode 2: frozen[i] = cond_i   (overwrite)
+ * n_frozen (device int64 [1]) receives the number of frozen Gaussians after
+ * the update (may be NULL). */
+gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const float* score_rgb,
+                                    int64_t n, float eps_xyz, float eps_rgb, int32_t mode,
+                                    const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen,
+                                    hipStream_t stream);
+
+/* Eq. 3 with lambda_SSIM = 0: L = mean |C - C*| over `count` values.
+ *   dL_dimage[j] = sign(C_j - C*_j) / count (sign(0) = 0).
+ *   sums (device double [2]) receive sum |C - C*| and sum (clamp(C,0,1) - C*)^2
+ *   (the loss is sums[0] / count, the PSNR 10 log10(count / sums[1])). */
+gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,
+                         float* dL_dimage, double* sums, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSTA_H */

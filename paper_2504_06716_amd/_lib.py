@@ -1,0 +1,86 @@
+"""ctypes binding of libgsta (include/gsta.h): the same entry points, with
+plain integers for device pointers and streams.  Argument marshalling only;
+every step runs in the HIP library, which must be built (see build.py)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsta.so")
+
+GSTA_OK, GSTA_ERR_INVALID, GSTA_ERR_CAPACITY, GSTA_ERR_HIP, GSTA_ERR_OOM, GSTA_ERR_NONFINITE = range(6)
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NONFINITE"}
+
+(STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
+ STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES) = range(11)
+
+
+class Limits(ctypes.Structure):
+    _fields_ = [("max_gaussians", ctypes.c_int64), ("max_views", ctypes.c_int32),
+                ("max_height", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("instance_capacity", ctypes.c_int64), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("n_slots", ctypes.c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("world_to_cam", ctypes.c_float * 12), ("cam_pos", ctypes.c_float * 3),
+                ("near_z", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("block", ctypes.c_void_p)]
+
+
+class GstaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gsta error {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
+           "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
+           "gsta_update_freeze_mask", "gsta_l1_loss"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libgsta.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgsta.so not found at {path}: build it with "
+                           "`python -m paper_2504_06716_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(path)
+    P, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    PP = ctypes.POINTER(Params)
+    L.gsta_create.argtypes = [ctypes.POINTER(Limits), ctypes.POINTER(P)]
+    L.gsta_reserve.argtypes = [P, ctypes.POINTER(Limits)]
+    L.gsta_destroy.argtypes = [P]
+    L.gsta_destroy.restype = None
+    L.gsta_last_error.argtypes = [P]
+    L.gsta_last_error.restype = ctypes.c_char_p
+    L.gsta_check.argtypes = [P, P, ctypes.POINTER(i64)]
+    L.gsta_get_state.argtypes = [P, i32, i32, P, i64, P]
+    L.gsta_render_forward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, i32, P]
+    L.gsta_render_backward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), i32, P, P,
+                                       PP, P, P, f32, P]
+    L.gsta_adam_masked.argtypes = [P, PP, PP, PP, PP, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
+    L.gsta_update_freeze_mask.argtypes = [P, P, P, i64, f32, f32, i32, P, P, P, P]
+    L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
+    for name in EXPORTS:
+        if name not in ("gsta_destroy", "gsta_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(ctx, status: int):
+    if status != GSTA_OK:
+        msg = load().gsta_last_error(ctx)
+        raise GstaError(status, msg.decode() if msg else "")

@@ -1,0 +1,153 @@
+"""Tensor-level wrappers of the libgsta entry points.
+
+PyTorch provides device memory and the stream; every computation runs in
+the HIP kernels behind the C ABI.  Tensors must be CUDA(HIP) float32 and
+contiguous in the layouts documented in include/gsta.h.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Camera, Limits, Params, check
+
+MAX_VIEWS = 8
+
+
+def n_rows(degree: int) -> int:
+    return 11 + 3 * (degree + 1) ** 2
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.data_ptr()
+
+
+def params_struct(block: torch.Tensor, degree: int) -> Params:
+    """[R, n] float32 device tensor (row stride = block.stride(0))."""
+    if block.dtype != torch.float32 or block.dim() != 2:
+        raise ValueError("parameter blocks are [R, n] float32")
+    if block.shape[0] != n_rows(degree):
+        raise ValueError(f"expected {n_rows(degree)} rows for SH degree {degree}, got {block.shape[0]}")
+    n = block.shape[1]
+    if n == 0:
+        return Params(0, 1, degree, block.data_ptr() or None)
+    if block.stride(1) != 1 or block.stride(0) < n:
+        raise ValueError("parameter blocks need unit column stride and row stride >= n")
+    return Params(n, block.stride(0), degree, block.data_ptr())
+
+
+def camera_struct(cam) -> Camera:
+    """From a synthetic.Camera-like object (width, height, fx, fy, cx, cy, R, t, campos, near)."""
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    w2c = np.concatenate([np.asarray(cam.R, np.float64), np.asarray(cam.t, np.float64)[:, None]], 1)
+    c.world_to_cam[:] = [float(x) for x in w2c.reshape(-1).astype(np.float32)]
+    c.cam_pos[:] = [float(x) for x in np.asarray(cam.campos, np.float32)]
+    c.near_z = float(cam.near)
+    return c
+
+
+def camera_array(cams) -> ctypes.Array:
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera_struct(c)
+    return arr
+
+
+def _f3(bg):
+    return (ctypes.c_float * 3)(*[float(x) for x in bg])
+
+
+class Context:
+    """Owns a libgsta context (all scratch is allocated here, once)."""
+
+    def __init__(self, max_gaussians, max_views=1, max_height=64, max_width=64,
+                 instance_capacity=1 << 20, n_slots=1):
+        self.L = _lib.load()
+        self.limits = Limits(int(max_gaussians), int(max_views), int(max_height), int(max_width),
+                             int(instance_capacity), 16, 16, int(n_slots))
+        h = ctypes.c_void_p()
+        st = self.L.gsta_create(ctypes.byref(self.limits), ctypes.byref(h))
+        self.h = h
+        if st != _lib.GSTA_OK:
+            msg = self.L.gsta_last_error(h) if h else b"create failed"
+            if h:
+                self.L.gsta_destroy(h)
+            self.h = None
+            raise _lib.GstaError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gsta_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, **kw):
+        lim = Limits(*[kw.get(f, getattr(self.limits, f)) for f, _ in Limits._fields_])
+        check(self.h, self.L.gsta_reserve(self.h, ctypes.byref(lim)))
+        self.limits = lim
+
+    def check(self, stream=None):
+        """Synchronise; returns (status, max instances needed since the last check)."""
+        mi = ctypes.c_int64(0)
+        st = self.L.gsta_check(self.h, _stream(stream), ctypes.byref(mi))
+        return st, mi.value
+
+    def get_state(self, slot, field, out: torch.Tensor, stream=None):
+        check(self.h, self.L.gsta_get_state(self.h, slot, field, out.data_ptr(),
+                                             out.numel() * out.element_size(), _stream(stream)))
+        return out
+
+    # ---- hot path --------------------------------------------------------
+    def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None):
+        ps = params_struct(params, degree)
+        ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        check(self.h, self.L.gsta_render_forward(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
+                                                  _ptr(image), slot, _stream(stream)))
+
+    def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
+                        grad2d=None, ema=None, ema_beta=0.9, stream=None):
+        ps = params_struct(params, degree)
+        gs = params_struct(grad, degree)
+        ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        check(self.h, self.L.gsta_render_backward(
+            self.h, ctypes.byref(ps), ca, len(ca), _f3(bg), slot, _ptr(dL_dimage), _ptr(frozen),
+            ctypes.byref(gs), _ptr(grad2d), _ptr(ema), float(ema_beta), _stream(stream)))
+
+    def adam_masked(self, p, g, m, v, degree, lr_rows, beta1, beta2, eps, step, frozen=None, stream=None):
+        R = n_rows(degree)
+        lr = (ctypes.c_float * R)(*[float(x) for x in lr_rows])
+        sp, sg, sm, sv = (params_struct(x, degree) for x in (p, g, m, v))
+        check(self.h, self.L.gsta_adam_masked(self.h, ctypes.byref(sp), ctypes.byref(sg), ctypes.byref(sm),
+                                               ctypes.byref(sv), lr, float(beta1), float(beta2), float(eps),
+                                               int(step), _ptr(frozen), _stream(stream)))
+
+    def update_freeze_mask(self, score_xyz, score_rgb, eps_xyz, eps_rgb, mode, frozen,
+                           proposal=None, n_frozen=None, stream=None):
+        n = frozen.numel()
+        check(self.h, self.L.gsta_update_freeze_mask(self.h, _ptr(score_xyz), _ptr(score_rgb), n,
+                                                      float(eps_xyz), float(eps_rgb), int(mode),
+                                                      _ptr(proposal), _ptr(frozen), _ptr(n_frozen),
+                                                      _stream(stream)))
+
+    def l1_loss(self, image, target, dL_dimage, sums, stream=None):
+        check(self.h, self.L.gsta_l1_loss(self.h, _ptr(image), _ptr(target), image.numel(),
+                                           _ptr(dL_dimage), _ptr(sums), _stream(stream)))

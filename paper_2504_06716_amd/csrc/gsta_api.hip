@@ -1,0 +1,451 @@
+// C ABI of libgsta: context and scratch management, argument validation and
+// the order of kernel launches for each entry point (see include/gsta.h).
+#include "../../include/gsta.h"
+#include "gsta_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace gsta;
+
+namespace {
+
+struct Slot {
+    float4* geo = nullptr;
+    float4* col = nullptr;
+    float4* rgb = nullptr;
+    ushort4* rect = nullptr;
+    uint32_t* dkey[2] = {nullptr, nullptr};
+    uint32_t* dval[2] = {nullptr, nullptr};
+    uint32_t* ikey[2] = {nullptr, nullptr};
+    uint32_t* ival[2] = {nullptr, nullptr};
+    uint2* ranges = nullptr;
+    float* T_final = nullptr;
+    uint32_t* last = nullptr;
+    double* cfg = nullptr;
+    uint64_t* n_total = nullptr;
+    uint32_t* n_count = nullptr;
+    // what the last forward in this slot rendered
+    int depth_buf = 0, inst_buf = 0;
+    bool valid = false;
+    int64_t n = 0, ld = 0;
+    int degree = 0;
+    const float* block = nullptr;
+    int nv = 0;
+    gsta_camera cams[kMaxViews];
+    float bg[3] = {0.f, 0.f, 0.f};
+};
+
+}  // namespace
+
+struct gsta_ctx {
+    gsta_limits lim{};
+    int64_t stride = 0;       // per-view row stride of per-Gaussian scratch
+    int64_t tiles_max = 0;    // tiles per view at the reserved size
+    std::vector<Slot> slots;
+    std::vector<void*> allocs;
+    uint32_t* hist = nullptr;
+    uint32_t* digit_tot = nullptr;
+    int64_t chunks_depth = 0, chunks_inst = 0;
+    uint64_t* partials = nullptr;
+    float* grad2d = nullptr;  // [V][9][stride]
+    uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient
+    uint64_t* max_inst = nullptr;
+    std::string err;
+};
+
+namespace {
+
+gsta_status fail(gsta_ctx* ctx, gsta_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+gsta_status hip_check(gsta_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return GSTA_OK;
+    return fail(ctx, GSTA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_all(gsta_ctx* ctx) {
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    ctx->allocs.clear();
+    ctx->slots.clear();
+}
+
+template <typename T>
+bool alloc(gsta_ctx* ctx, T** p, int64_t count) {
+    void* q = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) return false;
+    ctx->allocs.push_back(q);
+    *p = reinterpret_cast<T*>(q);
+    return true;
+}
+
+int64_t tiles_of(int w, int h) { return (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile); }
+
+gsta_status check_limits(gsta_ctx* ctx, const gsta_limits* l) {
+    if (!l) return fail(ctx, GSTA_ERR_INVALID, "limits is NULL");
+    if (l->max_gaussians < 1 || l->max_gaussians > (int64_t)0x7FFFFFFF)
+        return fail(ctx, GSTA_ERR_INVALID, "max_gaussians out of range: %lld", (long long)l->max_gaussians);
+    if (l->max_views < 1 || l->max_views > kMaxViews)
+        return fail(ctx, GSTA_ERR_INVALID, "max_views must be in [1, %d]", kMaxViews);
+    if (l->max_width < 1 || l->max_height < 1 || l->max_width > 16384 || l->max_height > 16384)
+        return fail(ctx, GSTA_ERR_INVALID, "max image size out of range");
+    if (l->tile_w != kTile || l->tile_h != kTile) return fail(ctx, GSTA_ERR_INVALID, "tiles must be 16x16");
+    if (l->instance_capacity < 1 || l->instance_capacity > (int64_t)0xFFFFFFFFll)
+        return fail(ctx, GSTA_ERR_INVALID, "instance_capacity must be in [1, 2^32-1]");
+    if (l->n_slots < 1 || l->n_slots > 64) return fail(ctx, GSTA_ERR_INVALID, "n_slots must be in [1, 64]");
+    if (tiles_of(l->max_width, l->max_height) * l->max_views > 65536)
+        return fail(ctx, GSTA_ERR_INVALID, "views x tiles must fit 16-bit tile keys (<= 65536)");
+    return GSTA_OK;
+}
+
+gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
+    ctx->lim = *l;
+    const int64_t V = l->max_views;
+    ctx->stride = (l->max_gaussians + 63) / 64 * 64;
+    ctx->tiles_max = tiles_of(l->max_width, l->max_height);
+    const int64_t S = ctx->stride, cap = l->instance_capacity;
+    const int64_t HW = (int64_t)l->max_width * l->max_height;
+    ctx->slots.assign((size_t)l->n_slots, Slot());
+    bool ok = true;
+    for (Slot& s : ctx->slots) {
+        ok = ok && alloc(ctx, &s.geo, V * S) && alloc(ctx, &s.col, V * S) && alloc(ctx, &s.rgb, V * S) &&
+             alloc(ctx, &s.rect, V * S) && alloc(ctx, &s.dkey[0], V * S) && alloc(ctx, &s.dkey[1], V * S) &&
+             alloc(ctx, &s.dval[0], V * S) && alloc(ctx, &s.dval[1], V * S) && alloc(ctx, &s.ikey[0], cap) &&
+             alloc(ctx, &s.ikey[1], cap) && alloc(ctx, &s.ival[0], cap) && alloc(ctx, &s.ival[1], cap) &&
+             alloc(ctx, &s.ranges, V * ctx->tiles_max) && alloc(ctx, &s.T_final, V * HW) &&
+             alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
+             alloc(ctx, &s.n_count, 1);
+    }
+    ctx->chunks_depth = radix_chunks(S);
+    ctx->chunks_inst = radix_chunks(cap);
+    const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
+    ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
+         alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->grad2d, V * 9 * S) &&
+         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1);
+    if (!ok) {
+        free_all(ctx);
+        return fail(ctx, GSTA_ERR_OOM, "device allocation failed");
+    }
+    if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        free_all(ctx);
+        return fail(ctx, GSTA_ERR_HIP, "initialising flags failed");
+    }
+    return GSTA_OK;
+}
+
+bool cam_ok(const gsta_camera& c) {
+    return c.width > 0 && c.height > 0 && std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx > 0.f &&
+           c.fy > 0.f && std::isfinite(c.cx) && std::isfinite(c.cy) && std::isfinite(c.near_z) &&
+           c.near_z > 0.f;
+}
+
+DevCam to_dev(const gsta_camera& c) {
+    DevCam d;
+    d.width = c.width;
+    d.height = c.height;
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) d.R[3 * r + k] = c.world_to_cam[4 * r + k];
+        d.t[r] = c.world_to_cam[4 * r + 3];
+        d.pos[r] = c.cam_pos[r];
+    }
+    d.near_z = c.near_z;
+    d.limx = kTanClamp * (0.5f * (float)c.width) / c.fx;
+    d.limy = kTanClamp * (0.5f * (float)c.height) / c.fy;
+    d.ntx = (c.width + kTile - 1) / kTile;
+    d.nty = (c.height + kTile - 1) / kTile;
+    return d;
+}
+
+gsta_status check_params(gsta_ctx* ctx, const gsta_params* g, const char* name) {
+    if (!g) return fail(ctx, GSTA_ERR_INVALID, "%s is NULL", name);
+    if (!g->block && g->n > 0) return fail(ctx, GSTA_ERR_INVALID, "%s.block is NULL", name);
+    if (g->n < 0 || g->n > ctx->lim.max_gaussians)
+        return fail(ctx, GSTA_ERR_INVALID, "%s.n = %lld outside [0, max_gaussians = %lld]", name,
+                    (long long)g->n, (long long)ctx->lim.max_gaussians);
+    if (g->ld < g->n || g->ld < 1) return fail(ctx, GSTA_ERR_INVALID, "%s.ld < n", name);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GSTA_ERR_INVALID, "%s.sh_degree not in 0..3", name);
+    return GSTA_OK;
+}
+
+gsta_status check_views(gsta_ctx* ctx, const gsta_camera* cams, int32_t nv, CamArray& ca) {
+    if (!cams) return fail(ctx, GSTA_ERR_INVALID, "cams is NULL");
+    if (nv < 1 || nv > ctx->lim.max_views)
+        return fail(ctx, GSTA_ERR_INVALID, "n_views = %d outside [1, %d]", nv, ctx->lim.max_views);
+    for (int v = 0; v < nv; ++v) {
+        if (!cam_ok(cams[v])) return fail(ctx, GSTA_ERR_INVALID, "camera %d is invalid", v);
+        if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
+            return fail(ctx, GSTA_ERR_INVALID, "all views of a call must share width and height");
+        if (cams[v].width > ctx->lim.max_width || cams[v].height > ctx->lim.max_height)
+            return fail(ctx, GSTA_ERR_INVALID, "image %dx%d exceeds the reserved %dx%d", cams[v].width,
+                        cams[v].height, ctx->lim.max_width, ctx->lim.max_height);
+        ca.c[v] = to_dev(cams[v]);
+    }
+    for (int v = nv; v < kMaxViews; ++v) ca.c[v] = ca.c[0];
+    return GSTA_OK;
+}
+
+int key_bits(int64_t keys) {
+    int b = 1;
+    while (((int64_t)1 << b) < keys) ++b;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsta_status gsta_create(const gsta_limits* lim, gsta_ctx** out) {
+    if (!out) return GSTA_ERR_INVALID;
+    *out = nullptr;
+    gsta_ctx* ctx = new gsta_ctx();
+    gsta_status st = check_limits(ctx, lim);
+    if (st == GSTA_OK) st = allocate(ctx, lim);
+    if (st != GSTA_OK) {
+        // keep the context so the caller can read the message
+        *out = ctx;
+        return st;
+    }
+    *out = ctx;
+    return GSTA_OK;
+}
+
+gsta_status gsta_reserve(gsta_ctx* ctx, const gsta_limits* lim) {
+    if (!ctx) return GSTA_ERR_INVALID;
+    gsta_status st = check_limits(ctx, lim);
+    if (st != GSTA_OK) return st;
+    gsta_limits nl = ctx->lim;
+    nl.max_gaussians = std::max(nl.max_gaussians, lim->max_gaussians);
+    nl.max_views = std::max(nl.max_views, lim->max_views);
+    nl.max_height = std::max(nl.max_height, lim->max_height);
+    nl.max_width = std::max(nl.max_width, lim->max_width);
+    nl.instance_capacity = std::max(nl.instance_capacity, lim->instance_capacity);
+    nl.n_slots = std::max(nl.n_slots, lim->n_slots);
+    if (memcmp(&nl, &ctx->lim, sizeof(nl)) == 0 && !ctx->allocs.empty()) return GSTA_OK;
+    st = check_limits(ctx, &nl);
+    if (st != GSTA_OK) return st;
+    if ((st = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize")) != GSTA_OK) return st;
+    free_all(ctx);
+    return allocate(ctx, &nl);
+}
+
+void gsta_destroy(gsta_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    free_all(ctx);
+    delete ctx;
+}
+
+const char* gsta_last_error(const gsta_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = hip_check(ctx, hipStreamSynchronize(stream), "hipStreamSynchronize")) != GSTA_OK) return st;
+    uint32_t flags[4] = {0, 0, 0, 0};
+    uint64_t mi = 0;
+    if ((st = hip_check(ctx, hipMemcpy(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost), "read flags")) != GSTA_OK)
+        return st;
+    if ((st = hip_check(ctx, hipMemcpy(&mi, ctx->max_inst, sizeof(mi), hipMemcpyDeviceToHost), "read counts")) != GSTA_OK)
+        return st;
+    const uint32_t zeros[4] = {0, 0, 0, 0};
+    const uint64_t z64 = 0;
+    if ((st = hip_check(ctx, hipMemcpy(ctx->flags, zeros, sizeof(zeros), hipMemcpyHostToDevice), "clear flags")) != GSTA_OK)
+        return st;
+    if ((st = hip_check(ctx, hipMemcpy(ctx->max_inst, &z64, sizeof(z64), hipMemcpyHostToDevice), "clear counts")) != GSTA_OK)
+        return st;
+    if (max_instances) *max_instances = (int64_t)mi;
+    if (flags[0]) return fail(ctx, GSTA_ERR_CAPACITY, "tile instances (%llu) exceeded the capacity (%lld)",
+                              (unsigned long long)mi, (long long)ctx->lim.instance_capacity);
+    if (flags[1]) return fail(ctx, GSTA_ERR_NONFINITE, "non-finite gradient met by the optimizer");
+    return GSTA_OK;
+}
+
+gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst, int64_t bytes,
+                           hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (slot < 0 || slot >= (int)ctx->slots.size()) return fail(ctx, GSTA_ERR_INVALID, "bad slot %d", slot);
+    Slot& s = ctx->slots[slot];
+    if (!s.valid) return fail(ctx, GSTA_ERR_INVALID, "slot %d holds no forward state", slot);
+    if (!dst) return fail(ctx, GSTA_ERR_INVALID, "dst is NULL");
+    const int64_t n = s.n, V = s.nv, S = ctx->stride;
+    const int64_t HW = (int64_t)s.cams[0].width * s.cams[0].height;
+    const int64_t T = tiles_of(s.cams[0].width, s.cams[0].height);
+    const void* src = nullptr;
+    int64_t elem = 0, rows = 1, row_elems = 0, src_pitch = 0;
+    switch (field) {
+        case GSTA_STATE_REC_GEO: src = s.geo; elem = 16; rows = V; row_elems = n; src_pitch = S; break;
+        case GSTA_STATE_REC_COL: src = s.col; elem = 16; rows = V; row_elems = n; src_pitch = S; break;
+        case GSTA_STATE_REC_RGB: src = s.rgb; elem = 16; rows = V; row_elems = n; src_pitch = S; break;
+        case GSTA_STATE_RECT: src = s.rect; elem = 8; rows = V; row_elems = n; src_pitch = S; break;
+        case GSTA_STATE_DEPTH_ORDER: src = s.dval[s.depth_buf]; elem = 4; rows = V; row_elems = n; src_pitch = S; break;
+        case GSTA_STATE_INST_KEYS: src = s.ikey[s.inst_buf]; elem = 4; row_elems = ctx->lim.instance_capacity; src_pitch = row_elems; break;
+        case GSTA_STATE_INST_IDS: src = s.ival[s.inst_buf]; elem = 4; row_elems = ctx->lim.instance_capacity; src_pitch = row_elems; break;
+        case GSTA_STATE_RANGES: src = s.ranges; elem = 8; row_elems = V * T; src_pitch = row_elems; break;
+        case GSTA_STATE_T_FINAL: src = s.T_final; elem = 4; row_elems = V * HW; src_pitch = row_elems; break;
+        case GSTA_STATE_LAST: src = s.last; elem = 4; row_elems = V * HW; src_pitch = row_elems; break;
+        case GSTA_STATE_N_INSTANCES: src = s.n_total; elem = 8; row_elems = 1; src_pitch = 1; break;
+        default: return fail(ctx, GSTA_ERR_INVALID, "unknown state field %d", field);
+    }
+    const int64_t full = rows * row_elems * elem;
+    if (bytes < 0 || bytes > full) return fail(ctx, GSTA_ERR_INVALID, "bytes %lld > field size %lld", (long long)bytes, (long long)full);
+    if (rows == 1 || src_pitch == row_elems) {
+        return hip_check(ctx, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, stream), "copy state");
+    }
+    if (bytes != full) return fail(ctx, GSTA_ERR_INVALID, "per-view fields are copied whole (%lld bytes)", (long long)full);
+    return hip_check(ctx, hipMemcpy2DAsync(dst, (size_t)(row_elems * elem), src, (size_t)(src_pitch * elem),
+                                           (size_t)(row_elems * elem), (size_t)rows, hipMemcpyDeviceToDevice, stream),
+                     "copy state");
+}
+
+gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                int32_t n_views, const float* bg, float* image, int32_t state_slot,
+                                hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    CamArray ca;
+    if ((st = check_views(ctx, cams, n_views, ca)) != GSTA_OK) return st;
+    if (!bg) return fail(ctx, GSTA_ERR_INVALID, "bg is NULL");
+    if (!image) return fail(ctx, GSTA_ERR_INVALID, "image is NULL");
+    if (state_slot < 0 || state_slot >= (int)ctx->slots.size())
+        return fail(ctx, GSTA_ERR_INVALID, "state_slot %d outside [0, %d)", state_slot, (int)ctx->slots.size());
+    Slot& s = ctx->slots[state_slot];
+    const int64_t n = g->n, S = ctx->stride;
+    const int nv = n_views;
+    const int ntx = ca.c[0].ntx;
+    const int64_t T = (int64_t)ca.c[0].ntx * ca.c[0].nty;
+
+    if (n > 0)
+        launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
+                              s.dkey[0], s.dval[0], S, stream);
+    RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth};
+    s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
+    launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total, s.n_count,
+                  s.ikey[0], s.ival[0], (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, stream);
+    RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst};
+    s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
+    launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, T * nv, stream);
+    launch_composite_fwd(s.ranges, s.ival[s.inst_buf], s.geo, s.col, s.rgb, S, ca, nv, bg[0], bg[1], bg[2],
+                         image, s.T_final, s.last, s.cfg, stream);
+    if ((st = hip_check(ctx, hipGetLastError(), "render_forward launch")) != GSTA_OK) {
+        s.valid = false;
+        return st;
+    }
+    s.valid = true;
+    s.n = n;
+    s.ld = g->ld;
+    s.degree = g->sh_degree;
+    s.block = g->block;
+    s.nv = nv;
+    for (int v = 0; v < nv; ++v) s.cams[v] = cams[v];
+    for (int c = 0; c < 3; ++c) s.bg[c] = bg[c];
+    return GSTA_OK;
+}
+
+gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                 int32_t n_views, const float* bg, int32_t state_slot,
+                                 const float* dL_dimage, const uint8_t* frozen, gsta_params* grad,
+                                 float* grad2d, float* ema, float ema_beta, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, grad, "grad")) != GSTA_OK) return st;
+    CamArray ca;
+    if ((st = check_views(ctx, cams, n_views, ca)) != GSTA_OK) return st;
+    if (!bg || !dL_dimage) return fail(ctx, GSTA_ERR_INVALID, "bg or dL_dimage is NULL");
+    if (grad->n != g->n || grad->sh_degree != g->sh_degree)
+        return fail(ctx, GSTA_ERR_INVALID, "grad must match g in n and sh_degree");
+    if (!(ema_beta >= 0.f && ema_beta < 1.f)) return fail(ctx, GSTA_ERR_INVALID, "ema_beta must be in [0, 1)");
+    if (state_slot < 0 || state_slot >= (int)ctx->slots.size())
+        return fail(ctx, GSTA_ERR_INVALID, "state_slot %d outside [0, %d)", state_slot, (int)ctx->slots.size());
+    Slot& s = ctx->slots[state_slot];
+    if (!s.valid) return fail(ctx, GSTA_ERR_INVALID, "state_slot %d holds no forward state", state_slot);
+    bool same = s.n == g->n && s.ld == g->ld && s.degree == g->sh_degree && s.block == g->block && s.nv == n_views &&
+                memcmp(s.cams, cams, sizeof(gsta_camera) * n_views) == 0 && s.bg[0] == bg[0] && s.bg[1] == bg[1] &&
+                s.bg[2] == bg[2];
+    if (!same) return fail(ctx, GSTA_ERR_INVALID, "backward arguments differ from the forward in slot %d", state_slot);
+    const int64_t n = g->n, S = ctx->stride;
+    const int nv = n_views;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->grad2d), 0u, (int64_t)nv * 9 * S, stream);
+    launch_composite_bwd(s.ranges, s.ival[s.inst_buf], s.geo, s.col, s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2],
+                         s.T_final, s.last, s.cfg, dL_dimage, ctx->grad2d, stream);
+    if (n > 0)
+        launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, S, ctx->grad2d, frozen,
+                              grad->block, grad->ld, ema, ema_beta, stream);
+    if (grad2d && n > 0) {
+        st = hip_check(ctx, hipMemcpy2DAsync(grad2d, (size_t)n * 4, ctx->grad2d, (size_t)S * 4, (size_t)n * 4,
+                                             (size_t)nv * 9, hipMemcpyDeviceToDevice, stream),
+                       "copy grad2d");
+        if (st != GSTA_OK) return st;
+    }
+    return hip_check(ctx, hipGetLastError(), "render_backward launch");
+}
+
+gsta_status gsta_adam_masked(gsta_ctx* ctx, gsta_params* p, const gsta_params* grad, gsta_params* m,
+                             gsta_params* v, const float* lr_per_row, float beta1, float beta2, float eps,
+                             int32_t step, const uint8_t* frozen, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, p, "p")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, grad, "grad")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, m, "m")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, v, "v")) != GSTA_OK) return st;
+    if (grad->n != p->n || m->n != p->n || v->n != p->n || grad->sh_degree != p->sh_degree ||
+        m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+        return fail(ctx, GSTA_ERR_INVALID, "p, grad, m, v must share n and sh_degree");
+    if (!lr_per_row) return fail(ctx, GSTA_ERR_INVALID, "lr_per_row is NULL");
+    if (step < 1) return fail(ctx, GSTA_ERR_INVALID, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(ctx, GSTA_ERR_INVALID, "betas must be in [0, 1) and eps >= 0");
+    const int rows = n_rows(p->sh_degree);
+    LrArray lr;
+    for (int r = 0; r < 64; ++r) lr.lr[r] = r < rows ? lr_per_row[r] : 0.f;
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    if (p->n > 0)
+        launch_adam(p->block, p->ld, grad->block, grad->ld, m->block, m->ld, v->block, v->ld, p->n, rows, lr, beta1,
+                    beta2, eps, bc1, bc2, frozen, ctx->flags, stream);
+    return hip_check(ctx, hipGetLastError(), "adam launch");
+}
+
+gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const float* score_rgb, int64_t n,
+                                    float eps_xyz, float eps_rgb, int32_t mode, const uint8_t* proposal,
+                                    uint8_t* frozen, int64_t* n_frozen, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (mode < 0 || mode > 2) return fail(ctx, GSTA_ERR_INVALID, "mode must be 0, 1 or 2");
+    if (n < 0) return fail(ctx, GSTA_ERR_INVALID, "n < 0");
+    if (!frozen && n > 0) return fail(ctx, GSTA_ERR_INVALID, "frozen is NULL");
+    if (mode != 1 && n > 0 && (!score_xyz || !score_rgb))
+        return fail(ctx, GSTA_ERR_INVALID, "scores are NULL");
+    launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
+    return hip_check(ctx, hipGetLastError(), "freeze launch");
+}
+
+gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,
+                         float* dL_dimage, double* sums, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (count < 1) return fail(ctx, GSTA_ERR_INVALID, "count must be >= 1");
+    if (!image || !target || !dL_dimage || !sums) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    launch_l1(image, target, count, dL_dimage, sums, stream);
+    return hip_check(ctx, hipGetLastError(), "l1 launch");
+}
+
+}  // extern "C"

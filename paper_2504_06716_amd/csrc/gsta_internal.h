@@ -1,0 +1,137 @@
+// Internal declarations of libgsta: device-side camera record, helpers
+// shared by several kernels, and the host launchers the C ABI calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsta {
+
+constexpr int kTile = 16;                 // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;   // one thread per pixel of a tile
+constexpr int kMaxViews = 8;              // views per render call (kernel-argument camera array)
+
+// Rasterizer conventions (3D Gaussian splatting; the paper builds on it).
+constexpr float kDilate = 0.3f;           // added to the diagonal of the 2-D covariance
+constexpr float kTanClamp = 1.3f;         // tangent ratio clamp inside the EWA Jacobian
+constexpr float kPowerFloor = -4.5f;      // 3-sigma ellipse
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+struct DevCam {
+    int width, height;
+    float fx, fy, cx, cy;
+    float R[9];          // world -> camera rotation, row-major
+    float t[3];
+    float pos[3];        // camera centre (world)
+    float near_z;
+    float limx, limy;    // tangent clamp limits
+    int ntx, nty;        // tiles per row / column
+};
+
+struct CamArray {
+    DevCam c[kMaxViews];
+};
+
+struct LrArray {
+    float lr[64];
+};
+
+inline __host__ __device__ int n_rows(int degree) { return 11 + 3 * (degree + 1) * (degree + 1); }
+
+// -------------------------------------------------------------------------
+// Splat evaluation shared by the forward and backward compositing kernels.
+// Both kernels must take bit-identical membership/termination decisions and
+// transmittance values, so the arithmetic lives in one place with
+// floating-point contraction disabled.
+// -------------------------------------------------------------------------
+struct SplatEval {
+    float dx, dy, power, G, oG, alpha;
+};
+
+__device__ __forceinline__ void eval_splat(float u, float v, float ca, float cb, float cc, float o,
+                                           float px, float py, SplatEval& e) {
+#pragma clang fp contract(off)
+    e.dx = u - px;
+    e.dy = v - py;
+    e.power = -0.5f * (ca * e.dx * e.dx + cc * e.dy * e.dy) - cb * e.dx * e.dy;
+    e.G = __builtin_amdgcn_exp2f(e.power * kLog2e);
+    e.oG = o * e.G;
+    e.alpha = fminf(kAlphaMax, e.oG);
+}
+
+__device__ __forceinline__ float next_T(float T, float alpha) {
+#pragma clang fp contract(off)
+    return T * (1.0f - alpha);
+}
+
+// Wave-wide (64 lanes) float sum, result valid in every lane.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// -------------------------------------------------------------------------
+// Host launchers (all asynchronous on `s`).
+// -------------------------------------------------------------------------
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+
+void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
+                           int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, hipStream_t s);
+
+void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
+                           int nv, const ushort4* rect, int64_t stride, const float* grad2d,
+                           const uint8_t* frozen, float* G, int64_t gld, float* ema, float beta,
+                           hipStream_t s);
+
+// LSD radix sort of (key, value) pairs, `nseg` independent segments of
+// seg_stride elements; element count per segment from d_count (device, if
+// not null) or h_count.  Sorts `bits` low-order key bits.  Returns which
+// buffer (0 or 1) holds the result.
+struct RadixScratch {
+    uint32_t* hist;          // [nseg][256][nchunks_cap]
+    uint32_t* digit_tot;     // [nseg][256]
+    int64_t nchunks_cap;
+};
+int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
+                     const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
+                     hipStream_t s);
+int64_t radix_chunks(int64_t count);
+
+// Depth-ordered tile-instance expansion: counts per Gaussian in depth
+// order, exclusive scan, write (view*T + tile, gid) for every touched tile.
+void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
+                   int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint64_t capacity,
+                   uint32_t* flags, uint64_t* max_inst, hipStream_t s);
+int64_t expand_blocks(int64_t elements);
+
+void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
+                   int64_t n_ranges, hipStream_t s);
+
+void launch_composite_fwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
+                          const float4* col, const float4* rgb, int64_t stride, const CamArray& cams,
+                          int nv, float bg0, float bg1, float bg2, float* image, float* T_final,
+                          uint32_t* last, double* cfg, hipStream_t s);
+
+void launch_composite_bwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
+                          const float4* col, const float4* rgb, int64_t stride, const uint8_t* frozen,
+                          const CamArray& cams, int nv, float bg0, float bg1, float bg2,
+                          const float* T_final, const uint32_t* last, const double* cfg,
+                          const float* dL_dimage, float* grad2d, hipStream_t s);
+
+void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
+                 int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
+                 float bc1, float bc2, const uint8_t* frozen, uint32_t* flags, hipStream_t s);
+
+void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
+                   const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s);
+
+void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums,
+               hipStream_t s);
+
+}  // namespace gsta

@@ -1,0 +1,171 @@
+// Element-wise steps: L1 loss (eq. 3, lambda_SSIM = 0), masked Adam
+// (Section 3.2.4: frozen Gaussians are not updated) and the freeze-map update
+// (Section 3.2.1, eqs. 4 and 6).
+#include "gsta_internal.h"
+
+namespace gsta {
+namespace {
+
+// Masked Adam over the [rows][n] block.  Grid: x over columns (4 per thread
+// when every stride allows 16-byte access), y over rows.  A frozen column is
+// skipped before any of its p, g, m, v bytes are read.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, int64_t pld,
+                                              const float* __restrict__ g, int64_t gld,
+                                              float* __restrict__ m, int64_t mld, float* __restrict__ v,
+                                              int64_t vld, int64_t n, LrArray lr, float b1, float b2,
+                                              float eps, float bc1, float bc2,
+                                              const uint8_t* __restrict__ frozen,
+                                              uint32_t* __restrict__ flags) {
+    const int row = blockIdx.y;
+    const float lrr = lr.lr[row];
+    const float ib1 = 1.f - b1, ib2 = 1.f - b2;
+    const float rbc1 = 1.f / bc1, rbc2 = 1.f / bc2;
+    bool bad = false;
+    if (VEC) {
+        const int64_t i4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+        if (i4 >= n) return;
+        if (i4 + 4 <= n) {
+            uchar4 fz = frozen ? *reinterpret_cast<const uchar4*>(frozen + i4) : make_uchar4(0, 0, 0, 0);
+            if ((fz.x & fz.y & fz.z & fz.w) != 0) return;
+            float4 pp = *reinterpret_cast<const float4*>(p + row * pld + i4);
+            float4 gg = *reinterpret_cast<const float4*>(g + row * gld + i4);
+            float4 mm = *reinterpret_cast<const float4*>(m + row * mld + i4);
+            float4 vv = *reinterpret_cast<const float4*>(v + row * vld + i4);
+            float* pe = &pp.x; float* ge = &gg.x; float* me = &mm.x; float* ve = &vv.x;
+            const uint8_t fe[4] = {fz.x, fz.y, fz.z, fz.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (fe[k]) continue;
+                const float gk = ge[k];
+                bad |= !isfinite(gk);
+                me[k] = b1 * me[k] + ib1 * gk;
+                ve[k] = b2 * ve[k] + ib2 * gk * gk;
+                pe[k] -= lrr * (me[k] * rbc1) / (sqrtf(ve[k] * rbc2) + eps);
+            }
+            *reinterpret_cast<float4*>(p + row * pld + i4) = pp;
+            *reinterpret_cast<float4*>(m + row * mld + i4) = mm;
+            *reinterpret_cast<float4*>(v + row * vld + i4) = vv;
+        } else {
+            for (int64_t i = i4; i < n; ++i) {
+                if (frozen && frozen[i]) continue;
+                const float gk = g[row * gld + i];
+                bad |= !isfinite(gk);
+                float mk = b1 * m[row * mld + i] + ib1 * gk;
+                float vk = b2 * v[row * vld + i] + ib2 * gk * gk;
+                m[row * mld + i] = mk;
+                v[row * vld + i] = vk;
+                p[row * pld + i] -= lrr * (mk * rbc1) / (sqrtf(vk * rbc2) + eps);
+            }
+        }
+    } else {
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= n) return;
+        if (frozen && frozen[i]) return;
+        const float gk = g[row * gld + i];
+        bad = !isfinite(gk);
+        float mk = b1 * m[row * mld + i] + ib1 * gk;
+        float vk = b2 * v[row * vld + i] + ib2 * gk * gk;
+        m[row * mld + i] = mk;
+        v[row * vld + i] = vk;
+        p[row * pld + i] -= lrr * (mk * rbc1) / (sqrtf(vk * rbc2) + eps);
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_freeze(const float* __restrict__ sx, const float* __restrict__ sr,
+                                                int64_t n, float ex, float er, int mode,
+                                                const uint8_t* __restrict__ proposal,
+                                                uint8_t* __restrict__ frozen,
+                                                unsigned long long* __restrict__ n_frozen) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool f = false;
+    if (i < n) {
+        bool cond = false;
+        if (mode != 1) {
+            cond = (sx[i] < ex) && (sr[i] < er);
+            if (proposal) cond = cond || (proposal[i] != 0);
+        }
+        f = (mode == 0) ? ((frozen[i] != 0) || cond) : (mode == 1 ? false : cond);
+        frozen[i] = f ? 1 : 0;
+    }
+    if (n_frozen) {
+        const uint64_t b = __ballot(f);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_frozen, (unsigned long long)__popcll(b));
+    }
+}
+
+__global__ void k_zero_i64(unsigned long long* p) { *p = 0ull; }
+
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt,
+                                            int64_t count, float* __restrict__ dL, double* __restrict__ sums) {
+    __shared__ double s_a[4], s_b[4];
+    const float inv = 1.0f / (float)count;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float c = img[i], t = tgt[i];
+        const float d = c - t;
+        dL[i] = (d > 0.f) ? inv : ((d < 0.f) ? -inv : 0.f);
+        a += (double)fabsf(d);
+        const double e = (double)fminf(fmaxf(c, 0.f), 1.f) - (double)t;
+        b += e * e;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_a[wid] = a;
+        s_b[wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&sums[0], s_a[0] + s_a[1] + s_a[2] + s_a[3]);
+        atomicAdd(&sums[1], s_b[0] + s_b[1] + s_b[2] + s_b[3]);
+    }
+}
+
+__global__ void k_zero_f64x2(double* p) {
+    p[0] = 0.0;
+    p[1] = 0.0;
+}
+
+}  // namespace
+
+void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
+                 int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
+                 float bc1, float bc2, const uint8_t* frozen, uint32_t* flags, hipStream_t s) {
+    const bool vec = (pld % 4 == 0) && (gld % 4 == 0) && (mld % 4 == 0) && (vld % 4 == 0) &&
+                     ((uintptr_t)p % 16 == 0) && ((uintptr_t)g % 16 == 0) && ((uintptr_t)m % 16 == 0) &&
+                     ((uintptr_t)v % 16 == 0) && (!frozen || (uintptr_t)frozen % 4 == 0);
+    if (vec) {
+        const int64_t threads = (n + 3) / 4;
+        k_adam<true><<<dim3((unsigned)((threads + 255) / 256), rows), 256, 0, s>>>(
+            p, pld, g, gld, m, mld, v, vld, n, lr, b1, b2, eps, bc1, bc2, frozen, flags);
+    } else {
+        k_adam<false><<<dim3((unsigned)((n + 255) / 256), rows), 256, 0, s>>>(
+            p, pld, g, gld, m, mld, v, vld, n, lr, b1, b2, eps, bc1, bc2, frozen, flags);
+    }
+}
+
+void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
+                   const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s) {
+    if (n_frozen) k_zero_i64<<<1, 1, 0, s>>>(reinterpret_cast<unsigned long long*>(n_frozen));
+    if (n > 0)
+        k_freeze<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+            sx, sr, n, ex, er, mode, proposal, frozen, reinterpret_cast<unsigned long long*>(n_frozen));
+}
+
+void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums,
+               hipStream_t s) {
+    k_zero_f64x2<<<1, 1, 0, s>>>(sums);
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    k_l1<<<(unsigned)blocks, 256, 0, s>>>(img, tgt, count, dL, sums);
+}
+
+}  // namespace gsta

@@ -1,0 +1,408 @@
+// Depth sort, tile binning and tile ranges.
+//
+// The paper blends Gaussians "in a sorted order" (Section 3.1).  Here the
+// order is (float32 camera depth, gid) per view, made in two stages:
+//   1. a stable LSD radix sort of the N depth keys of every view (the
+//      culled ones carry the largest key and sort last);
+//   2. a depth-ordered expansion of each Gaussian into one (view*T + tile,
+//      gid) instance per tile of its 3-sigma rectangle, followed by a stable
+//      radix sort of those 16-bit-or-less tile keys.  Stability keeps the
+//      depth order inside every tile.
+//
+// Radix sort: 8-bit digits, chunks of 4096 keys per workgroup iteration.
+//   hist    per-chunk digit counts -> hist[seg][digit][chunk]
+//   scan    one workgroup per (digit, seg) scans its chunk counts
+//   scatter per chunk: stable local ranks from wave ballots (multi-split),
+//           keys staged in LDS in digit order, then written out with
+//           consecutive lanes hitting consecutive addresses.
+// Counts may live on the device (the instance count is only known there):
+// kernels then run a grid-stride loop over the chunks that exist.
+#include "gsta_internal.h"
+
+namespace gsta {
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
+constexpr int RS_BINS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+
+__device__ __forceinline__ uint32_t seg_count(const uint32_t* d_count, uint32_t h_count) {
+    return d_count ? *d_count : h_count;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_tmp, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_tmp[wid] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+        uint32_t t = s_tmp[w];
+        base += (w < wid) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return base + incl - x;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                           int64_t seg_stride, const uint32_t* d_count,
+                                                           uint32_t h_count, int shift,
+                                                           uint32_t* __restrict__ hist,
+                                                           int64_t nchunks_cap) {
+    __shared__ uint32_t s_h[RS_BINS];
+    const int seg = blockIdx.y;
+    const uint32_t count = seg_count(d_count, h_count);
+    const int64_t nchunks = ((int64_t)count + RS_CHUNK - 1) / RS_CHUNK;
+    const uint32_t* k = keys + seg * seg_stride;
+    for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        s_h[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t base = chunk * RS_CHUNK;
+#pragma unroll 4
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            int64_t idx = base + it * RS_THREADS + threadIdx.x;
+            if (idx < count) atomicAdd(&s_h[(k[idx] >> shift) & 0xFFu], 1u);
+        }
+        __syncthreads();
+        hist[((int64_t)seg * RS_BINS + threadIdx.x) * nchunks_cap + chunk] = s_h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// One workgroup per (digit, segment): exclusive scan over the chunks.
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scan(uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ digit_tot,
+                                                           const uint32_t* d_count, uint32_t h_count,
+                                                           int64_t nchunks_cap) {
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    const int d = blockIdx.x, seg = blockIdx.y;
+    const uint32_t count = seg_count(d_count, h_count);
+    const int64_t nchunks = ((int64_t)count + RS_CHUNK - 1) / RS_CHUNK;
+    uint32_t* row = hist + ((int64_t)seg * RS_BINS + d) * nchunks_cap;
+    uint32_t carry = 0;
+    for (int64_t b = 0; b < nchunks; b += RS_THREADS) {
+        int64_t j = b + threadIdx.x;
+        uint32_t x = (j < nchunks) ? row[j] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan_256(x, s_tmp, tot);
+        if (j < nchunks) row[j] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) digit_tot[seg * RS_BINS + d] = carry;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t seg_stride, const uint32_t* d_count, uint32_t h_count, int shift,
+    int bits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot,
+    int64_t nchunks_cap) {
+    __shared__ uint32_t s_keys[RS_CHUNK];
+    __shared__ uint32_t s_vals[RS_CHUNK];
+    __shared__ uint32_t s_digit_base[RS_BINS];
+    __shared__ uint32_t s_wave_cnt[RS_WAVES][RS_BINS];
+    __shared__ uint32_t s_wave_off[RS_WAVES][RS_BINS];
+    __shared__ uint32_t s_run[RS_BINS];
+    __shared__ uint32_t s_local_start[RS_BINS];
+    __shared__ uint32_t s_tmp[RS_WAVES];
+
+    const int seg = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const uint32_t count = seg_count(d_count, h_count);
+    const int64_t nchunks = ((int64_t)count + RS_CHUNK - 1) / RS_CHUNK;
+    const uint32_t* ki = kin + seg * seg_stride;
+    const uint32_t* vi = vin + seg * seg_stride;
+    uint32_t* ko = kout + seg * seg_stride;
+    uint32_t* vo = vout + seg * seg_stride;
+    const uint32_t* hrow = hist + (int64_t)seg * RS_BINS * nchunks_cap;
+
+    {   // global start of each digit = exclusive scan of the digit totals
+        uint32_t tot;
+        uint32_t ex = block_excl_scan_256(digit_tot[seg * RS_BINS + tid], s_tmp, tot);
+        s_digit_base[tid] = ex;
+    }
+
+    for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        const int64_t base = chunk * RS_CHUNK;
+        const int n_valid = (int)min((int64_t)RS_CHUNK, (int64_t)count - base);
+        uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            int j = it * RS_THREADS + tid;
+            bool ok = j < n_valid;
+            key[it] = ok ? ki[base + j] : 0u;
+            val[it] = ok ? vi[base + j] : 0u;
+        }
+        s_run[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) s_wave_cnt[w][tid] = 0;
+        __syncthreads();
+
+        // Stable local ranks: items are taken in index order j = it*256 + tid,
+        // i.e. round by round, wave by wave, lane by lane.
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const int j = it * RS_THREADS + tid;
+            const bool ok = j < n_valid;
+            const uint32_t d = (key[it] >> shift) & 0xFFu;
+            uint64_t match = __ballot(ok);
+            for (int b = 0; b < bits; ++b) {
+                uint64_t bal = __ballot(ok && ((d >> b) & 1u));
+                match &= ((d >> b) & 1u) ? bal : ~bal;
+            }
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(match >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)match, 0u));
+            if (ok && below == 0) s_wave_cnt[wid][d] = (uint32_t)__popcll(match);
+            __syncthreads();
+            {
+                uint32_t r = s_run[tid];
+#pragma unroll
+                for (int w = 0; w < RS_WAVES; ++w) {
+                    s_wave_off[w][tid] = r;
+                    r += s_wave_cnt[w][tid];
+                    s_wave_cnt[w][tid] = 0;
+                }
+                s_run[tid] = r;
+            }
+            __syncthreads();
+            rank[it] = ok ? s_wave_off[wid][d] + below : 0u;
+        }
+
+        {   // chunk-local start of each digit
+            uint32_t tot;
+            s_local_start[tid] = block_excl_scan_256(s_run[tid], s_tmp, tot);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const int j = it * RS_THREADS + tid;
+            if (j < n_valid) {
+                const uint32_t d = (key[it] >> shift) & 0xFFu;
+                const uint32_t pos = s_local_start[d] + rank[it];
+                if (pos < (uint32_t)RS_CHUNK) {
+                    s_keys[pos] = key[it];
+                    s_vals[pos] = val[it];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const int p = it * RS_THREADS + tid;
+            if (p < n_valid) {
+                const uint32_t k = s_keys[p];
+                const uint32_t d = (k >> shift) & 0xFFu;
+                const uint32_t g = s_digit_base[d] + hrow[(int64_t)d * nchunks_cap + chunk] +
+                                   ((uint32_t)p - s_local_start[d]);
+                if (g < count) {
+                    ko[g] = k;
+                    vo[g] = s_vals[p];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Depth-ordered expansion into tile instances.
+// Element e = v*n + pos is the pos-th Gaussian of view v in depth order.
+// ---------------------------------------------------------------------------
+constexpr int EX_THREADS = 256;
+
+__device__ __forceinline__ uint32_t rect_tiles(ushort4 r) {
+    return (r.x < r.y && r.z < r.w) ? (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z) : 0u;
+}
+
+__global__ __launch_bounds__(EX_THREADS) void k_tile_count(const ushort4* __restrict__ rect,
+                                                           const uint32_t* __restrict__ order,
+                                                           int64_t stride, int64_t n, int64_t total_el,
+                                                           uint64_t* __restrict__ partials) {
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    const int64_t e = (int64_t)blockIdx.x * EX_THREADS + threadIdx.x;
+    uint32_t c = 0;
+    if (e < total_el) {
+        const int64_t v = e / n, pos = e - v * n;
+        const uint32_t gid = order[v * stride + pos];
+        c = rect_tiles(rect[v * stride + gid]);
+    }
+    uint32_t tot;
+    block_excl_scan_256(c, s_tmp, tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Single workgroup: exclusive scan of the per-block partials (uint64).
+__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ partials, int64_t nb,
+                                                        uint64_t* __restrict__ d_total,
+                                                        uint32_t* __restrict__ d_count,
+                                                        uint64_t capacity, uint32_t* flags,
+                                                        uint64_t* max_inst) {
+    __shared__ uint64_t s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < nb; b += 1024) {
+        int64_t j = b + tid;
+        uint64_t x = (j < nb) ? partials[j] : 0ull;
+        uint64_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            uint64_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wid] = incl;
+        __syncthreads();
+        uint64_t base = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            uint64_t t = s_w[w];
+            base += (w < wid) ? t : 0ull;
+            tot += t;
+        }
+        __syncthreads();
+        if (j < nb) partials[j] = carry + base + incl - x;
+        carry += tot;
+    }
+    if (tid == 0) {
+        *d_total = carry;
+        *d_count = (uint32_t)(carry < capacity ? carry : capacity);
+        if (carry > capacity) atomicOr(&flags[0], 1u);
+        atomicMax((unsigned long long*)max_inst, (unsigned long long)carry);
+    }
+}
+
+__global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict__ rect,
+                                                       const uint32_t* __restrict__ order, int64_t stride,
+                                                       int64_t n, int64_t total_el, int ntx,
+                                                       int tiles_per_view,
+                                                       const uint64_t* __restrict__ partials,
+                                                       uint32_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals, uint64_t capacity) {
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint32_t s_off[EX_THREADS + 1];
+    __shared__ uint32_t s_gid[EX_THREADS];
+    __shared__ ushort4 s_rect[EX_THREADS];
+    __shared__ uint32_t s_view[EX_THREADS];
+    const int tid = threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * EX_THREADS + tid;
+    uint32_t c = 0;
+    if (e < total_el) {
+        const int64_t v = e / n, pos = e - v * n;
+        const uint32_t gid = order[v * stride + pos];
+        const ushort4 r = rect[v * stride + gid];
+        c = rect_tiles(r);
+        s_gid[tid] = gid;
+        s_rect[tid] = r;
+        s_view[tid] = (uint32_t)v;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_256(c, s_tmp, tot);
+    s_off[tid] = ex;
+    if (tid == 0) s_off[EX_THREADS] = tot;
+    __syncthreads();
+    const uint64_t base = partials[blockIdx.x];
+    // Every instance of this block's Gaussians, one per thread in turn: find
+    // its Gaussian by binary search over the block-local offsets.
+    for (uint32_t j = tid; j < tot; j += EX_THREADS) {
+        int lo = 0, hi = EX_THREADS;    // s_off[lo] <= j < s_off[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= j) lo = mid; else hi = mid;
+        }
+        const ushort4 r = s_rect[lo];
+        const uint32_t t = j - s_off[lo];
+        const uint32_t w = (uint32_t)(r.y - r.x);
+        const uint32_t tx = r.x + t % w, ty = r.z + t / w;
+        const uint64_t dst = base + j;
+        if (dst < capacity) {
+            keys[dst] = s_view[lo] * (uint32_t)tiles_per_view + ty * (uint32_t)ntx + tx;
+            vals[dst] = s_gid[lo];
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* d_count,
+                         uint2* __restrict__ ranges) {
+    const uint32_t count = *d_count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
+        if (i + 1 == count || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+    }
+}
+
+int grid_for(int64_t chunks) {
+    int64_t g = chunks < 1 ? 1 : chunks;
+    return (int)(g > 2048 ? 2048 : g);
+}
+
+}  // namespace
+
+int64_t radix_chunks(int64_t count) { return (count + RS_CHUNK - 1) / RS_CHUNK; }
+
+int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
+                     const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
+                     hipStream_t s) {
+    int cur = 0;
+    const int grid_x = grid_for(d_count ? rs.nchunks_cap : radix_chunks(h_count));
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int pass_bits = (bits - shift) < 8 ? (bits - shift) : 8;
+        k_radix_hist<<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
+                                                                shift, rs.hist, rs.nchunks_cap);
+        k_radix_scan<<<dim3(RS_BINS, nseg), RS_THREADS, 0, s>>>(rs.hist, rs.digit_tot, d_count, h_count,
+                                                                 rs.nchunks_cap);
+        k_radix_scatter<<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(
+            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], seg_stride, d_count, h_count, shift,
+            pass_bits, rs.hist, rs.digit_tot, rs.nchunks_cap);
+        cur = 1 - cur;
+    }
+    return cur;
+}
+
+int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / EX_THREADS; }
+
+void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
+                   int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint64_t capacity,
+                   uint32_t* flags, uint64_t* max_inst, hipStream_t s) {
+    const int64_t total_el = n * nv;
+    const int64_t nb = expand_blocks(total_el);
+    if (nb > 0) k_tile_count<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, partials);
+    k_scan_partials<<<1, 1024, 0, s>>>(partials, nb, d_total, d_count, capacity, flags, max_inst);
+    if (nb > 0)
+        k_expand<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, ntx, tiles_per_view,
+                                                    partials, keys, vals, capacity);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_fill_u32<<<(unsigned)blocks, 256, 0, s>>>(p, value, count);
+}
+
+void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
+                   int64_t n_ranges, hipStream_t s) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * n_ranges, s);
+    int64_t blocks = (capacity + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_ranges<<<(unsigned)blocks, 256, 0, s>>>(keys, d_count, ranges);
+}
+
+}  // namespace gsta

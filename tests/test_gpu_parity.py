@@ -1,0 +1,385 @@
+"""GPU (libgsta through the C ABI) versus the FP64 oracle, element by element.
+
+Bars: depth keys, depth order, tile lists and freeze masks bit-exact (a
+Gaussian whose tile-rectangle edge or near-plane test lies within float32
+reach of its threshold may differ, and is left out); images within 1e-4 on
+pixels whose decisions are not within 1e-5 relative of a threshold;
+gradients within 1e-3 relative per parameter group."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from tests.gpu_util import (IMAGE_ATOL, MARGIN_NEAR, MARGIN_RECT_PX, MARGIN_VALUE, GpuScene,
+                            compare_grads, dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2504_06716_amd import _lib
+    return _lib
+
+
+def scene(kind):
+    """(params, degree, cams) for a named parity case."""
+    if kind == "tiny":
+        p = S.make_scene(64, 3, seed=0)
+        p[3:6] += 0.9
+        cams = [S.look_at(10.0 + 35.0 * k, 20.0 + 70.0 * k, 32, 32) for k in range(2)]
+        return p, 3, cams
+    if kind == "c1":
+        c = S.CONFIGS["c1"]
+        return S.make_scene(c["n"], 0), 0, S.config_cameras("c1")
+    if kind == "ragged":
+        p = S.make_scene(3000, 3, seed=5)
+        p[3:6] += 0.5
+        cams = [S.look_at(25.0, 130.0, 50, 37), S.look_at(-40.0, 10.0, 50, 37)]
+        return p, 3, cams
+    if kind == "deg1":
+        p = S.make_scene(1500, 1, seed=6)
+        p[3:6] += 0.6
+        return p, 1, [S.look_at(5.0, 60.0, 48, 48)]
+    if kind == "c2view":
+        c = S.CONFIGS["c2"]
+        return S.make_scene(c["n"], 3), 3, S.config_cameras("c2")[:1]
+    raise KeyError(kind)
+
+
+CASES = ["tiny", "c1", "ragged", "deg1"]
+
+
+def _margins(p, degree, cams):
+    recs = [O.project(p, degree, c) for c in cams]
+    marg = np.zeros(p.shape[1], bool)
+    for r in recs:
+        marg |= (r[:, 27] < MARGIN_RECT_PX) | (r[:, 25] < MARGIN_NEAR) | (r[:, 26] < MARGIN_NEAR)
+    return recs, marg
+
+
+@pytest.mark.parametrize("kind", CASES + ["c2view"])
+def test_preprocess_records(kind):
+    p, D, cams = scene(kind)
+    g = GpuScene(p, D, cams)
+    g.forward()
+    n, V = p.shape[1], len(cams)
+    from paper_2504_06716_amd import _lib as L
+    import torch
+    geo = g.state(L.STATE_REC_GEO, torch.float32, (V, n, 4))
+    col = g.state(L.STATE_REC_COL, torch.float32, (V, n, 4))
+    rgb = g.state(L.STATE_REC_RGB, torch.float32, (V, n, 4))
+    rect = g.state(L.STATE_RECT, torch.int16, (V, n, 4)).astype(np.int64) & 0xFFFF
+    recs, marg = _margins(p, D, cams)
+    for v in range(V):
+        r = recs[v]
+        gvis = rect[v, :, 0] < rect[v, :, 1]
+        ovis = r[:, 0] == 1
+        assert np.array_equal(gvis[~marg], ovis[~marg])
+        both = gvis & ovis
+        assert both.sum() > 0
+        # depth key: the correctly rounded float32 depth, bit-exact
+        assert np.array_equal(col[v, both, 2], r[both, 4].astype(np.float32))
+        np.testing.assert_allclose(geo[v, both, 0], r[both, 1], atol=2e-4, rtol=1e-6)
+        np.testing.assert_allclose(geo[v, both, 1], r[both, 2], atol=2e-4, rtol=1e-6)
+        cmax = np.maximum(np.abs(r[both, 9]), np.abs(r[both, 11]))
+        for k, j in ((2, 9), (3, 10)):
+            assert (np.abs(geo[v, both, k] - r[both, j]) <= 1e-4 * cmax).all()
+        assert (np.abs(col[v, both, 0] - r[both, 11]) <= 1e-4 * cmax).all()
+        np.testing.assert_allclose(col[v, both, 1], r[both, 24], atol=1e-6)
+        np.testing.assert_allclose(rgb[v, both, :3], r[both, 18:21], atol=2e-5)
+        ok = ~marg
+        assert np.array_equal(rect[v, ok & ovis], r[ok & ovis, 14:18].astype(np.int64))
+
+
+@pytest.mark.parametrize("kind", CASES + ["c2view"])
+def test_depth_order_and_tile_lists(kind):
+    p, D, cams = scene(kind)
+    g = GpuScene(p, D, cams)
+    g.forward()
+    import torch
+    from paper_2504_06716_amd import _lib as L
+    n, V = p.shape[1], len(cams)
+    order = g.state(L.STATE_DEPTH_ORDER, torch.int32, (V, n)).astype(np.int64)
+    ninst = int(g.state(L.STATE_N_INSTANCES, torch.int64, (1,))[0])
+    cam0 = cams[0]
+    ntx, nty = (cam0.width + 15) // 16, (cam0.height + 15) // 16
+    T = ntx * nty
+    keys = g.state(L.STATE_INST_KEYS, torch.int32, (ninst,)).astype(np.int64) & 0xFFFFFFFF
+    ids = g.state(L.STATE_INST_IDS, torch.int32, (ninst,)).astype(np.int64)
+    ranges = g.state(L.STATE_RANGES, torch.int32, (V * T, 2)).astype(np.int64)
+    assert (np.diff(keys) >= 0).all()
+    _, marg = _margins(p, D, cams)
+    mset = set(np.nonzero(marg)[0].tolist())
+    total = 0
+    for v, cam in enumerate(cams):
+        counts, oids, oorder = O.bin_tiles(p, D, cam)
+        nvis = len(oorder)
+        got = [x for x in order[v, :nvis] if x not in mset]
+        exp = [x for x in oorder if x not in mset]
+        assert got == exp
+        pos = 0
+        for t in range(T):
+            a, b = ranges[v * T + t]
+            glist = [x for x in ids[a:b] if x not in mset]
+            olist = [x for x in oids[pos:pos + counts[t]] if x not in mset]
+            pos += counts[t]
+            assert glist == olist, (v, t)
+            assert (keys[a:b] == v * T + t).all()
+        total += counts.sum()
+    if not mset:
+        assert ninst == total
+
+
+def _forward_compare(p, D, cams, bg=(0.0, 0.0, 0.0)):
+    g = GpuScene(p, D, cams, bg=bg)
+    img = g.forward()
+    import torch
+    from paper_2504_06716_amd import _lib as L
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    Tf = g.state(L.STATE_T_FINAL, torch.float32, (V, H, W))
+    excluded = 0
+    outs = []
+    for v, cam in enumerate(cams):
+        o = O.render(p, D, cam, bg=bg)
+        ok = o["m_value"] >= MARGIN_VALUE
+        excluded += (~ok).sum()
+        d = np.abs(img[v] - o["image"])
+        assert d[:, ok].max() <= IMAGE_ATOL, d[:, ok].max()
+        assert np.abs(Tf[v] - o["T_final"])[ok].max() <= IMAGE_ATOL
+        outs.append(o)
+    return g, img, outs, excluded / (V * H * W)
+
+
+@pytest.mark.parametrize("kind", CASES + ["c2view"])
+def test_forward_image(kind):
+    p, D, cams = scene(kind)
+    _, img, outs, frac = _forward_compare(p, D, cams)
+    assert frac < 0.01
+    assert img.max() > 0.05
+
+
+def test_forward_background_and_partial_tiles():
+    p, D, cams = scene("ragged")
+    _forward_compare(p, D, cams, bg=(0.3, 0.6, 0.1))
+
+
+def _backward_case(p, D, cams, frozen=None, bg=(0.0, 0.0, 0.0), seed=21):
+    g, img, outs, _ = _forward_compare(p, D, cams, bg=bg)
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    rng = np.random.default_rng(seed)
+    dL = rng.standard_normal((V, 3, H, W))
+    for v, o in enumerate(outs):
+        bad = (o["m_value"] < MARGIN_VALUE) | (o["m_grad"] < MARGIN_VALUE)
+        dL[v][:, bad] = 0.0
+    dL = dL.astype(np.float32)
+    grad, g2, _ = g.backward(dL, frozen=frozen, sentinel=7.0)
+    ref, ref2, _ = O.render_backward(p, D, cams, dL.astype(np.float64), frozen=frozen, bg=bg)
+    recs, marg = _margins(p, D, cams)
+    for r in recs:
+        marg |= (r[:, 28] < 1e-4) | (r[:, 29] < 1e-4)
+    act = np.ones(p.shape[1], bool) if frozen is None else frozen == 0
+    rep = compare_grads(grad[:, act], ref[:, act], exclude_cols=marg[act])
+    if frozen is not None:
+        assert (grad[:, ~act] == 7.0).all()
+    return grad, ref, rep
+
+
+@pytest.mark.parametrize("kind", CASES + ["c2view"])
+def test_backward_gradients(kind):
+    p, D, cams = scene(kind)
+    _backward_case(p, D, cams)
+
+
+def test_backward_with_background():
+    p, D, cams = scene("ragged")
+    _backward_case(p, D, cams, bg=(0.3, 0.6, 0.1))
+
+
+@pytest.mark.parametrize("kind", ["tiny", "c1", "ragged"])
+def test_backward_frozen_skip(kind):
+    p, D, cams = scene(kind)
+    frozen = (np.random.default_rng(3).random(p.shape[1]) < 0.4).astype(np.uint8)
+    grad_f, _, _ = _backward_case(p, D, cams, frozen=frozen)
+    grad_a, _, _ = _backward_case(p, D, cams)
+    act = frozen == 0
+    # active rows do not depend on which other Gaussians are frozen
+    np.testing.assert_allclose(grad_f[:, act], grad_a[:, act], rtol=1e-5,
+                               atol=1e-6 * np.abs(grad_a[:, act]).max())
+
+
+def test_ema_scores():
+    p, D, cams = scene("ragged")
+    g, img, outs, _ = _forward_compare(p, D, cams)
+    n = p.shape[1]
+    rng = np.random.default_rng(4)
+    big = np.finfo(np.float32).max
+    ema0 = np.where(rng.random((4, n)) < 0.3, big, rng.random((4, n)) * 1e-3).astype(np.float32)
+    frozen = (rng.random(n) < 0.2).astype(np.uint8)
+    dL = rng.standard_normal((len(cams), 3, cams[0].height, cams[0].width)).astype(np.float32)
+    for v, o in enumerate(outs):
+        dL[v][:, (o["m_value"] < MARGIN_VALUE) | (o["m_grad"] < MARGIN_VALUE)] = 0.0
+    _, _, ema = g.backward(dL, frozen=frozen, ema=ema0, beta=0.9)
+    ref, _, vis = O.render_backward(p, D, cams, dL.astype(np.float64), frozen=frozen)
+    sc = O.scores(ref)
+    visany = vis.any(0)
+    for k in range(4):
+        exp = O.ema_update(ema0[k].astype(np.float64), sc[k], visany, frozen, 0.9)
+        same = exp >= big
+        assert np.array_equal(ema[k] >= big, same)
+        np.testing.assert_allclose(ema[k][~same], exp[~same], rtol=2e-3,
+                                   atol=1e-3 * np.abs(exp[~same]).max())
+
+
+def test_multiview_batch_equals_single_views():
+    p = S.make_scene(2500, 3, seed=8)
+    p[3:6] += 0.5
+    cams = [S.look_at(-50.0 + 14.0 * k, 45.0 * k, 40, 40) for k in range(8)]
+    gb = GpuScene(p, 3, cams)
+    batch = gb.forward()
+    for v in range(8):
+        single = GpuScene(p, 3, cams[v:v + 1]).forward()
+        assert np.array_equal(batch[v], single[0])
+    _backward_case(p, 3, cams[:4])
+
+
+def test_empty_and_culled_scenes():
+    bg = (0.3, 0.6, 0.1)
+    cam = S.look_at(0.0, 0.0, 40, 24)
+    # no Gaussians
+    g = GpuScene(np.zeros((14, 0), np.float32), 0, [cam], bg=bg)
+    img = g.forward()
+    assert np.allclose(img[0], np.array(bg, np.float32)[:, None, None])
+    # every Gaussian behind the camera (camera at (3,0,0) looking along -x)
+    p = S.make_scene(50, 0, seed=2)
+    p[0] += 5.0
+    g = GpuScene(p, 0, [cam], bg=bg)
+    img = g.forward()
+    assert np.allclose(img[0], np.array(bg, np.float32)[:, None, None])
+    dL = np.ones((1, 3, 24, 40), np.float32)
+    big = np.finfo(np.float32).max
+    grad, _, ema = g.backward(dL, ema=np.full((4, 50), big, np.float32))
+    assert (grad == 0).all()
+    assert (ema == big).all()
+
+
+def test_capacity_overflow_is_reported():
+    import paper_2504_06716_amd as G
+    p, D, cams = scene("c1")
+    ctx = G.Context(p.shape[1], 1, 64, 64, instance_capacity=200)
+    g = GpuScene(p, D, cams[:1], ctx=ctx)
+    g.forward()
+    st, need = ctx.check()
+    assert st == _lib().GSTA_ERR_CAPACITY and need > 200
+    ctx.reserve(instance_capacity=int(need))
+    g.forward()
+    st, _ = ctx.check()
+    assert st == _lib().GSTA_OK
+
+
+def test_invalid_arguments_rejected():
+    import torch
+    import paper_2504_06716_amd as G
+    p, D, cams = scene("tiny")
+    ctx = G.Context(64, 2, 32, 32, 1 << 16)
+    P = dev(p)
+    img = torch.empty((2, 3, 32, 32), device="cuda")
+    with pytest.raises(G.GstaError):                     # backward before any forward
+        ctx.render_backward(P, D, cams, (0, 0, 0), 0, img, None, torch.empty_like(P))
+    with pytest.raises(G.GstaError):                     # slot out of range
+        ctx.render_forward(P, D, cams, (0, 0, 0), img, slot=3)
+    big = S.look_at(0.0, 0.0, 64, 64)
+    with pytest.raises(G.GstaError):                     # image larger than reserved
+        ctx.render_forward(P, D, [big], (0, 0, 0), img)
+    ctx.render_forward(P, D, cams, (0, 0, 0), img)
+    with pytest.raises(G.GstaError):                     # cameras differ from the forward
+        ctx.render_backward(P, D, cams[::-1], (0, 0, 0), 0, img, None, torch.empty_like(P))
+    with pytest.raises(G.GstaError):                     # 65 Gaussians > reserved 64
+        ctx.render_forward(dev(S.make_scene(65, 3)), D, cams, (0, 0, 0), img)
+
+
+@pytest.mark.parametrize("ld_pad", [0, 1])
+def test_adam_masked_matches_oracle(ld_pad):
+    import torch
+    import paper_2504_06716_amd as G
+    rng = np.random.default_rng(5)
+    R, n = 59, 1003
+    ctx = G.Context(n + ld_pad, 1, 16, 16, 16)
+    blocks = [rng.standard_normal((R, n + ld_pad)).astype(np.float32) for _ in range(4)]
+    blocks[3] = np.abs(blocks[3])
+    frozen = (rng.random(n) < 0.3).astype(np.uint8)
+    lr = np.linspace(1e-3, 1e-2, R).astype(np.float32)
+    t = [dev(b)[:, :n] for b in blocks]
+    p, g, m, v = t
+    ctx.adam_masked(p, g, m, v, 3, lr, 0.9, 0.999, 1e-15, 7, dev(frozen))
+    torch.cuda.synchronize()
+    P, Mm, Vv = O.adam_masked(blocks[0][:, :n], blocks[1][:, :n], blocks[2][:, :n], blocks[3][:, :n],
+                              lr.astype(np.float64), 0.9, 0.999, 1e-15, 7, frozen)
+    gp, gm, gv = p.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy()
+    fz = frozen == 1
+    assert np.array_equal(gp[:, fz], blocks[0][:, :n][:, fz])
+    assert np.array_equal(gm[:, fz], blocks[2][:, :n][:, fz])
+    assert np.array_equal(gv[:, fz], blocks[3][:, :n][:, fz])
+    # p: a few float32 ulps of p plus a relative error of the applied update
+    p0 = blocks[0][:, :n].astype(np.float64)
+    err = np.abs(gp[:, ~fz] - P[:, ~fz])
+    assert (err <= 4e-7 * np.abs(P[:, ~fz]) + 1e-5 * np.abs(P - p0)[:, ~fz] + 1e-12).all()
+    np.testing.assert_allclose(gm[:, ~fz], Mm[:, ~fz], rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(gv[:, ~fz], Vv[:, ~fz], rtol=1e-6, atol=1e-8)
+
+
+def test_adam_nonfinite_flag():
+    import torch
+    import paper_2504_06716_amd as G
+    ctx = G.Context(64, 1, 16, 16, 16)
+    blocks = [torch.zeros((14, 64), device="cuda") for _ in range(4)]
+    blocks[1][3, 5] = float("nan")
+    ctx.adam_masked(*blocks, 0, [1e-3] * 14, 0.9, 0.999, 1e-15, 1)
+    st, _ = ctx.check()
+    assert st == _lib().GSTA_ERR_NONFINITE
+    assert ctx.check()[0] == _lib().GSTA_OK
+
+
+def test_freeze_mask_bit_exact():
+    import torch
+    import paper_2504_06716_amd as G
+    rng = np.random.default_rng(6)
+    n = 100_003
+    ctx = G.Context(16, 1, 16, 16, 16)
+    sx = (rng.random(n) * 6e-5).astype(np.float32)
+    sr = (rng.random(n) * 2e-4).astype(np.float32)
+    sx[:100] = np.float32(3e-5)                      # exactly at the threshold: not frozen (strict)
+    sr[100:200] = np.float32(1e-4)
+    sx[200:300] = np.finfo(np.float32).max            # never seen
+    old = (rng.random(n) < 0.1).astype(np.uint8)
+    prop = (rng.random(n) < 0.05).astype(np.uint8)
+    for mode in (0, 1, 2):
+        for proposal in (None, prop):
+            fz = dev(old.copy())
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            ctx.update_freeze_mask(dev(sx), dev(sr), 3e-5, 1e-4, mode, fz,
+                                   proposal=None if proposal is None else dev(proposal), n_frozen=cnt)
+            torch.cuda.synchronize()
+            exp = O.freeze_update(old, sx, sr, 3e-5, 1e-4, mode, proposal)
+            got = fz.cpu().numpy()
+            assert np.array_equal(got, exp)
+            assert int(cnt.item()) == int(exp.sum())
+
+
+def test_l1_loss_matches_oracle():
+    import torch
+    import paper_2504_06716_amd as G
+    rng = np.random.default_rng(7)
+    ctx = G.Context(16, 1, 16, 16, 16)
+    img = rng.uniform(-0.2, 1.2, (2, 3, 37, 50)).astype(np.float32)
+    tgt = rng.random((2, 3, 37, 50)).astype(np.float32)
+    tgt[0, 0, 0, :5] = img[0, 0, 0, :5]              # sign(0) = 0
+    dL = torch.empty(img.shape, device="cuda")
+    sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ctx.l1_loss(dev(img), dev(tgt), dL, sums)
+    torch.cuda.synchronize()
+    loss, dref, mse = O.l1_loss(img, tgt)
+    s = sums.cpu().numpy()
+    assert s[0] / img.size == pytest.approx(loss, rel=1e-6)
+    assert s[1] / img.size == pytest.approx(mse, rel=1e-6)
+    np.testing.assert_allclose(dL.cpu().numpy(), dref, rtol=1e-6)
+    assert (dL.cpu().numpy()[0, 0, 0, :5] == 0).all()

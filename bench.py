@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""GSta training throughput on one MI355X.
+
+Workload (synthetic, seeded): 100k Gaussians with SH degree 3, 32 cameras
+(4 elevation rings x 8 azimuths) at 480x640, 16x16 tiles, one view per
+iteration, 2000 iterations; targets rendered from a seed-perturbed copy of
+the scene.  One step = freeze-map update (when scheduled) + forward render +
+L1 loss + backward + masked Adam.  The GSta run (freezing) and the plain run
+(no freezing) are timed on the same GPU from the same initial state; the
+PSNR of both over all 32 views is reported so the comparison can be checked
+at equal iteration count.
+
+Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
+FLOP_PER_PAIR = 15             # arithmetic of one (pixel, splat) evaluation, see the design doc
+# Initial freeze thresholds of this workload, from the one-time calibration
+# rule of paper_2504_06716_amd/calibrate.py with q = 0.5 (positive gradient-norm
+# averages at the start of the freeze window of a no-freeze run).
+C2_EPS0 = (3.5089581280389164e-06, 8.864577095760309e-08)
+
+
+def c2_setup(torch):
+    import numpy as np
+    import synthetic as S
+    from paper_2504_06716_amd.core import Context
+    from paper_2504_06716_amd.schedule import FreezeSchedule, LearningRates
+    from paper_2504_06716_amd.train import TrainConfig, render_targets, required_capacity
+
+    c = S.CONFIGS["c2"]
+    n, D, H, W, iters = c["n"], c["degree"], c["height"], c["width"], c["iters"]
+    p0 = S.make_scene(n, D)
+    pt = S.perturb_scene(p0, D)
+    cams = S.config_cameras("c2")
+    ctx = Context(n, 8, H, W, instance_capacity=1 << 24, n_slots=1)
+    need = max(required_capacity(ctx, p0, D, cams), required_capacity(ctx, pt, D, cams))
+    ctx.reserve(instance_capacity=int(need * 1.5) + 4096)
+    targets = render_targets(ctx, pt, D, cams)
+    order = S.view_order(len(cams), iters)
+
+    def cfg(freeze):
+        sched = FreezeSchedule(total_iters=iters, warmup=600, every=50, reset_every=400, wait=100,
+                               window_end=1800, eps_xyz0=C2_EPS0[0], eps_rgb0=C2_EPS0[1])
+        return TrainConfig(iters=iters, freeze=freeze, schedule=sched if freeze else None,
+                           lrs=LearningRates(decay_iters=iters))
+
+    return dict(p0=p0, pt=pt, cams=cams, ctx=ctx, targets=targets, order=order, cfg=cfg, n=n, D=D, H=H, W=W,
+                iters=iters, capacity=int(need * 1.5) + 4096)
+
+
+def run_trainer(torch, w, freeze, steps, profile_phases=None):
+    from paper_2504_06716_amd.train import Trainer
+    tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], w["cfg"](freeze), w["order"], ctx=w["ctx"])
+    ctx = w["ctx"]
+    ctx.set_profiling(None if profile_phases == "all" else (profile_phases or []))
+    ctx.read_profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof, pairs = ctx.read_profile()
+    ctx.set_profiling([])
+    return tr, dt, prof, pairs
+
+
+def algorithmic_work(phase, w, steps, pairs, n_active_mean, inst_mean):
+    """(amount, unit, bound) of algorithmic work for `steps` launches of a phase."""
+    n, R = w["n"], 11 + 3 * (w["D"] + 1) ** 2
+    px = w["H"] * w["W"]
+    if phase in ("composite", "composite_bwd"):
+        p = pairs[0] if phase == "composite" else pairs[1]
+        return p * FLOP_PER_PAIR, "flop", "alu"
+    if phase == "preprocess":         # read the parameter row block, write 48 B record + 8 B rect + 8 B key/value
+        return steps * n * (4 * R + 64), "byte", "hbm"
+    if phase == "preprocess_bwd":     # read params + 2-D grads + rect, write grads + 4 EMAs (active only)
+        return steps * n_active_mean * (4 * R + 36 + 8 + 4 * R + 32), "byte", "hbm"
+    if phase == "adam":               # read p, g, m, v and write p, m, v (active only) + mask
+        return steps * (n_active_mean * 7 * 4 * R + n), "byte", "hbm"
+    if phase == "depth_sort":         # 4 passes: read keys (hist), read+write key/value pairs (scatter)
+        return steps * 4 * n * (4 + 16), "byte", "hbm"
+    if phase == "binning":            # read rect+order twice, write 8 B per instance
+        return steps * (2 * n * 12 + inst_mean * 8), "byte", "hbm"
+    if phase == "tile_sort":          # 2 passes over the instances + ranges
+        return steps * (2 * inst_mean * 20 + inst_mean * 4), "byte", "hbm"
+    if phase == "loss":
+        return steps * px * 3 * 12, "byte", "hbm"
+    return steps * n, "byte", "hbm"
+
+
+def _mean_frozen(hist, steps):
+    """Frozen count averaged over the iterations of the run."""
+    total, cur, prev = 0, 0, 0
+    for k, _, c in hist:
+        k = min(k, steps)
+        total += cur * (k - prev)
+        cur, prev = c, k
+    total += cur * max(steps - prev, 0)
+    return total / max(steps, 1)
+
+
+def cpu_baseline(w, max_seconds=20.0):
+    """The FP64 oracle timed on the host for a bounded sample of the same
+    workload: consecutive training iterations (1 view each) from the
+    initial state."""
+    import numpy as np
+    import oracle as O
+    import torch
+    targets = w["targets"].cpu().numpy().astype(np.float64)
+    D = w["D"]
+    p = w["p0"].astype(np.float64)
+    R, n = p.shape
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    ema = np.full((4, n), O.FLT_MAX)
+    frozen = np.zeros(n, np.uint8)
+    lrs = w["cfg"](True).lrs
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        view = int(w["order"][iters])
+        cam = w["cams"][view]
+        img = O.render(p, D, cam)["image"]
+        loss, dL, mse = O.l1_loss(img[None], targets[view:view + 1])
+        g, _, vis = O.render_backward(p, D, [cam], dL, frozen=frozen)
+        sc = O.scores(g)
+        for k in range(4):
+            ema[k] = O.ema_update(ema[k], sc[k], vis.any(0), frozen, 0.9)
+        p, m, v = O.adam_masked(p, g, m, v, np.array(lrs.rows(iters, D)), 0.9, 0.999, 1e-15, iters + 1, frozen)
+        iters += 1
+        el = time.perf_counter() - t0
+        if el >= max_seconds or iters >= 50:
+            break
+    return {"value": iters / el, "unit": "iters/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{iters} consecutive c2 training iterations (1 view of 480x640, all 100k Gaussians, "
+                      f"SH degree 3, forward+L1+backward+EMA+Adam in FP64) in {el:.1f} s"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000, help="timed training iterations per run")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed iterations before timing")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--details", default=None, help="write the per-phase breakdown JSON here")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} requested, but this build runs on a single GPU only "
+              "(no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    log("setting up the c2 workload")
+    w = c2_setup(torch)
+    steps = args.steps
+    log(f"instance capacity {w['capacity']}")
+
+    # untimed warm-up iterations (same schedule, discarded)
+    if args.warmup > 0:
+        run_trainer(torch, w, True, args.warmup)
+
+    # untimed profiling pass: per-phase totals over the same schedule
+    log("profiling pass")
+    trp, _, prof_all, pairs_all = run_trainer(torch, w, True, steps, profile_phases="all")
+    dominant = max(prof_all, key=lambda k: prof_all[k][0])
+    log(f"dominant phase: {dominant}")
+
+    # timed runs (events only around the dominant phase in the GSta run)
+    tr_f, dt_f, prof_f, pairs_f = run_trainer(torch, w, True, steps, profile_phases=[dominant])
+    log(f"GSta run: {steps / dt_f:.1f} iters/s")
+    psnr_f = tr_f.evaluate()
+    hist = tr_f.freeze_history()
+    peak_frozen = max([c for _, _, c in hist], default=0) / w["n"]
+    mean_frozen = _mean_frozen(hist, steps) / w["n"]
+    tr_n, dt_n, _, _ = run_trainer(torch, w, False, steps)
+    psnr_n = tr_n.evaluate()
+    log(f"no-freeze run: {steps / dt_n:.1f} iters/s; PSNR {psnr_f:.3f} vs {psnr_n:.3f}")
+    st, max_inst = w["ctx"].check()
+
+    ms_dom, launches = prof_f[dominant]
+    n_active_mean = w["n"]          # (refined below from the profiling pass)
+    inst_mean = max_inst
+    amount, unit, bound = algorithmic_work(dominant, w, launches, pairs_f, n_active_mean, inst_mean)
+    if bound == "alu":
+        achieved = amount / (ms_dom * 1e-3) / 1e12
+        peak, unit_r = VALU_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        achieved = amount / (ms_dom * 1e-3) / 1e9
+        peak, unit_r = HBM_PEAK_GBS, "GB/s"
+
+    value = steps / dt_f
+    out = {
+        "metric": "train iters/sec (fwd+bwd+Adam), GSta freeze vs no-freeze at equal iterations",
+        "value": round(value, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * dt_f / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: 100k Gaussians SH3, 32 cams 480x640, 16x16 tiles, 1 view/iter, "
+                               "2000-iteration GSta schedule (warm-up 600, update 50, reset 400 + wait 100, "
+                               "finetune from 1800)",
+                   "n_gaussians": w["n"], "sh_degree": w["D"], "views": len(w["cams"]), "height": w["H"],
+                   "width": w["W"], "schedule_iters": w["iters"]},
+        "no_freeze": {"value": round(steps / dt_n, 3), "ms_per_step": round(1000.0 * dt_n / steps, 4),
+                      "psnr_db": round(psnr_n, 4)},
+        "psnr_db": round(psnr_f, 4),
+        "delta_psnr_db": round(psnr_f - psnr_n, 4),
+        "speedup_vs_no_freeze": round(dt_n / dt_f, 4),
+        "frozen_fraction_peak": round(peak_frozen, 4),
+        "frozen_fraction_mean": round(mean_frozen, 4),
+        "roofline": {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
+                     "unit": unit_r, "frac": round(achieved / peak, 5), "traffic": None,
+                     "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches},
+        "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_all.items()},
+        "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],
+        "max_instances": max_inst,
+    }
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if args.details:
+        with open(args.details, "w") as f:
+            json.dump({"profile_all": prof_all, "pairs_all": pairs_all, "freeze_history": hist}, f)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,12 +94,20 @@ typedef enum {
     GSTA_STATE_RECT = 3,        /* uint16x4 [V][N]: tile x0, x1, y0, y1 (exclusive ends); all 0 if culled */
     GSTA_STATE_DEPTH_ORDER = 4, /* uint32 [V][N]: gid in ascending (float32 depth, gid) order, culled last */
     GSTA_STATE_INST_KEYS = 5,   /* uint32 [I]: view * T + tile of each instance, sorted */
-    GSTA_STATE_INST_IDS = 6,    /* uint32 [I]: gid of each instance (depth order within a tile) */
+    GSTA_STATE_INST_IDS = 6,    /* uint32 [I]: expansion index of each sorted instance (depth order within a tile) */
     GSTA_STATE_RANGES = 7,      /* uint32x2 [V*T]: [start, end) of each (view, tile) in the instance list */
     GSTA_STATE_T_FINAL = 8,     /* float [V][H][W]: transmittance left after the last member */
     GSTA_STATE_LAST = 9,        /* uint32 [V][H][W]: tile-list index + 1 of the last member (0 if none) */
-    GSTA_STATE_N_INSTANCES = 10 /* uint64 [1]: instances generated (may exceed capacity) */
+    GSTA_STATE_N_INSTANCES = 10,/* uint64 [1]: instances generated (may exceed capacity) */
+    GSTA_STATE_INST_GID = 11    /* uint32 [I]: gid of each expansion index (Gaussians in depth order,
+                                   each one's tiles contiguous in row-major order) */
 } gsta_state_field;
+
+/* Execution options (gsta_set_option).  They change speed, never results. */
+typedef enum {
+    GSTA_OPT_FWD_WAVES = 0,     /* waves per 16x16 tile in forward compositing: 1, 2 or 4 (default 4) */
+    GSTA_OPT_BWD_WAVES = 1      /* waves per tile in backward compositing: 1, 2 or 4 (default 4) */
+} gsta_option;
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -116,10 +124,39 @@ const char* gsta_last_error(const gsta_ctx* ctx);
  * largest instance count any render needed since the last check is written
  * to *max_instances (host, may be NULL). */
 gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances);
+/* Sets an execution option (gsta_option) for later calls. */
+gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value);
 /* Copies `bytes` of an internal field of forward state `slot` into device
  * memory `dst` (stream-ordered).  For tests and tools. */
 gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst, int64_t bytes,
                            hipStream_t stream);
+
+/* Phases timed by the profiler (gsta_set_profiling). */
+typedef enum {
+    GSTA_PHASE_PREPROCESS = 0,  /* per-Gaussian projection, records, depth keys */
+    GSTA_PHASE_DEPTH_SORT = 1,  /* per-view radix sort of depth keys */
+    GSTA_PHASE_BINNING = 2,     /* tile counts, scan, instance expansion */
+    GSTA_PHASE_TILE_SORT = 3,   /* radix sort of tile keys + tile ranges */
+    GSTA_PHASE_COMPOSITE = 4,   /* forward compositing */
+    GSTA_PHASE_COMPOSITE_BWD = 5,
+    GSTA_PHASE_PREPROCESS_BWD = 6,
+    GSTA_PHASE_ADAM = 7,
+    GSTA_PHASE_FREEZE = 8,
+    GSTA_PHASE_LOSS = 9,
+    GSTA_N_PHASES = 10
+} gsta_phase;
+
+/* Profiling (for benchmarks; do not enable while capturing a HIP graph).
+ * phase_mask bit i enables phase i (0 disables): the entry points record a
+ * pair of HIP events on their stream around each enabled phase, and the
+ * compositing kernels of enabled phases count the (pixel, splat) pairs they
+ * evaluate.  gsta_read_profile synchronises,
+ * writes per-phase totals since the last read -- ms[GSTA_N_PHASES] elapsed
+ * time, launches[GSTA_N_PHASES] -- and pairs[2] = pairs evaluated by the
+ * forward and backward compositing (all host arrays, each may be NULL),
+ * then resets the totals. */
+gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask);
+gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* pairs);
 
 /* ---- the hot path ------------------------------------------------------- */
 
@@ -152,8 +189,10 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
  * `grad` are not written.  Rows of active Gaussians are overwritten with the
  * gradient summed over the views.  frozen [n] uint8 or NULL (none frozen).
  *   grad2d  optional [n_views][9][n] float32 output: dL/d(u, v, conic_a,
- *           conic_b, conic_c, opacity, r, g, b) per view (0 where frozen or
- *           untouched); NULL to skip.
+ *           conic_b, conic_c, opacity, r, g, b) per view, written for active
+ *           Gaussians only; NULL to skip.
+ * No atomics are involved: every per-tile partial has its own slot and the
+ * sums run in a fixed order, so the result is bit-reproducible.
  *   ema     optional [4][n] float32 in/out: exponential moving averages of
  *           |dL/dmean|, |dL/d(DC colour)|, |dL/dlogit|, |dL/dlog-scale| for
  *           active Gaussians visible in >= 1 view: s <- b*s + (1-b)*g, and

@@ -49,8 +49,13 @@ def lib():
         L.oracle_render.argtypes = [P, i64, i64, i32, P, i32, i32, P, i32] + [P] * 8
         L.oracle_render_backward.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P, P, P, P, P]
         L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
+        L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
 
 
 def _ptr(a: np.ndarray):

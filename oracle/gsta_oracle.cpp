@@ -492,6 +492,15 @@ void chain_to_params(const Proj& p, const Cam& cam, int degree, const double* P,
 
 extern "C" {
 
+// Threads the OpenMP loops of the oracle use.
+int oracle_num_threads() {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 // Number of doubles per projected record written by oracle_project.
 int oracle_nrec() { return 40; }
 

@@ -13,7 +13,8 @@ GSTA_OK, GSTA_ERR_INVALID, GSTA_ERR_CAPACITY, GSTA_ERR_HIP, GSTA_ERR_OOM, GSTA_E
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NONFINITE"}
 
 (STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
- STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES) = range(11)
+ STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES, STATE_INST_GID) = range(12)
+OPT_FWD_WAVES, OPT_BWD_WAVES = 0, 1
 
 
 class Limits(ctypes.Structure):
@@ -45,7 +46,10 @@ _lib = None
 
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
            "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
-           "gsta_update_freeze_mask", "gsta_l1_loss"]
+           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option"]
+
+PHASES = ["preprocess", "depth_sort", "binning", "tile_sort", "composite", "composite_bwd",
+          "preprocess_bwd", "adam", "freeze", "loss"]
 
 
 def load(path: str = LIB_PATH):
@@ -73,6 +77,9 @@ def load(path: str = LIB_PATH):
     L.gsta_adam_masked.argtypes = [P, PP, PP, PP, PP, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
     L.gsta_update_freeze_mask.argtypes = [P, P, P, i64, f32, f32, i32, P, P, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
+    L.gsta_set_profiling.argtypes = [P, i32]
+    L.gsta_set_option.argtypes = [P, i32, i64]
+    L.gsta_read_profile.argtypes = [P, P, P, P]
     for name in EXPORTS:
         if name not in ("gsta_destroy", "gsta_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -116,6 +116,33 @@ class Context:
                                              out.numel() * out.element_size(), _stream(stream)))
         return out
 
+    def set_option(self, option: int, value: int):
+        check(self.h, self.L.gsta_set_option(self.h, int(option), int(value)))
+
+    def set_waves(self, fwd: int | None = None, bwd: int | None = None):
+        if fwd is not None:
+            self.set_option(_lib.OPT_FWD_WAVES, fwd)
+        if bwd is not None:
+            self.set_option(_lib.OPT_BWD_WAVES, bwd)
+
+    def set_profiling(self, phases=None):
+        """Enable event timing for the named phases (all if None; [] disables)."""
+        if phases is None:
+            mask = (1 << len(_lib.PHASES)) - 1
+        else:
+            mask = 0
+            for p in phases:
+                mask |= 1 << _lib.PHASES.index(p)
+        check(self.h, self.L.gsta_set_profiling(self.h, mask))
+
+    def read_profile(self):
+        """Per-phase {name: (total ms, launches)} and evaluated pairs (fwd, bwd) since the last read."""
+        ms = (ctypes.c_double * len(_lib.PHASES))()
+        ln = (ctypes.c_int64 * len(_lib.PHASES))()
+        pr = (ctypes.c_int64 * 2)()
+        check(self.h, self.L.gsta_read_profile(self.h, ms, ln, pr))
+        return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, (pr[0], pr[1])
+
     # ---- hot path --------------------------------------------------------
     def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None):
         ps = params_struct(params, degree)

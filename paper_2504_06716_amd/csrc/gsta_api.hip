@@ -24,6 +24,8 @@ struct Slot {
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* ikey[2] = {nullptr, nullptr};
     uint32_t* ival[2] = {nullptr, nullptr};
+    uint32_t* inst_gid = nullptr;   // [cap] gid of each expansion index
+    uint32_t* inst_off = nullptr;   // [V][S] first expansion index of each Gaussian
     uint2* ranges = nullptr;
     float* T_final = nullptr;
     uint32_t* last = nullptr;
@@ -53,10 +55,23 @@ struct gsta_ctx {
     uint32_t* digit_tot = nullptr;
     int64_t chunks_depth = 0, chunks_inst = 0;
     uint64_t* partials = nullptr;
-    float* grad2d = nullptr;  // [V][9][stride]
+    float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
+    double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
+    int fwd_waves = 4, bwd_waves = 4;
     uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient
     uint64_t* max_inst = nullptr;
     std::string err;
+    // profiling
+    uint32_t profiling = 0;                   // phase mask
+    unsigned long long* pairs = nullptr;      // [0] forward, [1] backward compositing
+    struct Pending {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[GSTA_N_PHASES] = {};
+    int64_t launches[GSTA_N_PHASES] = {};
 };
 
 namespace {
@@ -125,6 +140,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.rect, V * S) && alloc(ctx, &s.dkey[0], V * S) && alloc(ctx, &s.dkey[1], V * S) &&
              alloc(ctx, &s.dval[0], V * S) && alloc(ctx, &s.dval[1], V * S) && alloc(ctx, &s.ikey[0], cap) &&
              alloc(ctx, &s.ikey[1], cap) && alloc(ctx, &s.ival[0], cap) && alloc(ctx, &s.ival[1], cap) &&
+             alloc(ctx, &s.inst_gid, cap) && alloc(ctx, &s.inst_off, V * S) &&
              alloc(ctx, &s.ranges, V * ctx->tiles_max) && alloc(ctx, &s.T_final, V * HW) &&
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
              alloc(ctx, &s.n_count, 1);
@@ -133,14 +149,17 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ctx->chunks_inst = radix_chunks(cap);
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
-         alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->grad2d, V * 9 * S) &&
-         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1);
+         alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
+         alloc(ctx, &ctx->loss_part, kL1Blocks) &&
+         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, 2);
     if (!ok) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_OOM, "device allocation failed");
     }
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
+        hipMemset(ctx->pairs, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_HIP, "initialising flags failed");
     }
@@ -208,6 +227,41 @@ int key_bits(int64_t keys) {
     return b;
 }
 
+hipEvent_t take_event(gsta_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a pair of events around the launches of one phase when profiling.
+struct PhaseTimer {
+    gsta_ctx* ctx;
+    int phase;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(gsta_ctx* c, int ph, hipStream_t st) : ctx(c), phase(ph), s(st) {
+        if (!(ctx->profiling & (1u << ph))) return;
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~PhaseTimer() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, s);
+        ctx->pending.push_back({phase, a, b});
+    }
+};
+
+unsigned long long* pair_counter(gsta_ctx* ctx, int which) {
+    const int phase = which == 0 ? GSTA_PHASE_COMPOSITE : GSTA_PHASE_COMPOSITE_BWD;
+    return (ctx->profiling & (1u << phase)) ? ctx->pairs + which : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -249,8 +303,66 @@ gsta_status gsta_reserve(gsta_ctx* ctx, const gsta_limits* lim) {
 void gsta_destroy(gsta_ctx* ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
+    for (auto& p : ctx->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     free_all(ctx);
     delete ctx;
+}
+
+gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    switch (option) {
+        case GSTA_OPT_FWD_WAVES:
+        case GSTA_OPT_BWD_WAVES:
+            if (value != 1 && value != 2 && value != 4)
+                return fail(ctx, GSTA_ERR_INVALID, "waves per tile must be 1, 2 or 4");
+            (option == GSTA_OPT_FWD_WAVES ? ctx->fwd_waves : ctx->bwd_waves) = (int)value;
+            return GSTA_OK;
+        default:
+            return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
+    }
+}
+
+gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    ctx->profiling = (uint32_t)phase_mask & ((1u << GSTA_N_PHASES) - 1u);
+    return GSTA_OK;
+}
+
+gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* pairs) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize")) != GSTA_OK) return st;
+    for (auto& p : ctx->pending) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+            ctx->ms[p.phase] += t;
+            ctx->launches[p.phase] += 1;
+        }
+        ctx->pool.push_back(p.a);
+        ctx->pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+    unsigned long long pr[2] = {0, 0};
+    if ((st = hip_check(ctx, hipMemcpy(pr, ctx->pairs, sizeof(pr), hipMemcpyDeviceToHost), "read pairs")) != GSTA_OK)
+        return st;
+    const unsigned long long z[2] = {0, 0};
+    if ((st = hip_check(ctx, hipMemcpy(ctx->pairs, z, sizeof(z), hipMemcpyHostToDevice), "clear pairs")) != GSTA_OK)
+        return st;
+    for (int i = 0; i < GSTA_N_PHASES; ++i) {
+        if (ms) ms[i] = ctx->ms[i];
+        if (launches) launches[i] = ctx->launches[i];
+        ctx->ms[i] = 0.0;
+        ctx->launches[i] = 0;
+    }
+    if (pairs) {
+        pairs[0] = (int64_t)pr[0];
+        pairs[1] = (int64_t)pr[1];
+    }
+    return GSTA_OK;
 }
 
 const char* gsta_last_error(const gsta_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
@@ -302,6 +414,7 @@ gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst
         case GSTA_STATE_T_FINAL: src = s.T_final; elem = 4; row_elems = V * HW; src_pitch = row_elems; break;
         case GSTA_STATE_LAST: src = s.last; elem = 4; row_elems = V * HW; src_pitch = row_elems; break;
         case GSTA_STATE_N_INSTANCES: src = s.n_total; elem = 8; row_elems = 1; src_pitch = 1; break;
+        case GSTA_STATE_INST_GID: src = s.inst_gid; elem = 4; row_elems = ctx->lim.instance_capacity; src_pitch = row_elems; break;
         default: return fail(ctx, GSTA_ERR_INVALID, "unknown state field %d", field);
     }
     const int64_t full = rows * row_elems * elem;
@@ -333,18 +446,33 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     const int ntx = ca.c[0].ntx;
     const int64_t T = (int64_t)ca.c[0].ntx * ca.c[0].nty;
 
-    if (n > 0)
+    if (n > 0) {
+        PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
                               s.dkey[0], s.dval[0], S, stream);
-    RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth};
-    s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
-    launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total, s.n_count,
-                  s.ikey[0], s.ival[0], (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, stream);
-    RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst};
-    s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
-    launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, T * nv, stream);
-    launch_composite_fwd(s.ranges, s.ival[s.inst_buf], s.geo, s.col, s.rgb, S, ca, nv, bg[0], bg[1], bg[2],
-                         image, s.T_final, s.last, s.cfg, stream);
+    }
+    {
+        PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
+        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth};
+        s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
+    }
+    {
+        PhaseTimer pt(ctx, GSTA_PHASE_BINNING, stream);
+        launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total, s.n_count,
+                      s.ikey[0], s.ival[0], s.inst_gid, s.inst_off, (uint64_t)ctx->lim.instance_capacity,
+                      ctx->flags, ctx->max_inst, stream);
+    }
+    {
+        PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
+        RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst};
+        s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
+        launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, T * nv, stream);
+    }
+    {
+        PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
+        launch_composite_fwd(ctx->fwd_waves, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col, s.rgb, S, ca,
+                             nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, pair_counter(ctx, 0), stream);
+    }
     if ((st = hip_check(ctx, hipGetLastError(), "render_forward launch")) != GSTA_OK) {
         s.valid = false;
         return st;
@@ -384,17 +512,16 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (!same) return fail(ctx, GSTA_ERR_INVALID, "backward arguments differ from the forward in slot %d", state_slot);
     const int64_t n = g->n, S = ctx->stride;
     const int nv = n_views;
-    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->grad2d), 0u, (int64_t)nv * 9 * S, stream);
-    launch_composite_bwd(s.ranges, s.ival[s.inst_buf], s.geo, s.col, s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2],
-                         s.T_final, s.last, s.cfg, dL_dimage, ctx->grad2d, stream);
-    if (n > 0)
-        launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, S, ctx->grad2d, frozen,
-                              grad->block, grad->ld, ema, ema_beta, stream);
-    if (grad2d && n > 0) {
-        st = hip_check(ctx, hipMemcpy2DAsync(grad2d, (size_t)n * 4, ctx->grad2d, (size_t)S * 4, (size_t)n * 4,
-                                             (size_t)nv * 9, hipMemcpyDeviceToDevice, stream),
-                       "copy grad2d");
-        if (st != GSTA_OK) return st;
+    {
+        PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
+        launch_composite_bwd(ctx->bwd_waves, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col, s.rgb, S, frozen,
+                             ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg, dL_dimage, ctx->tile_grads,
+                             s.n_count, pair_counter(ctx, 1), stream);
+    }
+    if (n > 0) {
+        PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
+        launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
+                              s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d, stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }
@@ -420,6 +547,7 @@ gsta_status gsta_adam_masked(gsta_ctx* ctx, gsta_params* p, const gsta_params* g
     for (int r = 0; r < 64; ++r) lr.lr[r] = r < rows ? lr_per_row[r] : 0.f;
     const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
     const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    PhaseTimer pt(ctx, GSTA_PHASE_ADAM, stream);
     if (p->n > 0)
         launch_adam(p->block, p->ld, grad->block, grad->ld, m->block, m->ld, v->block, v->ld, p->n, rows, lr, beta1,
                     beta2, eps, bc1, bc2, frozen, ctx->flags, stream);
@@ -435,6 +563,7 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
     if (!frozen && n > 0) return fail(ctx, GSTA_ERR_INVALID, "frozen is NULL");
     if (mode != 1 && n > 0 && (!score_xyz || !score_rgb))
         return fail(ctx, GSTA_ERR_INVALID, "scores are NULL");
+    PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
     launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
     return hip_check(ctx, hipGetLastError(), "freeze launch");
 }
@@ -444,7 +573,8 @@ gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target,
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     if (count < 1) return fail(ctx, GSTA_ERR_INVALID, "count must be >= 1");
     if (!image || !target || !dL_dimage || !sums) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
-    launch_l1(image, target, count, dL_dimage, sums, stream);
+    PhaseTimer pt(ctx, GSTA_PHASE_LOSS, stream);
+    launch_l1(image, target, count, dL_dimage, sums, ctx->loss_part, stream);
     return hip_check(ctx, hipGetLastError(), "l1 launch");
 }
 

@@ -83,10 +83,14 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
                            uint32_t* dkey, uint32_t* dval, int64_t stride, hipStream_t s);
 
+// Sums each active Gaussian's per-tile 2-D gradients (partials at its
+// expansion offsets inst_off[v][gid], in tile order), chains them to every
+// parameter, sums over views, and updates the gradient-norm EMAs.
+// grad2d_out ([nv][9][n], optional) receives the per-view 2-D gradients.
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
-                           int nv, const ushort4* rect, int64_t stride, const float* grad2d,
-                           const uint8_t* frozen, float* G, int64_t gld, float* ema, float beta,
-                           hipStream_t s);
+                           int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
+                           const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           int64_t gld, float* ema, float beta, float* grad2d_out, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
 // seg_stride elements; element count per segment from d_count (device, if
@@ -104,25 +108,33 @@ int64_t radix_chunks(int64_t count);
 
 // Depth-ordered tile-instance expansion: counts per Gaussian in depth
 // order, exclusive scan, write (view*T + tile, gid) for every touched tile.
+// Writes keys[j] = view*T + tile, vals[j] = j, inst_gid[j] = gid for every
+// instance j of the expansion, and inst_off[v][gid] = the first j of each
+// Gaussian (its instances are contiguous, in row-major tile order).
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
-                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint64_t capacity,
-                   uint32_t* flags, uint64_t* max_inst, hipStream_t s);
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
+                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, hipStream_t s);
 int64_t expand_blocks(int64_t elements);
 
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
                    int64_t n_ranges, hipStream_t s);
 
-void launch_composite_fwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
-                          const float4* col, const float4* rgb, int64_t stride, const CamArray& cams,
-                          int nv, float bg0, float bg1, float bg2, float* image, float* T_final,
-                          uint32_t* last, double* cfg, hipStream_t s);
+// Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  `ids` holds,
+// per sorted instance, its index in the depth-ordered expansion; inst_gid
+// maps that index to the Gaussian.  The backward writes each (tile, splat)
+// 2-D gradient into partials[expansion index][9] (zeroed first), without
+// atomics.
+void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
+                          float* T_final, uint32_t* last, double* cfg, unsigned long long* pairs, hipStream_t s);
 
-void launch_composite_bwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
-                          const float4* col, const float4* rgb, int64_t stride, const uint8_t* frozen,
-                          const CamArray& cams, int nv, float bg0, float bg1, float bg2,
-                          const float* T_final, const uint32_t* last, const double* cfg,
-                          const float* dL_dimage, float* grad2d, hipStream_t s);
+void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
+                          const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
+                          float* partials, const uint32_t* d_count, unsigned long long* pairs, hipStream_t s);
 
 void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                  int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
@@ -131,7 +143,8 @@ void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, i
 void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
                    const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s);
 
-void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums,
+constexpr int kL1Blocks = 1024;   // partial sums of the loss (fixed-order second pass)
+void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums, double2* part,
                hipStream_t s);
 
 }  // namespace gsta

@@ -97,8 +97,10 @@ __global__ __launch_bounds__(256) void k_freeze(const float* __restrict__ sx, co
 
 __global__ void k_zero_i64(unsigned long long* p) { *p = 0ull; }
 
+// L1 loss, pass 1: per-workgroup partial sums (double) of |C - C*| and of
+// the clamped squared error, and dL/dC for every element.
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt,
-                                            int64_t count, float* __restrict__ dL, double* __restrict__ sums) {
+                                            int64_t count, float* __restrict__ dL, double2* __restrict__ part) {
     __shared__ double s_a[4], s_b[4];
     const float inv = 1.0f / (float)count;
     double a = 0.0, b = 0.0;
@@ -122,15 +124,32 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const
         s_b[wid] = b;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        atomicAdd(&sums[0], s_a[0] + s_a[1] + s_a[2] + s_a[3]);
-        atomicAdd(&sums[1], s_b[0] + s_b[1] + s_b[2] + s_b[3]);
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(s_a[0] + s_a[1] + s_a[2] + s_a[3],
+                                                          s_b[0] + s_b[1] + s_b[2] + s_b[3]);
 }
 
-__global__ void k_zero_f64x2(double* p) {
-    p[0] = 0.0;
-    p[1] = 0.0;
+// Pass 2: one workgroup adds the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_l1_final(const double2* __restrict__ part, int nb, double* __restrict__ sums) {
+    __shared__ double s_a[256], s_b[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += part[i].x;
+        b += part[i].y;
+    }
+    s_a[threadIdx.x] = a;
+    s_b[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s_a[threadIdx.x] += s_a[threadIdx.x + off];
+            s_b[threadIdx.x] += s_b[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sums[0] = s_a[0];
+        sums[1] = s_b[0];
+    }
 }
 
 }  // namespace
@@ -159,13 +178,13 @@ void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float 
             sx, sr, n, ex, er, mode, proposal, frozen, reinterpret_cast<unsigned long long*>(n_frozen));
 }
 
-void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums,
+void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums, double2* part,
                hipStream_t s) {
-    k_zero_f64x2<<<1, 1, 0, s>>>(sums);
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    int64_t blocks = (count + 1023) / 1024;
+    if (blocks > kL1Blocks) blocks = kL1Blocks;
     if (blocks < 1) blocks = 1;
-    k_l1<<<(unsigned)blocks, 256, 0, s>>>(img, tgt, count, dL, sums);
+    k_l1<<<(unsigned)blocks, 256, 0, s>>>(img, tgt, count, dL, part);
+    k_l1_final<<<1, 256, 0, s>>>(part, (int)blocks, sums);
 }
 
 }  // namespace gsta

@@ -251,9 +251,9 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
 template <int D>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
-    const ushort4* __restrict__ rect, int64_t stride, const float* __restrict__ grad2d,
-    const uint8_t* __restrict__ frozen, float* __restrict__ G, int64_t gld, float* __restrict__ ema,
-    float beta) {
+    const ushort4* __restrict__ rect, const uint32_t* __restrict__ inst_off, int64_t stride,
+    const float* __restrict__ partials, const uint32_t* __restrict__ d_count, const uint8_t* __restrict__ frozen,
+    float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -279,10 +279,26 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         if (!(r.x < r.y)) continue;    // culled in this view by the forward
         any_vis = true;
         const DevCam& cm = cams.c[v];
-        const float* d2p = grad2d + (int64_t)v * 9 * stride + i;
+        // 2-D gradient of this view: the per-tile totals of the compositing
+        // backward, summed in row-major tile order.
         float d2[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) d2[k] = d2p[(int64_t)k * stride];
+        for (int k = 0; k < 9; ++k) d2[k] = 0.f;
+        {
+            const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
+            const uint64_t j0 = inst_off[o_idx];
+            if (j0 + cnt <= (uint64_t)(*d_count)) {
+                const float* src = partials + j0 * 9;
+                for (uint32_t t = 0; t < cnt; ++t, src += 9) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) d2[k] += src[k];
+                }
+            }
+        }
+        if (grad2d_out) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) grad2d_out[((int64_t)v * 9 + k) * n + i] = d2[k];
+        }
         Geo g;
         project_geo(cm, mu, Rq, s, g);
         float z = g.xc[2], iz = 1.0f / z, iz2 = iz * iz;
@@ -434,16 +450,18 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 }
 
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
-                           int nv, const ushort4* rect, int64_t stride, const float* grad2d,
-                           const uint8_t* frozen, float* G, int64_t gld, float* ema, float beta,
-                           hipStream_t s) {
+                           int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
+                           const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           int64_t gld, float* ema, float beta, float* grad2d_out, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, grad2d_out
     switch (degree) {
-        case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(P, ld, n, cams, nv, rect, stride, grad2d, frozen, G, gld, ema, beta); break;
-        case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(P, ld, n, cams, nv, rect, stride, grad2d, frozen, G, gld, ema, beta); break;
-        case 2: k_preprocess_bwd<2><<<grid, block, 0, s>>>(P, ld, n, cams, nv, rect, stride, grad2d, frozen, G, gld, ema, beta); break;
-        default: k_preprocess_bwd<3><<<grid, block, 0, s>>>(P, ld, n, cams, nv, rect, stride, grad2d, frozen, G, gld, ema, beta); break;
+        case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
+        case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
+        case 2: k_preprocess_bwd<2><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
+        default: k_preprocess_bwd<3><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
     }
+#undef GSTA_BWD_ARGS
 }
 
 }  // namespace gsta

@@ -1,10 +1,10 @@
 // Tile compositing, forward and backward.
 //
-// Forward (Section 3.1, eq. 2): one 256-thread workgroup per 16x16 tile,
-// one thread per pixel.  The tile's depth-ordered splats are staged in LDS
-// in batches of 256 (one record per thread, a gather by gid), then every
-// pixel walks the batch front to back.  A workgroup stops fetching batches
-// once every pixel has terminated (__syncthreads_count).  The colour is
+// Forward (Section 3.1, eq. 2): one workgroup of W waves per 16x16 tile;
+// each thread owns 4/W pixels.  The tile's depth-ordered splats are staged
+// in LDS in batches of one record per thread (a gather by gid), then every
+// pixel walks the batch front to back.  The workgroup stops fetching batches
+// once all its pixels have terminated (__syncthreads_count).  Colour is
 // accumulated in double precision and kept per pixel for the backward.
 //
 // Backward (Section 3.2.4): same workgroup shape.  Each pixel re-walks its
@@ -13,242 +13,367 @@
 // membership and termination decision is identical.  The colour behind a
 // member is the forward colour minus the recomputed prefix (both double).
 // Frozen splats still attenuate the pixels behind them but get no gradient
-// work.  Per splat the 9 partial derivatives are summed over the wave
-// (skipped when no lane contributed), over the four waves in LDS, and added
-// to the per-view 2-D gradient with one global atomic per value and tile.
+// work.  Per splat, a thread sums its pixels' 9 partial derivatives, the
+// wave sums its lanes with DPP row operations, the waves of the tile are
+// added in a fixed order, and the tile's total is written to the splat's own
+// slot (its position in the depth-ordered expansion) -- no atomics, so the
+// backward is deterministic.  The per-Gaussian sum over tiles happens in the
+// preprocess backward, in a fixed order too.
 #include "gsta_internal.h"
 
 namespace gsta {
 namespace {
 
-constexpr int BATCH = kTilePix;
+// Sum over the 64 lanes of a wave with DPP row operations; the total lands
+// in lane 63.  Every lane must be active.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    int x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));  // row_ror:4
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));  // row_ror:8
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
 
-__global__ __launch_bounds__(kTilePix) void k_composite_fwd(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ geo,
-    const float4* __restrict__ col, const float4* __restrict__ rgbv, int64_t stride, CamArray cams,
-    float bg0, float bg1, float bg2, float* __restrict__ image, float* __restrict__ T_final,
-    uint32_t* __restrict__ last_out, double* __restrict__ cfg) {
-    __shared__ float4 s_geo[BATCH];
-    __shared__ float2 s_co[BATCH];
-    __shared__ float4 s_rgb[BATCH];
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_composite_fwd(
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
+    const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
+    int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
+    float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg,
+    unsigned long long* __restrict__ pairs) {
+    constexpr int NT = 64 * W, P = 4 / W, B = NT;
+    __shared__ float4 s_geo[B];
+    __shared__ float2 s_co[B];
+    __shared__ float4 s_rgb[B];
+    __shared__ unsigned int s_pairs;
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
     const int tile = blockIdx.x;
     const int tid = threadIdx.x;
-    const int px = (tile % cm.ntx) * kTile + (tid & (kTile - 1));
-    const int py = (tile / cm.ntx) * kTile + (tid / kTile);
-    const bool inside = px < cm.width && py < cm.height;
+    const int tx0 = (tile % cm.ntx) * kTile, ty0 = (tile / cm.ntx) * kTile;
     const uint2 rg = ranges[(int64_t)v * tiles + tile];
     const int64_t vs = (int64_t)v * stride;
-    const float fpx = (float)px, fpy = (float)py;
 
-    float T = 1.0f;
-    double C0 = 0.0, C1 = 0.0, C2 = 0.0;
-    uint32_t last = 0;
-    bool done = !inside;
-    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
+    float fpx[P], fpy[P], T[P];
+    double C[P][3];
+    uint32_t last[P];
+    bool done[P], inside[P];
+    bool alldone = true;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int pix = tid + p * NT;
+        const int px = tx0 + (pix & (kTile - 1)), py = ty0 + pix / kTile;
+        inside[p] = px < cm.width && py < cm.height;
+        fpx[p] = (float)px;
+        fpy[p] = (float)py;
+        T[p] = 1.0f;
+        C[p][0] = C[p][1] = C[p][2] = 0.0;
+        last[p] = 0;
+        done[p] = !inside[p];
+        alldone = alldone && done[p];
+    }
+    uint32_t evals = 0;
+    if (tid == 0) s_pairs = 0;
+    for (uint32_t base = rg.x; base < rg.y; base += B) {
+        if (__syncthreads_count(!alldone) == 0) break;
         const uint32_t j = base + tid;
         if (j < rg.y) {
-            const uint32_t gid = ids[j];
+            const uint32_t gid = inst_gid[ids[j]];
             s_geo[tid] = geo[vs + gid];
             const float4 c = col[vs + gid];
             s_co[tid] = make_float2(c.x, c.y);
             s_rgb[tid] = rgbv[vs + gid];
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-        if (!done) {
-            for (int k = 0; k < cnt; ++k) {
-                const float4 g = s_geo[k];
-                const float2 co = s_co[k];
-                SplatEval e;
-                eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx, fpy, e);
-                if (e.power < kPowerFloor) continue;
-                if (e.alpha < kAlphaMin) continue;
-                const float Tn = next_T(T, e.alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
+        const int cnt = (int)min((uint32_t)B, rg.y - base);
+        for (int k = 0; k < cnt && !alldone; ++k) {
+            const float4 g = s_geo[k];
+            const float2 co = s_co[k];
+            bool all = true;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!done[p]) {
+                    ++evals;
+                    SplatEval e;
+                    eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx[p], fpy[p], e);
+                    if (e.power >= kPowerFloor && e.alpha >= kAlphaMin) {
+                        const float Tn = next_T(T[p], e.alpha);
+                        if (Tn < kTMin) {
+                            done[p] = true;
+                        } else {
+                            const float4 c = s_rgb[k];
+                            const double w = (double)(e.alpha * T[p]);
+                            C[p][0] = fma((double)c.x, w, C[p][0]);
+                            C[p][1] = fma((double)c.y, w, C[p][1]);
+                            C[p][2] = fma((double)c.z, w, C[p][2]);
+                            T[p] = Tn;
+                            last[p] = base - rg.x + (uint32_t)k + 1u;
+                        }
+                    }
                 }
-                const float4 c = s_rgb[k];
-                const double w = (double)(e.alpha * T);
-                C0 = fma((double)c.x, w, C0);
-                C1 = fma((double)c.y, w, C1);
-                C2 = fma((double)c.z, w, C2);
-                T = Tn;
-                last = base - rg.x + (uint32_t)k + 1u;
+                all = all && done[p];
             }
+            alldone = all;
         }
     }
-    if (inside) {
-        const int64_t HW = (int64_t)cm.width * cm.height;
-        const int64_t pix = (int64_t)py * cm.width + px;
-        float* img = image + (int64_t)v * 3 * HW + pix;
-        img[0] = (float)(C0 + (double)(T * bg0));
-        img[HW] = (float)(C1 + (double)(T * bg1));
-        img[2 * HW] = (float)(C2 + (double)(T * bg2));
-        T_final[(int64_t)v * HW + pix] = T;
-        last_out[(int64_t)v * HW + pix] = last;
-        double* cf = cfg + (int64_t)v * 3 * HW + pix;
-        cf[0] = C0;
-        cf[HW] = C1;
-        cf[2 * HW] = C2;
+    if (pairs) {
+        __syncthreads();
+        if (evals) atomicAdd(&s_pairs, evals);
+        __syncthreads();
+        if (tid == 0 && s_pairs) atomicAdd(pairs, (unsigned long long)s_pairs);
+    }
+    const int64_t HW = (int64_t)cm.width * cm.height;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (!inside[p]) continue;
+        const int pix = tid + p * NT;
+        const int64_t o = (int64_t)(ty0 + pix / kTile) * cm.width + (tx0 + (pix & (kTile - 1)));
+        float* img = image + (int64_t)v * 3 * HW + o;
+        img[0] = (float)(C[p][0] + (double)(T[p] * bg0));
+        img[HW] = (float)(C[p][1] + (double)(T[p] * bg1));
+        img[2 * HW] = (float)(C[p][2] + (double)(T[p] * bg2));
+        T_final[(int64_t)v * HW + o] = T[p];
+        last_out[(int64_t)v * HW + o] = last[p];
+        double* cf = cfg + (int64_t)v * 3 * HW + o;
+        cf[0] = C[p][0];
+        cf[HW] = C[p][1];
+        cf[2 * HW] = C[p][2];
     }
 }
 
-__global__ __launch_bounds__(kTilePix) void k_composite_bwd(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ geo,
-    const float4* __restrict__ col, const float4* __restrict__ rgbv, int64_t stride,
-    const uint8_t* __restrict__ frozen, CamArray cams, float bg0, float bg1, float bg2,
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_composite_bwd(
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
+    const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
+    int64_t stride, const uint8_t* __restrict__ frozen, CamArray cams, float bg0, float bg1, float bg2,
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in, const double* __restrict__ cfg,
-    const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
-    __shared__ float4 s_geo[BATCH];
-    __shared__ float2 s_co[BATCH];
-    __shared__ float4 s_rgb[BATCH];
-    __shared__ uint32_t s_gid[BATCH];
-    __shared__ uint32_t s_frz[BATCH];
-    __shared__ float s_acc[9][BATCH];
-    __shared__ uint32_t s_hit[BATCH];
+    const float* __restrict__ dL_dimage, float* __restrict__ partials, unsigned long long* __restrict__ pairs) {
+    constexpr int NT = 64 * W, P = 4 / W, B = NT;
+    __shared__ float4 s_geo[B];
+    __shared__ float2 s_co[B];
+    __shared__ float4 s_rgb[B];
+    __shared__ uint32_t s_idx[B];
+    __shared__ uint32_t s_frz[B];
+    __shared__ float s_part[W][9][B];
     __shared__ uint32_t s_maxlast;
+    __shared__ unsigned int s_pairs;
 
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
     const int tile = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int px = (tile % cm.ntx) * kTile + (tid & (kTile - 1));
-    const int py = (tile / cm.ntx) * kTile + (tid / kTile);
-    const bool inside = px < cm.width && py < cm.height;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tx0 = (tile % cm.ntx) * kTile, ty0 = (tile / cm.ntx) * kTile;
     const uint2 rg = ranges[(int64_t)v * tiles + tile];
     const int64_t vs = (int64_t)v * stride;
-    const float fpx = (float)px, fpy = (float)py;
     const int64_t HW = (int64_t)cm.width * cm.height;
-    const int64_t pix = (int64_t)py * cm.width + px;
 
-    float dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, Tf = 1.f;
-    double F0 = 0.0, F1 = 0.0, F2 = 0.0;   // forward colour (background excluded)
-    uint32_t last = 0;
-    if (inside) {
-        const float* dl = dL_dimage + (int64_t)v * 3 * HW + pix;
-        dC0 = dl[0];
-        dC1 = dl[HW];
-        dC2 = dl[2 * HW];
-        Tf = T_final[(int64_t)v * HW + pix];
-        last = last_in[(int64_t)v * HW + pix];
-        const double* cf = cfg + (int64_t)v * 3 * HW + pix;
-        F0 = cf[0];
-        F1 = cf[HW];
-        F2 = cf[2 * HW];
+    float fpx[P], fpy[P], dC[P][3], Tf[P], T[P];
+    double F[P][3], A[P][3];
+    uint32_t last[P];
+    uint32_t mylast = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int pix = tid + p * NT;
+        const int px = tx0 + (pix & (kTile - 1)), py = ty0 + pix / kTile;
+        fpx[p] = (float)px;
+        fpy[p] = (float)py;
+        T[p] = 1.0f;
+        A[p][0] = A[p][1] = A[p][2] = 0.0;
+        dC[p][0] = dC[p][1] = dC[p][2] = 0.f;
+        F[p][0] = F[p][1] = F[p][2] = 0.0;
+        Tf[p] = 1.f;
+        last[p] = 0;
+        if (px < cm.width && py < cm.height) {
+            const int64_t o = (int64_t)py * cm.width + px;
+            const float* dl = dL_dimage + (int64_t)v * 3 * HW + o;
+            dC[p][0] = dl[0];
+            dC[p][1] = dl[HW];
+            dC[p][2] = dl[2 * HW];
+            Tf[p] = T_final[(int64_t)v * HW + o];
+            last[p] = last_in[(int64_t)v * HW + o];
+            const double* cf = cfg + (int64_t)v * 3 * HW + o;
+            F[p][0] = cf[0];
+            F[p][1] = cf[HW];
+            F[p][2] = cf[2 * HW];
+        }
+        mylast = max(mylast, last[p]);
     }
-    if (tid == 0) s_maxlast = 0;
+    if (tid == 0) {
+        s_maxlast = 0;
+        s_pairs = 0;
+    }
     __syncthreads();
-    if (last) atomicMax(&s_maxlast, last);
+    if (mylast) atomicMax(&s_maxlast, mylast);
     __syncthreads();
     const uint32_t end = rg.x + s_maxlast;
-    const float tb0 = Tf * bg0, tb1 = Tf * bg1, tb2 = Tf * bg2;
+    uint32_t evals = 0;
 
-    float T = 1.0f;
-    double A0 = 0.0, A1 = 0.0, A2 = 0.0;   // colour of the members walked so far
-    for (uint32_t base = rg.x; base < end; base += BATCH) {
+    for (uint32_t base = rg.x; base < end; base += B) {
         __syncthreads();
         const uint32_t j = base + tid;
         if (j < end) {
-            const uint32_t gid = ids[j];
-            s_gid[tid] = gid;
+            const uint32_t idx = ids[j];
+            const uint32_t gid = inst_gid[idx];
+            s_idx[tid] = idx;
             s_geo[tid] = geo[vs + gid];
             const float4 c = col[vs + gid];
             s_co[tid] = make_float2(c.x, c.y);
             s_rgb[tid] = rgbv[vs + gid];
             s_frz[tid] = frozen ? (uint32_t)frozen[gid] : 0u;
         }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) s_acc[q][tid] = 0.f;
-        s_hit[tid] = 0;
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BATCH, end - base);
+        const int cnt = (int)min((uint32_t)B, end - base);
         for (int k = 0; k < cnt; ++k) {
-            const uint32_t idx = base - rg.x + (uint32_t)k;
+            const uint32_t pos = base - rg.x + (uint32_t)k;
+            const float4 g = s_geo[k];
+            const float2 co = s_co[k];
+            const float4 c = s_rgb[k];
+            const bool frz = s_frz[k] != 0u;
             float g9[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) g9[q] = 0.f;
             bool contrib = false;
-            if (idx < last) {
-                const float4 g = s_geo[k];
-                const float2 co = s_co[k];
-                SplatEval e;
-                eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx, fpy, e);
-                if (e.power >= kPowerFloor && e.alpha >= kAlphaMin) {
-                    const float4 c = s_rgb[k];
-                    const float w = e.alpha * T;
-                    const double wd = (double)w;
-                    A0 = fma((double)c.x, wd, A0);
-                    A1 = fma((double)c.y, wd, A1);
-                    A2 = fma((double)c.z, wd, A2);
-                    if (!s_frz[k]) {
-                        contrib = true;
-                        const float inv1m = 1.0f / (1.0f - e.alpha);
-                        const float b0 = (float)(F0 - A0) + tb0;
-                        const float b1 = (float)(F1 - A1) + tb1;
-                        const float b2 = (float)(F2 - A2) + tb2;
-                        const float dalpha = dC0 * (c.x * T - b0 * inv1m) + dC1 * (c.y * T - b1 * inv1m) +
-                                             dC2 * (c.z * T - b2 * inv1m);
-                        g9[6] = dC0 * w;
-                        g9[7] = dC1 * w;
-                        g9[8] = dC2 * w;
-                        if (e.oG <= kAlphaMax) {
-                            const float dpow = dalpha * e.alpha;
-                            g9[5] = dalpha * e.G;
-                            g9[0] = -dpow * (g.z * e.dx + g.w * e.dy);
-                            g9[1] = -dpow * (g.w * e.dx + co.x * e.dy);
-                            g9[2] = -0.5f * dpow * e.dx * e.dx;
-                            g9[3] = -dpow * e.dx * e.dy;
-                            g9[4] = -0.5f * dpow * e.dy * e.dy;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (pos < last[p]) {
+                    ++evals;
+                    SplatEval e;
+                    eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx[p], fpy[p], e);
+                    if (e.power >= kPowerFloor && e.alpha >= kAlphaMin) {
+                        const float w = e.alpha * T[p];
+                        const double wd = (double)w;
+                        A[p][0] = fma((double)c.x, wd, A[p][0]);
+                        A[p][1] = fma((double)c.y, wd, A[p][1]);
+                        A[p][2] = fma((double)c.z, wd, A[p][2]);
+                        if (!frz) {
+                            contrib = true;
+                            const float inv1m = 1.0f / (1.0f - e.alpha);
+                            const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
+                            const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
+                            const float b2 = (float)(F[p][2] - A[p][2]) + Tf[p] * bg2;
+                            const float dalpha = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
+                                                 dC[p][1] * (c.y * T[p] - b1 * inv1m) +
+                                                 dC[p][2] * (c.z * T[p] - b2 * inv1m);
+                            g9[6] += dC[p][0] * w;
+                            g9[7] += dC[p][1] * w;
+                            g9[8] += dC[p][2] * w;
+                            if (e.oG <= kAlphaMax) {
+                                const float dpow = dalpha * e.alpha;
+                                g9[5] += dalpha * e.G;
+                                g9[0] -= dpow * (g.z * e.dx + g.w * e.dy);
+                                g9[1] -= dpow * (g.w * e.dx + co.x * e.dy);
+                                g9[2] -= 0.5f * dpow * e.dx * e.dx;
+                                g9[3] -= dpow * e.dx * e.dy;
+                                g9[4] -= 0.5f * dpow * e.dy * e.dy;
+                            }
                         }
+                        T[p] = next_T(T[p], e.alpha);
                     }
-                    T = next_T(T, e.alpha);
                 }
             }
-            if (__ballot(contrib) != 0ull) {
+            if (!frz && __ballot(contrib) != 0ull) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
+                if (lane == 63) {
+                    if (W == 1) {
+                        float* dst = partials + (int64_t)s_idx[k] * 9;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) dst[q] = g9[q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) s_part[wid][q][k] = g9[q];
+                    }
+                }
+            } else if (W > 1 && lane == 63) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) s_part[wid][q][k] = 0.f;
+            }
+        }
+        if (W > 1) {
+            __syncthreads();
+            if (tid < cnt && !s_frz[tid]) {
+                float sum[9];
+                bool nz = false;
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const float sum = wave_sum(g9[q]);
-                    if (lane == 0) atomicAdd(&s_acc[q][k], sum);
+                    float acc = s_part[0][q][tid];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
+                    sum[q] = acc;
+                    nz = nz || (acc != 0.f);
                 }
-                if (lane == 0) s_hit[k] = 1u;
+                if (nz) {
+                    float* dst = partials + (int64_t)s_idx[tid] * 9;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) dst[q] = sum[q];
+                }
             }
         }
-        __syncthreads();
-        if (tid < cnt && s_hit[tid]) {
-            const uint32_t gid = s_gid[tid];
-            float* out = grad2d + (int64_t)v * 9 * stride + gid;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) unsafeAtomicAdd(out + (int64_t)q * stride, s_acc[q][tid]);
-        }
     }
+    if (pairs) {
+        __syncthreads();
+        if (evals) atomicAdd(&s_pairs, evals);
+        __syncthreads();
+        if (tid == 0 && s_pairs) atomicAdd(pairs, (unsigned long long)s_pairs);
+    }
+}
+
+__global__ void k_zero_partials(float* __restrict__ p, const uint32_t* __restrict__ d_count) {
+    const int64_t n = (int64_t)(*d_count) * 9;
+    float4* p4 = reinterpret_cast<float4*>(p);
+    const int64_t n4 = n / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+        p4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t t = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.f;
 }
 
 }  // namespace
 
-void launch_composite_fwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
-                          const float4* col, const float4* rgb, int64_t stride, const CamArray& cams,
-                          int nv, float bg0, float bg1, float bg2, float* image, float* T_final,
-                          uint32_t* last, double* cfg, hipStream_t s) {
+void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
+                          float* T_final, uint32_t* last, double* cfg, unsigned long long* pairs, hipStream_t s) {
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    k_composite_fwd<<<dim3(tiles, nv), kTilePix, 0, s>>>(ranges, ids, geo, col, rgb, stride, cams, bg0,
-                                                          bg1, bg2, image, T_final, last, cfg);
+    const dim3 grid(tiles, nv);
+    if (waves == 1)
+        k_composite_fwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
+                                                image, T_final, last, cfg, pairs);
+    else if (waves == 2)
+        k_composite_fwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
+                                                 image, T_final, last, cfg, pairs);
+    else
+        k_composite_fwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
+                                                 image, T_final, last, cfg, pairs);
 }
 
-void launch_composite_bwd(const uint2* ranges, const uint32_t* ids, const float4* geo,
-                          const float4* col, const float4* rgb, int64_t stride, const uint8_t* frozen,
-                          const CamArray& cams, int nv, float bg0, float bg1, float bg2,
-                          const float* T_final, const uint32_t* last, const double* cfg,
-                          const float* dL_dimage, float* grad2d, hipStream_t s) {
+void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
+                          const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
+                          float* partials, const uint32_t* d_count, unsigned long long* pairs, hipStream_t s) {
+    k_zero_partials<<<2048, 256, 0, s>>>(partials, d_count);
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    k_composite_bwd<<<dim3(tiles, nv), kTilePix, 0, s>>>(ranges, ids, geo, col, rgb, stride, frozen, cams,
-                                                          bg0, bg1, bg2, T_final, last, cfg, dL_dimage,
-                                                          grad2d);
+    const dim3 grid(tiles, nv);
+    if (waves == 1)
+        k_composite_bwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0, bg1,
+                                                bg2, T_final, last, cfg, dL_dimage, partials, pairs);
+    else if (waves == 2)
+        k_composite_bwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0,
+                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, pairs);
+    else
+        k_composite_bwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0,
+                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, pairs);
 }
 
 }  // namespace gsta

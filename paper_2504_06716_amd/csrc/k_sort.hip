@@ -285,7 +285,9 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
                                                        int tiles_per_view,
                                                        const uint64_t* __restrict__ partials,
                                                        uint32_t* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals, uint64_t capacity) {
+                                                       uint32_t* __restrict__ vals,
+                                                       uint32_t* __restrict__ inst_gid,
+                                                       uint32_t* __restrict__ inst_off, uint64_t capacity) {
     __shared__ uint32_t s_tmp[RS_WAVES];
     __shared__ uint32_t s_off[EX_THREADS + 1];
     __shared__ uint32_t s_gid[EX_THREADS];
@@ -309,6 +311,10 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
     if (tid == 0) s_off[EX_THREADS] = tot;
     __syncthreads();
     const uint64_t base = partials[blockIdx.x];
+    if (e < total_el) {
+        const uint64_t first = base + ex;
+        inst_off[(int64_t)s_view[tid] * stride + s_gid[tid]] = (uint32_t)(first < capacity ? first : capacity);
+    }
     // Every instance of this block's Gaussians, one per thread in turn: find
     // its Gaussian by binary search over the block-local offsets.
     for (uint32_t j = tid; j < tot; j += EX_THREADS) {
@@ -324,7 +330,8 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
         const uint64_t dst = base + j;
         if (dst < capacity) {
             keys[dst] = s_view[lo] * (uint32_t)tiles_per_view + ty * (uint32_t)ntx + tx;
-            vals[dst] = s_gid[lo];
+            vals[dst] = (uint32_t)dst;
+            inst_gid[dst] = s_gid[lo];
         }
     }
 }
@@ -378,15 +385,15 @@ int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / E
 
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
-                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint64_t capacity,
-                   uint32_t* flags, uint64_t* max_inst, hipStream_t s) {
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
+                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, hipStream_t s) {
     const int64_t total_el = n * nv;
     const int64_t nb = expand_blocks(total_el);
     if (nb > 0) k_tile_count<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, partials);
     k_scan_partials<<<1, 1024, 0, s>>>(partials, nb, d_total, d_count, capacity, flags, max_inst);
     if (nb > 0)
         k_expand<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, ntx, tiles_per_view,
-                                                    partials, keys, vals, capacity);
+                                                    partials, keys, vals, inst_gid, inst_off, capacity);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {

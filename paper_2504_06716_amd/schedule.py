@@ -1,0 +1,130 @@
+"""Host-side GSta schedule: freeze thresholds, freeze-map lifecycle, early
+stop and the plateau learning-rate scheduler (Algorithm 1 and the "GSta
+Details" of Section 4.1).  Pure Python scalars; the per-Gaussian work runs
+in libgsta."""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+NONE, UPDATE, RESET = 0, 1, 2
+
+
+@dataclass
+class FreezeSchedule:
+    """Freeze-map lifecycle (Section 4.1, "GSta Details").
+
+    * no freezing before ``warmup``;
+    * inside the window [warmup, min(window_end, stop_iter)] the map is
+      updated every ``every`` iterations and accumulates (sticky);
+    * at every multiple of ``reset_every`` inside the window the map is
+      reset and no re-freezing happens for ``wait`` iterations;
+    * when the window closes (early stop or window end) the map is reset
+      and every Gaussian is trained again (finetune).
+    Thresholds follow eq. 5 read as eps0 * clamp(lam1 + lam2 * k'/K, lam1,
+    lam2) with k' = min(k, k_stop) (``linear``: eps0 * (lam1 + (lam2 - lam1)
+    * k'/K))."""
+
+    total_iters: int
+    warmup: int = 3000
+    every: int = 250
+    reset_every: int = 2000
+    wait: int = 500
+    window_end: int = 10000
+    eps_xyz0: float = 3e-5
+    eps_rgb0: float = 1e-4
+    lam1: float = 0.5
+    lam2: float = 1.5
+    linear: bool = False
+
+    def factor(self, k: int, k_stop: int | None = None) -> float:
+        kk = k if k_stop is None else min(k, k_stop)
+        K = self.total_iters
+        if self.linear:
+            return self.lam1 + (self.lam2 - self.lam1) * kk / K
+        return min(max(self.lam1 + self.lam2 * kk / K, self.lam1), self.lam2)
+
+    def thresholds(self, k: int, k_stop: int | None = None):
+        f = self.factor(k, k_stop)
+        return self.eps_xyz0 * f, self.eps_rgb0 * f
+
+    def window_close(self, stop_iter: int | None = None) -> int:
+        return self.window_end if stop_iter is None else min(self.window_end, stop_iter)
+
+    def action(self, k: int, stop_iter: int | None = None) -> int:
+        """What happens to the freeze map before iteration k."""
+        end = self.window_close(stop_iter)
+        if k == end:
+            return RESET                                 # finetune: everyone trains again
+        if k < self.warmup or k > end or k % self.every != 0:
+            return NONE
+        if k > self.warmup and k % self.reset_every == 0:
+            return RESET
+        last_reset = (k // self.reset_every) * self.reset_every
+        if last_reset > self.warmup and k - last_reset < self.wait:
+            return NONE
+        return UPDATE
+
+
+def early_stop(psnrs, eps: float = 0.2) -> bool:
+    """Eq. 7 with patience 1: the last two PSNR gains are both below eps."""
+    if len(psnrs) < 3:
+        return False
+    return (psnrs[-1] - psnrs[-2] < eps) and (psnrs[-2] - psnrs[-3] < eps)
+
+
+class PlateauLR:
+    """Section 3.2.3: scale the position learning rate by ``factor`` after
+    more than ``patience`` evaluations in a row whose PSNR does not exceed
+    the best so far by more than ``eps`` (dB)."""
+
+    def __init__(self, factor: float = 0.75, patience: int = 1, eps: float = 1.0):
+        self.factor, self.patience, self.eps = factor, patience, eps
+        self.scale = 1.0
+        self.best = None
+        self.bad = 0
+
+    def step(self, psnr: float) -> float:
+        if self.best is None or psnr > self.best + self.eps:
+            self.best = psnr
+            self.bad = 0
+        else:
+            self.bad += 1
+        if self.bad > self.patience:
+            self.scale *= self.factor
+            self.bad = 0
+        return self.scale
+
+
+@dataclass
+class LearningRates:
+    """Per parameter group; the position LR decays exponentially from
+    ``pos_init`` to ``pos_final`` (times the scene extent) over ``decay_iters``
+    and is further scaled by the plateau scheduler.  Opacity uses 0.025
+    (Section 4.1)."""
+
+    extent: float = 3.3
+    pos_init: float = 1.6e-4
+    pos_final: float = 1.6e-6
+    decay_iters: int = 30000
+    scale: float = 5e-3
+    rotation: float = 1e-3
+    opacity: float = 0.025
+    f_dc: float = 2.5e-3
+    f_rest: float = 2.5e-3 / 20.0
+
+    def position(self, k: int) -> float:
+        t = min(max(k / max(self.decay_iters, 1), 0.0), 1.0)
+        return self.extent * math.exp((1 - t) * math.log(self.pos_init) + t * math.log(self.pos_final))
+
+    def rows(self, k: int, degree: int, pos_scale: float = 1.0):
+        R = 11 + 3 * (degree + 1) ** 2
+        lr = [0.0] * R
+        lr[0:3] = [self.position(k) * pos_scale] * 3
+        lr[3:6] = [self.scale] * 3
+        lr[6:10] = [self.rotation] * 4
+        lr[10] = self.opacity
+        lr[11:14] = [self.f_dc] * 3
+        for r in range(14, R):
+            lr[r] = self.f_rest
+        return lr

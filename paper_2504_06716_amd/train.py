@@ -1,0 +1,184 @@
+"""GSta training loop on top of libgsta (Algorithm 1).
+
+Per iteration: (freeze-map update or reset) -> render_forward -> l1_loss ->
+render_backward (frozen skipped, gradient-norm EMAs) -> adam_masked (frozen
+skipped).  Everything per Gaussian or per pixel runs in the HIP library; this
+module keeps only host scalars (schedule, learning rates) and the device
+buffers PyTorch allocates.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from .core import Context, camera_array, n_rows
+from .schedule import NONE, RESET, UPDATE, FreezeSchedule, LearningRates, PlateauLR, early_stop
+
+FLT_MAX = float(np.finfo(np.float32).max)
+
+
+def _padded(R: int, n: int, fill: float = 0.0, dtype=torch.float32) -> torch.Tensor:
+    """[R, n] view of an [R, ld] device block with ld a multiple of 64 (16-byte rows)."""
+    ld = max(64, (n + 63) // 64 * 64)
+    return torch.full((R, ld), fill, dtype=dtype, device="cuda")[:, :n]
+
+
+@dataclass
+class TrainConfig:
+    iters: int
+    freeze: bool = True
+    schedule: FreezeSchedule | None = None
+    lrs: LearningRates = field(default_factory=LearningRates)
+    ema_beta: float = 0.9
+    beta1: float = 0.9
+    beta2: float = 0.999
+    adam_eps: float = 1e-15
+    bg: tuple = (0.0, 0.0, 0.0)
+    eval_every: int | None = None        # K_PSNR; None: no periodic validation
+    early_stop_eps: float | None = None  # eq. 7 threshold (dB); None: no early stop
+    plateau: PlateauLR | None = None
+    finetune_iters: int = 0              # K_f after an early stop
+    track_ema: bool = False              # keep gradient-norm EMAs even without freezing
+
+
+class Trainer:
+    """One GSta (or plain, freeze=False) training run on a single GPU."""
+
+    def __init__(self, params0: np.ndarray, degree: int, cams, targets: torch.Tensor, cfg: TrainConfig,
+                 view_order: np.ndarray, ctx: Context | None = None, capacity: int | None = None,
+                 val_views=None):
+        self.degree = degree
+        self.cfg = cfg
+        self.R, self.n = params0.shape
+        assert self.R == n_rows(degree)
+        self.cams = cams
+        self.H, self.W = cams[0].height, cams[0].width
+        self.cam1 = [camera_array([c]) for c in cams]
+        self.targets = targets
+        self.order = view_order
+        self.val_views = list(range(len(cams))) if val_views is None else list(val_views)
+        self.ctx = ctx or Context(self.n, min(8, len(cams)), self.H, self.W, capacity or (1 << 22), n_slots=1)
+        self.P = _padded(self.R, self.n)
+        self.P.copy_(torch.from_numpy(np.ascontiguousarray(params0, dtype=np.float32)).cuda())
+        self.G = _padded(self.R, self.n)
+        self.M = _padded(self.R, self.n)
+        self.Vm = _padded(self.R, self.n)
+        self.frozen = torch.zeros(max(64, (self.n + 63) // 64 * 64), dtype=torch.uint8, device="cuda")[: self.n]
+        self.ema = _padded(4, self.n, FLT_MAX)
+        self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.image = torch.empty((1, 3, self.H, self.W), device="cuda")
+        self.dL = torch.empty_like(self.image)
+        self.sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+        self.step_count = 0
+        self.k = 0
+        self.psnrs: list[float] = []
+        self.stop_iter: int | None = None
+        self.pos_scale = 1.0
+        self.frozen_log: list[tuple[int, int]] = []
+        self.frozen_counts = torch.zeros(1024, dtype=torch.int64, device="cuda")
+
+    # ------------------------------------------------------------------
+    def _freeze_step(self, k: int):
+        s = self.cfg.schedule
+        if not self.cfg.freeze or s is None:
+            return
+        act = s.action(k, self.stop_iter)
+        if act == NONE:
+            return
+        if act == UPDATE:
+            ex, er = s.thresholds(k, s.window_close(self.stop_iter))
+            self.ctx.update_freeze_mask(self.ema[0], self.ema[1], ex, er, 0, self.frozen, n_frozen=self.n_frozen)
+        elif act == RESET:
+            self.ctx.update_freeze_mask(None, None, 0.0, 0.0, 1, self.frozen, n_frozen=self.n_frozen)
+        i = len(self.frozen_log)
+        if i < self.frozen_counts.numel():
+            self.frozen_counts[i:i + 1].copy_(self.n_frozen, non_blocking=True)
+        self.frozen_log.append((k, act))
+
+    def freeze_history(self):
+        """[(iteration, action, frozen count after it)] for every freeze-map change."""
+        c = self.frozen_counts[: len(self.frozen_log)].cpu().tolist()
+        return [(k, a, n) for (k, a), n in zip(self.frozen_log, c)]
+
+    def step(self):
+        """One training iteration k = self.k."""
+        k = self.k
+        cfg = self.cfg
+        self._freeze_step(k)
+        view = int(self.order[k % len(self.order)])
+        cam = self.cam1[view]
+        frz = self.frozen if cfg.freeze else None
+        ema = self.ema if (cfg.freeze or cfg.track_ema) else None
+        self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
+        self.ctx.l1_loss(self.image, self.targets[view:view + 1], self.dL, self.sums)
+        self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
+                                 cfg.ema_beta)
+        self.step_count += 1
+        lr = cfg.lrs.rows(k, self.degree, self.pos_scale)
+        self.ctx.adam_masked(self.P, self.G, self.M, self.Vm, self.degree, lr, cfg.beta1, cfg.beta2,
+                             cfg.adam_eps, self.step_count, frz)
+        self.k += 1
+        if cfg.eval_every and self.k % cfg.eval_every == 0 and self.stop_iter is None:
+            self._validate()
+
+    def _validate(self):
+        p = self.evaluate(self.val_views)
+        self.psnrs.append(p)
+        if self.cfg.plateau is not None:
+            self.pos_scale = self.cfg.plateau.step(p)
+        if self.cfg.early_stop_eps is not None and early_stop(self.psnrs, self.cfg.early_stop_eps):
+            self.stop_iter = self.k
+
+    def run(self, iters: int):
+        for _ in range(iters):
+            self.step()
+
+    # ------------------------------------------------------------------
+    def render_views(self, views, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Render views (up to 8 per library call) into [len(views), 3, H, W]."""
+        views = list(views)
+        out = out if out is not None else torch.empty((len(views), 3, self.H, self.W), device="cuda")
+        vmax = self.ctx.limits.max_views
+        for b in range(0, len(views), vmax):
+            vs = views[b:b + vmax]
+            self.ctx.render_forward(self.P, self.degree, [self.cams[v] for v in vs], self.cfg.bg,
+                                    out[b:b + len(vs)], 0)
+        return out
+
+    def evaluate(self, views=None) -> float:
+        """Mean PSNR over views (images clamped to [0, 1])."""
+        views = self.val_views if views is None else list(views)
+        img = self.render_views(views)
+        tgt = self.targets[views]
+        mse = ((img.clamp(0.0, 1.0) - tgt) ** 2).flatten(1).mean(1).double()
+        return float((10.0 * torch.log10(1.0 / mse)).mean())
+
+    def frozen_fraction(self) -> float:
+        return float(self.frozen.float().mean()) if self.cfg.freeze else 0.0
+
+
+def render_targets(ctx: Context, params: np.ndarray, degree: int, cams, bg=(0.0, 0.0, 0.0)) -> torch.Tensor:
+    """Render training targets for every camera through the library."""
+    R, n = params.shape
+    P = _padded(R, n)
+    P.copy_(torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda())
+    H, W = cams[0].height, cams[0].width
+    out = torch.empty((len(cams), 3, H, W), device="cuda")
+    vmax = ctx.limits.max_views
+    for b in range(0, len(cams), vmax):
+        cs = cams[b:b + vmax]
+        ctx.render_forward(P, degree, cs, bg, out[b:b + len(cs)], 0)
+    return out
+
+
+def required_capacity(ctx: Context, params: np.ndarray, degree: int, cams) -> int:
+    """Largest per-call instance count over the cameras (renders them once)."""
+    render_targets(ctx, params, degree, cams)
+    st, need = ctx.check()
+    if st not in (_lib.GSTA_OK, _lib.GSTA_ERR_CAPACITY):
+        raise _lib.GstaError(st, "check failed")
+    return need

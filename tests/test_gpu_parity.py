@@ -105,7 +105,11 @@ def test_depth_order_and_tile_lists(kind):
     ntx, nty = (cam0.width + 15) // 16, (cam0.height + 15) // 16
     T = ntx * nty
     keys = g.state(L.STATE_INST_KEYS, torch.int32, (ninst,)).astype(np.int64) & 0xFFFFFFFF
-    ids = g.state(L.STATE_INST_IDS, torch.int32, (ninst,)).astype(np.int64)
+    eidx = g.state(L.STATE_INST_IDS, torch.int32, (ninst,)).astype(np.int64)
+    egid = g.state(L.STATE_INST_GID, torch.int32, (ninst,)).astype(np.int64)
+    ids = egid[eidx]
+    # the expansion lists Gaussians in depth order, each one's tiles contiguous
+    assert sorted(eidx.tolist()) == list(range(ninst))
     ranges = g.state(L.STATE_RANGES, torch.int32, (V * T, 2)).astype(np.int64)
     assert (np.diff(keys) >= 0).all()
     _, marg = _margins(p, D, cams)
@@ -312,8 +316,10 @@ def test_adam_masked_matches_oracle(ld_pad):
     p, g, m, v = t
     ctx.adam_masked(p, g, m, v, 3, lr, 0.9, 0.999, 1e-15, 7, dev(frozen))
     torch.cuda.synchronize()
+    # the oracle takes the float32 hyper-parameters the GPU receives
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
     P, Mm, Vv = O.adam_masked(blocks[0][:, :n], blocks[1][:, :n], blocks[2][:, :n], blocks[3][:, :n],
-                              lr.astype(np.float64), 0.9, 0.999, 1e-15, 7, frozen)
+                              lr.astype(np.float64), b1, b2, 1e-15, 7, frozen)
     gp, gm, gv = p.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy()
     fz = frozen == 1
     assert np.array_equal(gp[:, fz], blocks[0][:, :n][:, fz])
@@ -323,8 +329,12 @@ def test_adam_masked_matches_oracle(ld_pad):
     p0 = blocks[0][:, :n].astype(np.float64)
     err = np.abs(gp[:, ~fz] - P[:, ~fz])
     assert (err <= 4e-7 * np.abs(P[:, ~fz]) + 1e-5 * np.abs(P - p0)[:, ~fz] + 1e-12).all()
-    np.testing.assert_allclose(gm[:, ~fz], Mm[:, ~fz], rtol=1e-6, atol=1e-8)
-    np.testing.assert_allclose(gv[:, ~fz], Vv[:, ~fz], rtol=1e-6, atol=1e-8)
+    # m = b1 m + (1 - b1) g may cancel: bound by the float32 rounding of the operands
+    m0, g0, v0 = (blocks[k][:, :n].astype(np.float64) for k in (2, 1, 3))
+    mb = 4e-7 * (0.9 * np.abs(m0) + 0.1 * np.abs(g0)) + 1e-12
+    assert (np.abs(gm - Mm)[:, ~fz] <= mb[:, ~fz]).all()
+    vb = 4e-7 * (0.999 * v0 + 0.001 * g0 * g0) + 1e-12
+    assert (np.abs(gv - Vv)[:, ~fz] <= vb[:, ~fz]).all()
 
 
 def test_adam_nonfinite_flag():
@@ -383,3 +393,30 @@ def test_l1_loss_matches_oracle():
     assert s[1] / img.size == pytest.approx(mse, rel=1e-6)
     np.testing.assert_allclose(dL.cpu().numpy(), dref, rtol=1e-6)
     assert (dL.cpu().numpy()[0, 0, 0, :5] == 0).all()
+
+
+@pytest.mark.parametrize("fwd,bwd", [(1, 1), (2, 2), (4, 4), (4, 1), (1, 4)])
+def test_waves_per_tile_options(fwd, bwd):
+    """Waves per tile change the thread mapping only: images are bit-identical,
+    gradients agree to rounding of the reduction order."""
+    p, D, cams = scene("ragged")
+    ref = GpuScene(p, D, cams)
+    img_ref = ref.forward()
+    dL = np.random.default_rng(9).standard_normal((len(cams), 3, 37, 50)).astype(np.float32)
+    g_ref, _, _ = ref.backward(dL)
+    g = GpuScene(p, D, cams)
+    g.ctx.set_waves(fwd=fwd, bwd=bwd)
+    img = g.forward()
+    assert np.array_equal(img, img_ref)
+    grad, _, _ = g.backward(dL)
+    np.testing.assert_allclose(grad, g_ref, rtol=1e-4, atol=1e-6 * np.abs(g_ref).max())
+
+
+def test_backward_is_deterministic():
+    p, D, cams = scene("c2view")
+    g = GpuScene(p, D, cams)
+    g.forward()
+    dL = np.random.default_rng(10).standard_normal((1, 3, 480, 640)).astype(np.float32)
+    a, a2, _ = g.backward(dL)
+    b, b2, _ = g.backward(dL)
+    assert np.array_equal(a, b) and np.array_equal(a2, b2)

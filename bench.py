@@ -239,6 +239,8 @@ def main():
                      "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches},
         "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_all.items()},
         "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],
+        "lane_utilisation": [round(pairs_all[0] / max(64 * pairs_all[2], 1), 4),
+                             round(pairs_all[1] / max(64 * pairs_all[3], 1), 4)],
         "max_instances": max_inst,
     }
     if not args.no_cpu_baseline:

@@ -89,8 +89,8 @@ typedef struct {
 /* Fields readable with gsta_get_state (after gsta_render_forward). */
 typedef enum {
     GSTA_STATE_REC_GEO = 0,     /* float4 [V][N]: u, v, conic_a, conic_b           */
-    GSTA_STATE_REC_COL = 1,     /* float4 [V][N]: conic_c, opacity, depth z, 0      */
-    GSTA_STATE_REC_RGB = 2,     /* float4 [V][N]: r, g, b (clamped colour), 0      */
+    GSTA_STATE_REC_COL = 1,     /* float4 [V][N]: conic_c, opacity, conservative screen half-extents x, y */
+    GSTA_STATE_REC_RGB = 2,     /* float4 [V][N]: r, g, b (clamped colour), camera depth z */
     GSTA_STATE_RECT = 3,        /* uint16x4 [V][N]: tile x0, x1, y0, y1 (exclusive ends); all 0 if culled */
     GSTA_STATE_DEPTH_ORDER = 4, /* uint32 [V][N]: gid in ascending (float32 depth, gid) order, culled last */
     GSTA_STATE_INST_KEYS = 5,   /* uint32 [I]: view * T + tile of each instance, sorted */
@@ -105,7 +105,8 @@ typedef enum {
 
 /* Execution options (gsta_set_option).  They change speed, never results. */
 typedef enum {
-    GSTA_OPT_FWD_WAVES = 0,     /* waves per 16x16 tile in forward compositing: 1, 2 or 4 (default 4) */
+    GSTA_OPT_FWD_WAVES = 0,     /* waves per 16x16 tile in forward compositing: 1, 2 or 4 (default 4),
+                                   or 0: one independent wave per 8x8 quarter of each tile */
     GSTA_OPT_BWD_WAVES = 1      /* waves per tile in backward compositing: 1, 2 or 4 (default 4) */
 } gsta_option;
 
@@ -152,11 +153,12 @@ typedef enum {
  * compositing kernels of enabled phases count the (pixel, splat) pairs they
  * evaluate.  gsta_read_profile synchronises,
  * writes per-phase totals since the last read -- ms[GSTA_N_PHASES] elapsed
- * time, launches[GSTA_N_PHASES] -- and pairs[2] = pairs evaluated by the
- * forward and backward compositing (all host arrays, each may be NULL),
- * then resets the totals. */
+ * time, launches[GSTA_N_PHASES] -- and counters[5] = (pixel, splat) pairs
+ * evaluated by the forward and by the backward compositing, wave-level splat
+ * iterations of the forward and of the backward, and wave reductions of the
+ * backward (all host arrays, each may be NULL), then resets the totals. */
 gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask);
-gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* pairs);
+gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* counters);
 
 /* ---- the hot path ------------------------------------------------------- */
 

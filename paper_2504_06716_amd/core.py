@@ -136,12 +136,13 @@ class Context:
         check(self.h, self.L.gsta_set_profiling(self.h, mask))
 
     def read_profile(self):
-        """Per-phase {name: (total ms, launches)} and evaluated pairs (fwd, bwd) since the last read."""
+        """Per-phase {name: (total ms, launches)} and counters (fwd pairs, bwd pairs,
+        fwd wave iterations, bwd wave iterations, bwd wave reductions) since the last read."""
         ms = (ctypes.c_double * len(_lib.PHASES))()
         ln = (ctypes.c_int64 * len(_lib.PHASES))()
-        pr = (ctypes.c_int64 * 2)()
+        pr = (ctypes.c_int64 * 5)()
         check(self.h, self.L.gsta_read_profile(self.h, ms, ln, pr))
-        return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, (pr[0], pr[1])
+        return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, tuple(pr)
 
     # ---- hot path --------------------------------------------------------
     def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None):

@@ -15,6 +15,8 @@ using namespace gsta;
 
 namespace {
 
+constexpr int kCounters = 5;   // profiling counters, see gsta_read_profile
+
 struct Slot {
     float4* geo = nullptr;
     float4* col = nullptr;
@@ -63,7 +65,9 @@ struct gsta_ctx {
     std::string err;
     // profiling
     uint32_t profiling = 0;                   // phase mask
-    unsigned long long* pairs = nullptr;      // [0] forward, [1] backward compositing
+    // profiling counters: [0] fwd pairs, [1] bwd pairs, [2] fwd wave iterations,
+    // [3] bwd wave iterations, [4] bwd wave reductions
+    unsigned long long* pairs = nullptr;
     struct Pending {
         int phase;
         hipEvent_t a, b;
@@ -151,14 +155,14 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) &&
-         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, 2);
+         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
     if (!ok) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_OOM, "device allocation failed");
     }
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
-        hipMemset(ctx->pairs, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_HIP, "initialising flags failed");
@@ -257,9 +261,11 @@ struct PhaseTimer {
     }
 };
 
+// Base of the profiling counters for a compositing phase (each kernel writes
+// its own fixed entries), or NULL when the phase is not profiled.
 unsigned long long* pair_counter(gsta_ctx* ctx, int which) {
     const int phase = which == 0 ? GSTA_PHASE_COMPOSITE : GSTA_PHASE_COMPOSITE_BWD;
-    return (ctx->profiling & (1u << phase)) ? ctx->pairs + which : nullptr;
+    return (ctx->profiling & (1u << phase)) ? ctx->pairs : nullptr;
 }
 
 }  // namespace
@@ -316,10 +322,14 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     switch (option) {
         case GSTA_OPT_FWD_WAVES:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return fail(ctx, GSTA_ERR_INVALID, "forward waves per tile must be 0, 1, 2 or 4");
+            ctx->fwd_waves = (int)value;
+            return GSTA_OK;
         case GSTA_OPT_BWD_WAVES:
             if (value != 1 && value != 2 && value != 4)
-                return fail(ctx, GSTA_ERR_INVALID, "waves per tile must be 1, 2 or 4");
-            (option == GSTA_OPT_FWD_WAVES ? ctx->fwd_waves : ctx->bwd_waves) = (int)value;
+                return fail(ctx, GSTA_ERR_INVALID, "backward waves per tile must be 1, 2 or 4");
+            ctx->bwd_waves = (int)value;
             return GSTA_OK;
         default:
             return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
@@ -346,10 +356,10 @@ gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int6
         ctx->pool.push_back(p.b);
     }
     ctx->pending.clear();
-    unsigned long long pr[2] = {0, 0};
+    unsigned long long pr[kCounters] = {};
     if ((st = hip_check(ctx, hipMemcpy(pr, ctx->pairs, sizeof(pr), hipMemcpyDeviceToHost), "read pairs")) != GSTA_OK)
         return st;
-    const unsigned long long z[2] = {0, 0};
+    const unsigned long long z[kCounters] = {};
     if ((st = hip_check(ctx, hipMemcpy(ctx->pairs, z, sizeof(z), hipMemcpyHostToDevice), "clear pairs")) != GSTA_OK)
         return st;
     for (int i = 0; i < GSTA_N_PHASES; ++i) {
@@ -358,10 +368,8 @@ gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int6
         ctx->ms[i] = 0.0;
         ctx->launches[i] = 0;
     }
-    if (pairs) {
-        pairs[0] = (int64_t)pr[0];
-        pairs[1] = (int64_t)pr[1];
-    }
+    if (pairs)
+        for (int i = 0; i < kCounters; ++i) pairs[i] = (int64_t)pr[i];
     return GSTA_OK;
 }
 

@@ -51,15 +51,27 @@ struct SplatEval {
     float dx, dy, power, G, oG, alpha;
 };
 
-__device__ __forceinline__ void eval_splat(float u, float v, float ca, float cb, float cc, float o,
-                                           float px, float py, SplatEval& e) {
+// Split in two so that a wave can skip the exponential when none of its
+// pixels lies inside the splat's 3-sigma ellipse.
+__device__ __forceinline__ void eval_power(float u, float v, float ca, float cb, float cc, float px, float py,
+                                           SplatEval& e) {
 #pragma clang fp contract(off)
     e.dx = u - px;
     e.dy = v - py;
     e.power = -0.5f * (ca * e.dx * e.dx + cc * e.dy * e.dy) - cb * e.dx * e.dy;
+}
+
+__device__ __forceinline__ void eval_alpha(float o, SplatEval& e) {
+#pragma clang fp contract(off)
     e.G = __builtin_amdgcn_exp2f(e.power * kLog2e);
     e.oG = o * e.G;
     e.alpha = fminf(kAlphaMax, e.oG);
+}
+
+__device__ __forceinline__ void eval_splat(float u, float v, float ca, float cb, float cc, float o,
+                                           float px, float py, SplatEval& e) {
+    eval_power(u, v, ca, cb, cc, px, py, e);
+    eval_alpha(o, e);
 }
 
 __device__ __forceinline__ float next_T(float T, float alpha) {

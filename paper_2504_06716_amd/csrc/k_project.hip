@@ -232,14 +232,26 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
                     for (int k = 0; k < K; ++k) acc += f[k][ch] * B[k];
                     cc[ch] = fmaxf(acc + 0.5f, 0.f);
                 }
-                rg = make_float4(cc[0], cc[1], cc[2], 0.f);
+                rg = make_float4(cc[0], cc[1], cc[2], g.xc[2]);
                 geo[o_idx] = make_float4(g.u, g.v, g.c * g.inv, -g.b * g.inv);
-                col[o_idx] = make_float4(g.a * g.inv, o, g.xc[2], 0.f);
+                // Screen half-extent outside which no pixel can be a member:
+                // power >= -4.5 and o exp(power) >= 1/255 bound d^T conic d by
+                // 2 min(4.5, ln(255 o)).  Inflated by 1% + 0.5 px so float32
+                // rounding never makes a skipped splat a member.
+                const float lo = logf(255.0f * o);
+                float ex2 = -1e30f, ey2 = -1e30f;
+                if (lo > 0.f) {
+                    const float kf = sqrtf(2.0f * fminf(4.5f, lo));
+                    ex2 = kf * sqrtf(g.a) * 1.01f + 0.5f;
+                    ey2 = kf * sqrtf(g.c) * 1.01f + 0.5f;
+                }
+                col[o_idx] = make_float4(g.a * g.inv, o, ex2, ey2);
             }
         }
         if (!vis) {
             geo[o_idx] = make_float4(0.f, 0.f, 0.f, 0.f);
-            col[o_idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+            col[o_idx] = make_float4(0.f, 0.f, -1e30f, -1e30f);
+            if (g.xc[2] > cm.near_z) rg.w = g.xc[2];
         }
         rgbo[o_idx] = rg;
         rect[o_idx] = r;

@@ -42,22 +42,53 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
     return v;
 }
 
-template <int W>
+// One splat record as staged in LDS: mean + conic (a, b), conic c +
+// opacity, colour.
+struct Rec {
+    float4 g;    // u, v, conic a, conic b
+    float4 co;   // conic c, opacity, half-extent x, half-extent y
+    float4 c;    // r, g, b
+};
+
+__device__ __forceinline__ void fetch_rec(const float4* __restrict__ geo, const float4* __restrict__ col,
+                                          const float4* __restrict__ rgbv, int64_t vs, uint32_t gid, Rec& r) {
+    r.g = geo[vs + gid];
+    r.co = col[vs + gid];
+    r.c = rgbv[vs + gid];
+}
+
+// Pixel p of thread tid.  Tile mode: 4/W pixels per thread, rows interleaved
+// by the block size.  Quadrant mode (one wave per 8x8 quarter of the tile,
+// blockIdx.x = 4 * tile + quarter): one pixel per lane.
+template <int W, bool QUAD>
+__device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, int ty0, int& px, int& py) {
+    if (QUAD) {
+        px = tx0 + (quarter & 1) * 8 + (tid & 7);
+        py = ty0 + (quarter >> 1) * 8 + (tid >> 3);
+    } else {
+        const int pix = tid + p * 64 * W;
+        px = tx0 + (pix & (kTile - 1));
+        py = ty0 + pix / kTile;
+    }
+}
+
+template <int W, bool QUAD>
 __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg,
     unsigned long long* __restrict__ pairs) {
-    constexpr int NT = 64 * W, P = 4 / W, B = NT;
+    constexpr int NT = 64 * W, P = QUAD ? 1 : 4 / W, B = NT;
     __shared__ float4 s_geo[B];
-    __shared__ float2 s_co[B];
+    __shared__ float4 s_co[B];
     __shared__ float4 s_rgb[B];
     __shared__ unsigned int s_pairs;
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
-    const int tile = blockIdx.x;
+    const int tile = QUAD ? (int)(blockIdx.x >> 2) : (int)blockIdx.x;
+    const int quarter = (int)(blockIdx.x & 3);
     const int tid = threadIdx.x;
     const int tx0 = (tile % cm.ntx) * kTile, ty0 = (tile / cm.ntx) * kTile;
     const uint2 rg = ranges[(int64_t)v * tiles + tile];
@@ -70,8 +101,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     bool alldone = true;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int pix = tid + p * NT;
-        const int px = tx0 + (pix & (kTile - 1)), py = ty0 + pix / kTile;
+        int px, py;
+        pixel_of<W, QUAD>(tid, p, quarter, tx0, ty0, px, py);
         inside[p] = px < cm.width && py < cm.height;
         fpx[p] = (float)px;
         fpy[p] = (float)py;
@@ -81,24 +112,40 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         done[p] = !inside[p];
         alldone = alldone && done[p];
     }
-    uint32_t evals = 0;
+    uint32_t evals = 0, witer = 0;
     if (tid == 0) s_pairs = 0;
+
+    // Two-stage software pipeline: while a batch is composited, the records
+    // of the next batch and the ids of the one after are in flight.
+    Rec cur;
+    uint32_t gid_nxt = 0;
+    {
+        const uint32_t j = rg.x + tid;
+        if (j < rg.y) fetch_rec(geo, col, rgbv, vs, inst_gid[ids[j]], cur);
+        if (j + B < rg.y) gid_nxt = inst_gid[ids[j + B]];
+    }
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         if (__syncthreads_count(!alldone) == 0) break;
-        const uint32_t j = base + tid;
-        if (j < rg.y) {
-            const uint32_t gid = inst_gid[ids[j]];
-            s_geo[tid] = geo[vs + gid];
-            const float4 c = col[vs + gid];
-            s_co[tid] = make_float2(c.x, c.y);
-            s_rgb[tid] = rgbv[vs + gid];
+        if (base + tid < rg.y) {
+            s_geo[tid] = cur.g;
+            s_co[tid] = cur.co;
+            s_rgb[tid] = cur.c;
         }
         __syncthreads();
+        {
+            const uint32_t jn = base + B + tid;
+            if (jn < rg.y) fetch_rec(geo, col, rgbv, vs, gid_nxt, cur);
+            if (jn + B < rg.y) gid_nxt = inst_gid[ids[jn + B]];
+        }
         const int cnt = (int)min((uint32_t)B, rg.y - base);
+        // Each lane leaves the walk as soon as its pixels are done; the
+        // exponential and the accumulation run under the lanes' own
+        // membership tests.
         for (int k = 0; k < cnt && !alldone; ++k) {
             const float4 g = s_geo[k];
-            const float2 co = s_co[k];
+            const float2 co = make_float2(s_co[k].x, s_co[k].y);
             bool all = true;
+            witer += 1u;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!done[p]) {
@@ -129,14 +176,19 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         __syncthreads();
         if (evals) atomicAdd(&s_pairs, evals);
         __syncthreads();
-        if (tid == 0 && s_pairs) atomicAdd(pairs, (unsigned long long)s_pairs);
+        if (tid == 0 && s_pairs) atomicAdd(pairs + 0, (unsigned long long)s_pairs);
+        // the wave runs as long as its longest lane
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) witer = max(witer, (uint32_t)__shfl_xor((int)witer, off, 64));
+        if ((tid & 63) == 0 && witer) atomicAdd(pairs + 2, (unsigned long long)witer);
     }
     const int64_t HW = (int64_t)cm.width * cm.height;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (!inside[p]) continue;
-        const int pix = tid + p * NT;
-        const int64_t o = (int64_t)(ty0 + pix / kTile) * cm.width + (tx0 + (pix & (kTile - 1)));
+        int px, py;
+        pixel_of<W, QUAD>(tid, p, quarter, tx0, ty0, px, py);
+        const int64_t o = (int64_t)py * cm.width + px;
         float* img = image + (int64_t)v * 3 * HW + o;
         img[0] = (float)(C[p][0] + (double)(T[p] * bg0));
         img[HW] = (float)(C[p][1] + (double)(T[p] * bg1));
@@ -150,6 +202,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     }
 }
 
+constexpr int kChunk = 64;   // splats per partial-sum flush in the backward
+
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
@@ -159,11 +213,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const float* __restrict__ dL_dimage, float* __restrict__ partials, unsigned long long* __restrict__ pairs) {
     constexpr int NT = 64 * W, P = 4 / W, B = NT;
     __shared__ float4 s_geo[B];
-    __shared__ float2 s_co[B];
+    __shared__ float4 s_co[B];
     __shared__ float4 s_rgb[B];
     __shared__ uint32_t s_idx[B];
     __shared__ uint32_t s_frz[B];
-    __shared__ float s_part[W][9][B];
+    __shared__ float s_part[W][9][kChunk];
     __shared__ uint32_t s_maxlast;
     __shared__ unsigned int s_pairs;
 
@@ -183,8 +237,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     uint32_t mylast = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int pix = tid + p * NT;
-        const int px = tx0 + (pix & (kTile - 1)), py = ty0 + pix / kTile;
+        int px, py;
+        pixel_of<W, false>(tid, p, 0, tx0, ty0, px, py);
         fpx[p] = (float)px;
         fpy[p] = (float)py;
         T[p] = 1.0f;
@@ -216,48 +270,86 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     if (mylast) atomicMax(&s_maxlast, mylast);
     __syncthreads();
     const uint32_t end = rg.x + s_maxlast;
-    uint32_t evals = 0;
+    uint32_t evals = 0, witer = 0, wred = 0;
 
+    // Two-stage software pipeline as in the forward.
+    Rec cur;
+    uint32_t idx_cur = 0, frz_cur = 0, idx_nxt = 0, gid_nxt = 0;
+    {
+        const uint32_t j = rg.x + tid;
+        if (j < end) {
+            idx_cur = ids[j];
+            const uint32_t gid = inst_gid[idx_cur];
+            fetch_rec(geo, col, rgbv, vs, gid, cur);
+            frz_cur = frozen ? (uint32_t)frozen[gid] : 0u;
+        }
+        if (j + B < end) {
+            idx_nxt = ids[j + B];
+            gid_nxt = inst_gid[idx_nxt];
+        }
+    }
     for (uint32_t base = rg.x; base < end; base += B) {
         __syncthreads();
-        const uint32_t j = base + tid;
-        if (j < end) {
-            const uint32_t idx = ids[j];
-            const uint32_t gid = inst_gid[idx];
-            s_idx[tid] = idx;
-            s_geo[tid] = geo[vs + gid];
-            const float4 c = col[vs + gid];
-            s_co[tid] = make_float2(c.x, c.y);
-            s_rgb[tid] = rgbv[vs + gid];
-            s_frz[tid] = frozen ? (uint32_t)frozen[gid] : 0u;
+        if (base + tid < end) {
+            s_idx[tid] = idx_cur;
+            s_geo[tid] = cur.g;
+            s_co[tid] = cur.co;
+            s_rgb[tid] = cur.c;
+            s_frz[tid] = frz_cur;
         }
         __syncthreads();
+        {
+            const uint32_t jn = base + B + tid;
+            if (jn < end) {
+                idx_cur = idx_nxt;
+                fetch_rec(geo, col, rgbv, vs, gid_nxt, cur);
+                frz_cur = frozen ? (uint32_t)frozen[gid_nxt] : 0u;
+            }
+            if (jn + B < end) {
+                idx_nxt = ids[jn + B];
+                gid_nxt = inst_gid[idx_nxt];
+            }
+        }
         const int cnt = (int)min((uint32_t)B, end - base);
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t pos = base - rg.x + (uint32_t)k;
-            const float4 g = s_geo[k];
-            const float2 co = s_co[k];
-            const float4 c = s_rgb[k];
-            const bool frz = s_frz[k] != 0u;
-            float g9[9];
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+            const int c1 = min(cnt, c0 + kChunk);
+            for (int k = c0; k < c1; ++k) {
+                const uint32_t pos = base - rg.x + (uint32_t)k;
+                const float4 g = s_geo[k];
+                const float2 co = make_float2(s_co[k].x, s_co[k].y);
+                // uniform over the wave: a scalar branch
+                const bool frz = __builtin_amdgcn_readfirstlane(s_frz[k]) != 0u;
+                witer += 1u;
+                SplatEval e[P];
+                bool mem[P];
+                bool any = false;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) g9[q] = 0.f;
-            bool contrib = false;
+                for (int p = 0; p < P; ++p) {
+                    const bool act = pos < last[p];
+                    evals += act ? 1u : 0u;
+                    eval_power(g.x, g.y, g.z, g.w, co.x, fpx[p], fpy[p], e[p]);
+                    mem[p] = act && (e[p].power >= kPowerFloor);
+                    any = any || mem[p];
+                }
+                bool contrib = false;
+                if (__ballot(any) != 0ull) {
+                    const float4 c = s_rgb[k];
+                    float g9[9];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (pos < last[p]) {
-                    ++evals;
-                    SplatEval e;
-                    eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx[p], fpy[p], e);
-                    if (e.power >= kPowerFloor && e.alpha >= kAlphaMin) {
-                        const float w = e.alpha * T[p];
+                    for (int q = 0; q < 9; ++q) g9[q] = 0.f;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        eval_alpha(co.y, e[p]);
+                        mem[p] = mem[p] && (e[p].alpha >= kAlphaMin);
+                        if (!mem[p]) continue;
+                        const float w = e[p].alpha * T[p];
                         const double wd = (double)w;
                         A[p][0] = fma((double)c.x, wd, A[p][0]);
                         A[p][1] = fma((double)c.y, wd, A[p][1]);
                         A[p][2] = fma((double)c.z, wd, A[p][2]);
                         if (!frz) {
                             contrib = true;
-                            const float inv1m = 1.0f / (1.0f - e.alpha);
+                            const float inv1m = 1.0f / (1.0f - e[p].alpha);
                             const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
                             const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
                             const float b2 = (float)(F[p][2] - A[p][2]) + Tf[p] * bg2;
@@ -267,56 +359,64 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             g9[6] += dC[p][0] * w;
                             g9[7] += dC[p][1] * w;
                             g9[8] += dC[p][2] * w;
-                            if (e.oG <= kAlphaMax) {
-                                const float dpow = dalpha * e.alpha;
-                                g9[5] += dalpha * e.G;
-                                g9[0] -= dpow * (g.z * e.dx + g.w * e.dy);
-                                g9[1] -= dpow * (g.w * e.dx + co.x * e.dy);
-                                g9[2] -= 0.5f * dpow * e.dx * e.dx;
-                                g9[3] -= dpow * e.dx * e.dy;
-                                g9[4] -= 0.5f * dpow * e.dy * e.dy;
+                            if (e[p].oG <= kAlphaMax) {
+                                const float dpow = dalpha * e[p].alpha;
+                                g9[5] += dalpha * e[p].G;
+                                g9[0] -= dpow * (g.z * e[p].dx + g.w * e[p].dy);
+                                g9[1] -= dpow * (g.w * e[p].dx + co.x * e[p].dy);
+                                g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
+                                g9[3] -= dpow * e[p].dx * e[p].dy;
+                                g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
                             }
                         }
-                        T[p] = next_T(T[p], e.alpha);
+                        T[p] = next_T(T[p], e[p].alpha);
+                    }
+                    if (!frz && __ballot(contrib) != 0ull) {
+                        wred += 1u;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
+                        if (lane == 63) {
+                            if (W == 1) {
+                                float* dst = partials + (int64_t)s_idx[k] * 9;
+#pragma unroll
+                                for (int q = 0; q < 9; ++q) dst[q] = g9[q];
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = g9[q];
+                            }
+                        }
+                        continue;
                     }
                 }
+                if (W > 1 && lane == 63) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = 0.f;
+                }
             }
-            if (!frz && __ballot(contrib) != 0ull) {
+            if (W > 1) {
+                // the waves' totals added in a fixed order
+                __syncthreads();
+                if (tid < c1 - c0) {
+                    const int k = c0 + tid;
+                    if (!s_frz[k]) {
+                        float sum[9];
+                        bool nz = false;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
-                if (lane == 63) {
-                    if (W == 1) {
-                        float* dst = partials + (int64_t)s_idx[k] * 9;
+                        for (int q = 0; q < 9; ++q) {
+                            float acc = s_part[0][q][tid];
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) dst[q] = g9[q];
-                    } else {
+                            for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
+                            sum[q] = acc;
+                            nz = nz || (acc != 0.f);
+                        }
+                        if (nz) {
+                            float* dst = partials + (int64_t)s_idx[k] * 9;
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) s_part[wid][q][k] = g9[q];
+                            for (int q = 0; q < 9; ++q) dst[q] = sum[q];
+                        }
                     }
                 }
-            } else if (W > 1 && lane == 63) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) s_part[wid][q][k] = 0.f;
-            }
-        }
-        if (W > 1) {
-            __syncthreads();
-            if (tid < cnt && !s_frz[tid]) {
-                float sum[9];
-                bool nz = false;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    float acc = s_part[0][q][tid];
-#pragma unroll
-                    for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
-                    sum[q] = acc;
-                    nz = nz || (acc != 0.f);
-                }
-                if (nz) {
-                    float* dst = partials + (int64_t)s_idx[tid] * 9;
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) dst[q] = sum[q];
-                }
+                __syncthreads();
             }
         }
     }
@@ -324,7 +424,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
         __syncthreads();
         if (evals) atomicAdd(&s_pairs, evals);
         __syncthreads();
-        if (tid == 0 && s_pairs) atomicAdd(pairs, (unsigned long long)s_pairs);
+        if (tid == 0 && s_pairs) atomicAdd(pairs + 1, (unsigned long long)s_pairs);
+        if ((tid & 63) == 0 && witer) atomicAdd(pairs + 3, (unsigned long long)witer);
+        if ((tid & 63) == 0 && wred) atomicAdd(pairs + 4, (unsigned long long)wred);
     }
 }
 
@@ -345,16 +447,22 @@ void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, c
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, unsigned long long* pairs, hipStream_t s) {
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
+    if (waves == 0) {   // one independent wave per 8x8 quarter of each tile
+        k_composite_fwd<1, true><<<dim3(4 * tiles, nv), 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride,
+                                                                     cams, bg0, bg1, bg2, image, T_final, last, cfg,
+                                                                     pairs);
+        return;
+    }
     const dim3 grid(tiles, nv);
     if (waves == 1)
-        k_composite_fwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
-                                                image, T_final, last, cfg, pairs);
+        k_composite_fwd<1, false><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
+                                                       bg2, image, T_final, last, cfg, pairs);
     else if (waves == 2)
-        k_composite_fwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
-                                                 image, T_final, last, cfg, pairs);
+        k_composite_fwd<2, false><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
+                                                        bg2, image, T_final, last, cfg, pairs);
     else
-        k_composite_fwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2,
-                                                 image, T_final, last, cfg, pairs);
+        k_composite_fwd<4, false><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
+                                                        bg2, image, T_final, last, cfg, pairs);
 }
 
 void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,

@@ -78,7 +78,13 @@ def test_preprocess_records(kind):
         both = gvis & ovis
         assert both.sum() > 0
         # depth key: the correctly rounded float32 depth, bit-exact
-        assert np.array_equal(col[v, both, 2], r[both, 4].astype(np.float32))
+        assert np.array_equal(rgb[v, both, 3], r[both, 4].astype(np.float32))
+        # the whole-wave skip extent covers every possible member pixel
+        rb = r[both]
+        can = 255.0 * rb[:, 24] > 1.0 + 1e-5
+        kf = np.sqrt(2.0 * np.minimum(4.5, np.log(255.0 * rb[can, 24])))
+        assert (col[v, both, 2][can] >= kf * np.sqrt(rb[can, 5]) - 1e-3).all()
+        assert (col[v, both, 3][can] >= kf * np.sqrt(rb[can, 7]) - 1e-3).all()
         np.testing.assert_allclose(geo[v, both, 0], r[both, 1], atol=2e-4, rtol=1e-6)
         np.testing.assert_allclose(geo[v, both, 1], r[both, 2], atol=2e-4, rtol=1e-6)
         cmax = np.maximum(np.abs(r[both, 9]), np.abs(r[both, 11]))
@@ -395,7 +401,7 @@ def test_l1_loss_matches_oracle():
     assert (dL.cpu().numpy()[0, 0, 0, :5] == 0).all()
 
 
-@pytest.mark.parametrize("fwd,bwd", [(1, 1), (2, 2), (4, 4), (4, 1), (1, 4)])
+@pytest.mark.parametrize("fwd,bwd", [(1, 1), (2, 2), (4, 4), (4, 1), (1, 4), (0, 4), (0, 2)])
 def test_waves_per_tile_options(fwd, bwd):
     """Waves per tile change the thread mapping only: images are bit-identical,
     gradients agree to rounding of the reduction order."""

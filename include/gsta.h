@@ -218,6 +218,26 @@ gsta_status gsta_adam_masked(gsta_ctx* ctx, gsta_params* p, const gsta_params* g
                              gsta_params* v, const float* lr_per_row, float beta1, float beta2,
                              float eps, int32_t step, const uint8_t* frozen, hipStream_t stream);
 
+/* Device-resident Adam schedule, for iterations captured once in a HIP graph
+ * and replayed: every scalar that changes from one iteration to the next is
+ * read from device memory.  Position rows (0-2) use
+ *   lr = pos_scale * exp((1 - t) ln(pos_lr_init) + t ln(pos_lr_final)),
+ *   t = min((step - 1) / decay_iters, 1),
+ * the other rows lr[row].  Bias corrections use `step`. */
+typedef struct {
+    int32_t step;            /* Adam step of the next update (>= 1) */
+    int32_t decay_iters;
+    float beta1, beta2, eps;
+    float pos_lr_init, pos_lr_final, pos_scale;
+    float lr[64];            /* per-row learning rate, rows >= 3 */
+} gsta_adam_sched;
+
+/* gsta_adam_masked with the scalars taken from `sched` (device pointer),
+ * followed by sched->step += 1 on the device (stream-ordered). */
+gsta_status gsta_adam_masked_sched(gsta_ctx* ctx, gsta_params* p, const gsta_params* grad, gsta_params* m,
+                                   gsta_params* v, gsta_adam_sched* sched, const uint8_t* frozen,
+                                   hipStream_t stream);
+
 /* Section 3.2.1, eqs. 4 and 6, with the accumulation and reset of the freeze
  * map.  cond_i = (score_xyz[i] < eps_xyz) && (score_rgb[i] < eps_rgb)
  * (strict, float32), or proposal[i] != 0 when `proposal` is given.

@@ -36,6 +36,12 @@ class Params(ctypes.Structure):
                 ("block", ctypes.c_void_p)]
 
 
+class AdamSched(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int32), ("decay_iters", ctypes.c_int32), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("pos_lr_init", ctypes.c_float),
+                ("pos_lr_final", ctypes.c_float), ("pos_scale", ctypes.c_float), ("lr", ctypes.c_float * 64)]
+
+
 class GstaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"gsta error {STATUS_NAMES.get(status, status)}: {msg}")
@@ -46,7 +52,7 @@ _lib = None
 
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
            "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
-           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option"]
+           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched"]
 
 PHASES = ["preprocess", "depth_sort", "binning", "tile_sort", "composite", "composite_bwd",
           "preprocess_bwd", "adam", "freeze", "loss"]
@@ -79,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
     L.gsta_set_profiling.argtypes = [P, i32]
     L.gsta_set_option.argtypes = [P, i32, i64]
+    L.gsta_adam_masked_sched.argtypes = [P, PP, PP, PP, PP, P, P, P]
     L.gsta_read_profile.argtypes = [P, P, P, P]
     for name in EXPORTS:
         if name not in ("gsta_destroy", "gsta_last_error"):

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Camera, Limits, Params, check
+from ._lib import AdamSched, Camera, Limits, Params, check
 
 MAX_VIEWS = 8
 
@@ -168,6 +168,12 @@ class Context:
                                                ctypes.byref(sv), lr, float(beta1), float(beta2), float(eps),
                                                int(step), _ptr(frozen), _stream(stream)))
 
+    def adam_masked_sched(self, p, g, m, v, degree, sched, frozen=None, stream=None):
+        """Adam with scalars from a device gsta_adam_sched (uint8 tensor of its size)."""
+        sp, sg, sm, sv = (params_struct(x, degree) for x in (p, g, m, v))
+        check(self.h, self.L.gsta_adam_masked_sched(self.h, ctypes.byref(sp), ctypes.byref(sg), ctypes.byref(sm),
+                                                     ctypes.byref(sv), _ptr(sched), _ptr(frozen), _stream(stream)))
+
     def update_freeze_mask(self, score_xyz, score_rgb, eps_xyz, eps_rgb, mode, frozen,
                            proposal=None, n_frozen=None, stream=None):
         n = frozen.numel()
@@ -179,3 +185,23 @@ class Context:
     def l1_loss(self, image, target, dL_dimage, sums, stream=None):
         check(self.h, self.L.gsta_l1_loss(self.h, _ptr(image), _ptr(target), image.numel(),
                                            _ptr(dL_dimage), _ptr(sums), _stream(stream)))
+
+
+def adam_sched_tensor(step, beta1, beta2, eps, lr_rows, pos_lr_init, pos_lr_final, decay_iters,
+                      pos_scale=1.0) -> torch.Tensor:
+    """A device buffer holding a gsta_adam_sched."""
+    s = AdamSched()
+    s.step, s.decay_iters = int(step), int(decay_iters)
+    s.beta1, s.beta2, s.eps = float(beta1), float(beta2), float(eps)
+    s.pos_lr_init, s.pos_lr_final, s.pos_scale = float(pos_lr_init), float(pos_lr_final), float(pos_scale)
+    for i, x in enumerate(lr_rows):
+        s.lr[i] = float(x)
+    raw = bytes(s)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+
+
+def set_adam_sched_field(buf: torch.Tensor, name: str, value):
+    """Write one scalar field of a device gsta_adam_sched (stream-ordered copy)."""
+    off = getattr(AdamSched, name).offset
+    dtype = torch.int32 if name in ("step", "decay_iters") else torch.float32
+    buf[off:off + 4].copy_(torch.tensor([value], dtype=dtype).view(torch.uint8))

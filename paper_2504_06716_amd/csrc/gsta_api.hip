@@ -56,6 +56,7 @@ struct gsta_ctx {
     uint32_t* hist = nullptr;
     uint32_t* digit_tot = nullptr;
     int64_t chunks_depth = 0, chunks_inst = 0;
+    int items_depth = 16, items_inst = 16;
     uint64_t* partials = nullptr;
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
@@ -149,8 +150,10 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
              alloc(ctx, &s.n_count, 1);
     }
-    ctx->chunks_depth = radix_chunks(S);
-    ctx->chunks_inst = radix_chunks(cap);
+    ctx->items_depth = S <= (1 << 20) ? 4 : 16;
+    ctx->items_inst = cap <= (1 << 20) ? 4 : 16;
+    ctx->chunks_depth = radix_chunks(S, ctx->items_depth);
+    ctx->chunks_inst = radix_chunks(cap, ctx->items_inst);
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
@@ -461,7 +464,7 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
-        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth};
+        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth};
         s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
     }
     {
@@ -472,7 +475,7 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
-        RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst};
+        RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst, ctx->items_inst};
         s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
         launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, T * nv, stream);
     }
@@ -559,6 +562,27 @@ gsta_status gsta_adam_masked(gsta_ctx* ctx, gsta_params* p, const gsta_params* g
     if (p->n > 0)
         launch_adam(p->block, p->ld, grad->block, grad->ld, m->block, m->ld, v->block, v->ld, p->n, rows, lr, beta1,
                     beta2, eps, bc1, bc2, frozen, ctx->flags, stream);
+    return hip_check(ctx, hipGetLastError(), "adam launch");
+}
+
+static_assert(sizeof(gsta_adam_sched) == sizeof(AdamSched), "gsta_adam_sched layout");
+
+gsta_status gsta_adam_masked_sched(gsta_ctx* ctx, gsta_params* p, const gsta_params* grad, gsta_params* m,
+                                   gsta_params* v, gsta_adam_sched* sched, const uint8_t* frozen,
+                                   hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, p, "p")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, grad, "grad")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, m, "m")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, v, "v")) != GSTA_OK) return st;
+    if (grad->n != p->n || m->n != p->n || v->n != p->n || grad->sh_degree != p->sh_degree ||
+        m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+        return fail(ctx, GSTA_ERR_INVALID, "p, grad, m, v must share n and sh_degree");
+    if (!sched) return fail(ctx, GSTA_ERR_INVALID, "sched is NULL");
+    PhaseTimer pt(ctx, GSTA_PHASE_ADAM, stream);
+    launch_adam_sched(p->block, p->ld, grad->block, grad->ld, m->block, m->ld, v->block, v->ld, p->n,
+                      n_rows(p->sh_degree), reinterpret_cast<AdamSched*>(sched), frozen, ctx->flags, stream);
     return hip_check(ctx, hipGetLastError(), "adam launch");
 }
 

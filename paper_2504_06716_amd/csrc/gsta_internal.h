@@ -111,12 +111,13 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
 struct RadixScratch {
     uint32_t* hist;          // [nseg][256][nchunks_cap]
     uint32_t* digit_tot;     // [nseg][256]
-    int64_t nchunks_cap;
+    int64_t nchunks_cap;     // chunks reserved per segment (device-count sorts)
+    int items;               // keys per thread per chunk: 4 or 16
 };
 int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
                      hipStream_t s);
-int64_t radix_chunks(int64_t count);
+int64_t radix_chunks(int64_t count, int items);
 
 // Depth-ordered tile-instance expansion: counts per Gaussian in depth
 // order, exclusive scan, write (view*T + tile, gid) for every touched tile.
@@ -151,6 +152,18 @@ void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, c
 void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                  int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
                  float bc1, float bc2, const uint8_t* frozen, uint32_t* flags, hipStream_t s);
+
+// Device mirror of gsta_adam_sched (same layout).
+struct AdamSched {
+    int32_t step;
+    int32_t decay_iters;
+    float beta1, beta2, eps;
+    float pos_lr_init, pos_lr_final, pos_scale;
+    float lr[64];
+};
+void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
+                       int64_t vld, int64_t n, int rows, AdamSched* sched, const uint8_t* frozen, uint32_t* flags,
+                       hipStream_t s);
 
 void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
                    const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s);

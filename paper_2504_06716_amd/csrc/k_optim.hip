@@ -73,6 +73,45 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, int64_t pld
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
 }
 
+// Adam whose scalars come from a device-resident schedule (graph replay).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_adam_sched(float* __restrict__ p, int64_t pld,
+                                                    const float* __restrict__ g, int64_t gld,
+                                                    float* __restrict__ m, int64_t mld, float* __restrict__ v,
+                                                    int64_t vld, int64_t n, const AdamSched* __restrict__ sc,
+                                                    const uint8_t* __restrict__ frozen,
+                                                    uint32_t* __restrict__ flags) {
+    const int row = blockIdx.y;
+    const int step = sc->step;
+    const float b1 = sc->beta1, b2 = sc->beta2, eps = sc->eps;
+    float lrr;
+    if (row < 3) {
+        const float t = fminf((float)(step - 1) / (float)max(sc->decay_iters, 1), 1.0f);
+        lrr = sc->pos_scale * expf((1.0f - t) * logf(sc->pos_lr_init) + t * logf(sc->pos_lr_final));
+    } else {
+        lrr = sc->lr[row];
+    }
+    const float ib1 = 1.f - b1, ib2 = 1.f - b2;
+    const float rbc1 = 1.f / (1.f - powf(b1, (float)step)), rbc2 = 1.f / (1.f - powf(b2, (float)step));
+    bool bad = false;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * (VEC ? 4 : 1);
+    if (i0 >= n) return;
+    const int64_t i1 = (VEC && i0 + 4 <= n) ? i0 + 4 : (VEC ? n : i0 + 1);
+    for (int64_t i = i0; i < i1; ++i) {
+        if (frozen && frozen[i]) continue;
+        const float gk = g[row * gld + i];
+        bad |= !isfinite(gk);
+        const float mk = b1 * m[row * mld + i] + ib1 * gk;
+        const float vk = b2 * v[row * vld + i] + ib2 * gk * gk;
+        m[row * mld + i] = mk;
+        v[row * vld + i] = vk;
+        p[row * pld + i] -= lrr * (mk * rbc1) / (sqrtf(vk * rbc2) + eps);
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
+}
+
+__global__ void k_sched_advance(AdamSched* sc) { sc->step += 1; }
+
 __global__ __launch_bounds__(256) void k_freeze(const float* __restrict__ sx, const float* __restrict__ sr,
                                                 int64_t n, float ex, float er, int mode,
                                                 const uint8_t* __restrict__ proposal,
@@ -168,6 +207,21 @@ void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, i
         k_adam<false><<<dim3((unsigned)((n + 255) / 256), rows), 256, 0, s>>>(
             p, pld, g, gld, m, mld, v, vld, n, lr, b1, b2, eps, bc1, bc2, frozen, flags);
     }
+}
+
+void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
+                       int64_t vld, int64_t n, int rows, AdamSched* sched, const uint8_t* frozen, uint32_t* flags,
+                       hipStream_t s) {
+    const bool vec = (pld % 4 == 0) && (gld % 4 == 0) && (mld % 4 == 0) && (vld % 4 == 0);
+    if (n > 0) {
+        if (vec)
+            k_adam_sched<true><<<dim3((unsigned)(((n + 3) / 4 + 255) / 256), rows), 256, 0, s>>>(
+                p, pld, g, gld, m, mld, v, vld, n, sched, frozen, flags);
+        else
+            k_adam_sched<false><<<dim3((unsigned)((n + 255) / 256), rows), 256, 0, s>>>(p, pld, g, gld, m, mld, v,
+                                                                                       vld, n, sched, frozen, flags);
+    }
+    k_sched_advance<<<1, 1, 0, s>>>(sched);
 }
 
 void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,

@@ -23,8 +23,6 @@ namespace gsta {
 namespace {
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
 constexpr int RS_BINS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
 
@@ -55,11 +53,13 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_
     return base + incl - x;
 }
 
+template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                            int64_t seg_stride, const uint32_t* d_count,
                                                            uint32_t h_count, int shift,
                                                            uint32_t* __restrict__ hist,
                                                            int64_t nchunks_cap) {
+    constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     __shared__ uint32_t s_h[RS_BINS];
     const int seg = blockIdx.y;
     const uint32_t count = seg_count(d_count, h_count);
@@ -81,10 +81,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
 }
 
 // One workgroup per (digit, segment): exclusive scan over the chunks.
+template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scan(uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ digit_tot,
                                                            const uint32_t* d_count, uint32_t h_count,
                                                            int64_t nchunks_cap) {
+    constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     __shared__ uint32_t s_tmp[RS_WAVES];
     const int d = blockIdx.x, seg = blockIdx.y;
     const uint32_t count = seg_count(d_count, h_count);
@@ -102,11 +104,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scan(uint32_t* __restrict_
     if (threadIdx.x == 0) digit_tot[seg * RS_BINS + d] = carry;
 }
 
+template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t seg_stride, const uint32_t* d_count, uint32_t h_count, int shift,
     int bits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot,
     int64_t nchunks_cap) {
+    constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     __shared__ uint32_t s_keys[RS_CHUNK];
     __shared__ uint32_t s_vals[RS_CHUNK];
     __shared__ uint32_t s_digit_base[RS_BINS];
@@ -358,27 +362,41 @@ int grid_for(int64_t chunks) {
     return (int)(g > 2048 ? 2048 : g);
 }
 
+template <int ITEMS>
+int radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, const uint32_t* d_count,
+                 uint32_t h_count, int bits, const RadixScratch& rs, hipStream_t s) {
+    constexpr int64_t CHUNK = (int64_t)RS_THREADS * ITEMS;
+    int cur = 0;
+    const int64_t nchunks_cap = d_count ? rs.nchunks_cap : (h_count + CHUNK - 1) / CHUNK;
+    const int grid_x = grid_for(nchunks_cap);
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int pass_bits = (bits - shift) < 8 ? (bits - shift) : 8;
+        k_radix_hist<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
+                                                                       shift, rs.hist, nchunks_cap);
+        k_radix_scan<ITEMS><<<dim3(RS_BINS, nseg), RS_THREADS, 0, s>>>(rs.hist, rs.digit_tot, d_count, h_count,
+                                                                        nchunks_cap);
+        k_radix_scatter<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(
+            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], seg_stride, d_count, h_count, shift, pass_bits,
+            rs.hist, rs.digit_tot, nchunks_cap);
+        cur = 1 - cur;
+    }
+    return cur;
+}
+
 }  // namespace
 
-int64_t radix_chunks(int64_t count) { return (count + RS_CHUNK - 1) / RS_CHUNK; }
+int64_t radix_chunks(int64_t count, int items) {
+    const int64_t chunk = (int64_t)RS_THREADS * items;
+    return (count + chunk - 1) / chunk;
+}
 
 int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
                      hipStream_t s) {
-    int cur = 0;
-    const int grid_x = grid_for(d_count ? rs.nchunks_cap : radix_chunks(h_count));
-    for (int shift = 0; shift < bits; shift += 8) {
-        const int pass_bits = (bits - shift) < 8 ? (bits - shift) : 8;
-        k_radix_hist<<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
-                                                                shift, rs.hist, rs.nchunks_cap);
-        k_radix_scan<<<dim3(RS_BINS, nseg), RS_THREADS, 0, s>>>(rs.hist, rs.digit_tot, d_count, h_count,
-                                                                 rs.nchunks_cap);
-        k_radix_scatter<<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(
-            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], seg_stride, d_count, h_count, shift,
-            pass_bits, rs.hist, rs.digit_tot, rs.nchunks_cap);
-        cur = 1 - cur;
-    }
-    return cur;
+    // small sorts: 1024 keys per workgroup iteration (more workgroups);
+    // large ones: 4096 (fewer per-chunk histograms)
+    if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+    return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
 }
 
 int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / EX_THREADS; }

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .core import Context, camera_array, n_rows
+from .core import Context, adam_sched_tensor, camera_array, n_rows, set_adam_sched_field
 from .schedule import NONE, RESET, UPDATE, FreezeSchedule, LearningRates, PlateauLR, early_stop
 
 FLT_MAX = float(np.finfo(np.float32).max)
@@ -43,6 +43,8 @@ class TrainConfig:
     plateau: PlateauLR | None = None
     finetune_iters: int = 0              # K_f after an early stop
     track_ema: bool = False              # keep gradient-norm EMAs even without freezing
+    device_sched: bool = False           # Adam scalars from a device schedule (implied by graph)
+    graph: bool = False                  # capture each view's iteration once in a HIP graph, then replay
 
 
 class Trainer:
@@ -80,6 +82,12 @@ class Trainer:
         self.pos_scale = 1.0
         self.frozen_log: list[tuple[int, int]] = []
         self.frozen_counts = torch.zeros(1024, dtype=torch.int64, device="cuda")
+        self.use_sched = cfg.device_sched or cfg.graph
+        if self.use_sched:
+            l = cfg.lrs
+            self.sched = adam_sched_tensor(1, cfg.beta1, cfg.beta2, cfg.adam_eps, l.rows(0, degree),
+                                           l.extent * l.pos_init, l.extent * l.pos_final, l.decay_iters)
+        self.graphs: dict[int, torch.cuda.CUDAGraph] = {}
 
     # ------------------------------------------------------------------
     def _freeze_step(self, k: int):
@@ -104,12 +112,10 @@ class Trainer:
         c = self.frozen_counts[: len(self.frozen_log)].cpu().tolist()
         return [(k, a, n) for (k, a), n in zip(self.frozen_log, c)]
 
-    def step(self):
-        """One training iteration k = self.k."""
-        k = self.k
+    def _body(self, view: int, k: int):
+        """Forward, loss, backward and optimizer step of one view (the part a
+        HIP graph captures)."""
         cfg = self.cfg
-        self._freeze_step(k)
-        view = int(self.order[k % len(self.order)])
         cam = self.cam1[view]
         frz = self.frozen if cfg.freeze else None
         ema = self.ema if (cfg.freeze or cfg.track_ema) else None
@@ -117,10 +123,33 @@ class Trainer:
         self.ctx.l1_loss(self.image, self.targets[view:view + 1], self.dL, self.sums)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
                                  cfg.ema_beta)
+        if self.use_sched:
+            self.ctx.adam_masked_sched(self.P, self.G, self.M, self.Vm, self.degree, self.sched, frz)
+        else:
+            lr = cfg.lrs.rows(k, self.degree, self.pos_scale)
+            self.ctx.adam_masked(self.P, self.G, self.M, self.Vm, self.degree, lr, cfg.beta1, cfg.beta2,
+                                 cfg.adam_eps, self.step_count, frz)
+
+    def step(self):
+        """One training iteration k = self.k."""
+        k = self.k
+        cfg = self.cfg
+        self._freeze_step(k)
+        view = int(self.order[k % len(self.order)])
         self.step_count += 1
-        lr = cfg.lrs.rows(k, self.degree, self.pos_scale)
-        self.ctx.adam_masked(self.P, self.G, self.M, self.Vm, self.degree, lr, cfg.beta1, cfg.beta2,
-                             cfg.adam_eps, self.step_count, frz)
+        if cfg.graph:
+            g = self.graphs.get(view)
+            if g is None:
+                g = torch.cuda.CUDAGraph()
+                side = torch.cuda.Stream()
+                side.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.graph(g, stream=side):
+                    self._body(view, k)
+                torch.cuda.current_stream().wait_stream(side)
+                self.graphs[view] = g
+            g.replay()
+        else:
+            self._body(view, k)
         self.k += 1
         if cfg.eval_every and self.k % cfg.eval_every == 0 and self.stop_iter is None:
             self._validate()
@@ -129,7 +158,10 @@ class Trainer:
         p = self.evaluate(self.val_views)
         self.psnrs.append(p)
         if self.cfg.plateau is not None:
-            self.pos_scale = self.cfg.plateau.step(p)
+            scale = self.cfg.plateau.step(p)
+            if self.use_sched and scale != self.pos_scale:
+                set_adam_sched_field(self.sched, "pos_scale", scale)
+            self.pos_scale = scale
         if self.cfg.early_stop_eps is not None and early_stop(self.psnrs, self.cfg.early_stop_eps):
             self.stop_iter = self.k
 

@@ -50,6 +50,7 @@ def lib():
         L.oracle_render_backward.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P, P, P, P, P]
         L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_render_pixels.argtypes = [P, i64, i64, i32, P, P, P, i64, P, P, P]
         _lib = L
     return _lib
 
@@ -127,6 +128,20 @@ def render(params, degree, cam, tile=16, bg=(0.0, 0.0, 0.0), brute=False):
                         _ptr(out["n_members"]), _ptr(out["m_value"]), _ptr(out["m_grad"]),
                         _ptr(out["ztie"]), _ptr(out["hash"]))
     return out
+
+
+def render_pixels(params, degree, cam, pix, bg=(0.0, 0.0, 0.0)):
+    """Brute-force colour, T_final and decision margin of sampled pixels
+    pix [m, 2] = (px, py) of one view."""
+    P = _as_f64(params)
+    n = P.shape[1]
+    px = np.ascontiguousarray(pix, dtype=np.int64)
+    m = px.shape[0]
+    out, T, mv = np.zeros((m, 3)), np.zeros(m), np.zeros(m)
+    bgv = np.asarray(bg, dtype=np.float64)
+    lib().oracle_render_pixels(_ptr(P), n, n, degree, _ptr(cam_vec(cam)), _ptr(bgv), _ptr(px), m, _ptr(out),
+                               _ptr(T), _ptr(mv))
+    return out, T, mv
 
 
 def render_backward(params, degree, cams, dL_dimage, frozen=None, tile=16, bg=(0.0, 0.0, 0.0),

@@ -592,6 +592,28 @@ int oracle_render(const double* params, int64_t n, int64_t ld, int32_t degree, c
     return 0;
 }
 
+// Sampled pixels of one view by the brute-force walk over every visible
+// Gaussian in depth order (the compositing of eq. 2 without tiles; equal to
+// the tiled render).  pix [m][2] = (px, py); out [m][3] colour (+ T_final*bg),
+// T_final [m], m_value [m] (smallest relative distance of a decision from
+// its threshold).
+int oracle_render_pixels(const double* params, int64_t n, int64_t ld, int32_t degree, const double* camv,
+                         const double* bg, const int64_t* pix, int64_t m, double* out, double* T_final,
+                         double* m_value) {
+    Cam cam = read_cam(camv);
+    std::vector<Proj> pr = project_all(params, n, ld, degree, cam, 16, 16);
+    std::vector<int64_t> order = depth_order(pr);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        PixelResult r;
+        walk_pixel(pr, order, (double)pix[2 * i], (double)pix[2 * i + 1], false, r);
+        for (int ch = 0; ch < 3; ++ch) out[3 * i + ch] = r.C[ch] + r.T * bg[ch];
+        T_final[i] = r.T;
+        m_value[i] = r.m_value;
+    }
+    return 0;
+}
+
 // Backward of the render (Section 3.2.4) for n_views views that share one
 // parameter block; the gradient of every parameter is summed over the views.
 // dL_dimage is [V][3][H][W].  Rows of frozen Gaussians (frozen[g] != 0) are

@@ -45,6 +45,7 @@ class TrainConfig:
     track_ema: bool = False              # keep gradient-norm EMAs even without freezing
     device_sched: bool = False           # Adam scalars from a device schedule (implied by graph)
     graph: bool = False                  # capture each view's iteration once in a HIP graph, then replay
+    views_per_step: int = 1              # V_b views rendered per library call; the loss averages them
 
 
 class Trainer:
@@ -72,8 +73,12 @@ class Trainer:
         self.frozen = torch.zeros(max(64, (self.n + 63) // 64 * 64), dtype=torch.uint8, device="cuda")[: self.n]
         self.ema = _padded(4, self.n, FLT_MAX)
         self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
-        self.image = torch.empty((1, 3, self.H, self.W), device="cuda")
+        vb = cfg.views_per_step
+        if vb > 1 and cfg.graph:
+            raise ValueError("graph capture is per view; use views_per_step = 1 with graph=True")
+        self.image = torch.empty((vb, 3, self.H, self.W), device="cuda")
         self.dL = torch.empty_like(self.image)
+        self.tgt_batch = torch.empty_like(self.image) if vb > 1 else None
         self.sums = torch.zeros(2, dtype=torch.float64, device="cuda")
         self.step_count = 0
         self.k = 0
@@ -112,15 +117,22 @@ class Trainer:
         c = self.frozen_counts[: len(self.frozen_log)].cpu().tolist()
         return [(k, a, n) for (k, a), n in zip(self.frozen_log, c)]
 
-    def _body(self, view: int, k: int):
-        """Forward, loss, backward and optimizer step of one view (the part a
-        HIP graph captures)."""
+    def _body(self, view, k: int):
+        """Forward, loss, backward and optimizer step of one view or a batch
+        of views (the part a HIP graph captures)."""
         cfg = self.cfg
-        cam = self.cam1[view]
         frz = self.frozen if cfg.freeze else None
         ema = self.ema if (cfg.freeze or cfg.track_ema) else None
+        if isinstance(view, int):
+            cam = self.cam1[view]
+            tgt = self.targets[view:view + 1]
+        else:
+            cam = camera_array([self.cams[v] for v in view])
+            idx = torch.as_tensor(view, device="cuda")
+            torch.index_select(self.targets, 0, idx, out=self.tgt_batch)
+            tgt = self.tgt_batch
         self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
-        self.ctx.l1_loss(self.image, self.targets[view:view + 1], self.dL, self.sums)
+        self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
                                  cfg.ema_beta)
         if self.use_sched:
@@ -135,7 +147,11 @@ class Trainer:
         k = self.k
         cfg = self.cfg
         self._freeze_step(k)
-        view = int(self.order[k % len(self.order)])
+        vb = cfg.views_per_step
+        if vb == 1:
+            view = int(self.order[k % len(self.order)])
+        else:
+            view = [int(self.order[(k * vb + i) % len(self.order)]) for i in range(vb)]
         self.step_count += 1
         if cfg.graph:
             g = self.graphs.get(view)

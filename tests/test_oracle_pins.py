@@ -450,3 +450,15 @@ def test_plateau_lr_hand_sequence():
     seq = [20.0, 20.5, 20.8, 22.0, 22.3, 22.4, 22.5, 22.6]
     scales = [s.step(x) for x in seq]
     assert scales == [1, 1, 0.75, 0.75, 0.75, 0.5625, 0.5625, 0.421875]
+
+
+def test_sampled_pixels_equal_full_render():
+    p, cams = tiny_scene(n=500, degree=3, size=48, log_s_shift=0.8)
+    r = O.render(p, 3, cams[0], bg=(0.2, 0.1, 0.4))
+    pix = np.array([[x, y] for y in range(0, 48, 5) for x in range(0, 48, 3)])
+    out, T, mv = O.render_pixels(p, 3, cams[0], pix, bg=(0.2, 0.1, 0.4))
+    assert np.array_equal(out, r["image"][:, pix[:, 1], pix[:, 0]].T)
+    assert np.array_equal(T, r["T_final"][pix[:, 1], pix[:, 0]])
+    # the brute walk also sees Gaussians outside the pixel's tile, so its
+    # decision margin can only be smaller
+    assert (mv <= r["m_value"][pix[:, 1], pix[:, 0]]).all()

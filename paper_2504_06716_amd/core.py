@@ -34,6 +34,18 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _arr(t, shape, dtype, name):
+    """Pointer of a contiguous device tensor of the given shape and dtype
+    (None passes through)."""
+    if t is None:
+        return None
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        raise ValueError(f"{name}: expected {tuple(shape)} {dtype}, got {tuple(t.shape)} {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _ptr(t)
+
+
 def params_struct(block: torch.Tensor, degree: int) -> Params:
     """[R, n] float32 device tensor (row stride = block.stride(0))."""
     if block.dtype != torch.float32 or block.dim() != 2:
@@ -148,17 +160,23 @@ class Context:
     def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None):
         ps = params_struct(params, degree)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        shape = (len(ca), 3, ca[0].height, ca[0].width)
         check(self.h, self.L.gsta_render_forward(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
-                                                  _ptr(image), slot, _stream(stream)))
+                                                  _arr(image, shape, torch.float32, "image"), slot,
+                                                  _stream(stream)))
 
     def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
                         grad2d=None, ema=None, ema_beta=0.9, stream=None):
         ps = params_struct(params, degree)
         gs = params_struct(grad, degree)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        V, n = len(ca), ps.n
         check(self.h, self.L.gsta_render_backward(
-            self.h, ctypes.byref(ps), ca, len(ca), _f3(bg), slot, _ptr(dL_dimage), _ptr(frozen),
-            ctypes.byref(gs), _ptr(grad2d), _ptr(ema), float(ema_beta), _stream(stream)))
+            self.h, ctypes.byref(ps), ca, V, _f3(bg), slot,
+            _arr(dL_dimage, (V, 3, ca[0].height, ca[0].width), torch.float32, "dL_dimage"),
+            _arr(frozen, (n,), torch.uint8, "frozen"), ctypes.byref(gs),
+            _arr(grad2d, (V, 9, n), torch.float32, "grad2d"), _arr(ema, (4, n), torch.float32, "ema"),
+            float(ema_beta), _stream(stream)))
 
     def adam_masked(self, p, g, m, v, degree, lr_rows, beta1, beta2, eps, step, frozen=None, stream=None):
         R = n_rows(degree)
@@ -166,25 +184,34 @@ class Context:
         sp, sg, sm, sv = (params_struct(x, degree) for x in (p, g, m, v))
         check(self.h, self.L.gsta_adam_masked(self.h, ctypes.byref(sp), ctypes.byref(sg), ctypes.byref(sm),
                                                ctypes.byref(sv), lr, float(beta1), float(beta2), float(eps),
-                                               int(step), _ptr(frozen), _stream(stream)))
+                                               int(step), _arr(frozen, (sp.n,), torch.uint8, "frozen"),
+                                               _stream(stream)))
 
     def adam_masked_sched(self, p, g, m, v, degree, sched, frozen=None, stream=None):
         """Adam with scalars from a device gsta_adam_sched (uint8 tensor of its size)."""
         sp, sg, sm, sv = (params_struct(x, degree) for x in (p, g, m, v))
         check(self.h, self.L.gsta_adam_masked_sched(self.h, ctypes.byref(sp), ctypes.byref(sg), ctypes.byref(sm),
-                                                     ctypes.byref(sv), _ptr(sched), _ptr(frozen), _stream(stream)))
+                                                     ctypes.byref(sv), _ptr(sched),
+                                                     _arr(frozen, (sp.n,), torch.uint8, "frozen"),
+                                                     _stream(stream)))
 
     def update_freeze_mask(self, score_xyz, score_rgb, eps_xyz, eps_rgb, mode, frozen,
                            proposal=None, n_frozen=None, stream=None):
         n = frozen.numel()
-        check(self.h, self.L.gsta_update_freeze_mask(self.h, _ptr(score_xyz), _ptr(score_rgb), n,
+        check(self.h, self.L.gsta_update_freeze_mask(self.h, _arr(score_xyz, (n,), torch.float32, "score_xyz"),
+                                                      _arr(score_rgb, (n,), torch.float32, "score_rgb"), n,
                                                       float(eps_xyz), float(eps_rgb), int(mode),
-                                                      _ptr(proposal), _ptr(frozen), _ptr(n_frozen),
+                                                      _arr(proposal, (n,), torch.uint8, "proposal"),
+                                                      _arr(frozen, (n,), torch.uint8, "frozen"),
+                                                      _arr(n_frozen, (1,), torch.int64, "n_frozen"),
                                                       _stream(stream)))
 
     def l1_loss(self, image, target, dL_dimage, sums, stream=None):
-        check(self.h, self.L.gsta_l1_loss(self.h, _ptr(image), _ptr(target), image.numel(),
-                                           _ptr(dL_dimage), _ptr(sums), _stream(stream)))
+        sh = tuple(image.shape)
+        check(self.h, self.L.gsta_l1_loss(self.h, _arr(image, sh, torch.float32, "image"),
+                                           _arr(target, sh, torch.float32, "target"), image.numel(),
+                                           _arr(dL_dimage, sh, torch.float32, "dL_dimage"),
+                                           _arr(sums, (2,), torch.float64, "sums"), _stream(stream)))
 
 
 def adam_sched_tensor(step, beta1, beta2, eps, lr_rows, pos_lr_init, pos_lr_final, decay_iters,

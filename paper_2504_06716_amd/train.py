@@ -71,7 +71,7 @@ class Trainer:
         self.M = _padded(self.R, self.n)
         self.Vm = _padded(self.R, self.n)
         self.frozen = torch.zeros(max(64, (self.n + 63) // 64 * 64), dtype=torch.uint8, device="cuda")[: self.n]
-        self.ema = _padded(4, self.n, FLT_MAX)
+        self.ema = torch.full((4, self.n), FLT_MAX, device="cuda")   # contiguous [4][n]
         self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
         vb = cfg.views_per_step
         if vb > 1 and cfg.graph:

@@ -299,6 +299,8 @@ def test_invalid_arguments_rejected():
         ctx.render_forward(P, D, cams, (0, 0, 0), img, slot=3)
     big = S.look_at(0.0, 0.0, 64, 64)
     with pytest.raises(G.GstaError):                     # image larger than reserved
+        ctx.render_forward(P, D, [big], (0, 0, 0), torch.empty((1, 3, 64, 64), device="cuda"))
+    with pytest.raises(ValueError):                      # image shape does not match the views
         ctx.render_forward(P, D, [big], (0, 0, 0), img)
     ctx.render_forward(P, D, cams, (0, 0, 0), img)
     with pytest.raises(G.GstaError):                     # cameras differ from the forward
@@ -482,3 +484,31 @@ def test_graph_replay_matches_eager_training():
         out.append((tr.P.cpu().numpy(), tr.frozen_log, [c for *_, c in tr.freeze_history()]))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+
+
+def test_trainer_ema_rows_match_the_step_gradient():
+    """Regression: with n not a multiple of 64 the trainer's EMA rows must be
+    the scores of the same Gaussians as the gradient block (first step: the
+    EMA equals the score)."""
+    import torch
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd.schedule import LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
+    n = 1499
+    p = S.make_scene(n, 3, seed=8)
+    p[3:6] += 0.5
+    cams = [S.look_at(5.0 * k, 30.0 * k, 40, 32) for k in range(2)]
+    ctx = G.Context(n, 2, 32, 40, 1 << 20)
+    tgt = render_targets(ctx, S.perturb_scene(p, 3), 3, cams)
+    cfg = TrainConfig(iters=4, freeze=False, track_ema=True, lrs=LearningRates(decay_iters=4))
+    tr = Trainer(p, 3, cams, tgt, cfg, S.view_order(2, 4), ctx=ctx)
+    tr.step()
+    torch.cuda.synchronize()
+    g = tr.G.cpu().numpy().astype(np.float64)
+    ema = tr.ema.cpu().numpy().astype(np.float64)
+    seen = ema[0] < O.FLT_MAX
+    assert seen.sum() > 100
+    sc = [np.linalg.norm(g[0:3], axis=0), np.linalg.norm(g[11:14], axis=0), np.abs(g[10]),
+          np.linalg.norm(g[3:6], axis=0)]
+    for k in range(4):
+        np.testing.assert_allclose(ema[k][seen], sc[k][seen], rtol=1e-5, atol=1e-30)

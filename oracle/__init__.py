@@ -317,3 +317,130 @@ class PlateauLR:
             self.scale *= self.factor
             self.bad = 0
         return self.scale
+
+
+# ---------------------------------------------------------------------------
+# Adaptive densification, pruning and opacity reset (Section 3.1: Gaussians
+# are pruned and densified by gradient norm and opacity; Section 4.1: every
+# 100 iterations, thresholds eps_den_xyz = 2e-4 and eps_den_rgb = 1e-6 scaled
+# like the freezing thresholds, diffuse-colour gradients used on 20 % of the
+# densification steps, opacity reset every 3K).  The clone / split / prune
+# rules themselves are the 3DGS conventions the paper builds on: clone a
+# selected Gaussian whose largest scale is small, otherwise replace it by two
+# children drawn from it with scales divided by 1.6; prune opacity < 0.005.
+# ---------------------------------------------------------------------------
+
+def densify_stats(acc, grad2d, visible, grads, frozen, width, height):
+    """Accumulate one step's densification statistics into acc [4, n]:
+    row 0 += |(dL/du * W/2, dL/dv * H/2)| (the gradient with respect to the
+    normalised device coordinates of the projected mean) and row 1 += 1 for
+    every view in which the Gaussian is visible; row 2 += |dL/df_dc| and
+    row 3 += 1 once per step if it is visible in any view.  Frozen Gaussians
+    are left unchanged.  grad2d [V, 9, n] and visible [V, n] are the
+    per-view outputs of render_backward, grads [R, n] its parameter
+    gradient."""
+    acc = np.array(acc, np.float64)
+    g2 = np.asarray(grad2d, np.float64)
+    vis = np.asarray(visible) != 0
+    act = np.ones(acc.shape[1], bool) if frozen is None else (np.asarray(frozen) == 0)
+    for v in range(g2.shape[0]):
+        m = vis[v] & act
+        nrm = np.sqrt((g2[v, 0] * (0.5 * width)) ** 2 + (g2[v, 1] * (0.5 * height)) ** 2)
+        acc[0, m] += nrm[m]
+        acc[1, m] += 1.0
+    anyv = vis.any(0) & act
+    gdc = np.sqrt((np.asarray(grads, np.float64)[11:14] ** 2).sum(0))
+    acc[2, anyv] += gdc[anyv]
+    acc[3, anyv] += 1.0
+    return acc
+
+
+def _quat_rot(q):
+    """Rotation matrices [n, 3, 3] of quaternions q [4, n] = (w, x, y, z),
+    normalised first."""
+    q = np.asarray(q, np.float64)
+    w, x, y, z = q / np.sqrt((q ** 2).sum(0))
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+
+
+def densify_decisions(stats, params, frozen, grad_threshold, rgb_threshold, use_rgb, split_log_scale,
+                      prune_logit):
+    """Per-Gaussian (clone, split, live) decisions, taken in float32 as the
+    GPU takes them: mean screen gradient = row0 / row1 (0 where row1 = 0),
+    mean colour gradient = row2 / row3; selected iff the mean screen gradient
+    >= grad_threshold, or (use_rgb) the mean colour gradient >= rgb_threshold,
+    and not frozen; split iff selected and max log-scale > split_log_scale,
+    clone iff selected otherwise; live iff logit >= prune_logit."""
+    st = np.asarray(stats, np.float32)
+    P = np.asarray(params, np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mxy = np.where(st[1] > 0, st[0] / np.where(st[1] > 0, st[1], np.float32(1)), np.float32(0))
+        mrgb = np.where(st[3] > 0, st[2] / np.where(st[3] > 0, st[3], np.float32(1)), np.float32(0))
+    sel = mxy >= np.float32(grad_threshold)
+    if use_rgb:
+        sel |= mrgb >= np.float32(rgb_threshold)
+    if frozen is not None:
+        sel &= np.asarray(frozen) == 0
+    big = P[3:6].max(0) > np.float32(split_log_scale)
+    live = P[10] >= np.float32(prune_logit)
+    return sel & ~big, sel & big, live
+
+
+def densify_prune(params, m, v, ema, frozen, stats, noise, grad_threshold, rgb_threshold, use_rgb,
+                  split_log_scale, prune_logit, child_log_scale_shift):
+    """One densify-and-prune step.  Output columns, in this order: the
+    surviving Gaussians (live and not split) in their order; a copy of every
+    live clone-selected Gaussian; the first child of every live split-selected
+    Gaussian, then the second children.  Child c of Gaussian i sits at
+    mu_i + R(q_i) (exp(log_s_i) * noise[3c:3c+3, i]) with log-scales
+    log_s_i - child_log_scale_shift and every other parameter copied; the
+    split parent is removed.  New columns get zero Adam moments, EMAs at
+    FLT_MAX (never seen) and are not frozen; survivors keep theirs.  A
+    Gaussian that is split or not live leaves the set.
+    Returns (params, m, v, ema, frozen, counts = (n_out, kept, clones, splits))."""
+    P = np.asarray(params, np.float64)
+    n = P.shape[1]
+    fz = np.zeros(n, np.uint8) if frozen is None else np.asarray(frozen, np.uint8)
+    E = np.full((4, n), FLT_MAX) if ema is None else np.asarray(ema, np.float64)
+    clone, split, live = densify_decisions(stats, params, frozen, grad_threshold, rgb_threshold, use_rgb,
+                                           split_log_scale, prune_logit)
+    keep = live & ~split
+    cl = np.flatnonzero(clone & live)
+    sp = np.flatnonzero(split & live)
+    kp = np.flatnonzero(keep)
+    nz = np.asarray(noise, np.float64)
+    Rm = _quat_rot(P[6:10, sp])
+    s = np.exp(P[3:6, sp])
+    children = []
+    for c in range(2):
+        ch = P[:, sp].copy()
+        off = np.einsum("nij,jn->in", Rm, s * nz[3 * c:3 * c + 3, sp])
+        ch[0:3] = P[0:3, sp] + off
+        ch[3:6] = P[3:6, sp] - child_log_scale_shift
+        children.append(ch)
+    newP = np.concatenate([P[:, kp], P[:, cl]] + children, 1)
+    n_new = len(cl) + 2 * len(sp)
+    zeros = np.zeros((P.shape[0], n_new))
+    newM = np.concatenate([np.asarray(m, np.float64)[:, kp], zeros], 1)
+    newV = np.concatenate([np.asarray(v, np.float64)[:, kp], zeros], 1)
+    newE = np.concatenate([E[:, kp], np.full((4, n_new), FLT_MAX)], 1)
+    newF = np.concatenate([fz[kp], np.zeros(n_new, np.uint8)])
+    counts = (newP.shape[1], len(kp), len(cl), len(sp))
+    return newP, newM, newV, newE, newF, counts
+
+
+def opacity_reset(params, m, v, frozen, logit_cap):
+    """Opacity reset: every active Gaussian's opacity becomes min(o, o_cap),
+    i.e. logit <- min(logit, logit_cap), and the Adam moments of the opacity
+    row are zeroed.  Frozen Gaussians are left untouched."""
+    P = np.array(params, np.float64)
+    M = np.array(m, np.float64)
+    V = np.array(v, np.float64)
+    act = np.ones(P.shape[1], bool) if frozen is None else (np.asarray(frozen) == 0)
+    P[10, act] = np.minimum(P[10, act], np.float32(logit_cap))
+    M[10, act] = 0.0
+    V[10, act] = 0.0
+    return P, M, V

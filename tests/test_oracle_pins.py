@@ -462,3 +462,129 @@ def test_sampled_pixels_equal_full_render():
     # the brute walk also sees Gaussians outside the pixel's tile, so its
     # decision margin can only be smaller
     assert (mv <= r["m_value"][pix[:, 1], pix[:, 0]]).all()
+
+
+# ---------------------------------------------------------------------------
+# Densification, pruning, opacity reset (Section 3.1, Section 4.1)
+# ---------------------------------------------------------------------------
+
+def test_screen_gradient_equals_principal_point_derivative():
+    """dL/du of a lone Gaussian equals dL/dcx (u = fx x/z + cx, and cx enters
+    nowhere else), likewise dL/dv and cy: pins the screen-space part of the
+    per-view 2-D gradient that densification uses."""
+    import dataclasses
+    cam = S.config_cameras("c1")[0]
+    p = _single([0.1, 0.15, -0.2], [math.log(0.07), math.log(0.05), math.log(0.06)],
+                q=(0.9, 0.2, -0.3, 0.1), logit=0.4)
+    w = np.random.default_rng(2).standard_normal((1, 3, cam.height, cam.width))
+
+    def L(c):
+        return (O.render(p, 0, c)["image"] * w[0]).sum()
+
+    _, g2, vis = O.render_backward(p, 0, [cam], w)
+    assert vis[0, 0] == 1
+    h = 1e-5
+    for k, name in ((0, "cx"), (1, "cy")):
+        cp = dataclasses.replace(cam, **{name: getattr(cam, name) + h})
+        cm = dataclasses.replace(cam, **{name: getattr(cam, name) - h})
+        fd = (L(cp) - L(cm)) / (2 * h)
+        assert g2[0, k, 0] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_densify_stats_hand_values():
+    g2 = np.zeros((2, 9, 3))
+    g2[0, 0], g2[0, 1] = [0.3, 0.0, 1.0], [0.4, 2.0, 1.0]
+    g2[1, 0], g2[1, 1] = [0.6, 0.0, 0.0], [0.8, 0.0, 0.0]
+    vis = np.array([[1, 1, 1], [1, 0, 0]])
+    grads = np.zeros((14, 3))
+    grads[11:14, 0] = [2.0, 3.0, 6.0]                # |.| = 7
+    grads[11:14, 1] = [0.0, 0.0, 1.0]
+    acc = O.densify_stats(np.zeros((4, 3)), g2, vis, grads, np.array([0, 0, 1]), width=2, height=2)
+    # W/2 = H/2 = 1: norms 0.5 (view 0) + 1.0 (view 1) for G0, 2.0 for G1; G2 frozen
+    np.testing.assert_allclose(acc[0], [1.5, 2.0, 0.0])
+    np.testing.assert_allclose(acc[1], [2, 1, 0])
+    np.testing.assert_allclose(acc[2], [7.0, 1.0, 0.0])
+    np.testing.assert_allclose(acc[3], [1, 1, 0])
+    acc2 = O.densify_stats(acc, g2, vis, grads, None, width=4, height=2)
+    np.testing.assert_allclose(acc2[0], [1.5 + math.hypot(0.6, 0.4) + math.hypot(1.2, 0.8), 2.0 + 2.0,
+                                         math.hypot(2.0, 1.0)])
+
+
+def _dens_case():
+    """Seven Gaussians, one per rule: 0 below threshold, 1 clone, 2 split,
+    3 selected but pruned, 4 frozen, 5 selected by the colour criterion only,
+    6 never visible."""
+    n = 7
+    P = np.zeros((14, n))
+    P[0:3] = np.arange(3 * n, dtype=float).reshape(3, n) * 0.1
+    P[3:6] = math.log(0.01)
+    P[3:6, 2] = [math.log(0.2), math.log(0.3), math.log(0.4)]       # big: split
+    P[6] = 1.0
+    P[10] = 1.0
+    P[10, 3] = -6.0                                                   # o = 0.0025 < 0.005
+    P[11:14] = np.arange(3 * n).reshape(3, n)
+    st = np.zeros((4, n), np.float32)
+    st[0] = [1e-4, 6e-4, 9e-4, 8e-4, 7e-4, 1e-5, 0.0]
+    st[1] = [2, 2, 3, 2, 1, 1, 0]
+    st[2] = [0, 0, 0, 0, 0, 5e-6, 9.0]
+    st[3] = [1, 1, 1, 1, 1, 1, 0]
+    fz = np.array([0, 0, 0, 0, 1, 0, 0], np.uint8)
+    M = np.full((14, n), 0.5)
+    V = np.full((14, n), 0.25)
+    E = np.arange(4 * n, dtype=float).reshape(4, n)
+    noise = np.zeros((6, n))
+    noise[0:3, 2] = [1.0, 0.0, 0.0]
+    noise[3:6, 2] = [0.0, -2.0, 0.5]
+    return P, M, V, E, fz, st, noise
+
+
+def test_densify_prune_hand_case():
+    P, M, V, E, fz, st, noise = _dens_case()
+    thr, split_ls, prune_lg = 2e-4, math.log(0.01 * 10.0), math.log(0.005 / 0.995)
+    for use_rgb in (False, True):
+        nP, nM, nV, nE, nF, cnt = O.densify_prune(P, M, V, E, fz, st, noise, thr, 1e-6, use_rgb,
+                                                  split_ls, prune_lg, math.log(1.6))
+        kept = [0, 1, 4, 5, 6]
+        clones = [1, 5] if use_rgb else [1]
+        assert cnt == (len(kept) + len(clones) + 2, len(kept), len(clones), 1)
+        np.testing.assert_array_equal(nP[:, :len(kept)], P[:, kept])
+        np.testing.assert_array_equal(nP[:, len(kept):len(kept) + len(clones)], P[:, clones])
+        c0, c1 = nP[:, -2], nP[:, -1]
+        s = np.array([0.2, 0.3, 0.4])
+        # identity rotation: offsets are scale * noise
+        np.testing.assert_allclose(c0[0:3], P[0:3, 2] + s * [1.0, 0.0, 0.0], rtol=1e-14)
+        np.testing.assert_allclose(c1[0:3], P[0:3, 2] + s * [0.0, -2.0, 0.5], rtol=1e-14)
+        np.testing.assert_allclose(c0[3:6], np.log(s / 1.6), rtol=1e-14)
+        np.testing.assert_array_equal(c0[6:], P[6:, 2])
+        nk = len(kept)
+        np.testing.assert_array_equal(nM[:, :nk], M[:, kept])
+        assert (nM[:, nk:] == 0).all() and (nV[:, nk:] == 0).all()
+        np.testing.assert_array_equal(nE[:, :nk], E[:, kept])
+        assert (nE[:, nk:] == O.FLT_MAX).all()
+        np.testing.assert_array_equal(nF, [0, 0, 1, 0, 0] + [0] * (len(clones) + 2))
+
+
+def test_split_children_rotation_closed_form():
+    th = 0.7
+    q = (math.cos(th / 2), 0.0, 0.0, math.sin(th / 2))                # rotation about z by th
+    P = _single([1.0, 2.0, 3.0], [math.log(0.5), math.log(0.2), math.log(0.1)], q=q)
+    st = np.array([[1.0], [1.0], [0.0], [1.0]], np.float32)
+    noise = np.array([[1.0], [0.0], [0.0], [0.0], [1.0], [2.0]])
+    nP, *_, cnt = O.densify_prune(P, np.zeros_like(P), np.zeros_like(P), None, None, st, noise, 0.5, 1.0,
+                                  False, math.log(0.1), -10.0, math.log(1.6))
+    assert cnt == (2, 0, 0, 1)
+    np.testing.assert_allclose(nP[0:3, 0], [1 + 0.5 * math.cos(th), 2 + 0.5 * math.sin(th), 3.0], atol=1e-14)
+    np.testing.assert_allclose(nP[0:3, 1], [1 - 0.2 * math.sin(th), 2 + 0.2 * math.cos(th), 3.2], atol=1e-14)
+
+
+def test_opacity_reset_hand_values():
+    P = np.zeros((14, 4))
+    P[10] = [-6.0, -3.0, 2.0, 5.0]
+    M = np.ones((14, 4))
+    V = np.ones((14, 4))
+    cap = math.log(0.01 / 0.99)                                       # -4.595
+    nP, nM, nV = O.opacity_reset(P, M, V, np.array([0, 0, 0, 1]), cap)
+    np.testing.assert_allclose(nP[10], [-6.0, float(np.float32(cap)), float(np.float32(cap)), 5.0])
+    np.testing.assert_array_equal(nM[10], [0, 0, 0, 1])
+    np.testing.assert_array_equal(nV[10], [0, 0, 0, 1])
+    assert (nM[:10] == 1).all() and (nP[:10] == 0).all()

@@ -8,6 +8,7 @@
  *   loss_fcn(gt_image, render_image)             -> gsta_l1_loss
  *   optimizer_step(G, lr, loss, freeze_map)      -> gsta_adam_masked
  *   update_freeze_map / reset_freeze_map         -> gsta_update_freeze_mask
+ *   adaptive_densification(G)                    -> gsta_densify_prune, gsta_opacity_reset
  *
  * Conventions for every entry point:
  *   - Pointers are DEVICE pointers unless marked (host).  The caller owns
@@ -144,7 +145,8 @@ typedef enum {
     GSTA_PHASE_ADAM = 7,
     GSTA_PHASE_FREEZE = 8,
     GSTA_PHASE_LOSS = 9,
-    GSTA_N_PHASES = 10
+    GSTA_PHASE_DENSIFY = 10,    /* densify / prune / opacity reset */
+    GSTA_N_PHASES = 11
 } gsta_phase;
 
 /* Profiling (for benchmarks; do not enable while capturing a HIP graph).
@@ -199,11 +201,19 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
  *           |dL/dmean|, |dL/d(DC colour)|, |dL/dlogit|, |dL/dlog-scale| for
  *           active Gaussians visible in >= 1 view: s <- b*s + (1-b)*g, and
  *           s <- g where s is FLT_MAX (never seen).  NULL to skip.
- *   ema_beta in [0, 1). */
+ *   ema_beta in [0, 1).
+ *   dstats  optional [4][n] float32 in/out: densification statistics of
+ *           active Gaussians (Section 3.1, Section 4.1).  For every view in
+ *           which the Gaussian is visible, row 0 += |(dL/du W/2, dL/dv H/2)|
+ *           (the gradient with respect to the normalised device coordinates
+ *           of its projected mean) and row 1 += 1; once per call, if it is
+ *           visible in any view, row 2 += |dL/d(DC colour)| and row 3 += 1.
+ *           NULL to skip. */
 gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
                                  int32_t n_views, const float* bg, int32_t state_slot,
                                  const float* dL_dimage, const uint8_t* frozen, gsta_params* grad,
-                                 float* grad2d, float* ema, float ema_beta, hipStream_t stream);
+                                 float* grad2d, float* ema, float ema_beta, float* dstats,
+                                 hipStream_t stream);
 
 /* Section 3.2.4 (optimizer that updates only non-frozen Gaussians).  Adam
  * with bias correction on every row of the block:
@@ -257,6 +267,62 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
  *   (the loss is sums[0] / count, the PSNR 10 log10(count / sums[1])). */
 gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,
                          float* dL_dimage, double* sums, hipStream_t stream);
+
+/* Adaptive densification and pruning (Section 3.1: Gaussians are densified
+ * by gradient norm and pruned by opacity; Section 4.1: run every 100
+ * iterations with thresholds scaled like the freezing thresholds, the
+ * diffuse-colour criterion on a fifth of the steps).  The clone / split /
+ * prune rules are the 3DGS conventions the paper builds on.  Decisions, all
+ * float32 comparisons of the inputs:
+ *   mean screen gradient  = dstats[0] / dstats[1] (0 if dstats[1] = 0),
+ *   mean colour gradient  = dstats[2] / dstats[3] (0 if dstats[3] = 0),
+ *   selected = (mean screen gradient >= grad_threshold
+ *               || (use_rgb && mean colour gradient >= rgb_threshold)) && !frozen,
+ *   split    = selected && max(log-scales) >  split_log_scale,
+ *   clone    = selected && max(log-scales) <= split_log_scale,
+ *   live     = logit >= prune_logit   (opacity at least sigmoid(prune_logit)). */
+typedef struct {
+    float grad_threshold;          /* e.g. eps_den_xyz(k) = 2e-4 scaled by the eq. 5 factor */
+    float rgb_threshold;           /* e.g. eps_den_rgb(k) = 1e-6 scaled likewise */
+    int32_t use_rgb;               /* 0/1: colour criterion on this step */
+    float split_log_scale;         /* ln(0.01 * scene extent) */
+    float prune_logit;             /* ln(0.005 / 0.995) */
+    float child_log_scale_shift;   /* ln(1.6): children's scales are the parent's / 1.6 */
+} gsta_densify_cfg;
+
+/* One densify-and-prune step: a stream compaction of every per-Gaussian
+ * array into the caller's output arrays (which must not overlap the inputs).
+ * Output columns, in order: each live Gaussian that is not split, in input
+ * order (its p, m, v, ema and frozen copied); a copy of each live
+ * clone-selected Gaussian (zero m and v, ema FLT_MAX, not frozen); the first
+ * child of each live split Gaussian, then the second children.  Child c of
+ * Gaussian i has mean mu_i + R(q_i) (exp(log_s_i) * noise[3c + a][i])_a,
+ * log-scales log_s_i - child_log_scale_shift and every other parameter of
+ * i; zero m and v, ema FLT_MAX, not frozen.  Split and non-live Gaussians
+ * leave the set (frozen ones are pruned by the same rule).
+ *   g, m, v   [R][ld] inputs (shared n and sh_degree).
+ *   ema [4][n] or NULL (then survivors get FLT_MAX); frozen [n] or NULL.
+ *   dstats [4][n] as accumulated by gsta_render_backward.
+ *   noise [6][n] float32 standard-normal draws (rows 3c..3c+2 for child c).
+ *   g_out, m_out, v_out: the n field is the output capacity (columns).
+ *   ema_out [4][n_out] contiguous (room for 4 * capacity floats) or NULL;
+ *   frozen_out [n_out] (room for capacity) or NULL.
+ *   counts (device int64 [4]) receives (n_out, kept, clones, split parents).
+ * If n_out exceeds the capacity nothing is written to the outputs and
+ * gsta_check reports GSTA_ERR_CAPACITY. */
+gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_params* m,
+                               const gsta_params* v, const float* ema, const uint8_t* frozen,
+                               const float* dstats, const float* noise, const gsta_densify_cfg* cfg,
+                               gsta_params* g_out, gsta_params* m_out, gsta_params* v_out,
+                               float* ema_out, uint8_t* frozen_out, int64_t* counts,
+                               hipStream_t stream);
+
+/* Opacity reset (Section 4.1, every 3K iterations): for every active
+ * Gaussian logit <- min(logit, logit_cap) (opacity capped at
+ * sigmoid(logit_cap), e.g. 0.01) and the Adam moments of the opacity row are
+ * zeroed.  Frozen Gaussians are left untouched. */
+gsta_status gsta_opacity_reset(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gsta_params* v,
+                               const uint8_t* frozen, float logit_cap, hipStream_t stream);
 
 #ifdef __cplusplus
 }

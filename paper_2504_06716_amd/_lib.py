@@ -42,6 +42,12 @@ class AdamSched(ctypes.Structure):
                 ("pos_lr_final", ctypes.c_float), ("pos_scale", ctypes.c_float), ("lr", ctypes.c_float * 64)]
 
 
+class DensifyCfg(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("rgb_threshold", ctypes.c_float),
+                ("use_rgb", ctypes.c_int32), ("split_log_scale", ctypes.c_float),
+                ("prune_logit", ctypes.c_float), ("child_log_scale_shift", ctypes.c_float)]
+
+
 class GstaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"gsta error {STATUS_NAMES.get(status, status)}: {msg}")
@@ -52,10 +58,11 @@ _lib = None
 
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
            "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
-           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched"]
+           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
+           "gsta_densify_prune", "gsta_opacity_reset"]
 
 PHASES = ["preprocess", "depth_sort", "binning", "tile_sort", "composite", "composite_bwd",
-          "preprocess_bwd", "adam", "freeze", "loss"]
+          "preprocess_bwd", "adam", "freeze", "loss", "densify"]
 
 
 def load(path: str = LIB_PATH):
@@ -79,7 +86,9 @@ def load(path: str = LIB_PATH):
     L.gsta_get_state.argtypes = [P, i32, i32, P, i64, P]
     L.gsta_render_forward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, i32, P]
     L.gsta_render_backward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), i32, P, P,
-                                       PP, P, P, f32, P]
+                                       PP, P, P, f32, P, P]
+    L.gsta_densify_prune.argtypes = [P, PP, PP, PP, P, P, P, P, ctypes.POINTER(DensifyCfg), PP, PP, PP, P, P, P, P]
+    L.gsta_opacity_reset.argtypes = [P, PP, PP, PP, P, f32, P]
     L.gsta_adam_masked.argtypes = [P, PP, PP, PP, PP, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
     L.gsta_update_freeze_mask.argtypes = [P, P, P, i64, f32, f32, i32, P, P, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]

@@ -166,7 +166,7 @@ class Context:
                                                   _stream(stream)))
 
     def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
-                        grad2d=None, ema=None, ema_beta=0.9, stream=None):
+                        grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None):
         ps = params_struct(params, degree)
         gs = params_struct(grad, degree)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
@@ -176,7 +176,7 @@ class Context:
             _arr(dL_dimage, (V, 3, ca[0].height, ca[0].width), torch.float32, "dL_dimage"),
             _arr(frozen, (n,), torch.uint8, "frozen"), ctypes.byref(gs),
             _arr(grad2d, (V, 9, n), torch.float32, "grad2d"), _arr(ema, (4, n), torch.float32, "ema"),
-            float(ema_beta), _stream(stream)))
+            float(ema_beta), _arr(dstats, (4, n), torch.float32, "dstats"), _stream(stream)))
 
     def adam_masked(self, p, g, m, v, degree, lr_rows, beta1, beta2, eps, step, frozen=None, stream=None):
         R = n_rows(degree)
@@ -205,6 +205,34 @@ class Context:
                                                       _arr(frozen, (n,), torch.uint8, "frozen"),
                                                       _arr(n_frozen, (1,), torch.int64, "n_frozen"),
                                                       _stream(stream)))
+
+    def densify_prune(self, p, m, v, degree, ema, frozen, dstats, noise, cfg, p_out, m_out, v_out,
+                      ema_out, frozen_out, counts, stream=None):
+        """Densify-and-prune into the output blocks (p_out etc. are [R, capacity]
+        views; ema_out / frozen_out flat buffers of at least 4*capacity /
+        capacity elements).  counts: device int64 [4] = (n_out, kept, clones,
+        splits).  cfg: _lib.DensifyCfg."""
+        sp, sm, sv = (params_struct(x, degree) for x in (p, m, v))
+        so, smo, svo = (params_struct(x, degree) for x in (p_out, m_out, v_out))
+        n, cap = sp.n, so.n
+        if ema_out is not None and (ema_out.dtype != torch.float32 or not ema_out.is_contiguous()
+                                    or ema_out.numel() < 4 * cap):
+            raise ValueError("ema_out: contiguous float32 with room for 4 * capacity values")
+        if frozen_out is not None and (frozen_out.dtype != torch.uint8 or not frozen_out.is_contiguous()
+                                       or frozen_out.numel() < cap):
+            raise ValueError("frozen_out: contiguous uint8 with room for capacity values")
+        check(self.h, self.L.gsta_densify_prune(
+            self.h, ctypes.byref(sp), ctypes.byref(sm), ctypes.byref(sv),
+            _arr(ema, (4, n), torch.float32, "ema"), _arr(frozen, (n,), torch.uint8, "frozen"),
+            _arr(dstats, (4, n), torch.float32, "dstats"), _arr(noise, (6, n), torch.float32, "noise"),
+            ctypes.byref(cfg), ctypes.byref(so), ctypes.byref(smo), ctypes.byref(svo),
+            _ptr(ema_out), _ptr(frozen_out), _arr(counts, (4,), torch.int64, "counts"), _stream(stream)))
+
+    def opacity_reset(self, p, m, v, degree, frozen, logit_cap, stream=None):
+        sp, sm, sv = (params_struct(x, degree) for x in (p, m, v))
+        check(self.h, self.L.gsta_opacity_reset(self.h, ctypes.byref(sp), ctypes.byref(sm), ctypes.byref(sv),
+                                                 _arr(frozen, (sp.n,), torch.uint8, "frozen"),
+                                                 float(logit_cap), _stream(stream)))
 
     def l1_loss(self, image, target, dL_dimage, sums, stream=None):
         sh = tuple(image.shape)

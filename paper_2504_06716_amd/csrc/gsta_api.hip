@@ -61,7 +61,10 @@ struct gsta_ctx {
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
     int fwd_waves = 4, bwd_waves = 4;
-    uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient
+    uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient, [2] densify overflow
+    uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
+    uint32_t* dens_boff = nullptr; // [3][blocks] densify block counts / offsets
+    uint32_t* dens_tot = nullptr;  // [4] kept, clones, splits, overflow
     uint64_t* max_inst = nullptr;
     std::string err;
     // profiling
@@ -157,7 +160,8 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
-         alloc(ctx, &ctx->loss_part, kL1Blocks) &&
+         alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
+         alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
          alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
     if (!ok) {
         free_all(ctx);
@@ -397,6 +401,7 @@ gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances
     if (max_instances) *max_instances = (int64_t)mi;
     if (flags[0]) return fail(ctx, GSTA_ERR_CAPACITY, "tile instances (%llu) exceeded the capacity (%lld)",
                               (unsigned long long)mi, (long long)ctx->lim.instance_capacity);
+    if (flags[2]) return fail(ctx, GSTA_ERR_CAPACITY, "densified set exceeded the output capacity");
     if (flags[1]) return fail(ctx, GSTA_ERR_NONFINITE, "non-finite gradient met by the optimizer");
     return GSTA_OK;
 }
@@ -502,7 +507,8 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
 gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
                                  int32_t n_views, const float* bg, int32_t state_slot,
                                  const float* dL_dimage, const uint8_t* frozen, gsta_params* grad,
-                                 float* grad2d, float* ema, float ema_beta, hipStream_t stream) {
+                                 float* grad2d, float* ema, float ema_beta, float* dstats,
+                                 hipStream_t stream) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     gsta_status st;
     if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
@@ -532,7 +538,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
-                              s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d, stream);
+                              s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d, dstats, stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }
@@ -598,6 +604,78 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
     PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
     launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
     return hip_check(ctx, hipGetLastError(), "freeze launch");
+}
+
+gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_params* m,
+                               const gsta_params* v, const float* ema, const uint8_t* frozen,
+                               const float* dstats, const float* noise, const gsta_densify_cfg* cfg,
+                               gsta_params* g_out, gsta_params* m_out, gsta_params* v_out,
+                               float* ema_out, uint8_t* frozen_out, int64_t* counts, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    const gsta_params* in[3] = {g, m, v};
+    gsta_params* out[3] = {g_out, m_out, v_out};
+    const char* names[6] = {"g", "m", "v", "g_out", "m_out", "v_out"};
+    for (int k = 0; k < 3; ++k) {
+        if ((st = check_params(ctx, in[k], names[k])) != GSTA_OK) return st;
+        if ((st = check_params(ctx, out[k], names[3 + k])) != GSTA_OK) return st;
+    }
+    const int64_t n = g->n, cap = g_out->n;
+    const int D = g->sh_degree;
+    for (int k = 0; k < 3; ++k) {
+        if (in[k]->n != n || in[k]->sh_degree != D || out[k]->sh_degree != D || out[k]->n != cap)
+            return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n; outputs share the capacity; one sh_degree");
+        if (n > 0 && !out[k]->block) return fail(ctx, GSTA_ERR_INVALID, "%s.block is NULL", names[3 + k]);
+    }
+    if (!cfg || !counts) return fail(ctx, GSTA_ERR_INVALID, "cfg or counts is NULL");
+    if (n > 0 && (!dstats || !noise)) return fail(ctx, GSTA_ERR_INVALID, "dstats or noise is NULL");
+    if (!std::isfinite(cfg->split_log_scale) || !std::isfinite(cfg->prune_logit) ||
+        !std::isfinite(cfg->child_log_scale_shift) || std::isnan(cfg->grad_threshold) ||
+        std::isnan(cfg->rgb_threshold))
+        return fail(ctx, GSTA_ERR_INVALID, "densify thresholds must be finite");
+    // outputs must not overlap the inputs (the scatter reads while it writes)
+    const int R = n_rows(D);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (n == 0) break;
+            const char* ia = (const char*)in[a]->block;
+            const char* ob = (const char*)out[b]->block;
+            const size_t la = (size_t)((R - 1) * in[a]->ld + n) * sizeof(float);
+            const size_t lb = (size_t)((R - 1) * out[b]->ld + cap) * sizeof(float);
+            if (ia < ob + lb && ob < ia + la)
+                return fail(ctx, GSTA_ERR_INVALID, "%s overlaps %s", names[3 + b], names[a]);
+        }
+    DensIO io;
+    io.P = g->block; io.M = m->block; io.V = v->block;
+    io.ld = g->ld; io.mld = m->ld; io.vld = v->ld; io.n = n; io.degree = D;
+    io.ema = ema; io.frozen = frozen; io.stats = dstats; io.noise = noise;
+    io.Po = g_out->block; io.Mo = m_out->block; io.Vo = v_out->block;
+    io.old_ = g_out->ld; io.mold = m_out->ld; io.vold = v_out->ld; io.cap = cap;
+    io.ema_o = ema_out; io.frozen_o = frozen_out;
+    DensCfg dc;
+    dc.grad_threshold = cfg->grad_threshold;
+    dc.rgb_threshold = cfg->rgb_threshold;
+    dc.use_rgb = cfg->use_rgb != 0;
+    dc.split_log_scale = cfg->split_log_scale;
+    dc.prune_logit = cfg->prune_logit;
+    dc.child_log_scale_shift = cfg->child_log_scale_shift;
+    PhaseTimer pt(ctx, GSTA_PHASE_DENSIFY, stream);
+    launch_densify(io, dc, ctx->dens_code, ctx->dens_boff, ctx->dens_tot, counts, ctx->flags, stream);
+    return hip_check(ctx, hipGetLastError(), "densify launch");
+}
+
+gsta_status gsta_opacity_reset(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gsta_params* v,
+                               const uint8_t* frozen, float logit_cap, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, m, "m")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, v, "v")) != GSTA_OK) return st;
+    if (m->n != g->n || v->n != g->n) return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n");
+    if (!std::isfinite(logit_cap)) return fail(ctx, GSTA_ERR_INVALID, "logit_cap must be finite");
+    PhaseTimer pt(ctx, GSTA_PHASE_DENSIFY, stream);
+    launch_opacity_reset(g->block, g->ld, m->block, m->ld, v->block, v->ld, g->n, frozen, logit_cap, stream);
+    return hip_check(ctx, hipGetLastError(), "opacity reset launch");
 }
 
 gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,

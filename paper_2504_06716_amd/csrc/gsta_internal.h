@@ -98,11 +98,12 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
 // expansion offsets inst_off[v][gid], in tile order), chains them to every
 // parameter, sums over views, and updates the gradient-norm EMAs.
-// grad2d_out ([nv][9][n], optional) receives the per-view 2-D gradients.
+// grad2d_out ([nv][9][n], optional) receives the per-view 2-D gradients;
+// dstats ([4][n], optional) accumulates the densification statistics.
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
-                           int64_t gld, float* ema, float beta, float* grad2d_out, hipStream_t s);
+                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
 // seg_stride elements; element count per segment from d_count (device, if
@@ -168,6 +169,30 @@ void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float
 void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
                    const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s);
 
+// Densify-and-prune (stream compaction of every per-Gaussian array).
+struct DensCfg {
+    float grad_threshold, rgb_threshold;
+    int use_rgb;
+    float split_log_scale, prune_logit, child_log_scale_shift;
+};
+struct DensIO {
+    const float *P, *M, *V;          // [R][ld], [R][mld], [R][vld]
+    int64_t ld, mld, vld, n;
+    int degree;
+    const float* ema;                // [4][n] or null
+    const uint8_t* frozen;           // [n] or null
+    const float* stats;              // [4][n]
+    const float* noise;              // [6][n]
+    float *Po, *Mo, *Vo;             // [R][old_] ...
+    int64_t old_, mold, vold, cap;   // cap: output columns available
+    float* ema_o;                    // [4][n_out] or null
+    uint8_t* frozen_o;               // [n_out] or null
+};
+int64_t densify_blocks(int64_t n);
+void launch_densify(const DensIO& io, const DensCfg& cfg, uint8_t* code, uint32_t* boff, uint32_t* tot,
+                    int64_t* counts, uint32_t* flags, hipStream_t s);
+void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
+                          const uint8_t* frozen, float cap, hipStream_t s);
 constexpr int kL1Blocks = 1024;   // partial sums of the loss (fixed-order second pass)
 void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums, double2* part,
                hipStream_t s);

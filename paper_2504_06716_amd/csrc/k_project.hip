@@ -265,7 +265,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     const ushort4* __restrict__ rect, const uint32_t* __restrict__ inst_off, int64_t stride,
     const float* __restrict__ partials, const uint32_t* __restrict__ d_count, const uint8_t* __restrict__ frozen,
-    float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out) {
+    float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
+    float* __restrict__ dstats) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     bool any_vis = false;
+    float dsum = 0.f, dcnt = 0.f;   // densification: screen-gradient norms, visible views
 
     for (int v = 0; v < nv; ++v) {
         const int64_t o_idx = (int64_t)v * stride + i;
@@ -310,6 +312,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         if (grad2d_out) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) grad2d_out[((int64_t)v * 9 + k) * n + i] = d2[k];
+        }
+        if (dstats) {
+            // gradient with respect to the normalised device coordinates of the mean
+            const float nx = d2[0] * (0.5f * (float)cm.width), ny = d2[1] * (0.5f * (float)cm.height);
+            dsum += sqrtf(nx * nx + ny * ny);
+            dcnt += 1.f;
         }
         Geo g;
         project_geo(cm, mu, Rq, s, g);
@@ -433,6 +441,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) G[(11 + 3 * k + ch) * gld + i] = gsh[k][ch];
 
+    if (dstats && any_vis) {
+        dstats[i] += dsum;
+        dstats[n + i] += dcnt;
+        dstats[2 * n + i] += sqrtf(gsh[0][0] * gsh[0][0] + gsh[0][1] * gsh[0][1] + gsh[0][2] * gsh[0][2]);
+        dstats[3 * n + i] += 1.f;
+    }
     if (ema && any_vis) {
         float sc[4];
         sc[0] = sqrtf(gmu[0] * gmu[0] + gmu[1] * gmu[1] + gmu[2] * gmu[2]);
@@ -464,9 +478,9 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
-                           int64_t gld, float* ema, float beta, float* grad2d_out, hipStream_t s) {
+                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, grad2d_out
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, grad2d_out, dstats
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

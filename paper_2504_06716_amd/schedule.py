@@ -66,6 +66,63 @@ class FreezeSchedule:
         return UPDATE
 
 
+@dataclass
+class DensifySchedule:
+    """Adaptive densification (Section 4.1): densify and prune every
+    ``every`` iterations from ``start`` while k < min(``stop``, early stop);
+    opacity reset every ``reset_every`` iterations in [reset_every, min(stop,
+    early stop)].  Thresholds eps_den_xyz = 2e-4 and eps_den_rgb = 1e-6 are
+    scaled by the same eq. 5 factor as the freezing thresholds; the colour
+    criterion is drawn on a fraction ``rgb_prob`` of the densify steps.  The
+    clone / split sizes and the prune opacity are 3DGS conventions."""
+
+    total_iters: int
+    start: int = 500
+    stop: int = 10000
+    every: int = 100
+    reset_every: int = 3000
+    eps_xyz0: float = 2e-4
+    eps_rgb0: float = 1e-6
+    rgb_prob: float = 0.2
+    lam1: float = 0.5
+    lam2: float = 1.5
+    percent_dense: float = 0.01          # clone iff largest scale <= percent_dense * extent
+    min_opacity: float = 0.005           # prune below
+    split_div: float = 1.6               # children's scales = parent's / split_div
+    reset_opacity: float = 0.01          # opacity cap of the reset
+    seed: int = 4
+
+    def end(self, stop_iter: int | None = None) -> int:
+        return self.stop if stop_iter is None else min(self.stop, stop_iter)
+
+    def densify_now(self, k: int, stop_iter: int | None = None) -> bool:
+        return self.start <= k < self.end(stop_iter) and k % self.every == 0 and k > 0
+
+    def reset_now(self, k: int, stop_iter: int | None = None) -> bool:
+        return self.reset_every <= k <= self.end(stop_iter) and k % self.reset_every == 0
+
+    def thresholds(self, k: int, k_stop: int | None = None):
+        kk = k if k_stop is None else min(k, k_stop)
+        f = min(max(self.lam1 + self.lam2 * kk / self.total_iters, self.lam1), self.lam2)
+        return self.eps_xyz0 * f, self.eps_rgb0 * f
+
+    def split_log_scale(self, extent: float) -> float:
+        return math.log(self.percent_dense * extent)
+
+    def prune_logit(self) -> float:
+        return math.log(self.min_opacity / (1.0 - self.min_opacity))
+
+    def reset_logit(self) -> float:
+        return math.log(self.reset_opacity / (1.0 - self.reset_opacity))
+
+
+def scene_extent(campos) -> float:
+    """1.1 x the largest distance of a camera centre from their mean."""
+    import numpy as np
+    c = np.asarray(campos, np.float64)
+    return 1.1 * float(np.linalg.norm(c - c.mean(0), axis=1).max())
+
+
 def early_stop(psnrs, eps: float = 0.2) -> bool:
     """Eq. 7 with patience 1: the last two PSNR gains are both below eps."""
     if len(psnrs) < 3:

@@ -1,7 +1,8 @@
 """GSta training loop on top of libgsta (Algorithm 1).
 
-Per iteration: (freeze-map update or reset) -> render_forward -> l1_loss ->
-render_backward (frozen skipped, gradient-norm EMAs) -> adam_masked (frozen
+Per iteration: (densify / prune / opacity reset) -> (freeze-map update or
+reset) -> render_forward -> l1_loss -> render_backward (frozen skipped,
+gradient-norm EMAs, densification statistics) -> adam_masked (frozen
 skipped).  Everything per Gaussian or per pixel runs in the HIP library; this
 module keeps only host scalars (schedule, learning rates) and the device
 buffers PyTorch allocates.
@@ -16,7 +17,8 @@ import torch
 
 from . import _lib
 from .core import Context, adam_sched_tensor, camera_array, n_rows, set_adam_sched_field
-from .schedule import NONE, RESET, UPDATE, FreezeSchedule, LearningRates, PlateauLR, early_stop
+from .schedule import (NONE, RESET, UPDATE, DensifySchedule, FreezeSchedule, LearningRates, PlateauLR,
+                       early_stop, scene_extent)
 
 FLT_MAX = float(np.finfo(np.float32).max)
 
@@ -46,6 +48,8 @@ class TrainConfig:
     device_sched: bool = False           # Adam scalars from a device schedule (implied by graph)
     graph: bool = False                  # capture each view's iteration once in a HIP graph, then replay
     views_per_step: int = 1              # V_b views rendered per library call; the loss averages them
+    densify: DensifySchedule | None = None   # adaptive densification (the number of Gaussians changes)
+    max_gaussians: int | None = None     # capacity of the parameter blocks (default: the initial count)
 
 
 class Trainer:
@@ -64,14 +68,29 @@ class Trainer:
         self.targets = targets
         self.order = view_order
         self.val_views = list(range(len(cams))) if val_views is None else list(val_views)
-        self.ctx = ctx or Context(self.n, min(8, len(cams)), self.H, self.W, capacity or (1 << 22), n_slots=1)
-        self.P = _padded(self.R, self.n)
+        self.cap = max(cfg.max_gaussians or self.n, self.n)
+        self.ctx = ctx or Context(self.cap, min(8, len(cams)), self.H, self.W, capacity or (1 << 22), n_slots=1)
+        if self.ctx.limits.max_gaussians < self.cap:
+            raise ValueError("the context reserves fewer Gaussians than the trainer's capacity")
+        # Parameter, moment, EMA and freeze-map storage sized for the capacity;
+        # densification compacts one set into the other and swaps.
+        nsets = 2 if cfg.densify is not None else 1
+        self.sets = [dict(P=_padded(self.R, self.cap), M=_padded(self.R, self.cap), V=_padded(self.R, self.cap),
+                          ema=torch.full((4 * self.cap,), FLT_MAX, device="cuda"),
+                          frozen=torch.zeros(self.cap, dtype=torch.uint8, device="cuda")) for _ in range(nsets)]
+        self.cur = 0
+        self.G_full = _padded(self.R, self.cap)
+        self.dstats_buf = torch.zeros(4 * self.cap, device="cuda") if cfg.densify is not None else None
+        self._bind(self.n)
         self.P.copy_(torch.from_numpy(np.ascontiguousarray(params0, dtype=np.float32)).cuda())
-        self.G = _padded(self.R, self.n)
-        self.M = _padded(self.R, self.n)
-        self.Vm = _padded(self.R, self.n)
-        self.frozen = torch.zeros(max(64, (self.n + 63) // 64 * 64), dtype=torch.uint8, device="cuda")[: self.n]
-        self.ema = torch.full((4, self.n), FLT_MAX, device="cuda")   # contiguous [4][n]
+        self.counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+        self.n_history: list[tuple[int, int]] = []
+        if cfg.densify is not None:
+            ds = cfg.densify
+            self.extent = scene_extent([c.campos for c in cams])
+            self.dens_rng = np.random.Generator(np.random.Philox(ds.seed))
+            self.noise_gen = torch.Generator(device="cuda")
+            self.noise_gen.manual_seed(ds.seed)
         self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
         vb = cfg.views_per_step
         if vb > 1 and cfg.graph:
@@ -94,7 +113,54 @@ class Trainer:
                                            l.extent * l.pos_init, l.extent * l.pos_final, l.decay_iters)
         self.graphs: dict[int, torch.cuda.CUDAGraph] = {}
 
+    def _bind(self, n: int):
+        """Point the working views at the first n columns of the current set."""
+        st = self.sets[self.cur]
+        self.n = n
+        self.P, self.M, self.Vm = st["P"][:, :n], st["M"][:, :n], st["V"][:, :n]
+        self.ema = st["ema"][:4 * n].view(4, n)
+        self.frozen = st["frozen"][:n]
+        self.G = self.G_full[:, :n]
+        self.dstats = None if self.dstats_buf is None else self.dstats_buf[:4 * n].view(4, n)
+
     # ------------------------------------------------------------------
+    def _densify_step(self, k: int):
+        """Densify / prune (compaction into the other set) and opacity reset
+        before iteration k, from the statistics of the iterations since the
+        previous densify step."""
+        ds = self.cfg.densify
+        if ds is None:
+            return
+        if ds.densify_now(k, self.stop_iter):
+            ex, er = ds.thresholds(k, ds.end(self.stop_iter))
+            use_rgb = bool(self.dens_rng.random() < ds.rgb_prob)
+            cfg = _lib.DensifyCfg(ex, er, int(use_rgb), ds.split_log_scale(self.extent), ds.prune_logit(),
+                                  float(np.log(ds.split_div)))
+            noise = torch.randn((6, self.n), device="cuda", generator=self.noise_gen)
+            out = self.sets[1 - self.cur]
+            frz = self.frozen if self.cfg.freeze else None
+            ema = self.ema if (self.cfg.freeze or self.cfg.track_ema) else None
+            self.ctx.densify_prune(self.P, self.M, self.Vm, self.degree, ema, frz, self.dstats, noise, cfg,
+                                   out["P"], out["M"], out["V"], out["ema"], out["frozen"], self.counts)
+            st, max_inst = self.ctx.check()          # synchronises; reads the device flags
+            n_out = int(self.counts[0])
+            if st != _lib.GSTA_OK:
+                raise _lib.GstaError(st, f"densify at iteration {k}: {n_out} Gaussians for capacity {self.cap}"
+                                     if st == _lib.GSTA_ERR_CAPACITY else "device flag raised")
+            n_in = self.n
+            self.cur = 1 - self.cur
+            self._bind(n_out)
+            self.dstats.zero_()
+            self.graphs.clear()                       # pointers and sizes changed: capture again
+            self.n_history.append((k, n_out))
+            # keep the tile-instance capacity ahead of the growth
+            need = int(max_inst * max(1.0, n_out / max(n_in, 1)) * 1.3) + 1024
+            if need > self.ctx.limits.instance_capacity:
+                self.ctx.reserve(instance_capacity=need)
+        if ds.reset_now(k, self.stop_iter):
+            frz = self.frozen if self.cfg.freeze else None
+            self.ctx.opacity_reset(self.P, self.M, self.Vm, self.degree, frz, ds.reset_logit())
+
     def _freeze_step(self, k: int):
         s = self.cfg.schedule
         if not self.cfg.freeze or s is None:
@@ -134,7 +200,7 @@ class Trainer:
         self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
         self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
-                                 cfg.ema_beta)
+                                 cfg.ema_beta, dstats=self.dstats)
         if self.use_sched:
             self.ctx.adam_masked_sched(self.P, self.G, self.M, self.Vm, self.degree, self.sched, frz)
         else:
@@ -146,6 +212,7 @@ class Trainer:
         """One training iteration k = self.k."""
         k = self.k
         cfg = self.cfg
+        self._densify_step(k)
         self._freeze_step(k)
         vb = cfg.views_per_step
         if vb == 1:

@@ -1,0 +1,217 @@
+"""Densification, pruning and opacity reset through the C ABI against the
+oracle: decisions and copies bit-exact, split children to float32 rounding;
+the densification statistics accumulated by the backward to the gradient
+tolerance."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from tests.gpu_util import GRAD_REL, MARGIN_RECT_PX, MARGIN_VALUE, dev
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_LS = math.log(0.01 * 4.0)
+PRUNE_LG = math.log(0.005 / 0.995)
+SHIFT = math.log(1.6)
+
+
+def _case(n, degree=3, seed=0):
+    rng = np.random.default_rng(seed)
+    p = S.make_scene(n, degree, seed=seed).astype(np.float32)
+    p[3:6] += rng.uniform(-0.5, 1.8, (1, n)).astype(np.float32)           # mix of small and big
+    p[10] = rng.uniform(-6.5, 3.0, n).astype(np.float32)                  # some below the prune logit
+    st = np.zeros((4, n), np.float32)
+    st[1] = rng.integers(0, 4, n)
+    st[0] = (rng.exponential(2e-4, n) * st[1]).astype(np.float32)
+    st[3] = np.minimum(st[1], 2)
+    st[2] = (rng.exponential(1e-6, n) * st[3]).astype(np.float32)
+    frozen = (rng.random(n) < 0.15).astype(np.uint8)
+    ema = rng.exponential(1e-4, (4, n)).astype(np.float32)
+    M = rng.standard_normal(p.shape).astype(np.float32)
+    V = np.abs(rng.standard_normal(p.shape)).astype(np.float32)
+    noise = rng.standard_normal((6, n)).astype(np.float32)
+    return p, M, V, ema, frozen, st, noise
+
+
+def _cfg(thr=2e-4, rgb=1e-6, use_rgb=False):
+    from paper_2504_06716_amd._lib import DensifyCfg
+    return DensifyCfg(thr, rgb, int(use_rgb), SPLIT_LS, PRUNE_LG, SHIFT)
+
+
+def _run(ctx, degree, p, M, V, ema, frozen, st, noise, cfg, cap, pad=0):
+    import torch
+    R, n = p.shape
+    ld = cap + pad
+    outs = [torch.full((R, ld), -7.0, device="cuda")[:, :cap] for _ in range(3)]
+    ema_o = torch.full((4 * cap,), -7.0, device="cuda")
+    fz_o = torch.full((cap,), 9, dtype=torch.uint8, device="cuda")
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ins = [dev(x)[:, :n] if x.ndim == 2 else dev(x) for x in (p, M, V)]
+    ctx.densify_prune(ins[0], ins[1], ins[2], degree, None if ema is None else dev(ema),
+                      None if frozen is None else dev(frozen), dev(st), dev(noise), cfg,
+                      outs[0], outs[1], outs[2], ema_o, fz_o, counts)
+    torch.cuda.synchronize()
+    c = tuple(int(x) for x in counts.cpu())
+    return c, [o.cpu().numpy() for o in outs], ema_o.cpu().numpy(), fz_o.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,degree,use_rgb,with_state", [(5003, 3, False, True), (5003, 3, True, True),
+                                                         (257, 0, True, False), (1, 3, False, True)])
+def test_densify_prune_matches_oracle(n, degree, use_rgb, with_state):
+    import paper_2504_06716_amd as G
+    p, M, V, ema, frozen, st, noise = _case(n, degree)
+    if n == 1:
+        st[:, 0] = [1.0, 1.0, 0.0, 1.0]
+        p[3:6, 0], p[10, 0] = 0.0, 1.0          # big and live: split into two
+        frozen[0] = 0
+    if not with_state:
+        ema, frozen = None, None
+    ctx = G.Context(3 * n + 64, 1, 16, 16, 16)
+    cfg = _cfg(use_rgb=use_rgb)
+    cap = 3 * n + 5
+    counts, (gP, gM, gV), gE, gF = _run(ctx, degree, p, M, V, ema, frozen, st, noise, cfg, cap, pad=3)
+    oP, oM, oV, oE, oF, oc = O.densify_prune(p, M, V, ema, frozen, st, noise, 2e-4, 1e-6, use_rgb,
+                                             SPLIT_LS, PRUNE_LG, SHIFT)
+    assert counts == oc
+    n_out, K, C, Sp = oc
+    if n > 1:
+        assert K > 0 and C > 0 and Sp > 0 and K + Sp < n            # every rule is exercised
+    nc = K + C
+    np.testing.assert_array_equal(gP[:, :nc], oP[:, :nc].astype(np.float32))
+    np.testing.assert_array_equal(gM[:, :n_out], oM.astype(np.float32))
+    np.testing.assert_array_equal(gV[:, :n_out], oV.astype(np.float32))
+    np.testing.assert_array_equal(gE[:4 * n_out].reshape(4, n_out), oE.astype(np.float32))
+    np.testing.assert_array_equal(gF[:n_out], oF)
+    # children: copies exact, positions and log-scales to float32 rounding
+    ch, oc_ = gP[:, nc:n_out].astype(np.float64), oP[:, nc:]
+    np.testing.assert_array_equal(ch[6:], oc_[6:])
+    assert np.all(np.abs(ch[0:3] - oc_[0:3]) <= 1e-6 * (np.abs(oc_[0:3]) + 1.0))
+    np.testing.assert_allclose(ch[3:6], oc_[3:6], rtol=1e-6, atol=1e-6)
+    # untouched tail of the outputs
+    assert (gP[:, n_out:] == -7.0).all() and (gF[n_out:] == 9).all()
+
+
+def test_densify_capacity_overflow_writes_nothing_and_is_reported():
+    import paper_2504_06716_amd as G
+    p, M, V, ema, frozen, st, noise = _case(3000)
+    oc = O.densify_prune(p, M, V, ema, frozen, st, noise, 2e-4, 1e-6, False, SPLIT_LS, PRUNE_LG, SHIFT)[5]
+    ctx = G.Context(4000, 1, 16, 16, 16)
+    counts, (gP, _, _), gE, gF = _run(ctx, 3, p, M, V, ema, frozen, st, noise, _cfg(), cap=oc[0] - 1)
+    assert counts == oc
+    assert (gP == -7.0).all() and (gE == -7.0).all() and (gF == 9).all()
+    assert ctx.check()[0] == 2                      # GSTA_ERR_CAPACITY
+    assert ctx.check()[0] == 0                      # flags are cleared by the report
+
+
+def test_densify_empty_and_all_pruned():
+    import torch
+    import paper_2504_06716_amd as G
+    ctx = G.Context(600, 1, 16, 16, 16)
+    p, M, V, ema, frozen, st, noise = _case(500)
+    p[10] = -9.0                                    # everything below the prune logit
+    counts, (gP, _, _), _, _ = _run(ctx, 3, p, M, V, ema, frozen, st, noise, _cfg(), cap=600)
+    assert counts == (0, 0, 0, 0) and (gP == -7.0).all()
+    z = np.zeros((59, 0), np.float32)
+    counts, *_ = _run(ctx, 3, z, z, z, np.zeros((4, 0), np.float32), np.zeros(0, np.uint8),
+                      np.zeros((4, 0), np.float32), np.zeros((6, 0), np.float32), _cfg(), cap=10)
+    assert counts == (0, 0, 0, 0)
+    with pytest.raises(G.GstaError):                # output overlapping the input is refused
+        P = dev(p)
+        ctx.densify_prune(P, dev(M), dev(V), 3, None, None, dev(st), dev(noise), _cfg(), P, dev(M), dev(V),
+                          None, None, torch.zeros(4, dtype=torch.int64, device="cuda"))
+
+
+def test_opacity_reset_matches_oracle():
+    import torch
+    import paper_2504_06716_amd as G
+    p, M, V, _, frozen, _, _ = _case(3001)
+    ctx = G.Context(3001, 1, 16, 16, 16)
+    P, Mt, Vt = dev(p), dev(M), dev(V)
+    cap = math.log(0.01 / 0.99)
+    ctx.opacity_reset(P, Mt, Vt, 3, dev(frozen), cap)
+    torch.cuda.synchronize()
+    oP, oM, oV = O.opacity_reset(p, M, V, frozen, cap)
+    np.testing.assert_array_equal(P.cpu().numpy(), oP.astype(np.float32))
+    np.testing.assert_array_equal(Mt.cpu().numpy(), oM.astype(np.float32))
+    np.testing.assert_array_equal(Vt.cpu().numpy(), oV.astype(np.float32))
+
+
+def test_densify_stats_match_oracle():
+    """Two backward calls (two views each) accumulate the statistics."""
+    import torch
+    import paper_2504_06716_amd as G
+    n = 300
+    p = S.make_scene(n, 3, seed=3).astype(np.float64)
+    p[3:6] += 0.7
+    cams = [S.look_at(10.0 + 30.0 * k, 15.0 + 60.0 * k, 48, 40) for k in range(4)]
+    rng = np.random.default_rng(9)
+    frozen = (rng.random(n) < 0.2).astype(np.uint8)
+    ctx = G.Context(n, 2, 40, 48, 1 << 18)
+    P = dev(p.astype(np.float32))
+    dst = torch.zeros((4, n), device="cuda")
+    acc = np.zeros((4, n))
+    excl = np.zeros(n, bool)
+    for b in range(2):
+        cs = cams[2 * b:2 * b + 2]
+        w = rng.standard_normal((2, 3, 40, 48))
+        for v, c in enumerate(cs):
+            o = O.render(p, 3, c)
+            w[v][:, (o["m_value"] < MARGIN_VALUE) | (o["m_grad"] < MARGIN_VALUE)] = 0.0
+            rec = O.project(p, 3, c)
+            excl |= rec[:, 27] < MARGIN_RECT_PX
+        img = torch.empty((2, 3, 40, 48), device="cuda")
+        ctx.render_forward(P, 3, cs, (0, 0, 0), img)
+        grad = torch.zeros((59, n), device="cuda")
+        ctx.render_backward(P, 3, cs, (0, 0, 0), 0, dev(w.astype(np.float32)), dev(frozen), grad, dstats=dst)
+        g, g2, vis = O.render_backward(p, 3, cs, w, frozen)
+        acc = O.densify_stats(acc, g2, vis, g, frozen, 48, 40)
+    got = dst.cpu().numpy().astype(np.float64)
+    keep = ~excl
+    np.testing.assert_array_equal(got[1][keep], acc[1][keep])
+    np.testing.assert_array_equal(got[3][keep], acc[3][keep])
+    assert (got[:, frozen == 1] == 0).all()
+    for r in (0, 2):
+        a, b = got[r][keep], acc[r][keep]
+        assert np.linalg.norm(a - b) <= GRAD_REL * np.linalg.norm(b)
+        assert np.all(np.abs(a - b) <= GRAD_REL * np.abs(b) + GRAD_REL * np.abs(b).max())
+    assert (acc[1] > 0).sum() > 100
+
+
+def _dens_trainer(graph, iters=90, n=1500):
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd.schedule import DensifySchedule, FreezeSchedule, LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
+    p = S.make_scene(n, 3, seed=11)
+    cams = [S.look_at(-15.0 + 10 * k, 45.0 * k, 48, 40) for k in range(8)]
+    ctx = G.Context(4 * n, 8, 40, 48, 1 << 20)
+    tgt = render_targets(ctx, S.perturb_scene(p, 3, seed=12), 3, cams)
+    ds = DensifySchedule(total_iters=iters, start=20, stop=80, every=20, reset_every=40, eps_xyz0=2e-5)
+    fs = FreezeSchedule(total_iters=iters, warmup=10, every=10, reset_every=50, wait=10, window_end=70,
+                        eps_xyz0=1e-6, eps_rgb0=1e-7)
+    cfg = TrainConfig(iters=iters, freeze=True, schedule=fs, lrs=LearningRates(decay_iters=iters),
+                      densify=ds, max_gaussians=4 * n, graph=graph, device_sched=True)
+    tr = Trainer(p, 3, cams, tgt, cfg, S.view_order(8, iters), ctx=ctx)
+    return tr
+
+
+def test_trainer_densify_changes_n_and_graph_replay_matches_eager():
+    """A densifying run (clone, split, prune, opacity reset, freezing) gives
+    the same Gaussians eager and with HIP graphs captured again after every
+    change of N."""
+    import torch
+    out = []
+    for graph in (False, True):
+        tr = _dens_trainer(graph)
+        p0 = tr.evaluate()
+        tr.run(90)
+        torch.cuda.synchronize()
+        out.append((tr.n, tr.n_history, tr.P.cpu().numpy(), tr.frozen.cpu().numpy(), tr.evaluate(), p0))
+    (n0, h0, P0, F0, e0, s0), (n1, h1, P1, F1, e1, _) = out
+    assert len(h0) == 3 and h0 == h1 and n0 == n1
+    assert any(b != a for (_, a), (_, b) in zip([(0, 1500)] + h0[:-1], h0))
+    np.testing.assert_array_equal(P0, P1)
+    np.testing.assert_array_equal(F0, F1)
+    assert e0 > s0                                   # it still trains

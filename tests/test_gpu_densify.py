@@ -186,13 +186,13 @@ def _dens_trainer(graph, iters=90, n=1500):
     from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
     p = S.make_scene(n, 3, seed=11)
     cams = [S.look_at(-15.0 + 10 * k, 45.0 * k, 48, 40) for k in range(8)]
-    ctx = G.Context(4 * n, 8, 40, 48, 1 << 20)
+    ctx = G.Context(12 * n, 8, 40, 48, 1 << 20)
     tgt = render_targets(ctx, S.perturb_scene(p, 3, seed=12), 3, cams)
-    ds = DensifySchedule(total_iters=iters, start=20, stop=80, every=20, reset_every=40, eps_xyz0=2e-5)
+    ds = DensifySchedule(total_iters=iters, start=20, stop=60, every=20, reset_every=40, eps_xyz0=1e-4)
     fs = FreezeSchedule(total_iters=iters, warmup=10, every=10, reset_every=50, wait=10, window_end=70,
                         eps_xyz0=1e-6, eps_rgb0=1e-7)
     cfg = TrainConfig(iters=iters, freeze=True, schedule=fs, lrs=LearningRates(decay_iters=iters),
-                      densify=ds, max_gaussians=4 * n, graph=graph, device_sched=True)
+                      densify=ds, max_gaussians=12 * n, graph=graph, device_sched=True)
     tr = Trainer(p, 3, cams, tgt, cfg, S.view_order(8, iters), ctx=ctx)
     return tr
 
@@ -205,13 +205,15 @@ def test_trainer_densify_changes_n_and_graph_replay_matches_eager():
     out = []
     for graph in (False, True):
         tr = _dens_trainer(graph)
+        tr.run(41)                                   # densify at 20 and 40, opacity reset at 40
         p0 = tr.evaluate()
-        tr.run(90)
+        tr.run(49)
         torch.cuda.synchronize()
         out.append((tr.n, tr.n_history, tr.P.cpu().numpy(), tr.frozen.cpu().numpy(), tr.evaluate(), p0))
     (n0, h0, P0, F0, e0, s0), (n1, h1, P1, F1, e1, _) = out
-    assert len(h0) == 3 and h0 == h1 and n0 == n1
+    print("N after each densify step:", h0, "PSNR after the reset", s0, "at the end", e0)
+    assert len(h0) == 2 and h0 == h1 and n0 == n1
     assert any(b != a for (_, a), (_, b) in zip([(0, 1500)] + h0[:-1], h0))
     np.testing.assert_array_equal(P0, P1)
     np.testing.assert_array_equal(F0, F1)
-    assert e0 > s0                                   # it still trains
+    assert e0 > s0 + 1.0                             # it trains on after the reset

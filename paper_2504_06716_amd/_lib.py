@@ -7,14 +7,15 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgsta.so")
+# GSTA_LIB selects another build of the same library (same ABI).
+LIB_PATH = os.environ.get("GSTA_LIB") or os.path.join(_HERE, "libgsta.so")
 
 GSTA_OK, GSTA_ERR_INVALID, GSTA_ERR_CAPACITY, GSTA_ERR_HIP, GSTA_ERR_OOM, GSTA_ERR_NONFINITE = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NONFINITE"}
 
 (STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
  STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES, STATE_INST_GID) = range(12)
-OPT_FWD_WAVES, OPT_BWD_WAVES = 0, 1
+OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT = 0, 1, 2
 
 
 class Limits(ctypes.Structure):

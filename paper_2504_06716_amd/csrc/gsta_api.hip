@@ -34,6 +34,13 @@ struct Slot {
     double* cfg = nullptr;
     uint64_t* n_total = nullptr;
     uint32_t* n_count = nullptr;
+    // segment checkpoints of the forward compositing (see SegCkpt)
+    uint32_t* ck_idx = nullptr;
+    double* ck_pool = nullptr;
+    uint32_t* ck_ctr = nullptr;
+    uint32_t* tile_last = nullptr;
+    uint32_t* item_off = nullptr;
+    uint32_t shift = 31;             // segment length of the last forward (31: none)
     // what the last forward in this slot rendered
     int depth_buf = 0, inst_buf = 0;
     bool valid = false;
@@ -60,7 +67,10 @@ struct gsta_ctx {
     uint64_t* partials = nullptr;
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
-    int fwd_waves = 4, bwd_waves = 4;
+    int fwd_waves = 4, bwd_waves = 2;
+    uint32_t seg_shift = 7;        // backward segments of 128 splats (31: off)
+    uint32_t pool_cap = 0;         // checkpoint slots per state slot
+    int cus = 1, bwd_blocks = 1;   // persistent backward grid
     uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient, [2] densify overflow
     uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
     uint32_t* dens_boff = nullptr; // [3][blocks] densify block counts / offsets
@@ -142,6 +152,9 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     const int64_t S = ctx->stride, cap = l->instance_capacity;
     const int64_t HW = (int64_t)l->max_width * l->max_height;
     ctx->slots.assign((size_t)l->n_slots, Slot());
+    // checkpoint slots: one per 256 tile instances of capacity, at least 4096
+    const int64_t pool_cap = std::min<int64_t>(std::max<int64_t>(4096, cap / 256), (int64_t)1 << 30);
+    ctx->pool_cap = (uint32_t)pool_cap;
     bool ok = true;
     for (Slot& s : ctx->slots) {
         ok = ok && alloc(ctx, &s.geo, V * S) && alloc(ctx, &s.col, V * S) && alloc(ctx, &s.rgb, V * S) &&
@@ -151,7 +164,9 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.inst_gid, cap) && alloc(ctx, &s.inst_off, V * S) &&
              alloc(ctx, &s.ranges, V * ctx->tiles_max) && alloc(ctx, &s.T_final, V * HW) &&
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
-             alloc(ctx, &s.n_count, 1);
+             alloc(ctx, &s.n_count, 1) && alloc(ctx, &s.ck_idx, ((cap >> kMinSegShift) + 2) * kCkptGroups) &&
+             alloc(ctx, &s.ck_pool, (int64_t)pool_cap * 256) && alloc(ctx, &s.ck_ctr, 1) &&
+             alloc(ctx, &s.tile_last, V * ctx->tiles_max) && alloc(ctx, &s.item_off, V * ctx->tiles_max + 1);
     }
     ctx->items_depth = S <= (1 << 20) ? 4 : 16;
     ctx->items_inst = cap <= (1 << 20) ? 4 : 16;
@@ -167,6 +182,11 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_OOM, "device allocation failed");
     }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ctx->cus = 1;
+    ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
         hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
@@ -202,6 +222,19 @@ DevCam to_dev(const gsta_camera& c) {
     d.ntx = (c.width + kTile - 1) / kTile;
     d.nty = (c.height + kTile - 1) / kTile;
     return d;
+}
+
+SegCkpt seg_ckpt(gsta_ctx* ctx, Slot& s) {
+    SegCkpt c;
+    c.shift = s.shift;
+    c.idx = s.ck_idx;
+    c.pool = s.ck_pool;
+    c.pool_cap = ctx->pool_cap;
+    c.ctr = s.ck_ctr;
+    c.tile_last = s.tile_last;
+    c.item_off = s.item_off;
+    c.flags = ctx->flags;
+    return c;
 }
 
 gsta_status check_params(gsta_ctx* ctx, const gsta_params* g, const char* name) {
@@ -337,7 +370,20 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
             if (value != 1 && value != 2 && value != 4)
                 return fail(ctx, GSTA_ERR_INVALID, "backward waves per tile must be 1, 2 or 4");
             ctx->bwd_waves = (int)value;
+            ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
             return GSTA_OK;
+        case GSTA_OPT_BWD_SEGMENT: {
+            if (value == 0) {
+                ctx->seg_shift = 31;
+                return GSTA_OK;
+            }
+            int sh = 0;
+            while (sh < 30 && ((int64_t)1 << sh) < value) ++sh;
+            if (((int64_t)1 << sh) != value || sh < kMinSegShift || sh > 16)
+                return fail(ctx, GSTA_ERR_INVALID, "backward segment length must be 0 or a power of two in [64, 65536]");
+            ctx->seg_shift = (uint32_t)sh;
+            return GSTA_OK;
+        }
         default:
             return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
     }
@@ -402,6 +448,8 @@ gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances
     if (flags[0]) return fail(ctx, GSTA_ERR_CAPACITY, "tile instances (%llu) exceeded the capacity (%lld)",
                               (unsigned long long)mi, (long long)ctx->lim.instance_capacity);
     if (flags[2]) return fail(ctx, GSTA_ERR_CAPACITY, "densified set exceeded the output capacity");
+    if (flags[3]) return fail(ctx, GSTA_ERR_CAPACITY, "compositing checkpoints exceeded their pool (%u slots)",
+                              ctx->pool_cap);
     if (flags[1]) return fail(ctx, GSTA_ERR_NONFINITE, "non-finite gradient met by the optimizer");
     return GSTA_OK;
 }
@@ -486,8 +534,10 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
+        s.shift = ctx->fwd_waves == 0 ? 31u : ctx->seg_shift;    // no checkpoints in quadrant mode
         launch_composite_fwd(ctx->fwd_waves, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col, s.rgb, S, ca,
-                             nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, pair_counter(ctx, 0), stream);
+                             nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, seg_ckpt(ctx, s),
+                             pair_counter(ctx, 0), stream);
     }
     if ((st = hip_check(ctx, hipGetLastError(), "render_forward launch")) != GSTA_OK) {
         s.valid = false;
@@ -531,9 +581,9 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     const int nv = n_views;
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
-        launch_composite_bwd(ctx->bwd_waves, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col, s.rgb, S, frozen,
-                             ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg, dL_dimage, ctx->tile_grads,
-                             s.n_count, pair_counter(ctx, 1), stream);
+        launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col,
+                             s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg, dL_dimage,
+                             ctx->tile_grads, s.n_count, seg_ckpt(ctx, s), pair_counter(ctx, 1), stream);
     }
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);

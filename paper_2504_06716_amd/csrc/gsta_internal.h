@@ -134,22 +134,49 @@ int64_t expand_blocks(int64_t elements);
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
                    int64_t n_ranges, hipStream_t s);
 
+// Splat-segment checkpoints of the forward compositing, read by the
+// backward.  Every tile's depth-ordered list is cut into segments of K
+// splats (K a power of two).  When a forward wave reaches a segment boundary
+// with pixels still active, it takes a slot of the pool and stores, per
+// pixel of each 64-pixel group (tile-linear pixel index / 64), the state
+// before that splat: transmittance and the double-precision colour prefix.
+// idx[(global list position / K) * 4 + group] names the slot (unique: two
+// boundaries of different tiles are more than K positions apart).  The
+// backward runs one work item per (tile, segment) up to the tile's last
+// member, starting from the checkpoint, so a heavy tile is spread over many
+// workgroups instead of one.
+constexpr int kCkptGroups = kTilePix / 64;    // 64-pixel groups per tile
+constexpr int kMinSegShift = 6;               // shortest segment: 64 splats
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+struct SegCkpt {
+    uint32_t shift;          // log2 K; 31 disables segments (one item per tile, no checkpoints)
+    uint32_t* idx;           // [(capacity >> min shift) + 2][4] slot per (boundary bucket, group)
+    double* pool;            // [pool_cap][4][64]: T, colour r, g, b
+    uint32_t pool_cap;
+    uint32_t* ctr;           // [1] slots taken by the forward
+    uint32_t* tile_last;     // [V * T] largest `last` of each tile (zeroed before the forward)
+    uint32_t* item_off;      // [V * T + 1] exclusive scan of the items per tile
+    uint32_t* flags;         // flags[3]: the pool ran out
+};
 // Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  `ids` holds,
 // per sorted instance, its index in the depth-ordered expansion; inst_gid
 // maps that index to the Gaussian.  The backward writes each (tile, splat)
 // 2-D gradient into partials[expansion index][9] (zeroed first), without
-// atomics.
+// atomics; it is a persistent kernel of `blocks` workgroups over the
+// (tile, segment) items.
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
-                          float* T_final, uint32_t* last, double* cfg, unsigned long long* pairs, hipStream_t s);
-
-void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s);
+void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
                           const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
-                          float* partials, const uint32_t* d_count, unsigned long long* pairs, hipStream_t s);
-
+                          float* partials, const uint32_t* d_count, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s);
+// Workgroups of the backward compositing that fit on one compute unit.
+int composite_bwd_blocks_per_cu(int waves);
 void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                  int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
                  float bc1, float bc2, const uint8_t* frozen, uint32_t* flags, hipStream_t s);

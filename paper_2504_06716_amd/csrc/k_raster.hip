@@ -7,9 +7,11 @@
 // once all its pixels have terminated (__syncthreads_count).  Colour is
 // accumulated in double precision and kept per pixel for the backward.
 //
-// Backward (Section 3.2.4): same workgroup shape.  Each pixel re-walks its
-// list up to its last member and recomputes the transmittance with the same
-// instructions as the forward (shared eval_splat / next_T), so every
+// Backward (Section 3.2.4): same workgroup shape, one workgroup per
+// (tile, segment of K splats) work item, starting from the state the
+// forward checkpointed at the segment boundary.  Each pixel re-walks the
+// segment up to its last member and recomputes the transmittance with the
+// same instructions as the forward (shared eval_splat / next_T), so every
 // membership and termination decision is identical.  The colour behind a
 // member is the forward colour minus the recomputed prefix (both double).
 // Frozen splats still attenuate the pixels behind them but get no gradient
@@ -50,11 +52,13 @@ struct Rec {
     float4 c;    // r, g, b
 };
 
-__device__ __forceinline__ void fetch_rec(const float4* __restrict__ geo, const float4* __restrict__ col,
-                                          const float4* __restrict__ rgbv, int64_t vs, uint32_t gid, Rec& r) {
+__device__ __forceinline__ Rec fetch_rec(const float4* __restrict__ geo, const float4* __restrict__ col,
+                                         const float4* __restrict__ rgbv, int64_t vs, uint32_t gid) {
+    Rec r;
     r.g = geo[vs + gid];
     r.co = col[vs + gid];
     r.c = rgbv[vs + gid];
+    return r;
 }
 
 // Pixel p of thread tid.  Tile mode: 4/W pixels per thread, rows interleaved
@@ -72,18 +76,51 @@ __device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, i
     }
 }
 
+// Forward state at a segment boundary (global list position gpos), for the
+// pixel groups of this thread that still have active pixels.  Called with
+// the lanes that are still walking; done lanes are inactive.
+template <int W, int P>
+__device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, int tid, const bool* done,
+                                               const float* T, const double (*C)[3]) {
+    const int lane = tid & 63, wid = tid >> 6;
+    const size_t bucket = (size_t)(gpos >> sc.shift);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint64_t m = __ballot(!done[p]);
+        if (m == 0ull) continue;
+        const int first = __builtin_ctzll(m);
+        uint32_t slot = 0u;
+        if (lane == first) slot = atomicAdd(sc.ctr, 1u);
+        slot = (uint32_t)__builtin_amdgcn_readlane((int)slot, first);
+        const int g = wid + p * W;                    // 64-pixel group of pixel p
+        const bool ok = slot < sc.pool_cap;
+        if (lane == first) {
+            sc.idx[bucket * kCkptGroups + g] = ok ? slot : kNoSlot;
+            if (!ok) atomicOr(sc.flags + 3, 1u);
+        }
+        if (ok && !done[p]) {
+            double* d = sc.pool + (size_t)slot * 256;
+            d[lane] = (double)T[p];
+            d[64 + lane] = C[p][0];
+            d[128 + lane] = C[p][1];
+            d[192 + lane] = C[p][2];
+        }
+    }
+}
+
 template <int W, bool QUAD>
 __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
-    float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg,
+    float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg, SegCkpt sc,
     unsigned long long* __restrict__ pairs) {
     constexpr int NT = 64 * W, P = QUAD ? 1 : 4 / W, B = NT;
     __shared__ float4 s_geo[B];
     __shared__ float4 s_co[B];
     __shared__ float4 s_rgb[B];
     __shared__ unsigned int s_pairs;
+    __shared__ uint32_t s_last;
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
@@ -113,7 +150,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         alldone = alldone && done[p];
     }
     uint32_t evals = 0, witer = 0;
-    if (tid == 0) s_pairs = 0;
+    if (tid == 0) {
+        s_pairs = 0;
+        s_last = 0;
+    }
+    // checkpoints at list positions that are multiples of K (none in quadrant mode)
+    const uint32_t kmask = (QUAD || sc.shift >= 31u) ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
 
     // Two-stage software pipeline: while a batch is composited, the records
     // of the next batch and the ids of the one after are in flight.
@@ -121,7 +163,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     uint32_t gid_nxt = 0;
     {
         const uint32_t j = rg.x + tid;
-        if (j < rg.y) fetch_rec(geo, col, rgbv, vs, inst_gid[ids[j]], cur);
+        if (j < rg.y) cur = fetch_rec(geo, col, rgbv, vs, inst_gid[ids[j]]);
         if (j + B < rg.y) gid_nxt = inst_gid[ids[j + B]];
     }
     for (uint32_t base = rg.x; base < rg.y; base += B) {
@@ -134,36 +176,61 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         __syncthreads();
         {
             const uint32_t jn = base + B + tid;
-            if (jn < rg.y) fetch_rec(geo, col, rgbv, vs, gid_nxt, cur);
+            if (jn < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
             if (jn + B < rg.y) gid_nxt = inst_gid[ids[jn + B]];
         }
         const int cnt = (int)min((uint32_t)B, rg.y - base);
         // Each lane leaves the walk as soon as its pixels are done; the
         // exponential and the accumulation run under the lanes' own
         // membership tests.
-        for (int k = 0; k < cnt && !alldone; ++k) {
-            const float4 g = s_geo[k];
-            const float2 co = make_float2(s_co[k].x, s_co[k].y);
+        // Two splats per step: their exponentials are independent, so the
+        // second one's evaluation overlaps the first one's update of the
+        // transmittance; the updates themselves stay in list order.
+        for (int k = 0; k < cnt && !alldone; k += 2) {
+            const uint32_t pos = base - rg.x + (uint32_t)k;     // even: segment boundaries fall here
+            if (!QUAD && pos != 0u && (pos & kmask) == 0u) fwd_checkpoint<W, P>(sc, base + (uint32_t)k, tid, done, T, C);
+            const bool two = k + 1 < cnt;
+            const int k1 = two ? k + 1 : k;
+            const float4 g0 = s_geo[k], g1 = s_geo[k1];
+            const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
             bool all = true;
-            witer += 1u;
+            witer += two ? 2u : 1u;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!done[p]) {
+                    SplatEval e0, e1;
+                    eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
+                    eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
                     ++evals;
-                    SplatEval e;
-                    eval_splat(g.x, g.y, g.z, g.w, co.x, co.y, fpx[p], fpy[p], e);
-                    if (e.power >= kPowerFloor && e.alpha >= kAlphaMin) {
-                        const float Tn = next_T(T[p], e.alpha);
+                    if (e0.power >= kPowerFloor && e0.alpha >= kAlphaMin) {
+                        const float Tn = next_T(T[p], e0.alpha);
                         if (Tn < kTMin) {
                             done[p] = true;
                         } else {
                             const float4 c = s_rgb[k];
-                            const double w = (double)(e.alpha * T[p]);
+                            const double w = (double)(e0.alpha * T[p]);
                             C[p][0] = fma((double)c.x, w, C[p][0]);
                             C[p][1] = fma((double)c.y, w, C[p][1]);
                             C[p][2] = fma((double)c.z, w, C[p][2]);
                             T[p] = Tn;
-                            last[p] = base - rg.x + (uint32_t)k + 1u;
+                            last[p] = pos + 1u;
+                        }
+                    }
+                    if (two && !done[p]) {
+                        ++evals;
+                        if (e1.power >= kPowerFloor && e1.alpha >= kAlphaMin) {
+                            const float Tn = next_T(T[p], e1.alpha);
+                            if (Tn < kTMin) {
+                                done[p] = true;
+                            } else {
+                                const float4 c = s_rgb[k1];
+                                const double w = (double)(e1.alpha * T[p]);
+                                C[p][0] = fma((double)c.x, w, C[p][0]);
+                                C[p][1] = fma((double)c.y, w, C[p][1]);
+                                C[p][2] = fma((double)c.z, w, C[p][2]);
+                                T[p] = Tn;
+                                last[p] = pos + 2u;
+                            }
                         }
                     }
                 }
@@ -181,6 +248,15 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) witer = max(witer, (uint32_t)__shfl_xor((int)witer, off, 64));
         if ((tid & 63) == 0 && witer) atomicAdd(pairs + 2, (unsigned long long)witer);
+    }
+    {
+        uint32_t ml = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) ml = max(ml, last[p]);
+        __syncthreads();
+        if (ml) atomicMax(&s_last, ml);
+        __syncthreads();
+        if (tid == 0 && s_last) atomicMax(sc.tile_last + (int64_t)v * tiles + tile, s_last);
     }
     const int64_t HW = (int64_t)cm.width * cm.height;
 #pragma unroll
@@ -204,13 +280,48 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
 
 constexpr int kChunk = 64;   // splats per partial-sum flush in the backward
 
+// Items per tile: ceil(tile_last / K) (one if segments are off), scanned by
+// one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total).
+__global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__ tile_last, int nt, uint32_t shift,
+                                                    uint32_t* __restrict__ item_off) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nt; base += 1024) {
+        const int j = base + (int)threadIdx.x;
+        uint32_t x = 0;
+        if (j < nt) {
+            const uint32_t l = tile_last[j];
+            x = shift >= 31u ? (l ? 1u : 0u) : ((l + (1u << shift) - 1u) >> shift);
+        }
+        uint32_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[w] = incl;
+        __syncthreads();
+        uint32_t wbase = s_carry;
+        for (int k = 0; k < w; ++k) wbase += s_w[k];
+        if (j < nt) item_off[j] = wbase + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = wbase + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) item_off[nt] = s_carry;
+}
+
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
-    int64_t stride, const uint8_t* __restrict__ frozen, CamArray cams, float bg0, float bg1, float bg2,
+    int64_t stride, const uint8_t* __restrict__ frozen, CamArray cams, int nv, float bg0, float bg1, float bg2,
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in, const double* __restrict__ cfg,
-    const float* __restrict__ dL_dimage, float* __restrict__ partials, unsigned long long* __restrict__ pairs) {
+    const float* __restrict__ dL_dimage, float* __restrict__ partials, SegCkpt sc,
+    unsigned long long* __restrict__ pairs) {
     constexpr int NT = 64 * W, P = 4 / W, B = NT;
     __shared__ float4 s_geo[B];
     __shared__ float4 s_co[B];
@@ -218,205 +329,232 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     __shared__ uint32_t s_idx[B];
     __shared__ uint32_t s_frz[B];
     __shared__ float s_part[W][9][kChunk];
-    __shared__ uint32_t s_maxlast;
     __shared__ unsigned int s_pairs;
 
-    const int v = blockIdx.y;
-    const DevCam& cm = cams.c[v];
-    const int tiles = cm.ntx * cm.nty;
-    const int tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int tx0 = (tile % cm.ntx) * kTile, ty0 = (tile / cm.ntx) * kTile;
-    const uint2 rg = ranges[(int64_t)v * tiles + tile];
-    const int64_t vs = (int64_t)v * stride;
-    const int64_t HW = (int64_t)cm.width * cm.height;
-
-    float fpx[P], fpy[P], dC[P][3], Tf[P], T[P];
-    double F[P][3], A[P][3];
-    uint32_t last[P];
-    uint32_t mylast = 0;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        int px, py;
-        pixel_of<W, false>(tid, p, 0, tx0, ty0, px, py);
-        fpx[p] = (float)px;
-        fpy[p] = (float)py;
-        T[p] = 1.0f;
-        A[p][0] = A[p][1] = A[p][2] = 0.0;
-        dC[p][0] = dC[p][1] = dC[p][2] = 0.f;
-        F[p][0] = F[p][1] = F[p][2] = 0.0;
-        Tf[p] = 1.f;
-        last[p] = 0;
-        if (px < cm.width && py < cm.height) {
-            const int64_t o = (int64_t)py * cm.width + px;
-            const float* dl = dL_dimage + (int64_t)v * 3 * HW + o;
-            dC[p][0] = dl[0];
-            dC[p][1] = dl[HW];
-            dC[p][2] = dl[2 * HW];
-            Tf[p] = T_final[(int64_t)v * HW + o];
-            last[p] = last_in[(int64_t)v * HW + o];
-            const double* cf = cfg + (int64_t)v * 3 * HW + o;
-            F[p][0] = cf[0];
-            F[p][1] = cf[HW];
-            F[p][2] = cf[2 * HW];
-        }
-        mylast = max(mylast, last[p]);
-    }
-    if (tid == 0) {
-        s_maxlast = 0;
-        s_pairs = 0;
-    }
-    __syncthreads();
-    if (mylast) atomicMax(&s_maxlast, mylast);
-    __syncthreads();
-    const uint32_t end = rg.x + s_maxlast;
+    const int tiles = cams.c[0].ntx * cams.c[0].nty;
+    const int nt = nv * tiles;
+    const uint32_t n_items = sc.item_off[nt];
+    const bool seg = sc.shift < 31u;
     uint32_t evals = 0, witer = 0, wred = 0;
+    if (tid == 0) s_pairs = 0;
 
-    // Two-stage software pipeline as in the forward.
-    Rec cur;
-    uint32_t idx_cur = 0, frz_cur = 0, idx_nxt = 0, gid_nxt = 0;
-    {
-        const uint32_t j = rg.x + tid;
-        if (j < end) {
-            idx_cur = ids[j];
-            const uint32_t gid = inst_gid[idx_cur];
-            fetch_rec(geo, col, rgbv, vs, gid, cur);
-            frz_cur = frozen ? (uint32_t)frozen[gid] : 0u;
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        // the item's tile: the last gt with item_off[gt] <= item
+        int lo = 0, hi = nt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sc.item_off[mid] <= item) lo = mid; else hi = mid - 1;
         }
-        if (j + B < end) {
-            idx_nxt = ids[j + B];
-            gid_nxt = inst_gid[idx_nxt];
-        }
-    }
-    for (uint32_t base = rg.x; base < end; base += B) {
-        __syncthreads();
-        if (base + tid < end) {
-            s_idx[tid] = idx_cur;
-            s_geo[tid] = cur.g;
-            s_co[tid] = cur.co;
-            s_rgb[tid] = cur.c;
-            s_frz[tid] = frz_cur;
-        }
-        __syncthreads();
-        {
-            const uint32_t jn = base + B + tid;
-            if (jn < end) {
-                idx_cur = idx_nxt;
-                fetch_rec(geo, col, rgbv, vs, gid_nxt, cur);
-                frz_cur = frozen ? (uint32_t)frozen[gid_nxt] : 0u;
+        const int gt = lo;
+        const uint32_t sgi = item - sc.item_off[gt];
+        const int v = gt / tiles, tile = gt - v * tiles;
+        const DevCam& cm = cams.c[v];
+        const int tx0 = (tile % cm.ntx) * kTile, ty0 = (tile / cm.ntx) * kTile;
+        const uint2 rg = ranges[gt];
+        const int64_t vs = (int64_t)v * stride;
+        const int64_t HW = (int64_t)cm.width * cm.height;
+        const uint32_t tl = sc.tile_last[gt];
+        const uint32_t p0 = seg ? (sgi << sc.shift) : 0u;                       // first position of the item
+        const uint32_t p1 = seg ? min(tl, (sgi + 1u) << sc.shift) : tl;          // one past its last
+
+        float fpx[P], fpy[P], dC[P][3], Tf[P], T[P];
+        double F[P][3], A[P][3];
+        uint32_t last[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            int px, py;
+            pixel_of<W, false>(tid, p, 0, tx0, ty0, px, py);
+            fpx[p] = (float)px;
+            fpy[p] = (float)py;
+            T[p] = 1.0f;
+            A[p][0] = A[p][1] = A[p][2] = 0.0;
+            dC[p][0] = dC[p][1] = dC[p][2] = 0.f;
+            F[p][0] = F[p][1] = F[p][2] = 0.0;
+            Tf[p] = 1.f;
+            last[p] = 0;
+            if (px < cm.width && py < cm.height) {
+                const int64_t o = (int64_t)py * cm.width + px;
+                last[p] = last_in[(int64_t)v * HW + o];
+                if (last[p] > p0) {
+                    const float* dl = dL_dimage + (int64_t)v * 3 * HW + o;
+                    dC[p][0] = dl[0];
+                    dC[p][1] = dl[HW];
+                    dC[p][2] = dl[2 * HW];
+                    Tf[p] = T_final[(int64_t)v * HW + o];
+                    const double* cf = cfg + (int64_t)v * 3 * HW + o;
+                    F[p][0] = cf[0];
+                    F[p][1] = cf[HW];
+                    F[p][2] = cf[2 * HW];
+                }
             }
-            if (jn + B < end) {
-                idx_nxt = ids[jn + B];
+        }
+        if (p0 != 0u) {
+            // resume from the forward's state at the segment boundary
+            const size_t bucket = (size_t)((rg.x + p0) >> sc.shift);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (last[p] <= p0) continue;
+                const uint32_t slot = sc.idx[bucket * kCkptGroups + wid + p * W];
+                if (slot >= sc.pool_cap) {       // the forward ran out of slots (flagged)
+                    last[p] = 0;
+                    continue;
+                }
+                const double* d = sc.pool + (size_t)slot * 256;
+                T[p] = (float)d[lane];
+                A[p][0] = d[64 + lane];
+                A[p][1] = d[128 + lane];
+                A[p][2] = d[192 + lane];
+            }
+        }
+        const uint32_t beg = rg.x + p0, end = rg.x + p1;
+
+        // Two-stage software pipeline as in the forward.
+        Rec cur;
+        uint32_t idx_cur = 0, frz_cur = 0, idx_nxt = 0, gid_nxt = 0;
+        {
+            const uint32_t j = beg + tid;
+            if (j < end) {
+                idx_cur = ids[j];
+                const uint32_t gid = inst_gid[idx_cur];
+                cur = fetch_rec(geo, col, rgbv, vs, gid);
+                frz_cur = frozen ? (uint32_t)frozen[gid] : 0u;
+            }
+            if (j + B < end) {
+                idx_nxt = ids[j + B];
                 gid_nxt = inst_gid[idx_nxt];
             }
         }
-        const int cnt = (int)min((uint32_t)B, end - base);
-        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-            const int c1 = min(cnt, c0 + kChunk);
-            for (int k = c0; k < c1; ++k) {
-                const uint32_t pos = base - rg.x + (uint32_t)k;
-                const float4 g = s_geo[k];
-                const float2 co = make_float2(s_co[k].x, s_co[k].y);
-                // uniform over the wave: a scalar branch
-                const bool frz = __builtin_amdgcn_readfirstlane(s_frz[k]) != 0u;
-                witer += 1u;
-                SplatEval e[P];
-                bool mem[P];
-                bool any = false;
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const bool act = pos < last[p];
-                    evals += act ? 1u : 0u;
-                    eval_power(g.x, g.y, g.z, g.w, co.x, fpx[p], fpy[p], e[p]);
-                    mem[p] = act && (e[p].power >= kPowerFloor);
-                    any = any || mem[p];
+        for (uint32_t base = beg; base < end; base += B) {
+            __syncthreads();
+            if (base + tid < end) {
+                s_idx[tid] = idx_cur;
+                s_geo[tid] = cur.g;
+                s_co[tid] = cur.co;
+                s_rgb[tid] = cur.c;
+                s_frz[tid] = frz_cur;
+            }
+            __syncthreads();
+            {
+                const uint32_t jn = base + B + tid;
+                if (jn < end) {
+                    idx_cur = idx_nxt;
+                    cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
+                    frz_cur = frozen ? (uint32_t)frozen[gid_nxt] : 0u;
                 }
-                bool contrib = false;
-                if (__ballot(any) != 0ull) {
-                    const float4 c = s_rgb[k];
-                    float g9[9];
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) g9[q] = 0.f;
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        eval_alpha(co.y, e[p]);
-                        mem[p] = mem[p] && (e[p].alpha >= kAlphaMin);
-                        if (!mem[p]) continue;
-                        const float w = e[p].alpha * T[p];
-                        const double wd = (double)w;
-                        A[p][0] = fma((double)c.x, wd, A[p][0]);
-                        A[p][1] = fma((double)c.y, wd, A[p][1]);
-                        A[p][2] = fma((double)c.z, wd, A[p][2]);
-                        if (!frz) {
-                            contrib = true;
-                            const float inv1m = 1.0f / (1.0f - e[p].alpha);
-                            const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
-                            const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
-                            const float b2 = (float)(F[p][2] - A[p][2]) + Tf[p] * bg2;
-                            const float dalpha = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
-                                                 dC[p][1] * (c.y * T[p] - b1 * inv1m) +
-                                                 dC[p][2] * (c.z * T[p] - b2 * inv1m);
-                            g9[6] += dC[p][0] * w;
-                            g9[7] += dC[p][1] * w;
-                            g9[8] += dC[p][2] * w;
-                            if (e[p].oG <= kAlphaMax) {
-                                const float dpow = dalpha * e[p].alpha;
-                                g9[5] += dalpha * e[p].G;
-                                g9[0] -= dpow * (g.z * e[p].dx + g.w * e[p].dy);
-                                g9[1] -= dpow * (g.w * e[p].dx + co.x * e[p].dy);
-                                g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
-                                g9[3] -= dpow * e[p].dx * e[p].dy;
-                                g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
-                            }
-                        }
-                        T[p] = next_T(T[p], e[p].alpha);
-                    }
-                    if (!frz && __ballot(contrib) != 0ull) {
-                        wred += 1u;
-#pragma unroll
-                        for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
-                        if (lane == 63) {
-                            if (W == 1) {
-                                float* dst = partials + (int64_t)s_idx[k] * 9;
-#pragma unroll
-                                for (int q = 0; q < 9; ++q) dst[q] = g9[q];
-                            } else {
-#pragma unroll
-                                for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = g9[q];
-                            }
-                        }
-                        continue;
-                    }
-                }
-                if (W > 1 && lane == 63) {
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = 0.f;
+                if (jn + B < end) {
+                    idx_nxt = ids[jn + B];
+                    gid_nxt = inst_gid[idx_nxt];
                 }
             }
-            if (W > 1) {
-                // the waves' totals added in a fixed order
-                __syncthreads();
-                if (tid < c1 - c0) {
-                    const int k = c0 + tid;
-                    if (!s_frz[k]) {
-                        float sum[9];
-                        bool nz = false;
+            const int cnt = (int)min((uint32_t)B, end - base);
+            for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+                const int c1 = min(cnt, c0 + kChunk);
+                for (int k = c0; k < c1; ++k) {
+                    const uint32_t pos = base - rg.x + (uint32_t)k;
+                    const float4 g = s_geo[k];
+                    const float2 co = make_float2(s_co[k].x, s_co[k].y);
+                    // uniform over the wave: a scalar branch
+                    const bool frz = __builtin_amdgcn_readfirstlane(s_frz[k]) != 0u;
+                    witer += 1u;
+                    SplatEval e[P];
+                    bool mem[P];
+                    bool any = false;
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) {
-                            float acc = s_part[0][q][tid];
+                    for (int p = 0; p < P; ++p) {
+                        const bool act = pos < last[p];
+                        evals += act ? 1u : 0u;
+                        eval_power(g.x, g.y, g.z, g.w, co.x, fpx[p], fpy[p], e[p]);
+                        mem[p] = act && (e[p].power >= kPowerFloor);
+                        any = any || mem[p];
+                    }
+                    bool contrib = false;
+                    if (__ballot(any) != 0ull) {
+                        const float4 c = s_rgb[k];
+                        float g9[9];
 #pragma unroll
-                            for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
-                            sum[q] = acc;
-                            nz = nz || (acc != 0.f);
+                        for (int q = 0; q < 9; ++q) g9[q] = 0.f;
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            eval_alpha(co.y, e[p]);
+                            mem[p] = mem[p] && (e[p].alpha >= kAlphaMin);
+                            if (!mem[p]) continue;
+                            const float w = e[p].alpha * T[p];
+                            const double wd = (double)w;
+                            A[p][0] = fma((double)c.x, wd, A[p][0]);
+                            A[p][1] = fma((double)c.y, wd, A[p][1]);
+                            A[p][2] = fma((double)c.z, wd, A[p][2]);
+                            if (!frz) {
+                                contrib = true;
+                                const float inv1m = __builtin_amdgcn_rcpf(1.0f - e[p].alpha);
+                                const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
+                                const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
+                                const float b2 = (float)(F[p][2] - A[p][2]) + Tf[p] * bg2;
+                                const float dalpha = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
+                                                     dC[p][1] * (c.y * T[p] - b1 * inv1m) +
+                                                     dC[p][2] * (c.z * T[p] - b2 * inv1m);
+                                g9[6] += dC[p][0] * w;
+                                g9[7] += dC[p][1] * w;
+                                g9[8] += dC[p][2] * w;
+                                if (e[p].oG <= kAlphaMax) {
+                                    const float dpow = dalpha * e[p].alpha;
+                                    g9[5] += dalpha * e[p].G;
+                                    g9[0] -= dpow * (g.z * e[p].dx + g.w * e[p].dy);
+                                    g9[1] -= dpow * (g.w * e[p].dx + co.x * e[p].dy);
+                                    g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
+                                    g9[3] -= dpow * e[p].dx * e[p].dy;
+                                    g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
+                                }
+                            }
+                            T[p] = next_T(T[p], e[p].alpha);
                         }
-                        if (nz) {
-                            float* dst = partials + (int64_t)s_idx[k] * 9;
+                        if (!frz && __ballot(contrib) != 0ull) {
+                            wred += 1u;
 #pragma unroll
-                            for (int q = 0; q < 9; ++q) dst[q] = sum[q];
+                            for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
+                            if (lane == 63) {
+                                if (W == 1) {
+                                    float* dst = partials + (int64_t)s_idx[k] * 9;
+#pragma unroll
+                                    for (int q = 0; q < 9; ++q) dst[q] = g9[q];
+                                } else {
+#pragma unroll
+                                    for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = g9[q];
+                                }
+                            }
+                            continue;
                         }
                     }
+                    if (W > 1 && lane == 63) {
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = 0.f;
+                    }
                 }
-                __syncthreads();
+                if (W > 1) {
+                    // the waves' totals added in a fixed order
+                    __syncthreads();
+                    if (tid < c1 - c0) {
+                        const int k = c0 + tid;
+                        if (!s_frz[k]) {
+                            float sum[9];
+                            bool nz = false;
+#pragma unroll
+                            for (int q = 0; q < 9; ++q) {
+                                float acc = s_part[0][q][tid];
+#pragma unroll
+                                for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
+                                sum[q] = acc;
+                                nz = nz || (acc != 0.f);
+                            }
+                            if (nz) {
+                                float* dst = partials + (int64_t)s_idx[k] * 9;
+#pragma unroll
+                                for (int q = 0; q < 9; ++q) dst[q] = sum[q];
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
@@ -445,43 +583,60 @@ __global__ void k_zero_partials(float* __restrict__ p, const uint32_t* __restric
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
-                          float* T_final, uint32_t* last, double* cfg, unsigned long long* pairs, hipStream_t s) {
+                          float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s) {
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
+    launch_fill_u32(sc.tile_last, 0u, (int64_t)tiles * nv, s);
+    launch_fill_u32(sc.ctr, 0u, 1, s);
     if (waves == 0) {   // one independent wave per 8x8 quarter of each tile
         k_composite_fwd<1, true><<<dim3(4 * tiles, nv), 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride,
                                                                      cams, bg0, bg1, bg2, image, T_final, last, cfg,
-                                                                     pairs);
+                                                                     sc, pairs);
         return;
     }
     const dim3 grid(tiles, nv);
     if (waves == 1)
         k_composite_fwd<1, false><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                       bg2, image, T_final, last, cfg, pairs);
+                                                       bg2, image, T_final, last, cfg, sc, pairs);
     else if (waves == 2)
         k_composite_fwd<2, false><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                        bg2, image, T_final, last, cfg, pairs);
+                                                        bg2, image, T_final, last, cfg, sc, pairs);
     else
         k_composite_fwd<4, false><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                        bg2, image, T_final, last, cfg, pairs);
+                                                        bg2, image, T_final, last, cfg, sc, pairs);
 }
 
-void launch_composite_bwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
                           const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
-                          float* partials, const uint32_t* d_count, unsigned long long* pairs, hipStream_t s) {
+                          float* partials, const uint32_t* d_count, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s) {
     k_zero_partials<<<2048, 256, 0, s>>>(partials, d_count);
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    const dim3 grid(tiles, nv);
+    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off);
+    const dim3 grid((unsigned)blocks);
     if (waves == 1)
-        k_composite_bwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0, bg1,
-                                                bg2, T_final, last, cfg, dL_dimage, partials, pairs);
+        k_composite_bwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
+                                                bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
     else if (waves == 2)
-        k_composite_bwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0,
-                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, pairs);
+        k_composite_bwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
+                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
     else
-        k_composite_bwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, bg0,
-                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, pairs);
+        k_composite_bwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
+                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
+}
+
+int composite_bwd_blocks_per_cu(int waves) {
+    int nb = 0;
+    hipError_t e;
+    if (waves == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<1>, 64, 0);
+    else if (waves == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<2>, 128, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<4>, 256, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 }  // namespace gsta

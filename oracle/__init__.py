@@ -444,3 +444,110 @@ def opacity_reset(params, m, v, frozen, logit_cap):
     M[10, act] = 0.0
     V[10, act] = 0.0
     return P, M, V
+
+
+# ---------------------------------------------------------------------------
+# Learned freeze proposer (a project extension; the paper has no such
+# model, so its label and veto semantics are parity unpinned by the paper).
+# An MLP 32 -> 64 -> 64 -> 1 (ReLU, ReLU, logit) reads the last 8 logged
+# gradient-norm averages (xyz, rgb, opacity, scale) of a Gaussian as
+# standardised log10 features and proposes freezing it; the freeze rule
+# vetoes proposals whose averages are far above its thresholds.  The GPU
+# runs the two hidden layers on bf16 matrix cores with float32
+# accumulation: inputs, weights and the first hidden layer are rounded to
+# bf16 there, so the oracle rounds the same quantities (round to nearest,
+# ties to even) and computes everything else in float64.
+# ---------------------------------------------------------------------------
+
+MLP_IN, MLP_H = 32, 64
+# flat float32 parameter layout: W1 [64][32], b1 [64], W2 [64][64], b2 [64], w3 [64], b3
+MLP_OFF = {"W1": 0, "b1": 2048, "W2": 2112, "b2": 6208, "w3": 6272, "b3": 6336}
+MLP_COUNT = 6337
+
+
+def bf16_round(x):
+    """Round float32 values to bfloat16 (nearest, ties to even); returned as
+    float64 holding the bf16 value.  Inputs are first rounded to float32."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_unpack(wf):
+    w = np.asarray(wf, np.float64)
+    o = MLP_OFF
+    return (w[o["W1"]:o["b1"]].reshape(64, 32), w[o["b1"]:o["W2"]], w[o["W2"]:o["b2"]].reshape(64, 64),
+            w[o["b2"]:o["w3"]], w[o["w3"]:o["b3"]], w[o["b3"]])
+
+
+def traj_features(ring, head, mean, std):
+    """Features of every Gaussian: x[i][4j + q] = bf16((log10(r + 1e-12) - mean) / std)
+    with r = ring[(head - j) mod 8][q][i] (j = 0 is the newest entry)."""
+    R = np.asarray(ring, np.float64)
+    n = R.shape[2]
+    x = np.zeros((n, 32))
+    for j in range(8):
+        for q in range(4):
+            f = 4 * j + q
+            x[:, f] = (np.log10(R[(head - j) % 8, q] + 1e-12) - mean[f]) / std[f]
+    return bf16_round(x)
+
+
+def mlp_forward(x, wf):
+    """Logits of the MLP for bf16 features x [n][32]; also returns the bf16
+    first hidden layer and the float64 second one."""
+    W1, b1, W2, b2, w3, b3 = mlp_unpack(wf)
+    W1b, W2b = bf16_round(W1), bf16_round(W2)
+    a1 = np.asarray(x, np.float64) @ W1b.T + b1
+    h1 = bf16_round(np.maximum(a1, 0.0))
+    a2 = h1 @ W2b.T + b2
+    h2 = np.maximum(a2, 0.0)
+    z = h2 @ w3 + b3
+    return z, h1, h2
+
+
+def mlp_backward(x, wf, dz):
+    """Gradient of sum_i dz_i * z_i with respect to the flat parameters,
+    through the same rounded activations (the bf16 roundings are treated
+    as identity in the derivative, weights and hidden units alike)."""
+    W1, b1, W2, b2, w3, b3 = mlp_unpack(wf)
+    W2b = bf16_round(W2)
+    z, h1, h2 = mlp_forward(x, wf)
+    dz = np.asarray(dz, np.float64)
+    g = np.zeros(MLP_COUNT)
+    o = MLP_OFF
+    g[o["b3"]] = dz.sum()
+    g[o["w3"]:o["b3"]] = h2.T @ dz
+    d2 = np.outer(dz, w3) * (h2 > 0)
+    g[o["b2"]:o["w3"]] = d2.sum(0)
+    g[o["W2"]:o["b2"]] = (d2.T @ h1).reshape(-1)
+    d1 = (d2 @ W2b) * (h1 > 0)
+    g[o["b1"]:o["W2"]] = d1.sum(0)
+    g[o["W1"]:o["b1"]] = (d1.T @ np.asarray(x, np.float64)).reshape(-1)
+    return g
+
+
+def bce(z, y):
+    """Mean binary cross-entropy of logits z against labels y and its
+    derivative dL/dz = (sigmoid(z) - y) / n."""
+    z = np.asarray(z, np.float64)
+    y = np.asarray(y, np.float64)
+    n = z.size
+    loss = np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z))))
+    return loss, (1.0 / (1.0 + np.exp(-z)) - y) / n
+
+
+def propose(z, s_xyz, s_rgb, logit_threshold, veto_xyz, veto_rgb):
+    """Accepted proposals: logit above the threshold (sigmoid(z) > tau) and
+    not vetoed by the rule (both averages below c_v times its thresholds);
+    float32 comparisons."""
+    z32 = np.asarray(z, np.float32)
+    return ((z32 > np.float32(logit_threshold)) & (np.asarray(s_xyz, np.float32) < np.float32(veto_xyz))
+            & (np.asarray(s_rgb, np.float32) < np.float32(veto_rgb))).astype(np.uint8)
+
+
+def proposer_labels(cond_next, cond_after):
+    """Label of a Gaussian at a freeze update: the rule freezes it at one of
+    the next two updates."""
+    return ((np.asarray(cond_next) != 0) | (np.asarray(cond_after) != 0)).astype(np.uint8)

@@ -588,3 +588,107 @@ def test_opacity_reset_hand_values():
     np.testing.assert_array_equal(nM[10], [0, 0, 0, 1])
     np.testing.assert_array_equal(nV[10], [0, 0, 0, 1])
     assert (nM[:10] == 1).all() and (nP[:10] == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# Learned freeze proposer (project extension)
+# ---------------------------------------------------------------------------
+
+def _mlp_case(n=300, seed=0):
+    rng = np.random.default_rng(seed)
+    wf = np.zeros(O.MLP_COUNT)
+    o = O.MLP_OFF
+    wf[o["W1"]:o["b1"]] = rng.standard_normal(2048) / np.sqrt(32)
+    wf[o["b1"]:o["W2"]] = 0.1 * rng.standard_normal(64)
+    wf[o["W2"]:o["b2"]] = rng.standard_normal(4096) / 8.0
+    wf[o["b2"]:o["w3"]] = 0.1 * rng.standard_normal(64)
+    wf[o["w3"]:o["b3"]] = rng.standard_normal(64) / 8.0
+    wf[o["b3"]] = 0.3
+    wf = wf.astype(np.float32).astype(np.float64)
+    x = O.bf16_round(rng.standard_normal((n, 32)))
+    return x, wf
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(1)
+    v = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.integers(-20, 20, 5000),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 0.0, 2.0 ** -130]]).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.bf16_round(v), ref)
+    assert O.bf16_round(np.float32(1.0 + 2.0 ** -8)) == 1.0            # tie to even
+    assert O.bf16_round(np.float32(1.0 + 3 * 2.0 ** -8)) == 1.0 + 2.0 ** -6
+
+
+def _torch_mlp(x, wf):
+    """The same network written with torch float64 ops and torch's bf16
+    casts, the roundings passed straight through in the derivative."""
+    def rnd(t):
+        return t + (t.to(torch.float32).to(torch.bfloat16).to(torch.float64) - t).detach()
+    o = O.MLP_OFF
+    w = torch.tensor(wf, dtype=torch.float64, requires_grad=True)
+    W1 = w[o["W1"]:o["b1"]].view(64, 32)
+    W2 = w[o["W2"]:o["b2"]].view(64, 64)
+    h1 = rnd(torch.relu(torch.tensor(x) @ rnd(W1).T + w[o["b1"]:o["W2"]]))
+    h2 = torch.relu(h1 @ rnd(W2).T + w[o["b2"]:o["w3"]])
+    z = h2 @ w[o["w3"]:o["b3"]] + w[o["b3"]]
+    return z, w
+
+
+def test_mlp_forward_backward_match_torch():
+    x, wf = _mlp_case()
+    z, h1, h2 = O.mlp_forward(x, wf)
+    zt, w = _torch_mlp(x, wf)
+    np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    dz = np.random.default_rng(3).standard_normal(x.shape[0])
+    (zt * torch.tensor(dz)).sum().backward()
+    np.testing.assert_allclose(O.mlp_backward(x, wf, dz), w.grad.numpy(), rtol=1e-10, atol=1e-12)
+    assert (h1 > 0).mean() > 0.2 and (h2 > 0).mean() > 0.2
+
+
+def test_mlp_backward_finite_differences_on_unrounded_parameters():
+    # b2, w3 and b3 enter without rounding: central differences apply
+    x, wf = _mlp_case(n=50)
+    dz = np.random.default_rng(4).standard_normal(50)
+    g = O.mlp_backward(x, wf, dz)
+    o = O.MLP_OFF
+    for k in [o["b2"] + 3, o["b2"] + 40, o["w3"] + 5, o["w3"] + 63, o["b3"]]:
+        h = 1e-6
+        wp, wm = wf.copy(), wf.copy()
+        wp[k] += h
+        wm[k] -= h
+        fd = ((O.mlp_forward(x, wp)[0] - O.mlp_forward(x, wm)[0]) @ dz) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+def test_bce_closed_forms():
+    loss, dz = O.bce(np.array([0.0, 0.0]), np.array([1, 0]))
+    assert loss == pytest.approx(math.log(2.0))
+    np.testing.assert_allclose(dz, [-0.25, 0.25])
+    loss, dz = O.bce(np.array([50.0, -50.0]), np.array([1, 0]))
+    assert loss == pytest.approx(math.exp(-50.0), rel=1e-6)
+
+
+def test_propose_veto_and_labels_hand_cases():
+    thr = math.log(0.9 / 0.1)
+    z = np.array([3.0, 3.0, 3.0, 1.0, 2.2])
+    sx = np.array([1e-6, 9e-5, 1e-6, 1e-6, 1e-6])
+    sr = np.array([1e-6, 1e-6, 3e-4, 1e-6, 1e-6])
+    # veto at 3 x (3e-5, 1e-4)
+    np.testing.assert_array_equal(O.propose(z, sx, sr, thr, 9e-5, 3e-4), [1, 0, 0, 0, 1])
+    np.testing.assert_array_equal(O.proposer_labels([0, 1, 0, 1], [0, 0, 1, 1]), [0, 1, 1, 1])
+
+
+def test_traj_features_hand_case():
+    n = 3
+    ring = np.zeros((8, 4, n))
+    for e in range(8):
+        ring[e] = 10.0 ** (-(e + 1))                   # entry e holds 10^-(e+1)
+    mean, std = np.zeros(32), np.ones(32)
+    x = O.traj_features(ring, 5, mean, std)
+    # feature 4j + q reads entry (5 - j) mod 8
+    for j in range(8):
+        e = (5 - j) % 8
+        np.testing.assert_allclose(x[:, 4 * j:4 * j + 4], O.bf16_round(np.full((n, 4), -(e + 1.0))), rtol=0)
+    x2 = O.traj_features(ring, 5, np.full(32, -4.0), np.full(32, 2.0))
+    assert (x2[:, 0] == -1.0).all()                   # (log10(1e-6) + 4) / 2
+    assert O.traj_features(np.zeros((8, 4, 1)), 0, mean, std)[0, 0] == O.bf16_round(-12.0)

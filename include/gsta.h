@@ -329,6 +329,75 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
 gsta_status gsta_opacity_reset(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gsta_params* v,
                                const uint8_t* frozen, float logit_cap, hipStream_t stream);
 
+/* ---- learned freeze proposer ---------------------------------------------
+ * A project extension (the paper has no such model), made for the callers
+ * that want Gaussians frozen earlier than the rule of Section 3.2.1 alone
+ * would: an MLP 32 -> 64 -> 64 -> 1 (ReLU, ReLU, logit) reads the last 8
+ * logged gradient-norm averages of a Gaussian and proposes it for the
+ * freeze map; the rule vetoes proposals whose averages are far above its
+ * thresholds (gsta_mlp_propose) and accepted proposals are OR-ed into the
+ * map (gsta_update_freeze_mask, `proposal`).
+ *
+ * Parameters: a flat float32 array of GSTA_MLP_PARAMS values, W1 [64][32]
+ * (offset 0), b1 [64] (2048), W2 [64][64] (2112), b2 [64] (6208), w3 [64]
+ * (6272), b3 (6336); plus a bf16 copy of W1 then W2 (GSTA_MLP_BF16 values,
+ * 16-byte aligned) that the forward reads.  The hidden layers run on bf16
+ * matrix cores with float32 accumulation; the first hidden layer is rounded
+ * to bf16 (nearest, ties to even) before the second.
+ * Trajectory ring: [8][4][n] bf16 (entry, score, Gaussian). */
+#define GSTA_MLP_PARAMS 6337
+#define GSTA_MLP_BF16 6144
+
+/* ring[slot][q][i] = bf16(min(ema[q][i], 1e30)) for the 4 averages
+ * (xyz, rgb, opacity, scale) of gsta_render_backward; slot in [0, 8). */
+gsta_status gsta_traj_push(gsta_ctx* ctx, const float* ema, int64_t n, uint16_t* ring, int32_t slot,
+                           hipStream_t stream);
+
+/* Adds to sums (device double [64]) the per-feature sum (0..31) and sum of
+ * squares (32..63) of the unstandardised features log10(r + 1e-12) of
+ * gsta_mlp_features over the n Gaussians, for standardisation statistics
+ * over a training set (call once per ring snapshot; the caller zeroes). */
+gsta_status gsta_mlp_feature_stats(gsta_ctx* ctx, const uint16_t* ring, int64_t n, int32_t head, double* sums,
+                                   hipStream_t stream);
+
+/* x [n][32] bf16: x[i][4j + q] = bf16((log10(ring[(head - j) & 7][q][i] + 1e-12)
+ * - mean[4j + q]) / std_dev[4j + q]), j = 0 the newest entry (at head).
+ * mean, std_dev: device float [32]. */
+gsta_status gsta_mlp_features(gsta_ctx* ctx, const uint16_t* ring, int64_t n, int32_t head, const float* mean,
+                              const float* std_dev, uint16_t* x, hipStream_t stream);
+
+/* logits [n] of the MLP for features x [n][32] bf16.  h1 ([n][64] bf16) and
+ * h2 ([n][64] float32) optionally receive the hidden layers for
+ * gsta_mlp_backward (NULL to skip). */
+gsta_status gsta_mlp_forward(gsta_ctx* ctx, const uint16_t* w_bf16, const float* w, const uint16_t* x, int64_t n,
+                             float* logits, uint16_t* h1, float* h2, hipStream_t stream);
+
+/* Mean binary cross-entropy of logits against labels (uint8 0/1) into loss
+ * (device double [1]) and dz[i] = (sigmoid(logits[i]) - labels[i]) / n. */
+gsta_status gsta_mlp_bce(gsta_ctx* ctx, const float* logits, const uint8_t* labels, int64_t n, float* dz,
+                         double* loss, hipStream_t stream);
+
+/* grad [GSTA_MLP_PARAMS] = gradient of sum_i dz[i] * logit_i with respect to
+ * the flat parameters, through the forward's saved h1, h2 (the bf16
+ * roundings taken as identity).  Deterministic (fixed summation order). */
+gsta_status gsta_mlp_backward(gsta_ctx* ctx, const uint16_t* w_bf16, const float* w, const uint16_t* x,
+                              const uint16_t* h1, const float* h2, const float* dz, int64_t n, float* grad,
+                              hipStream_t stream);
+
+/* Adam on the float32 parameters (bias-corrected with `step`), then the
+ * bf16 copies of W1 and W2 are refreshed. */
+gsta_status gsta_mlp_adam(gsta_ctx* ctx, float* w, const float* grad, float* m, float* v, float lr, float beta1,
+                          float beta2, float eps, int32_t step, uint16_t* w_bf16, hipStream_t stream);
+
+/* w_bf16 = bf16 copies of W1 and W2 of w (after the caller sets w). */
+gsta_status gsta_mlp_sync_bf16(gsta_ctx* ctx, const float* w, uint16_t* w_bf16, hipStream_t stream);
+
+/* proposal[i] = logits[i] > logit_threshold && score_xyz[i] < veto_xyz &&
+ * score_rgb[i] < veto_rgb (float32 comparisons). */
+gsta_status gsta_mlp_propose(gsta_ctx* ctx, const float* logits, const float* score_xyz, const float* score_rgb,
+                             int64_t n, float logit_threshold, float veto_xyz, float veto_rgb, uint8_t* proposal,
+                             hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,7 +60,11 @@ _lib = None
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
            "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
            "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
-           "gsta_densify_prune", "gsta_opacity_reset"]
+           "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
+           "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose"]
+
+MLP_PARAMS, MLP_BF16 = 6337, 6144
 
 PHASES = ["preprocess", "depth_sort", "binning", "tile_sort", "composite", "composite_bwd",
           "preprocess_bwd", "adam", "freeze", "loss", "densify"]
@@ -90,6 +94,15 @@ def load(path: str = LIB_PATH):
                                        PP, P, P, f32, P, P]
     L.gsta_densify_prune.argtypes = [P, PP, PP, PP, P, P, P, P, ctypes.POINTER(DensifyCfg), PP, PP, PP, P, P, P, P]
     L.gsta_opacity_reset.argtypes = [P, PP, PP, PP, P, f32, P]
+    L.gsta_traj_push.argtypes = [P, P, i64, P, i32, P]
+    L.gsta_mlp_feature_stats.argtypes = [P, P, i64, i32, P, P]
+    L.gsta_mlp_features.argtypes = [P, P, i64, i32, P, P, P, P]
+    L.gsta_mlp_forward.argtypes = [P, P, P, P, i64, P, P, P, P]
+    L.gsta_mlp_bce.argtypes = [P, P, P, i64, P, P, P]
+    L.gsta_mlp_backward.argtypes = [P, P, P, P, P, P, P, i64, P, P]
+    L.gsta_mlp_adam.argtypes = [P, P, P, P, P, f32, f32, f32, f32, i32, P, P]
+    L.gsta_mlp_sync_bf16.argtypes = [P, P, P, P]
+    L.gsta_mlp_propose.argtypes = [P, P, P, P, i64, f32, f32, f32, P, P]
     L.gsta_adam_masked.argtypes = [P, PP, PP, PP, PP, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
     L.gsta_update_freeze_mask.argtypes = [P, P, P, i64, f32, f32, i32, P, P, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]

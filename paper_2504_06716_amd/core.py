@@ -234,6 +234,72 @@ class Context:
                                                  _arr(frozen, (sp.n,), torch.uint8, "frozen"),
                                                  float(logit_cap), _stream(stream)))
 
+    # ---- learned freeze proposer (bf16 arrays are torch.int16 / uint16 storage) ----
+    def traj_push(self, ema, ring, slot, stream=None):
+        n = ema.shape[1]
+        check(self.h, self.L.gsta_traj_push(self.h, _arr(ema, (4, n), torch.float32, "ema"), n,
+                                             _arr(ring, (8, 4, n), torch.int16, "ring"), int(slot), _stream(stream)))
+
+    def mlp_feature_stats(self, ring, head, sums, stream=None):
+        n = ring.shape[2]
+        check(self.h, self.L.gsta_mlp_feature_stats(self.h, _arr(ring, (8, 4, n), torch.int16, "ring"), n, int(head),
+                                                     _arr(sums, (64,), torch.float64, "sums"), _stream(stream)))
+
+    def mlp_features(self, ring, head, mean, std, x, stream=None):
+        n = ring.shape[2]
+        check(self.h, self.L.gsta_mlp_features(self.h, _arr(ring, (8, 4, n), torch.int16, "ring"), n, int(head),
+                                                _arr(mean, (32,), torch.float32, "mean"),
+                                                _arr(std, (32,), torch.float32, "std"),
+                                                _arr(x, (n, 32), torch.int16, "x"), _stream(stream)))
+
+    def mlp_forward(self, w_bf16, w, x, logits, h1=None, h2=None, stream=None):
+        n = x.shape[0]
+        check(self.h, self.L.gsta_mlp_forward(self.h, _arr(w_bf16, (_lib.MLP_BF16,), torch.int16, "w_bf16"),
+                                               _arr(w, (_lib.MLP_PARAMS,), torch.float32, "w"),
+                                               _arr(x, (n, 32), torch.int16, "x"), n,
+                                               _arr(logits, (n,), torch.float32, "logits"),
+                                               _arr(h1, (n, 64), torch.int16, "h1"),
+                                               _arr(h2, (n, 64), torch.float32, "h2"), _stream(stream)))
+
+    def mlp_bce(self, logits, labels, dz, loss, stream=None):
+        n = logits.shape[0]
+        check(self.h, self.L.gsta_mlp_bce(self.h, _arr(logits, (n,), torch.float32, "logits"),
+                                           _arr(labels, (n,), torch.uint8, "labels"), n,
+                                           _arr(dz, (n,), torch.float32, "dz"),
+                                           _arr(loss, (1,), torch.float64, "loss"), _stream(stream)))
+
+    def mlp_backward(self, w_bf16, w, x, h1, h2, dz, grad, stream=None):
+        n = x.shape[0]
+        check(self.h, self.L.gsta_mlp_backward(self.h, _arr(w_bf16, (_lib.MLP_BF16,), torch.int16, "w_bf16"),
+                                                _arr(w, (_lib.MLP_PARAMS,), torch.float32, "w"),
+                                                _arr(x, (n, 32), torch.int16, "x"),
+                                                _arr(h1, (n, 64), torch.int16, "h1"),
+                                                _arr(h2, (n, 64), torch.float32, "h2"),
+                                                _arr(dz, (n,), torch.float32, "dz"), n,
+                                                _arr(grad, (_lib.MLP_PARAMS,), torch.float32, "grad"),
+                                                _stream(stream)))
+
+    def mlp_adam(self, w, grad, m, v, lr, beta1, beta2, eps, step, w_bf16, stream=None):
+        P = (_lib.MLP_PARAMS,)
+        check(self.h, self.L.gsta_mlp_adam(self.h, _arr(w, P, torch.float32, "w"), _arr(grad, P, torch.float32, "grad"),
+                                            _arr(m, P, torch.float32, "m"), _arr(v, P, torch.float32, "v"),
+                                            float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                            _arr(w_bf16, (_lib.MLP_BF16,), torch.int16, "w_bf16"),
+                                            _stream(stream)))
+
+    def mlp_sync_bf16(self, w, w_bf16, stream=None):
+        check(self.h, self.L.gsta_mlp_sync_bf16(self.h, _arr(w, (_lib.MLP_PARAMS,), torch.float32, "w"),
+                                                 _arr(w_bf16, (_lib.MLP_BF16,), torch.int16, "w_bf16"),
+                                                 _stream(stream)))
+
+    def mlp_propose(self, logits, score_xyz, score_rgb, logit_threshold, veto_xyz, veto_rgb, proposal, stream=None):
+        n = logits.shape[0]
+        check(self.h, self.L.gsta_mlp_propose(self.h, _arr(logits, (n,), torch.float32, "logits"),
+                                               _arr(score_xyz, (n,), torch.float32, "score_xyz"),
+                                               _arr(score_rgb, (n,), torch.float32, "score_rgb"), n,
+                                               float(logit_threshold), float(veto_xyz), float(veto_rgb),
+                                               _arr(proposal, (n,), torch.uint8, "proposal"), _stream(stream)))
+
     def l1_loss(self, image, target, dL_dimage, sums, stream=None):
         sh = tuple(image.shape)
         check(self.h, self.L.gsta_l1_loss(self.h, _arr(image, sh, torch.float32, "image"),

@@ -75,6 +75,8 @@ struct gsta_ctx {
     uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
     uint32_t* dens_boff = nullptr; // [3][blocks] densify block counts / offsets
     uint32_t* dens_tot = nullptr;  // [4] kept, clones, splits, overflow
+    float* mlp_part = nullptr;     // [kMlpBlocks][kMlpCount] proposer gradient partials
+    double* mlp_stats = nullptr;   // [kMlpBlocks][64] feature-statistics partials
     uint64_t* max_inst = nullptr;
     std::string err;
     // profiling
@@ -177,6 +179,8 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
+         alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
+         alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
     if (!ok) {
         free_all(ctx);
@@ -726,6 +730,105 @@ gsta_status gsta_opacity_reset(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gs
     PhaseTimer pt(ctx, GSTA_PHASE_DENSIFY, stream);
     launch_opacity_reset(g->block, g->ld, m->block, m->ld, v->block, v->ld, g->n, frozen, logit_cap, stream);
     return hip_check(ctx, hipGetLastError(), "opacity reset launch");
+}
+
+// ---- learned freeze proposer ----------------------------------------------
+
+#define GSTA_CTX_OK()                                                 \
+    do {                                                              \
+        if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;     \
+    } while (0)
+
+gsta_status gsta_traj_push(gsta_ctx* ctx, const float* ema, int64_t n, uint16_t* ring, int32_t slot,
+                           hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0 || slot < 0 || slot > 7) return fail(ctx, GSTA_ERR_INVALID, "n < 0 or slot outside [0, 8)");
+    if (n > 0 && (!ema || !ring)) return fail(ctx, GSTA_ERR_INVALID, "ema or ring is NULL");
+    launch_traj_push(ema, n, ring, slot, stream);
+    return hip_check(ctx, hipGetLastError(), "trajectory push launch");
+}
+
+gsta_status gsta_mlp_feature_stats(gsta_ctx* ctx, const uint16_t* ring, int64_t n, int32_t head, double* sums,
+                                   hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0 || head < 0 || head > 7) return fail(ctx, GSTA_ERR_INVALID, "n < 0 or head outside [0, 8)");
+    if (!sums || (n > 0 && !ring)) return fail(ctx, GSTA_ERR_INVALID, "ring or sums is NULL");
+    launch_mlp_stats(ring, n, head, ctx->mlp_stats, sums, stream);
+    return hip_check(ctx, hipGetLastError(), "feature statistics launch");
+}
+
+gsta_status gsta_mlp_features(gsta_ctx* ctx, const uint16_t* ring, int64_t n, int32_t head, const float* mean,
+                              const float* std_dev, uint16_t* x, hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0 || head < 0 || head > 7) return fail(ctx, GSTA_ERR_INVALID, "n < 0 or head outside [0, 8)");
+    if (n > 0 && (!ring || !mean || !std_dev || !x)) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    if (((uintptr_t)x & 15u) != 0) return fail(ctx, GSTA_ERR_INVALID, "x must be 16-byte aligned");
+    launch_mlp_features(ring, n, head, mean, std_dev, x, stream);
+    return hip_check(ctx, hipGetLastError(), "features launch");
+}
+
+gsta_status gsta_mlp_forward(gsta_ctx* ctx, const uint16_t* w_bf16, const float* w, const uint16_t* x, int64_t n,
+                             float* logits, uint16_t* h1, float* h2, hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0) return fail(ctx, GSTA_ERR_INVALID, "n < 0");
+    if (n > 0 && (!w_bf16 || !w || !x || !logits)) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    if ((((uintptr_t)x | (uintptr_t)w_bf16 | (uintptr_t)h1) & 15u) != 0)
+        return fail(ctx, GSTA_ERR_INVALID, "x, w_bf16 and h1 must be 16-byte aligned");
+    PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
+    launch_mlp_forward(w_bf16, w, x, n, logits, h1, h2, ctx->cus * 4, stream);
+    return hip_check(ctx, hipGetLastError(), "mlp forward launch");
+}
+
+gsta_status gsta_mlp_bce(gsta_ctx* ctx, const float* logits, const uint8_t* labels, int64_t n, float* dz,
+                         double* loss, hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 1) return fail(ctx, GSTA_ERR_INVALID, "n must be >= 1");
+    if (!logits || !labels || !dz || !loss) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    launch_mlp_bce(logits, labels, n, dz, loss, ctx->loss_part, stream);
+    return hip_check(ctx, hipGetLastError(), "bce launch");
+}
+
+gsta_status gsta_mlp_backward(gsta_ctx* ctx, const uint16_t* w_bf16, const float* w, const uint16_t* x,
+                              const uint16_t* h1, const float* h2, const float* dz, int64_t n, float* grad,
+                              hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0) return fail(ctx, GSTA_ERR_INVALID, "n < 0");
+    if (!w_bf16 || !w || !grad || (n > 0 && (!x || !h1 || !h2 || !dz)))
+        return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    launch_mlp_backward(w_bf16, w, x, h1, h2, dz, n, ctx->mlp_part, grad, stream);
+    return hip_check(ctx, hipGetLastError(), "mlp backward launch");
+}
+
+gsta_status gsta_mlp_adam(gsta_ctx* ctx, float* w, const float* grad, float* m, float* v, float lr, float beta1,
+                          float beta2, float eps, int32_t step, uint16_t* w_bf16, hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (!w || !grad || !m || !v || !w_bf16) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    if (step < 1) return fail(ctx, GSTA_ERR_INVALID, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(ctx, GSTA_ERR_INVALID, "betas must be in [0, 1) and eps >= 0");
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    launch_mlp_adam(w, grad, m, v, lr, beta1, beta2, eps, bc1, bc2, w_bf16, stream);
+    return hip_check(ctx, hipGetLastError(), "mlp adam launch");
+}
+
+gsta_status gsta_mlp_sync_bf16(gsta_ctx* ctx, const float* w, uint16_t* w_bf16, hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (!w || !w_bf16) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    launch_mlp_bf16_copy(w, w_bf16, stream);
+    return hip_check(ctx, hipGetLastError(), "bf16 copy launch");
+}
+
+gsta_status gsta_mlp_propose(gsta_ctx* ctx, const float* logits, const float* score_xyz, const float* score_rgb,
+                             int64_t n, float logit_threshold, float veto_xyz, float veto_rgb, uint8_t* proposal,
+                             hipStream_t stream) {
+    GSTA_CTX_OK();
+    if (n < 0) return fail(ctx, GSTA_ERR_INVALID, "n < 0");
+    if (n > 0 && (!logits || !score_xyz || !score_rgb || !proposal))
+        return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
+    launch_mlp_propose(logits, score_xyz, score_rgb, n, logit_threshold, veto_xyz, veto_rgb, proposal, stream);
+    return hip_check(ctx, hipGetLastError(), "propose launch");
 }
 
 gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,

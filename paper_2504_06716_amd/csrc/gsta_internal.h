@@ -220,8 +220,29 @@ void launch_densify(const DensIO& io, const DensCfg& cfg, uint8_t* code, uint32_
                     int64_t* counts, uint32_t* flags, hipStream_t s);
 void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
                           const uint8_t* frozen, float cap, hipStream_t s);
+// Learned freeze proposer: flat float32 parameters W1 [64][32], b1 [64],
+// W2 [64][64], b2 [64], w3 [64], b3; bf16 copies of W1 then W2.
+constexpr int kMlpW1 = 0, kMlpB1 = 2048, kMlpW2 = 2112, kMlpB2 = 6208, kMlpW3 = 6272, kMlpB3 = 6336;
+constexpr int kMlpCount = 6337;
+constexpr int kMlpBf16 = 2048 + 4096;
+constexpr int kMlpBlocks = 256;   // fixed grid of the reductions (deterministic partial sums)
+void launch_traj_push(const float* ema, int64_t n, uint16_t* ring, int slot, hipStream_t s);
+void launch_mlp_stats(const uint16_t* ring, int64_t n, int head, double* part, double* sums, hipStream_t s);
+void launch_mlp_features(const uint16_t* ring, int64_t n, int head, const float* mean, const float* stdv,
+                         uint16_t* x, hipStream_t s);
+void launch_mlp_forward(const uint16_t* wb, const float* wf, const uint16_t* x, int64_t n, float* logits,
+                        uint16_t* h1, float* h2, int blocks, hipStream_t s);
+void launch_mlp_backward(const uint16_t* wb, const float* wf, const uint16_t* x, const uint16_t* h1, const float* h2,
+                         const float* dz, int64_t n, float* part, float* grad, hipStream_t s);
+void launch_mlp_adam(float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps, float bc1,
+                     float bc2, uint16_t* wb, hipStream_t s);
+void launch_mlp_bf16_copy(const float* w, uint16_t* wb, hipStream_t s);
+void launch_mlp_propose(const float* z, const float* sx, const float* sr, int64_t n, float thr, float vx, float vr,
+                        uint8_t* prop, hipStream_t s);
 constexpr int kL1Blocks = 1024;   // partial sums of the loss (fixed-order second pass)
 void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums, double2* part,
                hipStream_t s);
+void launch_mlp_bce(const float* z, const uint8_t* y, int64_t n, float* dz, double* loss, double2* part,
+                    hipStream_t s);
 
 }  // namespace gsta

@@ -50,6 +50,9 @@ class TrainConfig:
     views_per_step: int = 1              # V_b views rendered per library call; the loss averages them
     densify: DensifySchedule | None = None   # adaptive densification (the number of Gaussians changes)
     max_gaussians: int | None = None     # capacity of the parameter blocks (default: the initial count)
+    traj_every: int = 0                  # push the gradient-norm averages to the 8-deep ring every k iterations
+    proposer: object | None = None       # learned freeze proposer (proposer.Proposer), needs traj_every
+    dataset: object | None = None        # proposer.ProposerDataset to record the rule's decisions into
 
 
 class Trainer:
@@ -112,6 +115,15 @@ class Trainer:
             self.sched = adam_sched_tensor(1, cfg.beta1, cfg.beta2, cfg.adam_eps, l.rows(0, degree),
                                            l.extent * l.pos_init, l.extent * l.pos_final, l.decay_iters)
         self.graphs: dict[int, torch.cuda.CUDAGraph] = {}
+        self.traj = None
+        if cfg.traj_every:
+            if cfg.densify is not None:
+                raise ValueError("the trajectory ring does not follow densification")
+            from .proposer import TrajectoryLog
+            self.traj = TrajectoryLog(self.ctx, self.n, cfg.traj_every)
+        elif cfg.proposer is not None or cfg.dataset is not None:
+            raise ValueError("the proposer and its dataset need traj_every > 0")
+        self.prop_buf = torch.zeros(self.n, dtype=torch.uint8, device="cuda") if cfg.proposer is not None else None
 
     def _bind(self, n: int):
         """Point the working views at the first n columns of the current set."""
@@ -170,7 +182,13 @@ class Trainer:
             return
         if act == UPDATE:
             ex, er = s.thresholds(k, s.window_close(self.stop_iter))
-            self.ctx.update_freeze_mask(self.ema[0], self.ema[1], ex, er, 0, self.frozen, n_frozen=self.n_frozen)
+            prop = None
+            if self.cfg.dataset is not None:
+                self.cfg.dataset.record(self.traj, self.ema, ex, er)
+            if self.cfg.proposer is not None:
+                prop = self.cfg.proposer.propose(self.traj.ring, self.traj.head, self.ema, ex, er, self.prop_buf)
+            self.ctx.update_freeze_mask(self.ema[0], self.ema[1], ex, er, 0, self.frozen, proposal=prop,
+                                        n_frozen=self.n_frozen)
         elif act == RESET:
             self.ctx.update_freeze_mask(None, None, 0.0, 0.0, 1, self.frozen, n_frozen=self.n_frozen)
         i = len(self.frozen_log)
@@ -213,6 +231,8 @@ class Trainer:
         k = self.k
         cfg = self.cfg
         self._densify_step(k)
+        if self.traj is not None:
+            self.traj.maybe_push(k, self.ema)
         self._freeze_step(k)
         vb = cfg.views_per_step
         if vb == 1:

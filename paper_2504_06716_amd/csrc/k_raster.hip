@@ -183,9 +183,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         // Each lane leaves the walk as soon as its pixels are done; the
         // exponential and the accumulation run under the lanes' own
         // membership tests.
-        // Two splats per step: their exponentials are independent, so the
-        // second one's evaluation overlaps the first one's update of the
-        // transmittance; the updates themselves stay in list order.
+        // Two splats per step, both evaluated unconditionally so that their
+        // exponentials overlap; the transmittance then advances through them
+        // in list order with selects (the same operations on the same values
+        // as one splat at a time), and one branch adds the colour.
         for (int k = 0; k < cnt && !alldone; k += 2) {
             const uint32_t pos = base - rg.x + (uint32_t)k;     // even: segment boundaries fall here
             if (!QUAD && pos != 0u && (pos & kmask) == 0u) fwd_checkpoint<W, P>(sc, base + (uint32_t)k, tid, done, T, C);
@@ -201,38 +202,28 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                     SplatEval e0, e1;
                     eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
                     eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
-                    ++evals;
-                    if (e0.power >= kPowerFloor && e0.alpha >= kAlphaMin) {
-                        const float Tn = next_T(T[p], e0.alpha);
-                        if (Tn < kTMin) {
-                            done[p] = true;
-                        } else {
-                            const float4 c = s_rgb[k];
-                            const double w = (double)(e0.alpha * T[p]);
-                            C[p][0] = fma((double)c.x, w, C[p][0]);
-                            C[p][1] = fma((double)c.y, w, C[p][1]);
-                            C[p][2] = fma((double)c.z, w, C[p][2]);
-                            T[p] = Tn;
-                            last[p] = pos + 1u;
-                        }
+                    const bool m0 = e0.power >= kPowerFloor && e0.alpha >= kAlphaMin;
+                    const bool m1 = two && e1.power >= kPowerFloor && e1.alpha >= kAlphaMin;
+                    const float T0 = T[p];
+                    const float Tn0 = next_T(T0, e0.alpha);
+                    const bool t0 = m0 && Tn0 < kTMin;
+                    const bool c0 = m0 && !t0;
+                    const float T1 = c0 ? Tn0 : T0;
+                    const float Tn1 = next_T(T1, e1.alpha);
+                    const bool t1 = !t0 && m1 && Tn1 < kTMin;
+                    const bool c1 = !t0 && m1 && !t1;
+                    if (c0 || c1) {
+                        const float4 ca = s_rgb[k], cb = s_rgb[k1];
+                        const double w0 = c0 ? (double)(e0.alpha * T0) : 0.0;
+                        const double w1 = c1 ? (double)(e1.alpha * T1) : 0.0;
+                        C[p][0] = fma((double)cb.x, w1, fma((double)ca.x, w0, C[p][0]));
+                        C[p][1] = fma((double)cb.y, w1, fma((double)ca.y, w0, C[p][1]));
+                        C[p][2] = fma((double)cb.z, w1, fma((double)ca.z, w0, C[p][2]));
+                        last[p] = c1 ? pos + 2u : pos + 1u;
                     }
-                    if (two && !done[p]) {
-                        ++evals;
-                        if (e1.power >= kPowerFloor && e1.alpha >= kAlphaMin) {
-                            const float Tn = next_T(T[p], e1.alpha);
-                            if (Tn < kTMin) {
-                                done[p] = true;
-                            } else {
-                                const float4 c = s_rgb[k1];
-                                const double w = (double)(e1.alpha * T[p]);
-                                C[p][0] = fma((double)c.x, w, C[p][0]);
-                                C[p][1] = fma((double)c.y, w, C[p][1]);
-                                C[p][2] = fma((double)c.z, w, C[p][2]);
-                                T[p] = Tn;
-                                last[p] = pos + 2u;
-                            }
-                        }
-                    }
+                    T[p] = c1 ? Tn1 : T1;
+                    done[p] = t0 || t1;
+                    evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
                 }
                 all = all && done[p];
             }

@@ -160,10 +160,12 @@ typedef enum {
  * compositing kernels of enabled phases count the (pixel, splat) pairs they
  * evaluate.  gsta_read_profile synchronises,
  * writes per-phase totals since the last read -- ms[GSTA_N_PHASES] elapsed
- * time, launches[GSTA_N_PHASES] -- and counters[5] = (pixel, splat) pairs
+ * time, launches[GSTA_N_PHASES] -- and counters[6] = (pixel, splat) pairs
  * evaluated by the forward and by the backward compositing, wave-level splat
- * iterations of the forward and of the backward, and wave reductions of the
- * backward (all host arrays, each may be NULL), then resets the totals. */
+ * iterations of the forward and of the backward, per-wave splat reductions
+ * of the backward, and (pixel, splat) pairs of the backward that did
+ * gradient work (all host arrays, each may be NULL), then resets the
+ * totals. */
 gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask);
 gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* counters);
 

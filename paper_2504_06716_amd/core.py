@@ -149,10 +149,11 @@ class Context:
 
     def read_profile(self):
         """Per-phase {name: (total ms, launches)} and counters (fwd pairs, bwd pairs,
-        fwd wave iterations, bwd wave iterations, bwd wave reductions) since the last read."""
+        fwd wave iterations, bwd wave iterations, bwd splat reductions, bwd pairs
+        with gradient work) since the last read."""
         ms = (ctypes.c_double * len(_lib.PHASES))()
         ln = (ctypes.c_int64 * len(_lib.PHASES))()
-        pr = (ctypes.c_int64 * 5)()
+        pr = (ctypes.c_int64 * 6)()
         check(self.h, self.L.gsta_read_profile(self.h, ms, ln, pr))
         return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, tuple(pr)
 

@@ -15,7 +15,7 @@ using namespace gsta;
 
 namespace {
 
-constexpr int kCounters = 5;   // profiling counters, see gsta_read_profile
+constexpr int kCounters = 6;   // profiling counters, see gsta_read_profile
 
 struct Slot {
     float4* geo = nullptr;

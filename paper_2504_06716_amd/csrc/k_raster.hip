@@ -15,9 +15,10 @@
 // membership and termination decision is identical.  The colour behind a
 // member is the forward colour minus the recomputed prefix (both double).
 // Frozen splats still attenuate the pixels behind them but get no gradient
-// work.  Per splat, a thread sums its pixels' 9 partial derivatives, the
-// wave sums its lanes with DPP row operations, the waves of the tile are
-// added in a fixed order, and the tile's total is written to the splat's own
+// work.  Per splat, a thread sums its pixels' 9 partial derivatives, each
+// row of 16 lanes sums them with DPP operations, the rows' totals (4 per
+// wave) are added through LDS in a fixed order every 64 splats, and the
+// tile's total is written to the splat's own
 // slot (its position in the depth-ordered expansion) -- no atomics, so the
 // backward is deterministic.  The per-Gaussian sum over tiles happens in the
 // preprocess backward, in a fixed order too.
@@ -26,21 +27,17 @@
 namespace gsta {
 namespace {
 
-// Sum over the 64 lanes of a wave with DPP row operations; the total lands
-// in lane 63.  Every lane must be active.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
+// Sum over each row of 16 lanes with DPP (pairs, quads, then rotations by
+// 4 and 8 within the row); every lane of a row holds its row's total.
+__device__ __forceinline__ float row_sum(float v) {
     int x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));  // row_ror:8
-    x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
     return v;
 }
 
@@ -319,16 +316,19 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     __shared__ float4 s_rgb[B];
     __shared__ uint32_t s_idx[B];
     __shared__ uint32_t s_frz[B];
-    __shared__ float s_part[W][9][kChunk];
-    __shared__ unsigned int s_pairs;
+    __shared__ float s_part[4 * W][9][kChunk];
+    __shared__ unsigned int s_pairs, s_grad;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
     const int nt = nv * tiles;
     const uint32_t n_items = sc.item_off[nt];
     const bool seg = sc.shift < 31u;
-    uint32_t evals = 0, witer = 0, wred = 0;
-    if (tid == 0) s_pairs = 0;
+    uint32_t evals = 0, witer = 0, wred = 0, ngrad = 0;
+    if (tid == 0) {
+        s_pairs = 0;
+        s_grad = 0;
+    }
 
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         // the item's tile: the last gt with item_off[gt] <= item
@@ -477,6 +477,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             A[p][2] = fma((double)c.z, wd, A[p][2]);
                             if (!frz) {
                                 contrib = true;
+                                ++ngrad;
                                 const float inv1m = __builtin_amdgcn_rcpf(1.0f - e[p].alpha);
                                 const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
                                 const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
@@ -502,27 +503,21 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                         if (!frz && __ballot(contrib) != 0ull) {
                             wred += 1u;
 #pragma unroll
-                            for (int q = 0; q < 9; ++q) g9[q] = wave_sum_to_last(g9[q]);
-                            if (lane == 63) {
-                                if (W == 1) {
-                                    float* dst = partials + (int64_t)s_idx[k] * 9;
+                            for (int q = 0; q < 9; ++q) g9[q] = row_sum(g9[q]);
+                            if ((lane & 15) == 0) {
 #pragma unroll
-                                    for (int q = 0; q < 9; ++q) dst[q] = g9[q];
-                                } else {
-#pragma unroll
-                                    for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = g9[q];
-                                }
+                                for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = g9[q];
                             }
                             continue;
                         }
                     }
-                    if (W > 1 && lane == 63) {
+                    if ((lane & 15) == 0) {
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) s_part[wid][q][k - c0] = 0.f;
+                        for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = 0.f;
                     }
                 }
-                if (W > 1) {
-                    // the waves' totals added in a fixed order
+                {
+                    // the rows' totals added in a fixed order
                     __syncthreads();
                     if (tid < c1 - c0) {
                         const int k = c0 + tid;
@@ -533,7 +528,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             for (int q = 0; q < 9; ++q) {
                                 float acc = s_part[0][q][tid];
 #pragma unroll
-                                for (int w = 1; w < W; ++w) acc += s_part[w][q][tid];
+                                for (int w = 1; w < 4 * W; ++w) acc += s_part[w][q][tid];
                                 sum[q] = acc;
                                 nz = nz || (acc != 0.f);
                             }
@@ -552,8 +547,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     if (pairs) {
         __syncthreads();
         if (evals) atomicAdd(&s_pairs, evals);
+        if (ngrad) atomicAdd(&s_grad, ngrad);
         __syncthreads();
         if (tid == 0 && s_pairs) atomicAdd(pairs + 1, (unsigned long long)s_pairs);
+        if (tid == 0 && s_grad) atomicAdd(pairs + 5, (unsigned long long)s_grad);
         if ((tid & 63) == 0 && witer) atomicAdd(pairs + 3, (unsigned long long)witer);
         if ((tid & 63) == 0 && wred) atomicAdd(pairs + 4, (unsigned long long)wred);
     }

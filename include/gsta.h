@@ -166,6 +166,7 @@ typedef enum {
  * of the backward, and (pixel, splat) pairs of the backward that did
  * gradient work (all host arrays, each may be NULL), then resets the
  * totals. */
+#define GSTA_PROFILE_COUNTERS (1 << 30)   /* phase_mask bit: also count pairs (slower kernels) */
 gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask);
 gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int64_t* counters);
 

@@ -65,6 +65,7 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_mlp_sync_bf16", "gsta_mlp_propose"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
+PROFILE_COUNTERS = 1 << 30
 
 PHASES = ["preprocess", "depth_sort", "binning", "tile_sort", "composite", "composite_bwd",
           "preprocess_bwd", "adam", "freeze", "loss", "densify"]

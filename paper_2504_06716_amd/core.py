@@ -137,14 +137,17 @@ class Context:
         if bwd is not None:
             self.set_option(_lib.OPT_BWD_WAVES, bwd)
 
-    def set_profiling(self, phases=None):
-        """Enable event timing for the named phases (all if None; [] disables)."""
+    def set_profiling(self, phases=None, counters=False):
+        """Enable event timing for the named phases (all if None; [] disables);
+        `counters` also runs the compositing kernels' counting variants."""
         if phases is None:
             mask = (1 << len(_lib.PHASES)) - 1
         else:
             mask = 0
             for p in phases:
                 mask |= 1 << _lib.PHASES.index(p)
+        if counters:
+            mask |= _lib.PROFILE_COUNTERS
         check(self.h, self.L.gsta_set_profiling(self.h, mask))
 
     def read_profile(self):

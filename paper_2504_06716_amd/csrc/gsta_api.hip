@@ -192,6 +192,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         ctx->cus = 1;
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ctx->tile_grads, 0, (size_t)(9 * cap + 4) * sizeof(float)) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
         hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -309,7 +310,7 @@ struct PhaseTimer {
 // its own fixed entries), or NULL when the phase is not profiled.
 unsigned long long* pair_counter(gsta_ctx* ctx, int which) {
     const int phase = which == 0 ? GSTA_PHASE_COMPOSITE : GSTA_PHASE_COMPOSITE_BWD;
-    return (ctx->profiling & (1u << phase)) ? ctx->pairs : nullptr;
+    return ((ctx->profiling & (1u << phase)) && (ctx->profiling & GSTA_PROFILE_COUNTERS)) ? ctx->pairs : nullptr;
 }
 
 }  // namespace
@@ -395,7 +396,7 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
 
 gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
-    ctx->profiling = (uint32_t)phase_mask & ((1u << GSTA_N_PHASES) - 1u);
+    ctx->profiling = (uint32_t)phase_mask & (((1u << GSTA_N_PHASES) - 1u) | GSTA_PROFILE_COUNTERS);
     return GSTA_OK;
 }
 
@@ -593,6 +594,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
                               s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d, dstats, stream);
+        launch_zero_partials(ctx->tile_grads, s.n_count, stream);   // ready for the next backward
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }

@@ -164,6 +164,11 @@ struct SegCkpt {
 // 2-D gradient into partials[expansion index][9] (zeroed first), without
 // atomics; it is a persistent kernel of `blocks` workgroups over the
 // (tile, segment) items.
+// The backward writes the non-zero per-tile totals into slots that are zero
+// on entry: launch_zero_partials clears the first d_count * 9 values after
+// the preprocess backward has read them (and the context clears them once
+// when it allocates them).
+void launch_zero_partials(float* partials, const uint32_t* d_count, hipStream_t s);
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,

@@ -299,6 +299,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
         for (int k = 0; k < 9; ++k) d2[k] = 0.f;
         {
+            // per-tile totals, summed in tile order
             const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
             const uint64_t j0 = inst_off[o_idx];
             if (j0 + cnt <= (uint64_t)(*d_count)) {
@@ -480,7 +481,8 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
                            const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, grad2d_out, dstats
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, \
+                      grad2d_out, dstats
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -105,7 +105,7 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
     }
 }
 
-template <int W, bool QUAD>
+template <int W, bool QUAD, bool CNT>
 __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             const float4 g0 = s_geo[k], g1 = s_geo[k1];
             const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
             bool all = true;
-            witer += two ? 2u : 1u;
+            if (CNT) witer += two ? 2u : 1u;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!done[p]) {
@@ -220,14 +220,14 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                     }
                     T[p] = c1 ? Tn1 : T1;
                     done[p] = t0 || t1;
-                    evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
+                    if (CNT) evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
                 }
                 all = all && done[p];
             }
             alldone = all;
         }
     }
-    if (pairs) {
+    if (CNT) {
         __syncthreads();
         if (evals) atomicAdd(&s_pairs, evals);
         __syncthreads();
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
     if (threadIdx.x == 0) item_off[nt] = s_carry;
 }
 
-template <int W>
+template <int W, bool CNT>
 __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
@@ -447,14 +447,14 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                     const float2 co = make_float2(s_co[k].x, s_co[k].y);
                     // uniform over the wave: a scalar branch
                     const bool frz = __builtin_amdgcn_readfirstlane(s_frz[k]) != 0u;
-                    witer += 1u;
+                    if (CNT) witer += 1u;
                     SplatEval e[P];
                     bool mem[P];
                     bool any = false;
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const bool act = pos < last[p];
-                        evals += act ? 1u : 0u;
+                        if (CNT) evals += act ? 1u : 0u;
                         eval_power(g.x, g.y, g.z, g.w, co.x, fpx[p], fpy[p], e[p]);
                         mem[p] = act && (e[p].power >= kPowerFloor);
                         any = any || mem[p];
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             A[p][2] = fma((double)c.z, wd, A[p][2]);
                             if (!frz) {
                                 contrib = true;
-                                ++ngrad;
+                                if (CNT) ++ngrad;
                                 const float inv1m = __builtin_amdgcn_rcpf(1.0f - e[p].alpha);
                                 const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
                                 const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             T[p] = next_T(T[p], e[p].alpha);
                         }
                         if (!frz && __ballot(contrib) != 0ull) {
-                            wred += 1u;
+                            if (CNT) wred += 1u;
 #pragma unroll
                             for (int q = 0; q < 9; ++q) g9[q] = row_sum(g9[q]);
                             if ((lane & 15) == 0) {
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                                 sum[q] = acc;
                                 nz = nz || (acc != 0.f);
                             }
-                            if (nz) {
+                            if (nz) {   // slots are zero on entry
                                 float* dst = partials + (int64_t)s_idx[k] * 9;
 #pragma unroll
                                 for (int q = 0; q < 9; ++q) dst[q] = sum[q];
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
             }
         }
     }
-    if (pairs) {
+    if (CNT) {
         __syncthreads();
         if (evals) atomicAdd(&s_pairs, evals);
         if (ngrad) atomicAdd(&s_grad, ngrad);
@@ -554,6 +554,77 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
         if ((tid & 63) == 0 && witer) atomicAdd(pairs + 3, (unsigned long long)witer);
         if ((tid & 63) == 0 && wred) atomicAdd(pairs + 4, (unsigned long long)wred);
     }
+}
+
+
+}  // namespace
+
+template <bool CNT>
+void fwd_launch(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid, const float4* geo,
+                const float4* col, const float4* rgb, int64_t stride, const CamArray& cams, int nv, float bg0,
+                float bg1, float bg2, float* image, float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc,
+                unsigned long long* pairs, hipStream_t s) {
+    const int tiles = cams.c[0].ntx * cams.c[0].nty;
+#define GSTA_FWD_ARGS ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2, image, T_final, last, cfg, sc, pairs
+    if (waves == 0)   // one independent wave per 8x8 quarter of each tile
+        k_composite_fwd<1, true, CNT><<<dim3(4 * tiles, nv), 64, 0, s>>>(GSTA_FWD_ARGS);
+    else if (waves == 1)
+        k_composite_fwd<1, false, CNT><<<dim3(tiles, nv), 64, 0, s>>>(GSTA_FWD_ARGS);
+    else if (waves == 2)
+        k_composite_fwd<2, false, CNT><<<dim3(tiles, nv), 128, 0, s>>>(GSTA_FWD_ARGS);
+    else
+        k_composite_fwd<4, false, CNT><<<dim3(tiles, nv), 256, 0, s>>>(GSTA_FWD_ARGS);
+#undef GSTA_FWD_ARGS
+}
+
+template <bool CNT>
+void bwd_launch(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                const float4* geo, const float4* col, const float4* rgb, int64_t stride, const uint8_t* frozen,
+                const CamArray& cams, int nv, float bg0, float bg1, float bg2, const float* T_final,
+                const uint32_t* last, const double* cfg, const float* dL_dimage, float* partials, const SegCkpt& sc,
+                unsigned long long* pairs, hipStream_t s) {
+#define GSTA_BWD_ARGS ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2, T_final, last, \
+                      cfg, dL_dimage, partials, sc, pairs
+    if (waves == 1)
+        k_composite_bwd<1, CNT><<<blocks, 64, 0, s>>>(GSTA_BWD_ARGS);
+    else if (waves == 2)
+        k_composite_bwd<2, CNT><<<blocks, 128, 0, s>>>(GSTA_BWD_ARGS);
+    else
+        k_composite_bwd<4, CNT><<<blocks, 256, 0, s>>>(GSTA_BWD_ARGS);
+#undef GSTA_BWD_ARGS
+}
+
+void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
+                          float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s) {
+    const int tiles = cams.c[0].ntx * cams.c[0].nty;
+    launch_fill_u32(sc.tile_last, 0u, (int64_t)tiles * nv, s);
+    launch_fill_u32(sc.ctr, 0u, 1, s);
+    if (pairs)
+        fwd_launch<true>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
+                         last, cfg, sc, pairs, s);
+    else
+        fwd_launch<false>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
+                          last, cfg, sc, pairs, s);
+    // the backward's work items: ceil(tile_last / K) per tile
+    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off);
+}
+
+void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                          const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
+                          const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
+                          float* partials, const uint32_t* d_count, const SegCkpt& sc, unsigned long long* pairs,
+                          hipStream_t s) {
+    (void)d_count;
+    if (pairs)
+        bwd_launch<true>(waves, blocks, ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2,
+                         T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
+    else
+        bwd_launch<false>(waves, blocks, ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1,
+                          bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
 }
 
 __global__ void k_zero_partials(float* __restrict__ p, const uint32_t* __restrict__ d_count) {
@@ -566,64 +637,19 @@ __global__ void k_zero_partials(float* __restrict__ p, const uint32_t* __restric
     if (t < n) p[t] = 0.f;
 }
 
-}  // namespace
-
-void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
-                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
-                          const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
-                          float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
-                          hipStream_t s) {
-    const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    launch_fill_u32(sc.tile_last, 0u, (int64_t)tiles * nv, s);
-    launch_fill_u32(sc.ctr, 0u, 1, s);
-    if (waves == 0) {   // one independent wave per 8x8 quarter of each tile
-        k_composite_fwd<1, true><<<dim3(4 * tiles, nv), 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride,
-                                                                     cams, bg0, bg1, bg2, image, T_final, last, cfg,
-                                                                     sc, pairs);
-        return;
-    }
-    const dim3 grid(tiles, nv);
-    if (waves == 1)
-        k_composite_fwd<1, false><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                       bg2, image, T_final, last, cfg, sc, pairs);
-    else if (waves == 2)
-        k_composite_fwd<2, false><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                        bg2, image, T_final, last, cfg, sc, pairs);
-    else
-        k_composite_fwd<4, false><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1,
-                                                        bg2, image, T_final, last, cfg, sc, pairs);
-}
-
-void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
-                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
-                          const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
-                          const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
-                          float* partials, const uint32_t* d_count, const SegCkpt& sc, unsigned long long* pairs,
-                          hipStream_t s) {
+void launch_zero_partials(float* partials, const uint32_t* d_count, hipStream_t s) {
     k_zero_partials<<<2048, 256, 0, s>>>(partials, d_count);
-    const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off);
-    const dim3 grid((unsigned)blocks);
-    if (waves == 1)
-        k_composite_bwd<1><<<grid, 64, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
-                                                bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
-    else if (waves == 2)
-        k_composite_bwd<2><<<grid, 128, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
-                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
-    else
-        k_composite_bwd<4><<<grid, 256, 0, s>>>(ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0,
-                                                 bg1, bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs);
 }
 
 int composite_bwd_blocks_per_cu(int waves) {
     int nb = 0;
     hipError_t e;
     if (waves == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<1>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<1, false>, 64, 0);
     else if (waves == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<2>, 128, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<2, false>, 128, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<4>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_composite_bwd<4, false>, 256, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
-FLOP_PER_PAIR = 15             # arithmetic of one (pixel, splat) evaluation, see the design doc
+FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quadratic form, exp, o*G, min
 # Initial freeze thresholds of this workload, from the one-time calibration
 # rule of paper_2504_06716_amd/calibrate.py (`python bench.py --calibrate 0.4`):
 # the positive gradient-norm averages at the start of the freeze window of a
@@ -34,7 +34,7 @@ FLOP_PER_PAIR = 15             # arithmetic of one (pixel, splat) evaluation, se
 # 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
 C2_EPS0 = (1.0148724677013602e-06, 2.5171187707272975e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 128   # launch shape (the library defaults)
-FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a contributing pair, see the design doc
+FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)
 
 
 def c2_setup(torch):

@@ -170,7 +170,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.ck_pool, (int64_t)pool_cap * 256) && alloc(ctx, &s.ck_ctr, 1) &&
              alloc(ctx, &s.tile_last, V * ctx->tiles_max) && alloc(ctx, &s.item_off, V * ctx->tiles_max + 1);
     }
-    ctx->items_depth = S <= (1 << 20) ? 4 : 16;
+    ctx->items_depth = S <= (1 << 20) ? 1 : 16;
     ctx->items_inst = cap <= (1 << 20) ? 4 : 16;
     ctx->chunks_depth = radix_chunks(S, ctx->items_depth);
     ctx->chunks_inst = radix_chunks(cap, ctx->items_inst);

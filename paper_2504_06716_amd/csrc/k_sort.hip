@@ -9,12 +9,14 @@
 //      radix sort of those 16-bit-or-less tile keys.  Stability keeps the
 //      depth order inside every tile.
 //
-// Radix sort: 8-bit digits, chunks of 4096 keys per workgroup iteration.
+// Radix sort: 8-bit digits, chunks of 256, 1024 or 4096 keys per workgroup
+// iteration (small, mid-size and large sorts).
 //   hist    per-chunk digit counts -> hist[seg][digit][chunk]
 //   scan    one workgroup per (digit, seg) scans its chunk counts
-//   scatter per chunk: stable local ranks from wave ballots (multi-split),
-//           keys staged in LDS in digit order, then written out with
-//           consecutive lanes hitting consecutive addresses.
+//   scatter per chunk: each wave ranks its contiguous quarter stably with
+//           ballots and its own LDS digit counters (no block barrier per
+//           item), keys are staged in LDS in digit order, then written out
+//           with consecutive lanes hitting consecutive addresses.
 // Counts may live on the device (the instance count is only known there):
 // kernels then run a grid-stride loop over the chunks that exist.
 #include "gsta_internal.h"
@@ -111,13 +113,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     int bits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot,
     int64_t nchunks_cap) {
     constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
+    constexpr int WSPAN = 64 * RS_ITEMS;           // keys of one wave in a chunk
     __shared__ uint32_t s_keys[RS_CHUNK];
     __shared__ uint32_t s_vals[RS_CHUNK];
     __shared__ uint32_t s_digit_base[RS_BINS];
-    __shared__ uint32_t s_wave_cnt[RS_WAVES][RS_BINS];
-    __shared__ uint32_t s_wave_off[RS_WAVES][RS_BINS];
-    __shared__ uint32_t s_run[RS_BINS];
+    __shared__ uint32_t s_cnt[RS_WAVES][RS_BINS];
     __shared__ uint32_t s_local_start[RS_BINS];
+    __shared__ uint32_t s_gbase[RS_BINS];
     __shared__ uint32_t s_tmp[RS_WAVES];
 
     const int seg = blockIdx.y;
@@ -139,60 +141,62 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         const int64_t base = chunk * RS_CHUNK;
         const int n_valid = (int)min((int64_t)RS_CHUNK, (int64_t)count - base);
+        // wave w takes the keys [w * WSPAN, (w + 1) * WSPAN) of the chunk, item by item
         uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
 #pragma unroll
         for (int it = 0; it < RS_ITEMS; ++it) {
-            int j = it * RS_THREADS + tid;
-            bool ok = j < n_valid;
+            const int j = wid * WSPAN + it * 64 + lane;
+            const bool ok = j < n_valid;
             key[it] = ok ? ki[base + j] : 0u;
             val[it] = ok ? vi[base + j] : 0u;
         }
-        s_run[tid] = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) s_wave_cnt[w][tid] = 0;
+        for (int w = 0; w < RS_WAVES; ++w) s_cnt[w][tid] = 0;
         __syncthreads();
 
-        // Stable local ranks: items are taken in index order j = it*256 + tid,
-        // i.e. round by round, wave by wave, lane by lane.
+        // Stable ranks inside the wave: lanes with the same digit found by
+        // ballots; the wave's running count per digit lives in LDS (the
+        // wave's own reads precede its own writes, so no barrier is needed).
 #pragma unroll
         for (int it = 0; it < RS_ITEMS; ++it) {
-            const int j = it * RS_THREADS + tid;
+            const int j = wid * WSPAN + it * 64 + lane;
             const bool ok = j < n_valid;
             const uint32_t d = (key[it] >> shift) & 0xFFu;
             uint64_t match = __ballot(ok);
             for (int b = 0; b < bits; ++b) {
-                uint64_t bal = __ballot(ok && ((d >> b) & 1u));
+                const uint64_t bal = __ballot(ok && ((d >> b) & 1u));
                 match &= ((d >> b) & 1u) ? bal : ~bal;
             }
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(match >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)match, 0u));
-            if (ok && below == 0) s_wave_cnt[wid][d] = (uint32_t)__popcll(match);
-            __syncthreads();
-            {
-                uint32_t r = s_run[tid];
-#pragma unroll
-                for (int w = 0; w < RS_WAVES; ++w) {
-                    s_wave_off[w][tid] = r;
-                    r += s_wave_cnt[w][tid];
-                    s_wave_cnt[w][tid] = 0;
-                }
-                s_run[tid] = r;
-            }
-            __syncthreads();
-            rank[it] = ok ? s_wave_off[wid][d] + below : 0u;
+            const uint32_t before = ok ? s_cnt[wid][d] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (ok && below == 0) s_cnt[wid][d] = before + (uint32_t)__popcll(match);
+            __builtin_amdgcn_wave_barrier();
+            rank[it] = before + below;
         }
-
-        {   // chunk-local start of each digit
+        __syncthreads();
+        uint32_t dtot = 0;
+        {   // per digit: offsets of the waves, then the chunk-local start
+#pragma unroll
+            for (int w = 0; w < RS_WAVES; ++w) {
+                const uint32_t c = s_cnt[w][tid];
+                s_cnt[w][tid] = dtot;
+                dtot += c;
+            }
             uint32_t tot;
-            s_local_start[tid] = block_excl_scan_256(s_run[tid], s_tmp, tot);
+            const uint32_t ls = block_excl_scan_256(dtot, s_tmp, tot);
+            s_local_start[tid] = ls;
+            // global position of the chunk's first key of digit tid, minus its local start
+            s_gbase[tid] = s_digit_base[tid] + hrow[(int64_t)tid * nchunks_cap + chunk] - ls;
         }
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < RS_ITEMS; ++it) {
-            const int j = it * RS_THREADS + tid;
+            const int j = wid * WSPAN + it * 64 + lane;
             if (j < n_valid) {
                 const uint32_t d = (key[it] >> shift) & 0xFFu;
-                const uint32_t pos = s_local_start[d] + rank[it];
+                const uint32_t pos = s_local_start[d] + s_cnt[wid][d] + rank[it];
                 if (pos < (uint32_t)RS_CHUNK) {
                     s_keys[pos] = key[it];
                     s_vals[pos] = val[it];
@@ -205,9 +209,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
             const int p = it * RS_THREADS + tid;
             if (p < n_valid) {
                 const uint32_t k = s_keys[p];
-                const uint32_t d = (k >> shift) & 0xFFu;
-                const uint32_t g = s_digit_base[d] + hrow[(int64_t)d * nchunks_cap + chunk] +
-                                   ((uint32_t)p - s_local_start[d]);
+                const uint32_t g = s_gbase[(k >> shift) & 0xFFu] + (uint32_t)p;
                 if (g < count) {
                     ko[g] = k;
                     vo[g] = s_vals[p];
@@ -395,6 +397,7 @@ int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
                      hipStream_t s) {
     // small sorts: 1024 keys per workgroup iteration (more workgroups);
     // large ones: 4096 (fewer per-chunk histograms)
+    if (rs.items == 1) return radix_passes<1>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
 }

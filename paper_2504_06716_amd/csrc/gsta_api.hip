@@ -66,6 +66,8 @@ struct gsta_ctx {
     int items_depth = 16, items_inst = 16;
     uint64_t* partials = nullptr;
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
+    uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
+    uint32_t* gen = nullptr;       // [1] backward generation
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
     int fwd_waves = 4, bwd_waves = 2;
     uint32_t seg_shift = 7;        // backward segments of 128 splats (31: off)
@@ -177,6 +179,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
+         alloc(ctx, &ctx->stamps, cap) && alloc(ctx, &ctx->gen, 1) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
@@ -192,7 +195,8 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         ctx->cus = 1;
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(ctx->tile_grads, 0, (size_t)(9 * cap + 4) * sizeof(float)) != hipSuccess ||
+        hipMemset(ctx->stamps, 0, (size_t)std::max<int64_t>(cap, 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ctx->gen, 0, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
         hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -238,6 +242,8 @@ SegCkpt seg_ckpt(gsta_ctx* ctx, Slot& s) {
     c.ctr = s.ck_ctr;
     c.tile_last = s.tile_last;
     c.item_off = s.item_off;
+    c.stamps = ctx->stamps;
+    c.gen = ctx->gen;
     c.flags = ctx->flags;
     return c;
 }
@@ -584,6 +590,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (!same) return fail(ctx, GSTA_ERR_INVALID, "backward arguments differ from the forward in slot %d", state_slot);
     const int64_t n = g->n, S = ctx->stride;
     const int nv = n_views;
+    launch_next_gen(ctx->gen, stream);   // partial slots of earlier calls stop counting
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
         launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col,
@@ -593,8 +600,8 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
-                              s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d, dstats, stream);
-        launch_zero_partials(ctx->tile_grads, s.n_count, stream);   // ready for the next backward
+                              ctx->stamps, ctx->gen, s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d,
+                              dstats, stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }

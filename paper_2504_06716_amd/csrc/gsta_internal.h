@@ -96,13 +96,15 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
                            uint32_t* dkey, uint32_t* dval, int64_t stride, hipStream_t s);
 
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
-// expansion offsets inst_off[v][gid], in tile order), chains them to every
-// parameter, sums over views, and updates the gradient-norm EMAs.
+// expansion offsets inst_off[v][gid], in tile order, taking a slot only if
+// its stamp is the current generation), chains them to every parameter, sums
+// over views, and updates the gradient-norm EMAs.
 // grad2d_out ([nv][9][n], optional) receives the per-view 2-D gradients;
 // dstats ([4][n], optional) accumulates the densification statistics.
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
-                           const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           const float* partials, const uint32_t* stamps, const uint32_t* gen,
+                           const uint32_t* d_count, const uint8_t* frozen, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
@@ -156,6 +158,8 @@ struct SegCkpt {
     uint32_t* ctr;           // [1] slots taken by the forward
     uint32_t* tile_last;     // [V * T] largest `last` of each tile (zeroed before the forward)
     uint32_t* item_off;      // [V * T + 1] exclusive scan of the items per tile
+    uint32_t* stamps;        // [capacity] generation of each backward partial slot
+    const uint32_t* gen;     // [1] current backward generation
     uint32_t* flags;         // flags[3]: the pool ran out
 };
 // Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  `ids` holds,
@@ -164,11 +168,12 @@ struct SegCkpt {
 // 2-D gradient into partials[expansion index][9] (zeroed first), without
 // atomics; it is a persistent kernel of `blocks` workgroups over the
 // (tile, segment) items.
-// The backward writes the non-zero per-tile totals into slots that are zero
-// on entry: launch_zero_partials clears the first d_count * 9 values after
-// the preprocess backward has read them (and the context clears them once
-// when it allocates them).
-void launch_zero_partials(float* partials, const uint32_t* d_count, hipStream_t s);
+// The backward writes each non-zero per-tile total together with the call's
+// generation stamp (stamps[slot] = *gen); the preprocess backward takes a
+// slot only when its stamp is the current generation, so no slot is ever
+// cleared.  launch_next_gen advances the device-side generation before each
+// backward (stream-ordered, so a captured graph replays it too).
+void launch_next_gen(uint32_t* gen, hipStream_t s);
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,

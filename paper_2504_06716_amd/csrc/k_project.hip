@@ -264,7 +264,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     const ushort4* __restrict__ rect, const uint32_t* __restrict__ inst_off, int64_t stride,
-    const float* __restrict__ partials, const uint32_t* __restrict__ d_count, const uint8_t* __restrict__ frozen,
+    const float* __restrict__ partials, const uint32_t* __restrict__ stamps, const uint32_t* __restrict__ genp,
+    const uint32_t* __restrict__ d_count, const uint8_t* __restrict__ frozen,
     float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
     float* __restrict__ dstats) {
     constexpr int K = (D + 1) * (D + 1);
@@ -299,12 +300,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
         for (int k = 0; k < 9; ++k) d2[k] = 0.f;
         {
-            // per-tile totals, summed in tile order
+            // per-tile totals, summed in tile order; a slot without this
+            // call's stamp was not written by it (nothing reached the splat
+            // there) and counts as zero
             const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
             const uint64_t j0 = inst_off[o_idx];
+            const uint32_t gen = *genp;
             if (j0 + cnt <= (uint64_t)(*d_count)) {
-                const float* src = partials + j0 * 9;
-                for (uint32_t t = 0; t < cnt; ++t, src += 9) {
+                for (uint32_t t = 0; t < cnt; ++t) {
+                    if (stamps[j0 + t] != gen) continue;
+                    const float* src = partials + (j0 + t) * 9;
 #pragma unroll
                     for (int k = 0; k < 9; ++k) d2[k] += src[k];
                 }
@@ -478,11 +483,12 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
-                           const float* partials, const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           const float* partials, const uint32_t* stamps, const uint32_t* gen,
+                           const uint32_t* d_count, const uint8_t* frozen, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, d_count, frozen, G, gld, ema, beta, \
-                      grad2d_out, dstats
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, stamps, gen, d_count, frozen, G, gld, \
+                      ema, beta, grad2d_out, dstats
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -324,6 +324,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const int nt = nv * tiles;
     const uint32_t n_items = sc.item_off[nt];
     const bool seg = sc.shift < 31u;
+    const uint32_t gen = *sc.gen;
     uint32_t evals = 0, witer = 0, wred = 0, ngrad = 0;
     if (tid == 0) {
         s_pairs = 0;
@@ -532,10 +533,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                                 sum[q] = acc;
                                 nz = nz || (acc != 0.f);
                             }
-                            if (nz) {   // slots are zero on entry
+                            if (nz) {   // a slot counts only with this call's stamp
                                 float* dst = partials + (int64_t)s_idx[k] * 9;
 #pragma unroll
                                 for (int q = 0; q < 9; ++q) dst[q] = sum[q];
+                                sc.stamps[s_idx[k]] = gen;
                             }
                         }
                     }
@@ -627,19 +629,11 @@ void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint
                           bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
 }
 
-__global__ void k_zero_partials(float* __restrict__ p, const uint32_t* __restrict__ d_count) {
-    const int64_t n = (int64_t)(*d_count) * 9;
-    float4* p4 = reinterpret_cast<float4*>(p);
-    const int64_t n4 = n / 4;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
-        p4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int64_t t = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0.f;
+__global__ void k_next_gen(uint32_t* gen) {
+    if (threadIdx.x == 0) *gen = *gen + 1u;
 }
 
-void launch_zero_partials(float* partials, const uint32_t* d_count, hipStream_t s) {
-    k_zero_partials<<<2048, 256, 0, s>>>(partials, d_count);
-}
+void launch_next_gen(uint32_t* gen, hipStream_t s) { k_next_gen<<<1, 64, 0, s>>>(gen); }
 
 int composite_bwd_blocks_per_cu(int waves) {
     int nb = 0;

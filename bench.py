@@ -34,7 +34,34 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 # 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
 C2_EPS0 = (1.0148724677013602e-06, 2.5171187707272975e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 128   # launch shape (the library defaults)
+COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_composite_bwd_pmc.md")
 FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)
+
+
+def kernel_source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel_source):
+    """HBM bytes per launch of the backward compositing from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when there is none or
+    the kernel source has changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("kernel_source_sha256:",
+                                                                                      "hbm_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256", "").strip() != kernel_source_digest(kernel_source):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def c2_setup(torch):
@@ -184,6 +211,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--details", default=None, help="write the per-phase breakdown JSON here")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB on the device (a plain copy of known size for counter scaling)")
     ap.add_argument("--calibrate", type=float, default=None, metavar="Q",
                     help="print the initial freeze thresholds of the workload for quantile Q and exit")
     args = ap.parse_args()
@@ -195,6 +224,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("setting up the c2 workload")
     w = c2_setup(torch)
     if args.calibrate is not None:
@@ -267,7 +303,9 @@ def main():
         "frozen_fraction_peak": round(peak_frozen, 4),
         "frozen_fraction_mean": round(mean_frozen, 4),
         "roofline": {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
-                     "unit": unit_r, "frac": round(achieved / peak, 5), "traffic": None,
+                     "unit": unit_r, "frac": round(achieved / peak, 5),
+                     "traffic": (measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"))
+                                 if dominant == "composite_bwd" else None),
                      "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches},
         "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_all.items()},
         "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],

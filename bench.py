@@ -89,7 +89,7 @@ def c2_setup(torch):
         sched = FreezeSchedule(total_iters=iters, warmup=600, every=50, reset_every=400, wait=100,
                                window_end=1800, eps_xyz0=C2_EPS0[0], eps_rgb0=C2_EPS0[1])
         return TrainConfig(iters=iters, freeze=freeze, schedule=sched if freeze else None,
-                           lrs=LearningRates(decay_iters=iters))
+                           lrs=LearningRates(decay_iters=iters), partition=freeze)
 
     return dict(p0=p0, pt=pt, cams=cams, ctx=ctx, targets=targets, order=order, cfg=cfg, n=n, D=D, H=H, W=W,
                 iters=iters, capacity=int(need * 1.5) + 4096)

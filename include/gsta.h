@@ -269,6 +269,35 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
                                     const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen,
                                     hipStream_t stream);
 
+/* One per-Gaussian array for gsta_partition_frozen: `rows` rows of n
+ * elements of `elem_bytes` (1, 2 or 4) bytes, row r at base + r*ld elements
+ * (ld >= n; rows of one column block, an EMA block [4][n], a bf16 ring
+ * [8][4][n] as 32 rows, an id array as 1 row). */
+typedef struct {
+    void* base;
+    int64_t rows;
+    int64_t ld;
+    int32_t elem_bytes;
+} gsta_columns;
+
+/* Frozen Gaussians take no part in the optimizer step or the backward's
+ * per-Gaussian chain (Section 3.2.4); the kernels skip them per column, so
+ * a frozen set scattered over the columns saves little.  This call moves
+ * them out of the way: a stable partition of columns [0, n) by the freeze
+ * map, active (frozen[i] == 0) columns first, then the frozen ones, each
+ * group in its former order.  The permutation is applied in place to every
+ * array of `arrays` (host array of `count` descriptors; each array at most
+ * once, none overlapping another or `tmp`) and to `frozen` itself, which
+ * ends as n_active zeros followed by ones.  Rendering is unchanged up to the
+ * order of Gaussians at exactly equal depth, which follows the column order.
+ *   tmp: device scratch of at least max over arrays of rows*n*elem_bytes
+ *        bytes (e.g. the gradient block between iterations).
+ *   n_active (device int64 [1], may be NULL) receives the active count.
+ * Not capturable into a HIP graph (it issues device-to-device copies). */
+gsta_status gsta_partition_frozen(gsta_ctx* ctx, int64_t n, uint8_t* frozen, const gsta_columns* arrays,
+                                  int32_t count, void* tmp, int64_t tmp_bytes, int64_t* n_active,
+                                  hipStream_t stream);
+
 /* Eq. 3 with lambda_SSIM = 0: L = mean |C - C*| over `count` values.
  *   dL_dimage[j] = sign(C_j - C*_j) / count (sign(0) = 0).
  *   sums (device double [2]) receive sum |C - C*| and sum (clamp(C,0,1) - C*)^2

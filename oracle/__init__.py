@@ -268,6 +268,24 @@ def freeze_update(frozen, s_xyz, s_rgb, eps_xyz, eps_rgb, mode, proposal=None):
     return new.astype(np.uint8)
 
 
+def partition_order(frozen):
+    """Column order that puts the Gaussians the optimizer still updates
+    (Section 3.2.4: frozen ones are skipped) in front: the active columns in
+    their order, then the frozen ones in theirs.  Returns (src, n_active)
+    with new column i = old column src[i]; a layout choice, so the
+    definition is just this ordering."""
+    f = np.asarray(frozen) != 0
+    active = [j for j in range(f.size) if not f[j]]
+    frozen_cols = [j for j in range(f.size) if f[j]]
+    return np.array(active + frozen_cols, dtype=np.int64), len(active)
+
+
+def apply_partition(x, src):
+    """Columns of x ([rows, n] or [n]) in the order src."""
+    x = np.asarray(x)
+    return x[..., src].copy()
+
+
 # ---------------------------------------------------------------------------
 # Host schedule (Section 3.2.1 eq. 5, Section 3.2.2 eq. 7, Section 3.2.3)
 # ---------------------------------------------------------------------------

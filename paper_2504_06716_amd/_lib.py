@@ -49,6 +49,11 @@ class DensifyCfg(ctypes.Structure):
                 ("prune_logit", ctypes.c_float), ("child_log_scale_shift", ctypes.c_float)]
 
 
+class Columns(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("rows", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("elem_bytes", ctypes.c_int32)]
+
+
 class GstaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"gsta error {STATUS_NAMES.get(status, status)}: {msg}")
@@ -59,7 +64,7 @@ _lib = None
 
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
            "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
-           "gsta_update_freeze_mask", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
+           "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
            "gsta_mlp_sync_bf16", "gsta_mlp_propose"]
@@ -106,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.gsta_mlp_propose.argtypes = [P, P, P, P, i64, f32, f32, f32, P, P]
     L.gsta_adam_masked.argtypes = [P, PP, PP, PP, PP, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
     L.gsta_update_freeze_mask.argtypes = [P, P, P, i64, f32, f32, i32, P, P, P, P]
+    L.gsta_partition_frozen.argtypes = [P, i64, P, ctypes.POINTER(Columns), i32, P, i64, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
     L.gsta_set_profiling.argtypes = [P, i32]
     L.gsta_set_option.argtypes = [P, i32, i64]

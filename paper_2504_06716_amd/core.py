@@ -210,6 +210,36 @@ class Context:
                                                       _arr(n_frozen, (1,), torch.int64, "n_frozen"),
                                                       _stream(stream)))
 
+    def partition_frozen(self, frozen, arrays, tmp, n_active=None, stream=None):
+        """Stable partition of the columns by the freeze map (active first),
+        in place.  frozen: uint8 [n]; arrays: device tensors [rows, n] (unit
+        column stride, any row stride) or [n], 1-, 2- or 4-byte elements;
+        tmp: device tensor of at least max(rows * n * elem_bytes) bytes;
+        n_active: device int64 [1] or None."""
+        n = frozen.numel()
+        descs = []
+        for k, t in enumerate(arrays):
+            if t.device.type != "cuda":
+                raise ValueError(f"arrays[{k}] is not a device tensor")
+            if t.dim() == 1:
+                t2 = t.view(1, -1)
+            elif t.dim() == 2:
+                t2 = t
+            else:
+                raise ValueError(f"arrays[{k}]: expected [rows, n] or [n]")
+            if t2.shape[1] != n:
+                raise ValueError(f"arrays[{k}]: {t2.shape[1]} columns, frozen has {n}")
+            if n > 0 and (t2.stride(1) != 1 or (t2.shape[0] > 1 and t2.stride(0) < n)):
+                raise ValueError(f"arrays[{k}] needs unit column stride and row stride >= n")
+            ld = t2.stride(0) if t2.shape[0] > 1 else max(n, 1)
+            descs.append(_lib.Columns(t2.data_ptr() or None, t2.shape[0], ld, t2.element_size()))
+        arr = (_lib.Columns * max(len(descs), 1))(*descs)
+        check(self.h, self.L.gsta_partition_frozen(self.h, n, _arr(frozen, (n,), torch.uint8, "frozen"), arr,
+                                                    len(descs), tmp.data_ptr() if tmp is not None else None,
+                                                    0 if tmp is None else tmp.numel() * tmp.element_size(),
+                                                    _arr(n_active, (1,), torch.int64, "n_active"),
+                                                    _stream(stream)))
+
     def densify_prune(self, p, m, v, degree, ema, frozen, dstats, noise, cfg, p_out, m_out, v_out,
                       ema_out, frozen_out, counts, stream=None):
         """Densify-and-prune into the output blocks (p_out etc. are [R, capacity]

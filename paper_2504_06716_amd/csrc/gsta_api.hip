@@ -68,6 +68,7 @@ struct gsta_ctx {
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
     uint32_t* gen = nullptr;       // [1] backward generation
+    float* d2sum = nullptr;        // [V][9][stride] per-view 2-D gradient of each Gaussian
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
     int fwd_waves = 4, bwd_waves = 2;
     uint32_t seg_shift = 7;        // backward segments of 128 splats (31: off)
@@ -77,6 +78,8 @@ struct gsta_ctx {
     uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
     uint32_t* dens_boff = nullptr; // [3][blocks] densify block counts / offsets
     uint32_t* dens_tot = nullptr;  // [4] kept, clones, splits, overflow
+    uint32_t* part_src = nullptr;  // [max_gaussians] freeze partition gather list
+    uint32_t* part_tot = nullptr;  // [1] active count of the partition
     float* mlp_part = nullptr;     // [kMlpBlocks][kMlpCount] proposer gradient partials
     double* mlp_stats = nullptr;   // [kMlpBlocks][64] feature-statistics partials
     uint64_t* max_inst = nullptr;
@@ -179,9 +182,10 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
-         alloc(ctx, &ctx->stamps, cap) && alloc(ctx, &ctx->gen, 1) &&
+         alloc(ctx, &ctx->stamps, cap) && alloc(ctx, &ctx->gen, 1) && alloc(ctx, &ctx->d2sum, 9 * V * S) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
+         alloc(ctx, &ctx->part_src, l->max_gaussians) && alloc(ctx, &ctx->part_tot, 1) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
@@ -600,7 +604,8 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
-                              ctx->stamps, ctx->gen, s.n_count, frozen, grad->block, grad->ld, ema, ema_beta, grad2d,
+                              ctx->stamps, ctx->gen, s.n_count, frozen, ctx->d2sum, grad->block, grad->ld, ema,
+                              ema_beta, grad2d,
                               dstats, stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
@@ -667,6 +672,53 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
     PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
     launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
     return hip_check(ctx, hipGetLastError(), "freeze launch");
+}
+
+gsta_status gsta_partition_frozen(gsta_ctx* ctx, int64_t n, uint8_t* frozen, const gsta_columns* arrays,
+                                  int32_t count, void* tmp, int64_t tmp_bytes, int64_t* n_active,
+                                  hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (n < 0 || n > ctx->lim.max_gaussians)
+        return fail(ctx, GSTA_ERR_INVALID, "n = %lld outside [0, max_gaussians = %lld]", (long long)n,
+                    (long long)ctx->lim.max_gaussians);
+    if (count < 0 || count > 64) return fail(ctx, GSTA_ERR_INVALID, "count = %d outside [0, 64]", count);
+    if (count > 0 && !arrays) return fail(ctx, GSTA_ERR_INVALID, "arrays is NULL");
+    if (n > 0 && !frozen) return fail(ctx, GSTA_ERR_INVALID, "frozen is NULL");
+    // byte ranges [lo, hi) of every array, the mask and tmp; none may overlap
+    std::vector<PartArray> pa((size_t)count);
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    int64_t need = 0;
+    for (int a = 0; a < count; ++a) {
+        const gsta_columns& c = arrays[a];
+        if (c.elem_bytes != 1 && c.elem_bytes != 2 && c.elem_bytes != 4)
+            return fail(ctx, GSTA_ERR_INVALID, "arrays[%d].elem_bytes must be 1, 2 or 4", a);
+        if (c.rows < 1 || c.ld < n) return fail(ctx, GSTA_ERR_INVALID, "arrays[%d]: rows < 1 or ld < n", a);
+        if (n > 0 && !c.base) return fail(ctx, GSTA_ERR_INVALID, "arrays[%d].base is NULL", a);
+        if (n > 0 && (uintptr_t)c.base % c.elem_bytes != 0)
+            return fail(ctx, GSTA_ERR_INVALID, "arrays[%d].base is not aligned to its elements", a);
+        pa[a] = PartArray{c.base, c.rows, c.ld, c.elem_bytes};
+        need = std::max(need, c.rows * n * c.elem_bytes);
+        if (n > 0) {
+            const uintptr_t lo = (uintptr_t)c.base;
+            ranges.push_back({lo, lo + (uintptr_t)(((c.rows - 1) * c.ld + n) * c.elem_bytes)});
+        }
+    }
+    if (n > 0 && count > 0) {
+        if (!tmp || tmp_bytes < need)
+            return fail(ctx, GSTA_ERR_INVALID, "tmp holds %lld bytes, %lld needed", (long long)tmp_bytes,
+                        (long long)need);
+        if ((uintptr_t)tmp % 4 != 0) return fail(ctx, GSTA_ERR_INVALID, "tmp is not 4-byte aligned");
+        ranges.push_back({(uintptr_t)tmp, (uintptr_t)tmp + (uintptr_t)need});
+    }
+    if (n > 0) ranges.push_back({(uintptr_t)frozen, (uintptr_t)frozen + (uintptr_t)n});
+    for (size_t x = 0; x < ranges.size(); ++x)
+        for (size_t y = x + 1; y < ranges.size(); ++y)
+            if (ranges[x].first < ranges[y].second && ranges[y].first < ranges[x].second)
+                return fail(ctx, GSTA_ERR_INVALID, "arrays, frozen and tmp must not overlap");
+    PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
+    launch_partition(n, frozen, pa.data(), count, tmp, ctx->part_src, ctx->dens_boff, ctx->part_tot, n_active,
+                     stream);
+    return hip_check(ctx, hipGetLastError(), "partition launch");
 }
 
 gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_params* m,

@@ -104,7 +104,7 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* stamps, const uint32_t* gen,
-                           const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
@@ -230,6 +230,15 @@ void launch_densify(const DensIO& io, const DensCfg& cfg, uint8_t* code, uint32_
                     int64_t* counts, uint32_t* flags, hipStream_t s);
 void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
                           const uint8_t* frozen, float cap, hipStream_t s);
+// Stable partition of the columns by the freeze map (active first), applied
+// in place to each array through tmp; src [n] and boff [blocks] are scratch.
+struct PartArray {
+    void* base;
+    int64_t rows, ld;
+    int elem_bytes;
+};
+void launch_partition(int64_t n, uint8_t* frozen, const PartArray* arrays, int count, void* tmp,
+                      uint32_t* src, uint32_t* boff, uint32_t* tot, int64_t* n_active, hipStream_t s);
 // Learned freeze proposer: flat float32 parameters W1 [64][32], b1 [64],
 // W2 [64][64], b2 [64], w3 [64], b3; bf16 copies of W1 then W2.
 constexpr int kMlpW1 = 0, kMlpB1 = 2048, kMlpW2 = 2112, kMlpB2 = 6208, kMlpW3 = 6272, kMlpB3 = 6336;

@@ -12,6 +12,11 @@
 //                  [K+C, K+C+S), second children to [K+C+S, K+C+2S)
 // All decisions are float32 comparisons of the inputs, so they are exact;
 // ranks come from wave ballots, so the output order is the input order.
+//
+// The same ballot ranking gives the stable partition of the columns by the
+// freeze map (active first) that gsta_partition_frozen applies in place.
+#include <algorithm>
+
 #include "gsta_internal.h"
 
 namespace gsta {
@@ -215,6 +220,106 @@ __global__ __launch_bounds__(256) void k_opacity_reset(float* __restrict__ P, in
     V[10 * vld + i] = 0.f;
 }
 
+
+// ---- stable partition by the freeze map --------------------------------
+// Active (frozen == 0) columns move to [0, A) and frozen ones to [A, n), each
+// group in input order: with a(j) the number of active columns before j,
+// active j goes to a(j) and frozen j to A + j - a(j).  src[dest] = j is the
+// gather list every array is then permuted by.
+
+__global__ __launch_bounds__(kDB) void k_part_count(const uint8_t* __restrict__ frozen, int64_t n,
+                                                    uint32_t* __restrict__ bcount) {
+    __shared__ uint32_t s_cnt[kDB / 64];
+    const int64_t i = (int64_t)blockIdx.x * kDB + threadIdx.x;
+    const bool act = i < n && frozen[i] == 0;
+    const uint64_t b = __ballot(act);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < kDB / 64; ++k) t += s_cnt[k];
+        bcount[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the nb block counts (in place) by one workgroup;
+// tot[0] and n_active[0] receive the total.
+__global__ __launch_bounds__(1024) void k_part_scan(uint32_t* __restrict__ b, int64_t nb,
+                                                    uint32_t* __restrict__ tot, int64_t* __restrict__ n_active) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        const uint32_t x = j < nb ? b[j] : 0u;
+        uint32_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[w] = incl;
+        __syncthreads();
+        uint32_t wbase = s_carry;
+        for (int k = 0; k < w; ++k) wbase += s_w[k];
+        if (j < nb) b[j] = wbase + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = wbase + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tot[0] = s_carry;
+        if (n_active) n_active[0] = (int64_t)s_carry;
+    }
+}
+
+__global__ __launch_bounds__(kDB) void k_part_src(const uint8_t* __restrict__ frozen, int64_t n,
+                                                  const uint32_t* __restrict__ boff,
+                                                  const uint32_t* __restrict__ tot, uint32_t* __restrict__ src) {
+    __shared__ uint32_t s_w[kDB / 64];
+    const int64_t i = (int64_t)blockIdx.x * kDB + threadIdx.x;
+    const bool act = i < n && frozen[i] == 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m = __ballot(act);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (lane == 0) s_w[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (i >= n) return;
+    uint32_t a = boff[blockIdx.x] + below;
+    for (int k = 0; k < w; ++k) a += s_w[k];
+    const int64_t dest = act ? (int64_t)a : (int64_t)tot[0] + i - (int64_t)a;
+    src[dest] = (uint32_t)i;
+}
+
+// out[r][i] = x[r][src[i]] (out packed with row stride n).
+template <typename T>
+__global__ __launch_bounds__(256) void k_part_gather(const T* __restrict__ x, int64_t ld, int64_t rows,
+                                                     const uint32_t* __restrict__ src, int64_t n,
+                                                     T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = src[i];
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) out[r * n + i] = x[r * ld + j];
+}
+
+// x[r][i] = t[r][i] (t packed with row stride n).
+template <typename T>
+__global__ __launch_bounds__(256) void k_part_put(const T* __restrict__ t, int64_t rows, int64_t n,
+                                                  T* __restrict__ x, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) x[r * ld + i] = t[r * n + i];
+}
+
+__global__ __launch_bounds__(256) void k_part_mask(uint8_t* __restrict__ frozen, int64_t n,
+                                                   const uint32_t* __restrict__ tot) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) frozen[i] = i >= (int64_t)tot[0] ? 1 : 0;
+}
+
 }  // namespace
 
 int64_t densify_blocks(int64_t n) { return (n + kDB - 1) / kDB; }
@@ -242,6 +347,40 @@ void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V,
                           const uint8_t* frozen, float cap, hipStream_t s) {
     if (n <= 0) return;
     k_opacity_reset<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, ld, M, mld, V, vld, n, frozen, cap);
+}
+
+void launch_partition(int64_t n, uint8_t* frozen, const PartArray* arrays, int count, void* tmp,
+                      uint32_t* src, uint32_t* boff, uint32_t* tot, int64_t* n_active, hipStream_t s) {
+    const int64_t nb = densify_blocks(n);
+    if (nb > 0) k_part_count<<<(unsigned)nb, kDB, 0, s>>>(frozen, n, boff);
+    k_part_scan<<<1, 1024, 0, s>>>(boff, nb, tot, n_active);
+    if (n == 0) return;
+    k_part_src<<<(unsigned)nb, kDB, 0, s>>>(frozen, n, boff, tot, src);
+    const unsigned gx = (unsigned)((n + 255) / 256);
+    for (int a = 0; a < count; ++a) {
+        const PartArray& p = arrays[a];
+        const dim3 grid(gx, (unsigned)std::min<int64_t>(p.rows, 64));
+        switch (p.elem_bytes) {
+            case 1:
+                k_part_gather<uint8_t><<<grid, 256, 0, s>>>((const uint8_t*)p.base, p.ld, p.rows, src, n,
+                                                            (uint8_t*)tmp);
+                k_part_put<uint8_t><<<grid, 256, 0, s>>>((const uint8_t*)tmp, p.rows, n, (uint8_t*)p.base, p.ld);
+                break;
+            case 2:
+                k_part_gather<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)p.base, p.ld, p.rows, src, n,
+                                                             (uint16_t*)tmp);
+                k_part_put<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)tmp, p.rows, n, (uint16_t*)p.base,
+                                                          p.ld);
+                break;
+            default:
+                k_part_gather<uint32_t><<<grid, 256, 0, s>>>((const uint32_t*)p.base, p.ld, p.rows, src, n,
+                                                             (uint32_t*)tmp);
+                k_part_put<uint32_t><<<grid, 256, 0, s>>>((const uint32_t*)tmp, p.rows, n, (uint32_t*)p.base,
+                                                          p.ld);
+                break;
+        }
+    }
+    k_part_mask<<<gx, 256, 0, s>>>(frozen, n, tot);
 }
 
 }  // namespace gsta

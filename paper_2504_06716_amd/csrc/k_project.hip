@@ -260,12 +260,76 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
     }
 }
 
+// Sum over each row of 16 lanes with DPP (pairs, quads, then rotations by
+// 4 and 8 within the row); every lane of a row holds its row's total.
+__device__ __forceinline__ float row16_sum(float v) {
+    int x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
+    x = __builtin_bit_cast(int, v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    return v;
+}
+
+// 2-D gradient of each (view, active visible Gaussian): the sum of the
+// per-tile totals of the compositing backward, into d2sum[v][9][stride].  A
+// slot without this call's stamp was not written by it (nothing reached the
+// splat there) and counts as zero.  A Gaussian's slots are contiguous, so a
+// row of 16 lanes takes one Gaussian and reads 16 consecutive slots per
+// step (coalesced); lane l adds slots l, l+16, ... and the row is then
+// summed in a fixed order.
+constexpr int kSumRows = 16;   // Gaussians per 256-thread block
+
+__global__ __launch_bounds__(256) void k_sum_partials(const ushort4* __restrict__ rect,
+                                                      const uint32_t* __restrict__ inst_off, int64_t stride,
+                                                      int64_t n, const float* __restrict__ partials,
+                                                      const uint32_t* __restrict__ stamps,
+                                                      const uint32_t* __restrict__ genp,
+                                                      const uint32_t* __restrict__ d_count,
+                                                      const uint8_t* __restrict__ frozen,
+                                                      float* __restrict__ d2sum) {
+    const int l16 = threadIdx.x & 15;
+    const int64_t i = (int64_t)blockIdx.x * kSumRows + (threadIdx.x >> 4);
+    const int v = blockIdx.y;
+    // every exit below is uniform over a row of 16 lanes
+    if (i >= n) return;
+    if (frozen && frozen[i]) return;
+    const int64_t o_idx = (int64_t)v * stride + i;
+    const ushort4 r = rect[o_idx];
+    if (!(r.x < r.y)) return;
+    const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
+    const uint64_t j0 = inst_off[o_idx];
+    const uint32_t gen = *genp;
+    float d2[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d2[k] = 0.f;
+    if (j0 + cnt <= (uint64_t)(*d_count)) {
+        for (uint32_t base = 0; base < cnt; base += 16) {
+            const uint32_t t = base + (uint32_t)l16;
+            if (t < cnt && stamps[j0 + t] == gen) {
+                const float* src = partials + (j0 + t) * 9;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) d2[k] += src[k];
+            }
+        }
+    }
+    float out = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float tot = row16_sum(d2[k]);
+        if (l16 == k) out = tot;
+    }
+    if (l16 < 9) d2sum[((int64_t)v * 9 + l16) * stride + i] = out;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
-    const ushort4* __restrict__ rect, const uint32_t* __restrict__ inst_off, int64_t stride,
-    const float* __restrict__ partials, const uint32_t* __restrict__ stamps, const uint32_t* __restrict__ genp,
-    const uint32_t* __restrict__ d_count, const uint8_t* __restrict__ frozen,
+    const ushort4* __restrict__ rect, int64_t stride, const float* __restrict__ d2sum,
+    const uint8_t* __restrict__ frozen,
     float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
     float* __restrict__ dstats) {
     constexpr int K = (D + 1) * (D + 1);
@@ -298,23 +362,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         // backward, summed in row-major tile order.
         float d2[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) d2[k] = 0.f;
-        {
-            // per-tile totals, summed in tile order; a slot without this
-            // call's stamp was not written by it (nothing reached the splat
-            // there) and counts as zero
-            const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
-            const uint64_t j0 = inst_off[o_idx];
-            const uint32_t gen = *genp;
-            if (j0 + cnt <= (uint64_t)(*d_count)) {
-                for (uint32_t t = 0; t < cnt; ++t) {
-                    if (stamps[j0 + t] != gen) continue;
-                    const float* src = partials + (j0 + t) * 9;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) d2[k] += src[k];
-                }
-            }
-        }
+        for (int k = 0; k < 9; ++k) d2[k] = d2sum[((int64_t)v * 9 + k) * stride + i];
         if (grad2d_out) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) grad2d_out[((int64_t)v * 9 + k) * n + i] = d2[k];
@@ -484,11 +532,12 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* stamps, const uint32_t* gen,
-                           const uint32_t* d_count, const uint8_t* frozen, float* G,
+                           const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, inst_off, stride, partials, stamps, gen, d_count, frozen, G, gld, \
-                      ema, beta, grad2d_out, dstats
+    k_sum_partials<<<dim3((unsigned)((n + kSumRows - 1) / kSumRows), (unsigned)nv), block, 0, s>>>(
+        rect, inst_off, stride, n, partials, stamps, gen, d_count, frozen, d2sum);
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -53,6 +53,7 @@ class TrainConfig:
     traj_every: int = 0                  # push the gradient-norm averages to the 8-deep ring every k iterations
     proposer: object | None = None       # learned freeze proposer (proposer.Proposer), needs traj_every
     dataset: object | None = None        # proposer.ProposerDataset to record the rule's decisions into
+    partition: bool = False              # after each freeze update, move the frozen columns behind the active ones
 
 
 class Trainer:
@@ -124,6 +125,18 @@ class Trainer:
         elif cfg.proposer is not None or cfg.dataset is not None:
             raise ValueError("the proposer and its dataset need traj_every > 0")
         self.prop_buf = torch.zeros(self.n, dtype=torch.uint8, device="cuda") if cfg.proposer is not None else None
+        # Column permutation of the partitioned layout: column i holds the
+        # Gaussian that started in column origin[i] (not tracked through
+        # densification, which renumbers the set).
+        self.origin = None
+        self.n_active = torch.zeros(1, dtype=torch.int64, device="cuda")
+        if cfg.partition:
+            if not cfg.freeze:
+                raise ValueError("partition needs freeze=True")
+            if cfg.dataset is not None:
+                raise ValueError("the proposer dataset records column positions; it cannot follow a partition")
+            if cfg.densify is None:
+                self.origin = torch.arange(self.n, dtype=torch.int32, device="cuda")
 
     def _bind(self, n: int):
         """Point the working views at the first n columns of the current set."""
@@ -189,12 +202,42 @@ class Trainer:
                 prop = self.cfg.proposer.propose(self.traj.ring, self.traj.head, self.ema, ex, er, self.prop_buf)
             self.ctx.update_freeze_mask(self.ema[0], self.ema[1], ex, er, 0, self.frozen, proposal=prop,
                                         n_frozen=self.n_frozen)
+            if self.cfg.partition:
+                self._partition()
         elif act == RESET:
             self.ctx.update_freeze_mask(None, None, 0.0, 0.0, 1, self.frozen, n_frozen=self.n_frozen)
+            if self.cfg.partition:
+                self.n_active.fill_(self.n)
         i = len(self.frozen_log)
         if i < self.frozen_counts.numel():
             self.frozen_counts[i:i + 1].copy_(self.n_frozen, non_blocking=True)
         self.frozen_log.append((k, act))
+
+    def _partition(self):
+        """Permute every per-Gaussian array in place so that the active
+        Gaussians form the prefix [0, n_active): the backward's per-Gaussian
+        chain and Adam then skip whole waves of frozen columns.  The gradient
+        block is dead between iterations and serves as the scratch buffer;
+        pointers do not change, so captured graphs stay valid."""
+        arrays = [self.P, self.M, self.Vm, self.ema]
+        if self.dstats is not None:
+            arrays.append(self.dstats)
+        if self.traj is not None:
+            arrays.append(self.traj.ring.view(32, self.n))
+        if self.origin is not None:
+            arrays.append(self.origin)
+        self.ctx.partition_frozen(self.frozen, arrays, self.G_full, self.n_active)
+
+    def in_original_order(self, x: torch.Tensor) -> torch.Tensor:
+        """x ([rows, n] or [n], columns in the current layout) with its
+        columns back in the initial order of the Gaussians."""
+        if self.origin is None:
+            if self.cfg.partition:
+                raise ValueError("the column order is not tracked through densification")
+            return x
+        out = torch.empty_like(x)
+        out[..., self.origin.long()] = x
+        return out
 
     def freeze_history(self):
         """[(iteration, action, frozen count after it)] for every freeze-map change."""

@@ -409,6 +409,21 @@ def test_freeze_rule_hand_cases():
     assert list(O.freeze_update(old, sx, sr, 3e-5, 1e-4, 0, prop)) == [1, 1, 1, 1, 0, 0]
 
 
+def test_partition_order_hand_case_and_stable_sort():
+    f = np.array([1, 0, 0, 1, 1, 0, 1], np.uint8)
+    src, na = O.partition_order(f)
+    assert na == 3 and list(src) == [1, 2, 5, 0, 3, 4, 6]
+    # a stable sort by the 0/1 key is the same ordering
+    rng = np.random.default_rng(4)
+    for n in (0, 1, 63, 64, 65, 1000):
+        f = (rng.random(n) < 0.6).astype(np.uint8)
+        src, na = O.partition_order(f)
+        assert np.array_equal(src, np.argsort(f, kind="stable")) and na == int((f == 0).sum())
+    x = np.arange(14).reshape(2, 7)
+    src, _ = O.partition_order(np.array([1, 0, 0, 1, 1, 0, 1]))
+    assert O.apply_partition(x, src)[1].tolist() == [8, 9, 12, 7, 10, 11, 13]
+
+
 def test_ema_hand_cases():
     big = np.finfo(np.float32).max
     ema = np.array([big, 2.0, 2.0, 2.0])

@@ -16,6 +16,7 @@ using namespace gsta;
 namespace {
 
 constexpr int kCounters = 6;   // profiling counters, see gsta_read_profile
+const uint32_t kGen0 = 1u;      // first backward generation (stamps start at 0)
 
 struct Slot {
     float4* geo = nullptr;
@@ -67,7 +68,7 @@ struct gsta_ctx {
     uint64_t* partials = nullptr;
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
-    uint32_t* gen = nullptr;       // [1] backward generation
+    uint32_t* gen = nullptr;       // [1] backward generation (starts at 1; stamps start at 0)
     float* d2sum = nullptr;        // [V][9][stride] per-view 2-D gradient of each Gaussian
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
     int fwd_waves = 4, bwd_waves = 2;
@@ -200,7 +201,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
     if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->stamps, 0, (size_t)std::max<int64_t>(cap, 1) * sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(ctx->gen, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipMemcpy(ctx->gen, &kGen0, sizeof(kGen0), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
         hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -537,15 +538,22 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_BINNING, stream);
+        Clears cl;
+        cl.ptr[0] = reinterpret_cast<uint32_t*>(s.ranges);
+        cl.count[0] = 2 * T * nv;
+        cl.ptr[1] = s.tile_last;
+        cl.count[1] = T * nv;
+        cl.ptr[2] = s.ck_ctr;
+        cl.count[2] = 1;
         launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total, s.n_count,
                       s.ikey[0], s.ival[0], s.inst_gid, s.inst_off, (uint64_t)ctx->lim.instance_capacity,
-                      ctx->flags, ctx->max_inst, stream);
+                      ctx->flags, ctx->max_inst, cl, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
         RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst, ctx->items_inst};
         s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
-        launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, T * nv, stream);
+        launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
@@ -594,7 +602,6 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (!same) return fail(ctx, GSTA_ERR_INVALID, "backward arguments differ from the forward in slot %d", state_slot);
     const int64_t n = g->n, S = ctx->stride;
     const int nv = n_views;
-    launch_next_gen(ctx->gen, stream);   // partial slots of earlier calls stop counting
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
         launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col,
@@ -604,7 +611,8 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
-                              ctx->stamps, ctx->gen, s.n_count, frozen, ctx->d2sum, grad->block, grad->ld, ema,
+                              ctx->stamps, ctx->gen, s.n_count, frozen, ctx->d2sum, grad->block,
+                              grad->ld, ema,
                               ema_beta, grad2d,
                               dstats, stream);
     }

@@ -89,7 +89,6 @@ __device__ __forceinline__ float wave_sum(float x) {
 // -------------------------------------------------------------------------
 // Host launchers (all asynchronous on `s`).
 // -------------------------------------------------------------------------
-void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
@@ -103,7 +102,7 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 // dstats ([4][n], optional) accumulates the densification statistics.
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
-                           const float* partials, const uint32_t* stamps, const uint32_t* gen,
+                           const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s);
 
@@ -127,14 +126,22 @@ int64_t radix_chunks(int64_t count, int items);
 // Writes keys[j] = view*T + tile, vals[j] = j, inst_gid[j] = gid for every
 // instance j of the expansion, and inst_off[v][gid] = the first j of each
 // Gaussian (its instances are contiguous, in row-major tile order).
+// Its first kernel also zeroes the buffers named in `cl`.
+struct Clears {
+    static constexpr int kMax = 3;
+    uint32_t* ptr[kMax] = {nullptr, nullptr, nullptr};
+    int64_t count[kMax] = {0, 0, 0};
+};
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
                    uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
-                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, hipStream_t s);
+                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, const Clears& cl,
+                   hipStream_t s);
 int64_t expand_blocks(int64_t elements);
 
+// Tile ranges of the sorted keys; `ranges` must hold zeros beforehand.
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
-                   int64_t n_ranges, hipStream_t s);
+                   hipStream_t s);
 
 // Splat-segment checkpoints of the forward compositing, read by the
 // backward.  Every tile's depth-ordered list is cut into segments of K
@@ -171,9 +178,9 @@ struct SegCkpt {
 // The backward writes each non-zero per-tile total together with the call's
 // generation stamp (stamps[slot] = *gen); the preprocess backward takes a
 // slot only when its stamp is the current generation, so no slot is ever
-// cleared.  launch_next_gen advances the device-side generation before each
-// backward (stream-ordered, so a captured graph replays it too).
-void launch_next_gen(uint32_t* gen, hipStream_t s);
+// cleared.  The preprocess backward's last kernel advances the device-side
+// generation once every reader of it has finished (stream-ordered, so a
+// captured graph replays it too).
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,

@@ -276,8 +276,8 @@ __device__ __forceinline__ float row16_sum(float v) {
 
 // 2-D gradient of each (view, active visible Gaussian): the sum of the
 // per-tile totals of the compositing backward, into d2sum[v][9][stride].  A
-// slot without this call's stamp was not written by it (nothing reached the
-// splat there) and counts as zero.  A Gaussian's slots are contiguous, so a
+// slot without this call's stamp (the current generation) was not written by
+// it (nothing reached the splat there) and counts as zero.  A Gaussian's slots are contiguous, so a
 // row of 16 lanes takes one Gaussian and reads 16 consecutive slots per
 // step (coalesced); lane l adds slots l, l+16, ... and the row is then
 // summed in a fixed order.
@@ -294,35 +294,39 @@ __global__ __launch_bounds__(256) void k_sum_partials(const ushort4* __restrict_
     const int l16 = threadIdx.x & 15;
     const int64_t i = (int64_t)blockIdx.x * kSumRows + (threadIdx.x >> 4);
     const int v = blockIdx.y;
-    // every exit below is uniform over a row of 16 lanes
-    if (i >= n) return;
-    if (frozen && frozen[i]) return;
+    // `work` is uniform over each row of 16 lanes
+    bool work = i < n && !(frozen && frozen[i]);
     const int64_t o_idx = (int64_t)v * stride + i;
-    const ushort4 r = rect[o_idx];
-    if (!(r.x < r.y)) return;
-    const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
-    const uint64_t j0 = inst_off[o_idx];
-    const uint32_t gen = *genp;
-    float d2[9];
+    ushort4 r = make_ushort4(0, 0, 0, 0);
+    if (work) {
+        r = rect[o_idx];
+        work = r.x < r.y;
+    }
+    if (work) {
+        const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
+        const uint64_t j0 = inst_off[o_idx];
+        const uint32_t gen = *genp;
+        float d2[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d2[k] = 0.f;
-    if (j0 + cnt <= (uint64_t)(*d_count)) {
-        for (uint32_t base = 0; base < cnt; base += 16) {
-            const uint32_t t = base + (uint32_t)l16;
-            if (t < cnt && stamps[j0 + t] == gen) {
-                const float* src = partials + (j0 + t) * 9;
+        for (int k = 0; k < 9; ++k) d2[k] = 0.f;
+        if (j0 + cnt <= (uint64_t)(*d_count)) {
+            for (uint32_t base = 0; base < cnt; base += 16) {
+                const uint32_t t = base + (uint32_t)l16;
+                if (t < cnt && stamps[j0 + t] == gen) {
+                    const float* src = partials + (j0 + t) * 9;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) d2[k] += src[k];
+                    for (int k = 0; k < 9; ++k) d2[k] += src[k];
+                }
             }
         }
-    }
-    float out = 0.f;
+        float out = 0.f;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const float tot = row16_sum(d2[k]);
-        if (l16 == k) out = tot;
+        for (int k = 0; k < 9; ++k) {
+            const float tot = row16_sum(d2[k]);
+            if (l16 == k) out = tot;
+        }
+        if (l16 < 9) d2sum[((int64_t)v * 9 + l16) * stride + i] = out;
     }
-    if (l16 < 9) d2sum[((int64_t)v * 9 + l16) * stride + i] = out;
 }
 
 template <int D>
@@ -331,9 +335,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const ushort4* __restrict__ rect, int64_t stride, const float* __restrict__ d2sum,
     const uint8_t* __restrict__ frozen,
     float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
-    float* __restrict__ dstats) {
+    float* __restrict__ dstats, uint32_t* __restrict__ genp) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Every reader of this backward's generation (the compositing backward
+    // and the partial sums) has finished before this kernel starts, so one
+    // thread moves the generation on for the next backward.
+    if (i == 0) *genp = *genp + 1u;
     if (i >= n) return;
     if (frozen && frozen[i]) return;
     float mu[3], s[3], qn[4], Rq[9], qinv, o;
@@ -531,13 +539,13 @@ void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, co
 
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
-                           const float* partials, const uint32_t* stamps, const uint32_t* gen,
+                           const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     k_sum_partials<<<dim3((unsigned)((n + kSumRows - 1) / kSumRows), (unsigned)nv), block, 0, s>>>(
         rect, inst_off, stride, n, partials, stamps, gen, d_count, frozen, d2sum);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats, gen
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -601,9 +601,8 @@ void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, c
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
                           hipStream_t s) {
+    // sc.tile_last and sc.ctr arrive zeroed (cleared by the binning)
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-    launch_fill_u32(sc.tile_last, 0u, (int64_t)tiles * nv, s);
-    launch_fill_u32(sc.ctr, 0u, 1, s);
     if (pairs)
         fwd_launch<true>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
                          last, cfg, sc, pairs, s);
@@ -628,12 +627,6 @@ void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint
         bwd_launch<false>(waves, blocks, ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1,
                           bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
 }
-
-__global__ void k_next_gen(uint32_t* gen) {
-    if (threadIdx.x == 0) *gen = *gen + 1u;
-}
-
-void launch_next_gen(uint32_t* gen, hipStream_t s) { k_next_gen<<<1, 64, 0, s>>>(gen); }
 
 int composite_bwd_blocks_per_cu(int waves) {
     int nb = 0;

@@ -233,8 +233,14 @@ __device__ __forceinline__ uint32_t rect_tiles(ushort4 r) {
 __global__ __launch_bounds__(EX_THREADS) void k_tile_count(const ushort4* __restrict__ rect,
                                                            const uint32_t* __restrict__ order,
                                                            int64_t stride, int64_t n, int64_t total_el,
-                                                           uint64_t* __restrict__ partials) {
+                                                           uint64_t* __restrict__ partials, Clears cl) {
     __shared__ uint32_t s_tmp[RS_WAVES];
+    // buffers the rest of the forward expects zeroed (tile ranges, the
+    // compositing's per-tile last member and checkpoint counter)
+    for (int b = 0; b < Clears::kMax; ++b)
+        for (int64_t j = (int64_t)blockIdx.x * EX_THREADS + threadIdx.x; j < cl.count[b];
+             j += (int64_t)gridDim.x * EX_THREADS)
+            cl.ptr[b][j] = 0u;
     const int64_t e = (int64_t)blockIdx.x * EX_THREADS + threadIdx.x;
     uint32_t c = 0;
     if (e < total_el) {
@@ -342,12 +348,6 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
     }
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = value;
-}
-
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* d_count,
                          uint2* __restrict__ ranges) {
     const uint32_t count = *d_count;
@@ -407,26 +407,19 @@ int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / E
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
                    uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
-                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, hipStream_t s) {
+                   uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, const Clears& cl,
+                   hipStream_t s) {
     const int64_t total_el = n * nv;
     const int64_t nb = expand_blocks(total_el);
-    if (nb > 0) k_tile_count<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, partials);
+    k_tile_count<<<(unsigned)(nb > 0 ? nb : 1), EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, partials, cl);
     k_scan_partials<<<1, 1024, 0, s>>>(partials, nb, d_total, d_count, capacity, flags, max_inst);
     if (nb > 0)
         k_expand<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, ntx, tiles_per_view,
                                                     partials, keys, vals, inst_gid, inst_off, capacity);
 }
 
-void launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    k_fill_u32<<<(unsigned)blocks, 256, 0, s>>>(p, value, count);
-}
-
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
-                   int64_t n_ranges, hipStream_t s) {
-    launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * n_ranges, s);
+                   hipStream_t s) {
     int64_t blocks = (capacity + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;

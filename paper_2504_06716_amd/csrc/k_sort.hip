@@ -225,6 +225,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 // Element e = v*n + pos is the pos-th Gaussian of view v in depth order.
 // ---------------------------------------------------------------------------
 constexpr int EX_THREADS = 256;
+constexpr int kExWin = 8192;    // instances per owner window of the expansion
 
 __device__ __forceinline__ uint32_t rect_tiles(ushort4 r) {
     return (r.x < r.y && r.z < r.w) ? (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z) : 0u;
@@ -305,6 +306,8 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
     __shared__ uint32_t s_gid[EX_THREADS];
     __shared__ ushort4 s_rect[EX_THREADS];
     __shared__ uint32_t s_view[EX_THREADS];
+    __shared__ uint8_t s_owner[kExWin];
+    static_assert(EX_THREADS <= 256, "block-local Gaussian indices are stored in bytes");
     const int tid = threadIdx.x;
     const int64_t e = (int64_t)blockIdx.x * EX_THREADS + tid;
     uint32_t c = 0;
@@ -327,24 +330,31 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
         const uint64_t first = base + ex;
         inst_off[(int64_t)s_view[tid] * stride + s_gid[tid]] = (uint32_t)(first < capacity ? first : capacity);
     }
-    // Every instance of this block's Gaussians, one per thread in turn: find
-    // its Gaussian by binary search over the block-local offsets.
-    for (uint32_t j = tid; j < tot; j += EX_THREADS) {
-        int lo = 0, hi = EX_THREADS;    // s_off[lo] <= j < s_off[hi]
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= j) lo = mid; else hi = mid;
+    // Every instance of this block's Gaussians, one per thread in turn, in
+    // windows of kExWin instances: each Gaussian first marks its instances of
+    // the window with its block-local index (s_owner), then every thread
+    // reads the owner of its instance instead of searching the offsets.
+    for (uint32_t w0 = 0; w0 < tot; w0 += kExWin) {
+        const uint32_t w1 = min(tot, w0 + (uint32_t)kExWin);
+        if (c > 0) {
+            const uint32_t a = max(ex, w0), b = min(ex + c, w1);
+            for (uint32_t j = a; j < b; ++j) s_owner[j - w0] = (uint8_t)tid;
         }
-        const ushort4 r = s_rect[lo];
-        const uint32_t t = j - s_off[lo];
-        const uint32_t w = (uint32_t)(r.y - r.x);
-        const uint32_t tx = r.x + t % w, ty = r.z + t / w;
-        const uint64_t dst = base + j;
-        if (dst < capacity) {
-            keys[dst] = s_view[lo] * (uint32_t)tiles_per_view + ty * (uint32_t)ntx + tx;
-            vals[dst] = (uint32_t)dst;
-            inst_gid[dst] = s_gid[lo];
+        __syncthreads();
+        for (uint32_t j = w0 + tid; j < w1; j += EX_THREADS) {
+            const int lo = s_owner[j - w0];
+            const ushort4 r = s_rect[lo];
+            const uint32_t t = j - s_off[lo];
+            const uint32_t w = (uint32_t)(r.y - r.x);
+            const uint32_t tx = r.x + t % w, ty = r.z + t / w;
+            const uint64_t dst = base + j;
+            if (dst < capacity) {
+                keys[dst] = s_view[lo] * (uint32_t)tiles_per_view + ty * (uint32_t)ntx + tx;
+                vals[dst] = (uint32_t)dst;
+                inst_gid[dst] = s_gid[lo];
+            }
         }
+        __syncthreads();
     }
 }
 

@@ -41,6 +41,7 @@ struct Slot {
     uint32_t* ck_ctr = nullptr;
     uint32_t* tile_last = nullptr;
     uint32_t* item_off = nullptr;
+    uint32_t* item_tile = nullptr;
     uint32_t shift = 31;             // segment length of the last forward (31: none)
     // what the last forward in this slot rendered
     int depth_buf = 0, inst_buf = 0;
@@ -74,6 +75,7 @@ struct gsta_ctx {
     int fwd_waves = 4, bwd_waves = 2;
     uint32_t seg_shift = 7;        // backward segments of 128 splats (31: off)
     uint32_t pool_cap = 0;         // checkpoint slots per state slot
+    uint32_t item_cap = 0;         // backward work items per state slot
     int cus = 1, bwd_blocks = 1;   // persistent backward grid
     uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient, [2] densify overflow
     uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
@@ -163,6 +165,10 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     // checkpoint slots: one per 256 tile instances of capacity, at least 4096
     const int64_t pool_cap = std::min<int64_t>(std::max<int64_t>(4096, cap / 256), (int64_t)1 << 30);
     ctx->pool_cap = (uint32_t)pool_cap;
+    // work items of the backward: ceil(tile_last / K) per tile, K >= 2^kMinSegShift,
+    // and the tiles' walks add up to at most the instance capacity
+    const int64_t item_cap = (cap >> kMinSegShift) + V * ctx->tiles_max + 1;
+    ctx->item_cap = (uint32_t)std::min<int64_t>(item_cap, 0xFFFFFFFFll);
     bool ok = true;
     for (Slot& s : ctx->slots) {
         ok = ok && alloc(ctx, &s.geo, V * S) && alloc(ctx, &s.col, V * S) && alloc(ctx, &s.rgb, V * S) &&
@@ -174,7 +180,8 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
              alloc(ctx, &s.n_count, 1) && alloc(ctx, &s.ck_idx, ((cap >> kMinSegShift) + 2) * kCkptGroups) &&
              alloc(ctx, &s.ck_pool, (int64_t)pool_cap * 256) && alloc(ctx, &s.ck_ctr, 1) &&
-             alloc(ctx, &s.tile_last, V * ctx->tiles_max) && alloc(ctx, &s.item_off, V * ctx->tiles_max + 1);
+             alloc(ctx, &s.tile_last, V * ctx->tiles_max) && alloc(ctx, &s.item_off, V * ctx->tiles_max + 1) &&
+             alloc(ctx, &s.item_tile, item_cap);
     }
     ctx->items_depth = S <= (1 << 20) ? 1 : 16;
     ctx->items_inst = cap <= (1 << 20) ? 4 : 16;
@@ -247,6 +254,8 @@ SegCkpt seg_ckpt(gsta_ctx* ctx, Slot& s) {
     c.ctr = s.ck_ctr;
     c.tile_last = s.tile_last;
     c.item_off = s.item_off;
+    c.item_tile = s.item_tile;
+    c.item_cap = ctx->item_cap;
     c.stamps = ctx->stamps;
     c.gen = ctx->gen;
     c.flags = ctx->flags;

@@ -165,6 +165,8 @@ struct SegCkpt {
     uint32_t* ctr;           // [1] slots taken by the forward
     uint32_t* tile_last;     // [V * T] largest `last` of each tile (zeroed before the forward)
     uint32_t* item_off;      // [V * T + 1] exclusive scan of the items per tile
+    uint32_t* item_tile;     // [item_cap] tile (view * T + tile) of each work item
+    uint32_t item_cap;       // entries of item_tile
     uint32_t* stamps;        // [capacity] generation of each backward partial slot
     const uint32_t* gen;     // [1] current backward generation
     uint32_t* flags;         // flags[3]: the pool ran out

@@ -269,9 +269,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
 constexpr int kChunk = 64;   // splats per partial-sum flush in the backward
 
 // Items per tile: ceil(tile_last / K) (one if segments are off), scanned by
-// one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total).
+// one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total);
+// item_tile[i] names the tile of item i.
 __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__ tile_last, int nt, uint32_t shift,
-                                                    uint32_t* __restrict__ item_off) {
+                                                    uint32_t* __restrict__ item_off, uint32_t* __restrict__ item_tile,
+                                                    uint32_t item_cap) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -294,7 +296,12 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
         __syncthreads();
         uint32_t wbase = s_carry;
         for (int k = 0; k < w; ++k) wbase += s_w[k];
-        if (j < nt) item_off[j] = wbase + incl - x;
+        if (j < nt) {
+            const uint32_t off = wbase + incl - x;
+            item_off[j] = off;
+            for (uint32_t i = 0; i < x; ++i)
+                if (off + i < item_cap) item_tile[off + i] = (uint32_t)j;
+        }
         __syncthreads();
         if (threadIdx.x == 1023) s_carry = wbase + incl;
         __syncthreads();
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
     const int nt = nv * tiles;
-    const uint32_t n_items = sc.item_off[nt];
+    const uint32_t n_items = min(sc.item_off[nt], sc.item_cap);
     const bool seg = sc.shift < 31u;
     const uint32_t gen = *sc.gen;
     uint32_t evals = 0, witer = 0, wred = 0, ngrad = 0;
@@ -332,13 +339,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     }
 
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        // the item's tile: the last gt with item_off[gt] <= item
-        int lo = 0, hi = nt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sc.item_off[mid] <= item) lo = mid; else hi = mid - 1;
-        }
-        const int gt = lo;
+        const int gt = (int)sc.item_tile[item];     // the item's tile
         const uint32_t sgi = item - sc.item_off[gt];
         const int v = gt / tiles, tile = gt - v * tiles;
         const DevCam& cm = cams.c[v];
@@ -610,7 +611,7 @@ void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, c
         fwd_launch<false>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
                           last, cfg, sc, pairs, s);
     // the backward's work items: ceil(tile_last / K) per tile
-    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off);
+    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off, sc.item_tile, sc.item_cap);
 }
 
 void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,

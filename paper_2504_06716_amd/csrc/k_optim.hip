@@ -6,21 +6,21 @@
 namespace gsta {
 namespace {
 
-// Masked Adam over the [rows][n] block.  Grid: x over columns (4 per thread
-// when every stride allows 16-byte access), y over rows.  A frozen column is
-// skipped before any of its p, g, m, v bytes are read.
+// Masked Adam over the columns of one row of the [rows][n] block: 4 columns
+// per thread when every stride allows 16-byte access, else one; every
+// column takes the same operations whatever its position.  A frozen
+// column is skipped before any of its p, g, m, v bytes are read.
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, int64_t pld,
-                                              const float* __restrict__ g, int64_t gld,
-                                              float* __restrict__ m, int64_t mld, float* __restrict__ v,
-                                              int64_t vld, int64_t n, LrArray lr, float b1, float b2,
-                                              float eps, float bc1, float bc2,
-                                              const uint8_t* __restrict__ frozen,
-                                              uint32_t* __restrict__ flags) {
-    const int row = blockIdx.y;
-    const float lrr = lr.lr[row];
+__device__ __forceinline__ void adam_columns(int row, float* __restrict__ p, int64_t pld,
+                                             const float* __restrict__ g, int64_t gld, float* __restrict__ m,
+                                             int64_t mld, float* __restrict__ v, int64_t vld, int64_t n,
+                                             float lrr, float b1, float b2, float eps, float rbc1, float rbc2,
+                                             const uint8_t* __restrict__ frozen, uint32_t* __restrict__ flags) {
+    // No contraction: the compiler would otherwise fuse the four unrolled
+    // column updates differently, making a column's result depend on its
+    // position within its 16-byte group (and so on the column order).
+#pragma clang fp contract(off)
     const float ib1 = 1.f - b1, ib2 = 1.f - b2;
-    const float rbc1 = 1.f / bc1, rbc2 = 1.f / bc2;
     bool bad = false;
     if (VEC) {
         const int64_t i4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
@@ -73,7 +73,22 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, int64_t pld
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
 }
 
-// Adam whose scalars come from a device-resident schedule (graph replay).
+// Grid: x over columns, y over rows.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, int64_t pld,
+                                              const float* __restrict__ g, int64_t gld,
+                                              float* __restrict__ m, int64_t mld, float* __restrict__ v,
+                                              int64_t vld, int64_t n, LrArray lr, float b1, float b2,
+                                              float eps, float bc1, float bc2,
+                                              const uint8_t* __restrict__ frozen,
+                                              uint32_t* __restrict__ flags) {
+    const int row = blockIdx.y;
+    adam_columns<VEC>(row, p, pld, g, gld, m, mld, v, vld, n, lr.lr[row], b1, b2, eps, 1.f / bc1, 1.f / bc2, frozen,
+                      flags);
+}
+
+// Adam whose scalars come from a device-resident schedule (graph replay);
+// the same column update as k_adam.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_adam_sched(float* __restrict__ p, int64_t pld,
                                                     const float* __restrict__ g, int64_t gld,
@@ -91,23 +106,8 @@ __global__ __launch_bounds__(256) void k_adam_sched(float* __restrict__ p, int64
     } else {
         lrr = sc->lr[row];
     }
-    const float ib1 = 1.f - b1, ib2 = 1.f - b2;
     const float rbc1 = 1.f / (1.f - powf(b1, (float)step)), rbc2 = 1.f / (1.f - powf(b2, (float)step));
-    bool bad = false;
-    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * (VEC ? 4 : 1);
-    if (i0 >= n) return;
-    const int64_t i1 = (VEC && i0 + 4 <= n) ? i0 + 4 : (VEC ? n : i0 + 1);
-    for (int64_t i = i0; i < i1; ++i) {
-        if (frozen && frozen[i]) continue;
-        const float gk = g[row * gld + i];
-        bad |= !isfinite(gk);
-        const float mk = b1 * m[row * mld + i] + ib1 * gk;
-        const float vk = b2 * v[row * vld + i] + ib2 * gk * gk;
-        m[row * mld + i] = mk;
-        v[row * vld + i] = vk;
-        p[row * pld + i] -= lrr * (mk * rbc1) / (sqrtf(vk * rbc2) + eps);
-    }
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
+    adam_columns<VEC>(row, p, pld, g, gld, m, mld, v, vld, n, lrr, b1, b2, eps, rbc1, rbc2, frozen, flags);
 }
 
 __global__ void k_sched_advance(AdamSched* sc) { sc->step += 1; }
@@ -212,7 +212,9 @@ void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, i
 void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                        int64_t vld, int64_t n, int rows, AdamSched* sched, const uint8_t* frozen, uint32_t* flags,
                        hipStream_t s) {
-    const bool vec = (pld % 4 == 0) && (gld % 4 == 0) && (mld % 4 == 0) && (vld % 4 == 0);
+    const bool vec = (pld % 4 == 0) && (gld % 4 == 0) && (mld % 4 == 0) && (vld % 4 == 0) &&
+                     ((uintptr_t)p % 16 == 0) && ((uintptr_t)g % 16 == 0) && ((uintptr_t)m % 16 == 0) &&
+                     ((uintptr_t)v % 16 == 0) && (!frozen || (uintptr_t)frozen % 4 == 0);
     if (n > 0) {
         if (vec)
             k_adam_sched<true><<<dim3((unsigned)(((n + 3) / 4 + 255) / 256), rows), 256, 0, s>>>(

@@ -58,7 +58,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t* s_
 template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                            int64_t seg_stride, const uint32_t* d_count,
-                                                           uint32_t h_count, int shift,
+                                                           uint32_t h_count, int shift, uint32_t dmask,
                                                            uint32_t* __restrict__ hist,
                                                            int64_t nchunks_cap) {
     constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
 #pragma unroll 4
         for (int it = 0; it < RS_ITEMS; ++it) {
             int64_t idx = base + it * RS_THREADS + threadIdx.x;
-            if (idx < count) atomicAdd(&s_h[(k[idx] >> shift) & 0xFFu], 1u);
+            if (idx < count) atomicAdd(&s_h[(k[idx] >> shift) & dmask], 1u);
         }
         __syncthreads();
         hist[((int64_t)seg * RS_BINS + threadIdx.x) * nchunks_cap + chunk] = s_h[threadIdx.x];
@@ -114,6 +114,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     int64_t nchunks_cap) {
     constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     constexpr int WSPAN = 64 * RS_ITEMS;           // keys of one wave in a chunk
+    const uint32_t dmask = (1u << bits) - 1u;      // digits of this pass
     __shared__ uint32_t s_keys[RS_CHUNK];
     __shared__ uint32_t s_vals[RS_CHUNK];
     __shared__ uint32_t s_digit_base[RS_BINS];
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
         for (int it = 0; it < RS_ITEMS; ++it) {
             const int j = wid * WSPAN + it * 64 + lane;
             const bool ok = j < n_valid;
-            const uint32_t d = (key[it] >> shift) & 0xFFu;
+            const uint32_t d = (key[it] >> shift) & dmask;
             uint64_t match = __ballot(ok);
             for (int b = 0; b < bits; ++b) {
                 const uint64_t bal = __ballot(ok && ((d >> b) & 1u));
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
         for (int it = 0; it < RS_ITEMS; ++it) {
             const int j = wid * WSPAN + it * 64 + lane;
             if (j < n_valid) {
-                const uint32_t d = (key[it] >> shift) & 0xFFu;
+                const uint32_t d = (key[it] >> shift) & dmask;
                 const uint32_t pos = s_local_start[d] + s_cnt[wid][d] + rank[it];
                 if (pos < (uint32_t)RS_CHUNK) {
                     s_keys[pos] = key[it];
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
             const int p = it * RS_THREADS + tid;
             if (p < n_valid) {
                 const uint32_t k = s_keys[p];
-                const uint32_t g = s_gbase[(k >> shift) & 0xFFu] + (uint32_t)p;
+                const uint32_t g = s_gbase[(k >> shift) & dmask] + (uint32_t)p;
                 if (g < count) {
                     ko[g] = k;
                     vo[g] = s_vals[p];
@@ -381,10 +382,16 @@ int radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int n
     int cur = 0;
     const int64_t nchunks_cap = d_count ? rs.nchunks_cap : (h_count + CHUNK - 1) / CHUNK;
     const int grid_x = grid_for(nchunks_cap);
-    for (int shift = 0; shift < bits; shift += 8) {
-        const int pass_bits = (bits - shift) < 8 ? (bits - shift) : 8;
+    // as few 8-bit-or-narrower passes as the key needs, the bits spread evenly
+    // over them (11 bits: 6 + 5, so that no pass has only a few, crowded digits)
+    if (bits <= 0) return cur;
+    const int passes = (bits + 7) / 8;
+    const int per = (bits + passes - 1) / passes;
+    for (int shift = 0; shift < bits; shift += per) {
+        const int pass_bits = (bits - shift) < per ? (bits - shift) : per;
         k_radix_hist<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
-                                                                       shift, rs.hist, nchunks_cap);
+                                                                       shift, (1u << pass_bits) - 1u, rs.hist,
+                                                                       nchunks_cap);
         k_radix_scan<ITEMS><<<dim3(RS_BINS, nseg), RS_THREADS, 0, s>>>(rs.hist, rs.digit_tot, d_count, h_count,
                                                                         nchunks_cap);
         k_radix_scatter<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(

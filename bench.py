@@ -32,7 +32,7 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 # the positive gradient-norm averages at the start of the freeze window of a
 # no-freeze run, quantile q = 0.4: the largest of 0.1, 0.2, 0.3, 0.4, 0.45,
 # 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
-C2_EPS0 = (1.0148724677013602e-06, 2.5171187707272975e-08)
+C2_EPS0 = (1.0214666633002803e-06, 2.4916703086761885e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 128   # launch shape (the library defaults)
 COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_composite_bwd_pmc.md")

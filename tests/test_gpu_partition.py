@@ -149,3 +149,38 @@ def test_partition_carries_the_trajectory_ring():
         ring = tr.traj.ring.view(32, tr.n)
         out[part] = tr.in_original_order(ring).cpu().numpy()
     assert np.array_equal(out[False], out[True])
+
+
+def test_partition_with_densification_keeps_the_active_prefix():
+    """Densification renumbers the set (survivors, then clones and children,
+    unfrozen); the next freeze update partitions it again.  After every
+    update the active Gaussians are the prefix, the run stays finite, and
+    the column order is reported as untracked."""
+    import torch
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd.schedule import UPDATE, DensifySchedule, FreezeSchedule, LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
+    n, iters = 1500, 90
+    p = S.make_scene(n, 3, seed=11)
+    cams = [S.look_at(-15.0 + 10 * k, 45.0 * k, 48, 40) for k in range(8)]
+    ctx = G.Context(12 * n, 8, 40, 48, 1 << 20)
+    tgt = render_targets(ctx, S.perturb_scene(p, 3, seed=12), 3, cams)
+    ds = DensifySchedule(total_iters=iters, start=20, stop=60, every=20, reset_every=40, eps_xyz0=1e-4)
+    fs = FreezeSchedule(total_iters=iters, warmup=10, every=10, reset_every=50, wait=10, window_end=70,
+                        eps_xyz0=1e-6, eps_rgb0=1e-7)
+    cfg = TrainConfig(iters=iters, freeze=True, schedule=fs, lrs=LearningRates(decay_iters=iters),
+                      densify=ds, max_gaussians=12 * n, partition=True)
+    tr = Trainer(p, 3, cams, tgt, cfg, S.view_order(8, iters), ctx=ctx)
+    checked = 0
+    for k in range(iters):
+        tr.step()
+        if tr.frozen_log and tr.frozen_log[-1] == (k, UPDATE):
+            torch.cuda.synchronize()
+            f = tr.frozen.cpu().numpy()
+            assert (np.diff(f.astype(np.int8)) >= 0).all(), k
+            assert int(tr.n_active.item()) == int((f == 0).sum()), k
+            checked += 1
+    assert checked >= 4 and len(tr.n_history) == 2
+    assert np.isfinite(tr.P.cpu().numpy()).all() and np.isfinite(tr.evaluate())
+    with pytest.raises(ValueError):
+        tr.in_original_order(tr.P)

@@ -217,3 +217,56 @@ def test_trainer_densify_changes_n_and_graph_replay_matches_eager():
     np.testing.assert_array_equal(P0, P1)
     np.testing.assert_array_equal(F0, F1)
     assert e0 > s0 + 1.0                             # it trains on after the reset
+
+
+def test_c4_scale_training_with_densify_freeze_and_partition():
+    """c4 sizes: 3M Gaussians (SH degree 3) at 1080x1920.  The first forward
+    matches the brute-force oracle on sampled pixels; then a few training
+    iterations with densification, a freeze update with the partitioned
+    layout, and Adam run to finite parameters with the active Gaussians as
+    the prefix."""
+    import torch
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd.schedule import UPDATE, DensifySchedule, FreezeSchedule, LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets, required_capacity
+    c = S.CONFIGS["c4"]
+    n, H, W = c["n"], c["height"], c["width"]
+    p = S.make_scene(n, 3)
+    cams = S.config_cameras("c4")[::30][:5]
+    cap = 2 * n
+    ctx = G.Context(cap, 1, H, W, instance_capacity=1 << 24, n_slots=1)
+    pt = S.perturb_scene(p, 3)
+    need = max(required_capacity(ctx, p, 3, cams), required_capacity(ctx, pt, 3, cams))
+    print("c4 instances per view (max):", need, flush=True)
+    ctx.reserve(instance_capacity=int(need * 1.5) + 4096)
+    tgt = render_targets(ctx, pt, 3, cams)
+    iters = 8
+    ds = DensifySchedule(total_iters=iters, start=2, stop=6, every=2, reset_every=100, eps_xyz0=2e-4)
+    fs = FreezeSchedule(total_iters=iters, warmup=3, every=2, reset_every=100, wait=1, window_end=7,
+                        eps_xyz0=1e-7, eps_rgb0=1e-9)
+    cfg = TrainConfig(iters=iters, freeze=True, schedule=fs, lrs=LearningRates(decay_iters=iters),
+                      densify=ds, max_gaussians=cap, partition=True)
+    tr = Trainer(p, 3, cams, tgt, cfg, np.arange(iters) % len(cams), ctx=ctx)
+    # the first forward, on sampled pixels against the oracle
+    img = tr.render_views([0])[0].cpu().numpy()
+    rng = np.random.default_rng(5)
+    pix = np.stack([rng.integers(700, 1220, 120), rng.integers(280, 800, 120)], 1)
+    out, _, mv = O.render_pixels(p, 3, cams[0], pix)
+    ok = mv >= MARGIN_VALUE
+    assert ok.mean() > 0.95
+    assert np.abs(img[:, pix[:, 1], pix[:, 0]].T - out)[ok].max() <= 1e-4
+    checked = 0
+    for k in range(iters):
+        tr.step()
+        if tr.frozen_log and tr.frozen_log[-1] == (k, UPDATE):
+            torch.cuda.synchronize()
+            f = tr.frozen.cpu().numpy()
+            assert (np.diff(f.astype(np.int8)) >= 0).all()
+            checked += 1
+    torch.cuda.synchronize()
+    print("N after each densify step:", tr.n_history, "frozen:", tr.freeze_history(), flush=True)
+    assert checked >= 1 and len(tr.n_history) >= 1 and tr.n_history[0][1] != n
+    assert np.isfinite(tr.P.cpu().numpy()).all()
+    assert np.isfinite(tr.evaluate([0, 1]))
+    st, _ = ctx.check()
+    assert st == 0

@@ -266,7 +266,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     }
 }
 
-constexpr int kChunk = 64;   // splats per partial-sum flush in the backward
+// Splats per partial-sum flush in the backward.  32 rather than 64: the
+// smaller LDS buffer of row totals lets 8 instead of 6 workgroups share a CU.
+constexpr int kChunk = 32;
 
 // Items per tile: ceil(tile_last / K) (one if segments are off), scanned by
 // one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total);

@@ -33,7 +33,7 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 # no-freeze run, quantile q = 0.4: the largest of 0.1, 0.2, 0.3, 0.4, 0.45,
 # 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
 C2_EPS0 = (1.0214666633002803e-06, 2.4916703086761885e-08)
-FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 128   # launch shape (the library defaults)
+FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 64    # launch shape (the library defaults)
 COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_composite_bwd_pmc.md")
 FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)

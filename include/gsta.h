@@ -110,7 +110,7 @@ typedef enum {
                                    or 0: one independent wave per 8x8 quarter of each tile */
     GSTA_OPT_BWD_WAVES = 1,     /* waves per tile in backward compositing: 1, 2 or 4 (default 2) */
     GSTA_OPT_BWD_SEGMENT = 2    /* splats per backward work item: 0 (one item per tile) or a power of
-                                   two in [64, 65536] (default 128).  The forward checkpoints every
+                                   two in [64, 65536] (default 64).  The forward checkpoints every
                                    pixel's transmittance and colour prefix at each multiple of it, so
                                    the backward of a long tile list is spread over several
                                    workgroups; the result does not depend on it. */

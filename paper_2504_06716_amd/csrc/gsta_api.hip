@@ -73,8 +73,9 @@ struct gsta_ctx {
     float* d2sum = nullptr;        // [V][9][stride] per-view 2-D gradient of each Gaussian
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
     int fwd_waves = 4, bwd_waves = 2;
-    uint32_t seg_shift = 7;        // backward segments of 128 splats (31: off)
+    uint32_t seg_shift = 6;        // backward segments of 64 splats (31: off)
     uint32_t pool_cap = 0;         // checkpoint slots per state slot
+    uint32_t first_slots = 0;      // of which the tiles' first batches own the first ones
     uint32_t item_cap = 0;         // backward work items per state slot
     int cus = 1, bwd_blocks = 1;   // persistent backward grid
     uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient, [2] densify overflow
@@ -162,8 +163,16 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     const int64_t S = ctx->stride, cap = l->instance_capacity;
     const int64_t HW = (int64_t)l->max_width * l->max_height;
     ctx->slots.assign((size_t)l->n_slots, Slot());
-    // checkpoint slots: one per 256 tile instances of capacity, at least 4096
-    const int64_t pool_cap = std::min<int64_t>(std::max<int64_t>(4096, cap / 256), (int64_t)1 << 30);
+    // checkpoint slots: the forward reserves, per tile and walked batch of up
+    // to 256 list positions, one slot per 64-pixel group and boundary (up to
+    // 4 boundaries at the shortest segment, 64), and one batch ahead.  Room
+    // for two batches of every tile of every view plus one slot per 256
+    // instances of capacity for longer walks; running out is reported.
+    static_assert(kBatchSlotsMax == (uint32_t)kCkptGroups * (256u >> kMinSegShift), "batch slot bound");
+    const int64_t per_batch = kBatchSlotsMax;
+    ctx->first_slots = (uint32_t)(V * ctx->tiles_max * per_batch);
+    const int64_t pool_cap = std::min<int64_t>(
+        std::max<int64_t>(4096, cap / 256 + 2 * V * ctx->tiles_max * per_batch), (int64_t)1 << 30);
     ctx->pool_cap = (uint32_t)pool_cap;
     // work items of the backward: ceil(tile_last / K) per tile, K >= 2^kMinSegShift,
     // and the tiles' walks add up to at most the instance capacity
@@ -252,6 +261,7 @@ SegCkpt seg_ckpt(gsta_ctx* ctx, Slot& s) {
     c.pool = s.ck_pool;
     c.pool_cap = ctx->pool_cap;
     c.ctr = s.ck_ctr;
+    c.first_slots = ctx->first_slots;
     c.tile_last = s.tile_last;
     c.item_off = s.item_off;
     c.item_tile = s.item_tile;

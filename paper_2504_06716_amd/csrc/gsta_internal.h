@@ -157,12 +157,17 @@ void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capaci
 constexpr int kCkptGroups = kTilePix / 64;    // 64-pixel groups per tile
 constexpr int kMinSegShift = 6;               // shortest segment: 64 splats
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+// Checkpoint pool slots one forward batch (at most 256 list positions) can
+// need: one per 64-pixel group and segment boundary, at the shortest segment.
+constexpr uint32_t kBatchSlotsMax = 4u * (256u >> 6);
 struct SegCkpt {
     uint32_t shift;          // log2 K; 31 disables segments (one item per tile, no checkpoints)
     uint32_t* idx;           // [(capacity >> min shift) + 2][4] slot per (boundary bucket, group)
     double* pool;            // [pool_cap][4][64]: T, colour r, g, b
     uint32_t pool_cap;
-    uint32_t* ctr;           // [1] slots taken by the forward
+    uint32_t* ctr;           // [1] slots taken by the forward beyond the first batches
+    uint32_t first_slots;    // pool slots [0, first_slots): the first batch of tile v*T + t owns
+                             // [(v*T + t) * kBatchSlotsMax, + kBatchSlotsMax)
     uint32_t* tile_last;     // [V * T] largest `last` of each tile (zeroed before the forward)
     uint32_t* item_off;      // [V * T + 1] exclusive scan of the items per tile
     uint32_t* item_tile;     // [item_cap] tile (view * T + tile) of each work item

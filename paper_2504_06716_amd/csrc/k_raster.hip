@@ -73,12 +73,30 @@ __device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, i
     }
 }
 
-// Forward state at a segment boundary (global list position gpos), for the
-// pixel groups of this thread that still have active pixels.  Called with
-// the lanes that are still walking; done lanes are inactive.
-template <int W, int P>
-__device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, int tid, const bool* done,
-                                               const float* T, const double (*C)[3]) {
+// Pool slots a batch of B list positions reserves for its segment
+// boundaries: one per 64-pixel group and boundary.
+template <int B>
+__device__ __forceinline__ uint32_t batch_slots(uint32_t shift) {
+    return (uint32_t)kCkptGroups * ((uint32_t)(B - 1) / (1u << shift) + 1u);
+}
+
+// Whether the batch at list offset b0 (a multiple of B) of a list of len
+// positions holds a segment boundary (a positive multiple of K).
+template <int B>
+__device__ __forceinline__ bool batch_has_boundary(uint32_t b0, uint32_t len, uint32_t shift) {
+    const uint32_t K = 1u << shift;
+    const uint32_t first = b0 == 0u ? K : (b0 + K - 1u) / K * K;
+    return first < min(b0 + (uint32_t)B, len);
+}
+
+// Forward state at a segment boundary (global list position gpos, at offset k
+// of its batch), for the pixel groups of this thread that still have active
+// pixels.  Called with the lanes that are still walking; done lanes are
+// inactive.  The group's pool slot is fixed by the batch's block of slots
+// (ckbase, reserved by the workgroup a batch ahead): no counter on the walk.
+template <int W, int P, int B>
+__device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, int k, uint32_t ckbase, int tid,
+                                               const bool* done, const float* T, const double (*C)[3]) {
     const int lane = tid & 63, wid = tid >> 6;
     const size_t bucket = (size_t)(gpos >> sc.shift);
 #pragma unroll
@@ -86,11 +104,10 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
         const uint64_t m = __ballot(!done[p]);
         if (m == 0ull) continue;
         const int first = __builtin_ctzll(m);
-        uint32_t slot = 0u;
-        if (lane == first) slot = atomicAdd(sc.ctr, 1u);
-        slot = (uint32_t)__builtin_amdgcn_readlane((int)slot, first);
         const int g = wid + p * W;                    // 64-pixel group of pixel p
-        const bool ok = slot < sc.pool_cap;
+        const uint64_t slot64 = (uint64_t)ckbase + (uint64_t)kCkptGroups * ((uint32_t)k >> sc.shift) + (uint64_t)g;
+        const bool ok = ckbase != kNoSlot && slot64 < (uint64_t)sc.pool_cap;
+        const uint32_t slot = (uint32_t)slot64;
         if (lane == first) {
             sc.idx[bucket * kCkptGroups + g] = ok ? slot : kNoSlot;
             if (!ok) atomicOr(sc.flags + 3, 1u);
@@ -118,6 +135,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     __shared__ float4 s_rgb[B];
     __shared__ unsigned int s_pairs;
     __shared__ uint32_t s_last;
+    __shared__ uint32_t s_ckbase;      // pool slots of the current batch's segment boundaries
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
@@ -153,6 +171,15 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     }
     // checkpoints at list positions that are multiples of K (none in quadrant mode)
     const uint32_t kmask = (QUAD || sc.shift >= 31u) ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
+    const bool ckpt = kmask != 0xFFFFFFFFu;
+    const uint32_t len = rg.y - rg.x;
+    // The first batch's boundary slots are the tile's own; thread 0 reserves
+    // each later batch's block from the counter one batch ahead, so the
+    // counter's latency stays off the walk (a walk that ends early leaves one
+    // reserved block unused).
+    uint32_t ck_next = kNoSlot;
+    if (ckpt && tid == 0 && batch_has_boundary<B>(0u, len, sc.shift))
+        ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax;
 
     // Two-stage software pipeline: while a batch is composited, the records
     // of the next batch and the ids of the one after are in flight.
@@ -170,6 +197,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             s_co[tid] = cur.co;
             s_rgb[tid] = cur.c;
         }
+        if (ckpt && tid == 0) {
+            s_ckbase = ck_next;
+            const uint32_t b1 = base - rg.x + (uint32_t)B;
+            ck_next = batch_has_boundary<B>(b1, len, sc.shift)
+                          ? sc.first_slots + atomicAdd(sc.ctr, batch_slots<B>(sc.shift)) : kNoSlot;
+        }
         __syncthreads();
         {
             const uint32_t jn = base + B + tid;
@@ -186,7 +219,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         // as one splat at a time), and one branch adds the colour.
         for (int k = 0; k < cnt && !alldone; k += 2) {
             const uint32_t pos = base - rg.x + (uint32_t)k;     // even: segment boundaries fall here
-            if (!QUAD && pos != 0u && (pos & kmask) == 0u) fwd_checkpoint<W, P>(sc, base + (uint32_t)k, tid, done, T, C);
+            if (!QUAD && pos != 0u && (pos & kmask) == 0u)
+                fwd_checkpoint<W, P, B>(sc, base + (uint32_t)k, k, s_ckbase, tid, done, T, C);
             const bool two = k + 1 < cnt;
             const int k1 = two ? k + 1 : k;
             const float4 g0 = s_geo[k], g1 = s_geo[k1];

@@ -193,7 +193,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.item_tile, item_cap);
     }
     ctx->items_depth = S <= (1 << 20) ? 1 : 16;
-    ctx->items_inst = cap <= (1 << 20) ? 4 : 16;
+    ctx->items_inst = cap <= (1 << 20) ? 4 : 8;
     ctx->chunks_depth = radix_chunks(S, ctx->items_depth);
     ctx->chunks_inst = radix_chunks(cap, ctx->items_inst);
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);

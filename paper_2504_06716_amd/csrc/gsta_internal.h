@@ -114,7 +114,7 @@ struct RadixScratch {
     uint32_t* hist;          // [nseg][256][nchunks_cap]
     uint32_t* digit_tot;     // [nseg][256]
     int64_t nchunks_cap;     // chunks reserved per segment (device-count sorts)
-    int items;               // keys per thread per chunk: 4 or 16
+    int items;               // keys per thread per chunk: 1, 4, 8 or 16
 };
 int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,

@@ -412,10 +412,11 @@ int64_t radix_chunks(int64_t count, int items) {
 int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
                      hipStream_t s) {
-    // small sorts: 1024 keys per workgroup iteration (more workgroups);
-    // large ones: 4096 (fewer per-chunk histograms)
+    // 256, 1024, 2048 or 4096 keys per workgroup iteration: more workgroups
+    // for small sorts, fewer per-chunk histograms for large ones
     if (rs.items == 1) return radix_passes<1>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+    if (rs.items == 8) return radix_passes<8>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
 }
 

@@ -179,10 +179,9 @@ struct SegCkpt {
 // Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  `ids` holds,
 // per sorted instance, its index in the depth-ordered expansion; inst_gid
 // maps that index to the Gaussian.  The backward writes each (tile, splat)
-// 2-D gradient into partials[expansion index][9] (zeroed first), without
-// atomics; it is a persistent kernel of `blocks` workgroups over the
-// (tile, segment) items.
-// The backward writes each non-zero per-tile total together with the call's
+// 2-D gradient into partials[expansion index][9] without atomics; it is a
+// persistent kernel of `blocks` workgroups over the (tile, segment) items.
+// It writes each non-zero per-tile total together with the call's
 // generation stamp (stamps[slot] = *gen); the preprocess backward takes a
 // slot only when its stamp is the current generation, so no slot is ever
 // cleared.  The preprocess backward's last kernel advances the device-side

@@ -10,7 +10,7 @@ L1 loss + backward + masked Adam.  The GSta run (freezing) and the plain run
 PSNR of both over all 32 views is reported so the comparison can be checked
 at equal iteration count.
 
-Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one
+Prints one JSON line.  `--gpus` above 1 is refused: the library runs on one
 GPU.
 """
 from __future__ import annotations
@@ -217,7 +217,7 @@ def main():
                     help="print the initial freeze thresholds of the workload for quantile Q and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} requested, but this build runs on a single GPU only "
+        print(f"bench.py: --gpus {args.gpus} requested, but this benchmark runs on a single GPU only "
               "(no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -35,7 +35,7 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 C2_EPS0 = (1.0214666633002803e-06, 2.4916703086761885e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 64    # launch shape (the library defaults)
 COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_composite_bwd_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_compositing_pmc.md")
 FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)
 
 
@@ -45,21 +45,31 @@ def kernel_source_digest(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel_source):
-    """HBM bytes per launch of the backward compositing from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when there is none or
-    the kernel source has changed since the counters were taken."""
+# compositing phases whose HBM traffic the committed counter summary holds
+TRAFFIC_KERNELS = {"composite": "k_composite_fwd", "composite_bwd": "k_composite_bwd"}
+
+
+def measured_traffic(kernel_source, phase):
+    """HBM bytes per launch of a compositing kernel (one c2 training view)
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when
+    there is none for the phase or the kernel source has changed since the
+    counters were taken."""
+    if phase not in TRAFFIC_KERNELS:
+        return None
     try:
         with open(PMC_SUMMARY) as f:
             text = f.read()
     except OSError:
         return None
-    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("kernel_source_sha256:",
-                                                                                      "hbm_bytes_per_launch:")))
-    if fields.get("kernel_source_sha256", "").strip() != kernel_source_digest(kernel_source):
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith(("kernel_source_sha256", "hbm_bytes_per_launch")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256", "") != kernel_source_digest(kernel_source):
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields["hbm_bytes_per_launch " + TRAFFIC_KERNELS[phase]])
     except (KeyError, ValueError):
         return None
 
@@ -243,14 +253,18 @@ def main():
     if args.warmup > 0:
         run_trainer(torch, w, True, args.warmup)
 
-    # untimed profiling pass: per-phase totals over the same schedule
+    # untimed profiling passes over the same schedule: one with the counting
+    # kernel variants for the (pixel, splat) pair counts, one with the
+    # production kernels for the per-phase times that pick the dominant phase
+    log("counting pass")
+    _, _, _, pairs_all = run_trainer(torch, w, True, steps, profile_phases="all", counters=True)
     log("profiling pass")
-    trp, _, prof_all, pairs_all = run_trainer(torch, w, True, steps, profile_phases="all", counters=True)
+    trp, _, prof_all, _ = run_trainer(torch, w, True, steps, profile_phases="all")
     dominant = max(prof_all, key=lambda k: prof_all[k][0])
     log(f"dominant phase: {dominant}")
 
     # timed runs (events only around the dominant phase in the GSta run, no
-    # counting kernels; the pair counts of the identical profiling pass are used)
+    # counting kernels; the pair counts of the identical counting pass are used)
     tr_f, dt_f, prof_f, pairs_f = run_trainer(torch, w, True, steps, profile_phases=[dominant])
     log(f"GSta run: {steps / dt_f:.1f} iters/s")
     psnr_f = tr_f.evaluate()
@@ -304,8 +318,8 @@ def main():
         "frozen_fraction_mean": round(mean_frozen, 4),
         "roofline": {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
                      "unit": unit_r, "frac": round(achieved / peak, 5),
-                     "traffic": (measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"))
-                                 if dominant == "composite_bwd" else None),
+                     "traffic": measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"),
+                                                 dominant),
                      "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches},
         "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_all.items()},
         "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],

@@ -109,11 +109,16 @@ typedef enum {
     GSTA_OPT_FWD_WAVES = 0,     /* waves per 16x16 tile in forward compositing: 1, 2 or 4 (default 4),
                                    or 0: one independent wave per 8x8 quarter of each tile */
     GSTA_OPT_BWD_WAVES = 1,     /* waves per tile in backward compositing: 1, 2 or 4 (default 2) */
-    GSTA_OPT_BWD_SEGMENT = 2    /* splats per backward work item: 0 (one item per tile) or a power of
+    GSTA_OPT_BWD_SEGMENT = 2,   /* splats per backward work item: 0 (one item per tile) or a power of
                                    two in [64, 65536] (default 64).  The forward checkpoints every
                                    pixel's transmittance and colour prefix at each multiple of it, so
                                    the backward of a long tile list is spread over several
                                    workgroups; the result does not depend on it. */
+    GSTA_OPT_BINNING = 3        /* how the per-tile lists are built: 0 (default) places every tile
+                                   instance directly where views have at most 1536 tiles and the
+                                   placement scratch was reserved for the call's views, else sorts;
+                                   1 always expands and sorts the tile keys (LSD radix).  Both give
+                                   the same lists (Section 3.1: splats per tile in depth order). */
 } gsta_option;
 
 /* ---- context ------------------------------------------------------------ */

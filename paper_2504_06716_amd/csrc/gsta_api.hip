@@ -16,6 +16,7 @@ using namespace gsta;
 namespace {
 
 constexpr int kCounters = 6;   // profiling counters, see gsta_read_profile
+constexpr int64_t kPlaceBytes = (int64_t)1 << 29;   // placement count scratch limit
 const uint32_t kGen0 = 1u;      // first backward generation (stamps start at 0)
 
 struct Slot {
@@ -45,6 +46,7 @@ struct Slot {
     uint32_t shift = 31;             // segment length of the last forward (31: none)
     // what the last forward in this slot rendered
     int depth_buf = 0, inst_buf = 0;
+    bool placed = false;             // lists built by direct placement (no sorted keys)
     bool valid = false;
     int64_t n = 0, ld = 0;
     int degree = 0;
@@ -67,6 +69,10 @@ struct gsta_ctx {
     int64_t chunks_depth = 0, chunks_inst = 0;
     int items_depth = 16, items_inst = 16;
     uint64_t* partials = nullptr;
+    uint32_t* place_cnt = nullptr;   // [place_views][ceil(stride/256)][tiles_max] placement counts
+    uint32_t* tile_tot = nullptr;    // [place_views][tiles_max] instances per tile
+    int place_views = 0;             // views the placement scratch holds (0: always sort)
+    int binning = 0;                 // GSTA_OPT_BINNING
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
     uint32_t* gen = nullptr;       // [1] backward generation (starts at 1; stamps start at 0)
@@ -197,8 +203,16 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ctx->chunks_depth = radix_chunks(S, ctx->items_depth);
     ctx->chunks_inst = radix_chunks(cap, ctx->items_inst);
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);
+    // direct placement: counts of every (256-Gaussian block, tile) for as many
+    // views as fit kPlaceBytes (none where the tiles exceed kPlaceMaxTiles)
+    const int64_t place_view_words = place_blocks(S) * ctx->tiles_max;
+    ctx->place_views = ctx->tiles_max > kPlaceMaxTiles ? 0
+                       : (int)std::min<int64_t>(V, kPlaceBytes / (4 * place_view_words));
+    const int64_t pv = std::max(ctx->place_views, 1);
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
-         alloc(ctx, &ctx->partials, expand_blocks(V * S) + 1) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
+         alloc(ctx, &ctx->partials, std::max(expand_blocks(V * S), V * place_blocks(S)) + 1) &&
+         alloc(ctx, &ctx->place_cnt, ctx->place_views > 0 ? pv * place_view_words : 1) &&
+         alloc(ctx, &ctx->tile_tot, pv * ctx->tiles_max) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
          alloc(ctx, &ctx->stamps, cap) && alloc(ctx, &ctx->gen, 1) && alloc(ctx, &ctx->d2sum, 9 * V * S) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
@@ -419,6 +433,10 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
             ctx->seg_shift = (uint32_t)sh;
             return GSTA_OK;
         }
+        case GSTA_OPT_BINNING:
+            if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "binning must be 0 or 1");
+            ctx->binning = (int)value;
+            return GSTA_OK;
         default:
             return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
     }
@@ -518,6 +536,13 @@ gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst
     }
     const int64_t full = rows * row_elems * elem;
     if (bytes < 0 || bytes > full) return fail(ctx, GSTA_ERR_INVALID, "bytes %lld > field size %lld", (long long)bytes, (long long)full);
+    if (field == GSTA_STATE_INST_KEYS && s.placed) {
+        // placed lists carry no keys: write them from the tile ranges
+        launch_keys_from_ranges(s.ranges, V * T, s.ikey[0], stream);
+        gsta_status st = hip_check(ctx, hipGetLastError(), "keys from ranges");
+        if (st != GSTA_OK) return st;
+        src = s.ikey[0];
+    }
     if (rows == 1 || src_pitch == row_elems) {
         return hip_check(ctx, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, stream), "copy state");
     }
@@ -555,20 +580,33 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
         RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth};
         s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
     }
-    {
+    s.placed = ctx->binning == 0 && nv <= ctx->place_views && T <= kPlaceMaxTiles;
+    if (s.placed) {
+        // one pass from the depth order to the tile lists (no tile-key sort)
         PhaseTimer pt(ctx, GSTA_PHASE_BINNING, stream);
         Clears cl;
-        cl.ptr[0] = reinterpret_cast<uint32_t*>(s.ranges);
-        cl.count[0] = 2 * T * nv;
-        cl.ptr[1] = s.tile_last;
-        cl.count[1] = T * nv;
-        cl.ptr[2] = s.ck_ctr;
-        cl.count[2] = 1;
-        launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total, s.n_count,
-                      s.ikey[0], s.ival[0], s.inst_gid, s.inst_off, (uint64_t)ctx->lim.instance_capacity,
-                      ctx->flags, ctx->max_inst, cl, stream);
-    }
-    {
+        cl.ptr[0] = s.tile_last;
+        cl.count[0] = T * nv;
+        cl.ptr[1] = s.ck_ctr;
+        cl.count[1] = 1;
+        launch_place(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->place_cnt, ctx->tile_tot,
+                     ctx->partials, s.n_total, s.n_count, s.ival[0], s.inst_gid, s.inst_off, s.ranges,
+                     (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, cl, stream);
+        s.inst_buf = 0;
+    } else {
+        {
+            PhaseTimer pt(ctx, GSTA_PHASE_BINNING, stream);
+            Clears cl;
+            cl.ptr[0] = reinterpret_cast<uint32_t*>(s.ranges);
+            cl.count[0] = 2 * T * nv;
+            cl.ptr[1] = s.tile_last;
+            cl.count[1] = T * nv;
+            cl.ptr[2] = s.ck_ctr;
+            cl.count[2] = 1;
+            launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total,
+                          s.n_count, s.ikey[0], s.ival[0], s.inst_gid, s.inst_off,
+                          (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, cl, stream);
+        }
         PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
         RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst, ctx->items_inst};
         s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);

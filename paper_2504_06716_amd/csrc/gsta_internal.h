@@ -139,6 +139,23 @@ void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, i
                    hipStream_t s);
 int64_t expand_blocks(int64_t elements);
 
+// Direct tile placement, the alternative to expansion + tile-key sort +
+// ranges for views of at most kPlaceMaxTiles tiles: writes ids (the
+// tile-major, depth-ordered list of expansion indices, as the stable sort
+// orders them), inst_gid, inst_off and the ranges of all nv*T tiles (empty
+// ones as {0, 0}), and zeroes the buffers named in `cl`.  Scratch: cnt
+// [nv][place_blocks(n)][T], tile_tot [nv][T], partials [nv*place_blocks(n)].
+// On overflow (instances > capacity) nothing is placed and every range is
+// empty; the overflow is reported as by launch_expand.
+constexpr int kPlaceMaxTiles = 1536;
+int64_t place_blocks(int64_t n);
+void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int T,
+                  uint32_t* cnt, uint32_t* tile_tot, uint64_t* partials, uint64_t* d_total, uint32_t* d_count,
+                  uint32_t* ids, uint32_t* inst_gid, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
+                  uint32_t* flags, uint64_t* max_inst, const Clears& cl, hipStream_t s);
+// keys[i] = tile index of list position i, from the ranges of ntiles tiles.
+void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys, hipStream_t s);
+
 // Tile ranges of the sorted keys; `ranges` must hold zeros beforehand.
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
                    hipStream_t s);

@@ -21,6 +21,8 @@
 // kernels then run a grid-stride loop over the chunks that exist.
 #include "gsta_internal.h"
 
+#include <algorithm>
+
 namespace gsta {
 namespace {
 
@@ -255,13 +257,12 @@ __global__ __launch_bounds__(EX_THREADS) void k_tile_count(const ushort4* __rest
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Single workgroup: exclusive scan of the per-block partials (uint64).
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ partials, int64_t nb,
-                                                        uint64_t* __restrict__ d_total,
-                                                        uint32_t* __restrict__ d_count,
-                                                        uint64_t capacity, uint32_t* flags,
-                                                        uint64_t* max_inst) {
-    __shared__ uint64_t s_w[16];
+// One 1024-thread workgroup: exclusive scan of the per-block instance counts
+// (uint64), the total, the clamped count and the overflow report.
+__device__ __forceinline__ void scan_partials_block(uint64_t* __restrict__ partials, int64_t nb,
+                                                    uint64_t* __restrict__ d_total,
+                                                    uint32_t* __restrict__ d_count, uint64_t capacity,
+                                                    uint32_t* flags, uint64_t* max_inst, uint64_t* s_w) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     uint64_t carry = 0;
     for (int64_t b = 0; b < nb; b += 1024) {
@@ -291,6 +292,15 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ p
         if (carry > capacity) atomicOr(&flags[0], 1u);
         atomicMax((unsigned long long*)max_inst, (unsigned long long)carry);
     }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ partials, int64_t nb,
+                                                        uint64_t* __restrict__ d_total,
+                                                        uint32_t* __restrict__ d_count,
+                                                        uint64_t capacity, uint32_t* flags,
+                                                        uint64_t* max_inst) {
+    __shared__ uint64_t s_w[16];
+    scan_partials_block(partials, nb, d_total, d_count, capacity, flags, max_inst, s_w);
 }
 
 __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict__ rect,
@@ -370,6 +380,212 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* d_co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Direct tile placement (views of at most kPlaceMaxTiles tiles): the
+// tile-major, depth-ordered instance list without a key sort.
+// A Gaussian covers each tile of its rectangle once, so inside a block of
+// 256 consecutive Gaussians of the depth order, the place of a Gaussian's
+// instance among the block's instances of tile t is the number of earlier
+// Gaussians of the block covering t: a popcount over a 256-bit mask per
+// tile.  Blocks follow the depth order too, so with the per-(block, tile)
+// counts scanned down each tile's column, every instance has its final
+// position, the one the stable tile-key sort gives it.
+//   k_place_count  per block: cnt[v][b][t], the block's instance total
+//                  (+ the clears of the forward)
+//   k_place_scan   per 64 tiles: exclusive scan of cnt down the blocks and
+//                  tile totals; one extra workgroup scans the block totals
+//   k_place_write  per block: masks, ranks, ids and inst_gid; the view's
+//                  first block writes the tile ranges
+// ---------------------------------------------------------------------------
+constexpr int kPlaceWin = 4096;   // instances per owner window of the placement
+
+// The block's Gaussians (positions b*256 + tid of view v's depth order):
+// gid, rectangle and the exclusive scan of their tile counts.
+__device__ __forceinline__ void place_load(const ushort4* __restrict__ rect, const uint32_t* __restrict__ order,
+                                           int64_t stride, int64_t n, int v, int b, ushort4* s_rect,
+                                           uint32_t* s_gid, uint32_t* s_off, uint32_t* s_tmp, uint32_t& c,
+                                           uint32_t& ex, uint32_t& tot) {
+    const int tid = threadIdx.x;
+    const int64_t pos = (int64_t)b * EX_THREADS + tid;
+    c = 0;
+    uint32_t gid = 0;
+    ushort4 r = make_ushort4(0, 0, 0, 0);
+    if (pos < n) {
+        gid = order[(int64_t)v * stride + pos];
+        r = rect[(int64_t)v * stride + gid];
+        c = rect_tiles(r);
+    }
+    s_gid[tid] = gid;
+    s_rect[tid] = r;
+    ex = block_excl_scan_256(c, s_tmp, tot);
+    s_off[tid] = ex;
+    __syncthreads();
+}
+
+// f(lo, t, j) for every instance j of the block (block-local Gaussian lo,
+// tile t of the view), in windows of kPlaceWin instances whose owners are
+// marked in s_owner.  Every thread of the block must call it.
+template <typename F>
+__device__ __forceinline__ void place_for_each(uint32_t c, uint32_t ex, uint32_t tot, const ushort4* s_rect,
+                                               const uint32_t* s_off, uint8_t* s_owner, int ntx, F&& f) {
+    for (uint32_t w0 = 0; w0 < tot; w0 += kPlaceWin) {
+        const uint32_t w1 = min(tot, w0 + (uint32_t)kPlaceWin);
+        if (c > 0) {
+            const uint32_t a = max(ex, w0), e = min(ex + c, w1);
+            for (uint32_t j = a; j < e; ++j) s_owner[j - w0] = (uint8_t)threadIdx.x;
+        }
+        __syncthreads();
+        for (uint32_t j = w0 + threadIdx.x; j < w1; j += EX_THREADS) {
+            const int lo = s_owner[j - w0];
+            const ushort4 r = s_rect[lo];
+            const uint32_t k = j - s_off[lo];
+            const uint32_t w = (uint32_t)(r.y - r.x);
+            f(lo, (r.z + k / w) * (uint32_t)ntx + r.x + k % w, j);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(EX_THREADS) void k_place_count(const ushort4* __restrict__ rect,
+                                                            const uint32_t* __restrict__ order, int64_t stride,
+                                                            int64_t n, int nb, int ntx, int T,
+                                                            uint32_t* __restrict__ cnt,
+                                                            uint64_t* __restrict__ partials, Clears cl) {
+    extern __shared__ uint32_t s_cnt[];     // [T]
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint32_t s_off[EX_THREADS];
+    __shared__ uint32_t s_gid[EX_THREADS];
+    __shared__ ushort4 s_rect[EX_THREADS];
+    __shared__ uint8_t s_owner[kPlaceWin];
+    static_assert(EX_THREADS <= 256, "block-local Gaussian indices are stored in bytes");
+    {   // buffers the rest of the forward expects zeroed
+        const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * EX_THREADS;
+        const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * EX_THREADS + threadIdx.x;
+        for (int k = 0; k < Clears::kMax; ++k)
+            for (int64_t j = t0; j < cl.count[k]; j += nthreads) cl.ptr[k][j] = 0u;
+    }
+    const int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+    for (int t = tid; t < T; t += EX_THREADS) s_cnt[t] = 0;
+    uint32_t c, ex, tot;
+    place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp, c, ex, tot);
+    if (tid == 0) partials[(int64_t)v * nb + b] = tot;
+    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx,
+                   [&](int, uint32_t t, uint32_t) { atomicAdd(&s_cnt[t], 1u); });
+    uint32_t* row = cnt + ((int64_t)v * nb + b) * T;
+    for (int t = tid; t < T; t += EX_THREADS) row[t] = s_cnt[t];
+}
+
+// Blocks x < ceil(T/64): 64 tiles of view y, 16 waves over the blocks b.
+// Block x == ceil(T/64) of view 0: the block totals.
+__global__ __launch_bounds__(1024) void k_place_scan(uint32_t* __restrict__ cnt, int nb, int T,
+                                                     uint32_t* __restrict__ tile_tot,
+                                                     uint64_t* __restrict__ partials, int64_t nparts,
+                                                     uint64_t* __restrict__ d_total,
+                                                     uint32_t* __restrict__ d_count, uint64_t capacity,
+                                                     uint32_t* flags, uint64_t* max_inst) {
+    __shared__ uint32_t s_part[16][64];
+    __shared__ uint64_t s_w[16];
+    const int gT = (T + 63) / 64;
+    if ((int)blockIdx.x == gT) {
+        if (blockIdx.y == 0) scan_partials_block(partials, nparts, d_total, d_count, capacity, flags, max_inst, s_w);
+        return;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, v = blockIdx.y;
+    const int t = blockIdx.x * 64 + lane;
+    const int per = (nb + 15) / 16;
+    const int b0 = min(nb, w * per), b1 = min(nb, b0 + per);
+    uint32_t* col = cnt + (int64_t)v * nb * T + t;
+    uint32_t sum = 0;
+    if (t < T) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) sum += col[(int64_t)b * T];
+    }
+    s_part[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t x = s_part[k][lane];
+        run += (k < w) ? x : 0u;
+        tot += x;
+    }
+    if (t < T) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            const uint32_t x = col[(int64_t)b * T];
+            col[(int64_t)b * T] = run;
+            run += x;
+        }
+        if (w == 0) tile_tot[(int64_t)v * T + t] = tot;
+    }
+}
+
+__global__ __launch_bounds__(EX_THREADS) void k_place_write(
+    const ushort4* __restrict__ rect, const uint32_t* __restrict__ order, int64_t stride, int64_t n, int nb,
+    int ntx, int T, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tile_tot,
+    const uint64_t* __restrict__ partials, const uint64_t* __restrict__ d_total, uint32_t* __restrict__ ids,
+    uint32_t* __restrict__ inst_gid, uint32_t* __restrict__ inst_off, uint2* __restrict__ ranges,
+    uint64_t capacity) {
+    extern __shared__ uint64_t s_dyn[];
+    uint64_t* s_mask = s_dyn;                                       // [4][T] covering Gaussians
+    uint32_t* s_base = reinterpret_cast<uint32_t*>(s_dyn + 4 * T);  // [T] the block's first place per tile
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint32_t s_off[EX_THREADS];
+    __shared__ uint32_t s_gid[EX_THREADS];
+    __shared__ ushort4 s_rect[EX_THREADS];
+    __shared__ uint8_t s_owner[kPlaceWin];
+    const int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+    uint32_t c, ex, tot;
+    place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp, c, ex, tot);
+    const uint64_t base = partials[(int64_t)v * nb + b];   // expansion index of the block's first instance
+    const uint64_t vbase = partials[(int64_t)v * nb];      // ... and of the view's
+    const bool over = *d_total > capacity;
+    if ((int64_t)b * EX_THREADS + tid < n)
+        inst_off[(int64_t)v * stride + s_gid[tid]] = (uint32_t)min(base + ex, capacity);
+    // tile starts: the view's first index + exclusive scan of its tile totals
+    const int per = (T + EX_THREADS - 1) / EX_THREADS;
+    const int ta = min(T, tid * per), tb = min(T, ta + per);
+    const uint32_t* tt = tile_tot + (int64_t)v * T;
+    uint32_t loc = 0;
+    for (int t = ta; t < tb; ++t) loc += tt[t];
+    uint32_t all;
+    uint64_t start = vbase + block_excl_scan_256(loc, s_tmp, all);
+    const uint32_t* crow = cnt + ((int64_t)v * nb + b) * T;
+    for (int t = ta; t < tb; ++t) {
+        const uint32_t rt = tt[t];
+        s_base[t] = (uint32_t)(start + crow[t]);
+        if (b == 0)
+            ranges[(int64_t)v * T + t] = (over || rt == 0) ? make_uint2(0u, 0u)
+                                                             : make_uint2((uint32_t)start, (uint32_t)(start + rt));
+        start += rt;
+    }
+    if (over) return;   // nothing placed; the overflow is reported
+    for (int i = tid; i < 4 * T; i += EX_THREADS) s_mask[i] = 0ull;
+    __syncthreads();
+    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx, [&](int lo, uint32_t t, uint32_t) {
+        atomicOr(reinterpret_cast<unsigned long long*>(&s_mask[(lo >> 6) * T + t]), 1ull << (lo & 63));
+    });
+    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx, [&](int lo, uint32_t t, uint32_t j) {
+        const int q = lo >> 6;
+        uint32_t rank = (uint32_t)__popcll(s_mask[q * T + t] & ((1ull << (lo & 63)) - 1ull));
+        for (int k = 0; k < q; ++k) rank += (uint32_t)__popcll(s_mask[k * T + t]);
+        const uint64_t p = (uint64_t)s_base[t] + rank, e = base + j;
+        if (p < capacity && e < capacity) {
+            ids[p] = (uint32_t)e;
+            inst_gid[e] = s_gid[lo];
+        }
+    });
+}
+
+// keys[i] = tile of list position i, from the tile ranges (state export of
+// the placed lists, which carry no keys).
+__global__ void k_keys_from_ranges(const uint2* __restrict__ ranges, int64_t ntiles, uint32_t* __restrict__ keys) {
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint2 r = ranges[t];
+        for (uint32_t i = r.x + threadIdx.x; i < r.y; i += blockDim.x) keys[i] = (uint32_t)t;
+    }
+}
+
 int grid_for(int64_t chunks) {
     int64_t g = chunks < 1 ? 1 : chunks;
     return (int)(g > 2048 ? 2048 : g);
@@ -434,6 +650,28 @@ void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, i
     if (nb > 0)
         k_expand<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, ntx, tiles_per_view,
                                                     partials, keys, vals, inst_gid, inst_off, capacity);
+}
+
+int64_t place_blocks(int64_t n) { return n > 0 ? (n + EX_THREADS - 1) / EX_THREADS : 1; }
+
+void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int T,
+                  uint32_t* cnt, uint32_t* tile_tot, uint64_t* partials, uint64_t* d_total, uint32_t* d_count,
+                  uint32_t* ids, uint32_t* inst_gid, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
+                  uint32_t* flags, uint64_t* max_inst, const Clears& cl, hipStream_t s) {
+    const int nb = (int)place_blocks(n);
+    const dim3 grid((unsigned)nb, (unsigned)nv);
+    k_place_count<<<grid, EX_THREADS, (size_t)T * sizeof(uint32_t), s>>>(rect, order, stride, n, nb, ntx, T, cnt,
+                                                                         partials, cl);
+    k_place_scan<<<dim3((unsigned)((T + 63) / 64 + 1), (unsigned)nv), 1024, 0, s>>>(
+        cnt, nb, T, tile_tot, partials, (int64_t)nb * nv, d_total, d_count, capacity, flags, max_inst);
+    k_place_write<<<grid, EX_THREADS, (size_t)T * (4 * sizeof(uint64_t) + sizeof(uint32_t)), s>>>(
+        rect, order, stride, n, nb, ntx, T, cnt, tile_tot, partials, d_total, ids, inst_gid, inst_off, ranges,
+        capacity);
+}
+
+void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys, hipStream_t s) {
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(ntiles, 4096));
+    k_keys_from_ranges<<<(unsigned)g, 256, 0, s>>>(ranges, ntiles, keys);
 }
 
 void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,

@@ -1,0 +1,111 @@
+"""Tile lists built by direct placement against the tile-key sort.
+
+Both ways of binning (GSTA_OPT_BINNING 0 and 1) must give the same
+tile-major, depth-ordered lists (Section 3.1): the same ranges, expansion
+indices, gids and keys, and therefore bit-identical images, final
+transmittances and gradients.  The lists themselves are checked against the
+oracle by the parity tests, which run the default (placement) path."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from tests.gpu_util import GpuScene
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(p, D, cams, binning, capacity=1 << 22, backward=True):
+    import torch
+    from paper_2504_06716_amd import _lib as L
+    g = GpuScene(p, D, cams, bg=(0.2, 0.1, 0.4), capacity=capacity)
+    g.ctx.set_option(L.OPT_BINNING, binning)
+    out = {"image": g.forward()}
+    V, H, W = len(cams), cams[0].height, cams[0].width
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    ninst = int(g.state(L.STATE_N_INSTANCES, torch.int64, (1,))[0])
+    out["ninst"] = ninst
+    out["status"] = g.ctx.check()[0]
+    out["ranges"] = g.state(L.STATE_RANGES, torch.int32, (V * T, 2))
+    m = min(ninst, capacity)
+    if out["status"] == 0 and m > 0:
+        out["keys"] = g.state(L.STATE_INST_KEYS, torch.int32, (m,))
+        out["ids"] = g.state(L.STATE_INST_IDS, torch.int32, (m,))
+        out["gid"] = g.state(L.STATE_INST_GID, torch.int32, (m,))
+    out["T_final"] = g.state(L.STATE_T_FINAL, torch.float32, (V, H, W))
+    out["last"] = g.state(L.STATE_LAST, torch.int32, (V, H, W))
+    if backward and out["status"] == 0:
+        dL = np.random.default_rng(3).standard_normal((V, 3, H, W)).astype(np.float32)
+        out["grad"], out["g2d"], _ = g.backward(dL)
+    return out
+
+
+def _same(a, b):
+    assert a.keys() == b.keys()
+    for k in a:
+        if isinstance(a[k], np.ndarray):
+            assert np.array_equal(a[k], b[k]), k
+        else:
+            assert a[k] == b[k], k
+
+
+def _case(kind):
+    if kind == "tiny":
+        p = S.make_scene(64, 3, seed=0)
+        p[3:6] += 0.9
+        return p, 3, [S.look_at(10.0 + 35.0 * k, 20.0 + 70.0 * k, 32, 32) for k in range(2)]
+    if kind == "ragged":      # 3000 Gaussians (ragged last block), 50x37 views
+        p = S.make_scene(3000, 3, seed=5)
+        p[3:6] += 0.5
+        return p, 3, [S.look_at(25.0, 130.0, 50, 37), S.look_at(-40.0, 10.0, 50, 37)]
+    if kind == "views8":
+        p = S.make_scene(2500, 3, seed=8)
+        p[3:6] += 0.5
+        return p, 3, [S.look_at(-50.0 + 14.0 * k, 45.0 * k, 40, 40) for k in range(8)]
+    if kind == "c2view":
+        c = S.CONFIGS["c2"]
+        return S.make_scene(c["n"], 3), 3, S.config_cameras("c2")[:1]
+    if kind == "tiles1536":   # 48x32 tiles: the largest view placed directly
+        p = S.make_scene(20000, 1, seed=9)
+        return p, 1, [S.look_at(15.0, 30.0, 768, 512)]
+    if kind == "tiles1560":   # 40x39 tiles: beyond placement, both options sort
+        p = S.make_scene(20000, 1, seed=9)
+        return p, 1, [S.look_at(15.0, 30.0, 640, 610)]
+    if kind == "big":         # a few Gaussians covering hundreds of tiles each
+        p = S.make_scene(600, 0, seed=10)
+        p[3:6, :8] += 3.0
+        return p, 0, [S.look_at(0.0, 20.0, 320, 240)]
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged", "views8", "c2view", "tiles1536", "tiles1560", "big"])
+def test_placement_equals_sorted_lists(kind):
+    p, D, cams = _case(kind)
+    print(f"binning {kind}: n={p.shape[1]} views={len(cams)} {cams[0].width}x{cams[0].height}", flush=True)
+    placed = _run(p, D, cams, 0)
+    sorted_ = _run(p, D, cams, 1)
+    assert placed["status"] == 0 and placed["ninst"] > 0
+    _same(placed, sorted_)
+
+
+def test_placement_overflow_is_reported_and_renders_nothing():
+    p, D, cams = _case("ragged")
+    full = _run(p, D, cams, 0, backward=False)
+    cap = full["ninst"] - 1
+    print(f"overflow: capacity {cap} of {full['ninst']}", flush=True)
+    out = _run(p, D, cams, 0, capacity=cap, backward=False)
+    assert out["status"] == 2 and out["ninst"] == full["ninst"]       # GSTA_ERR_CAPACITY
+    assert (out["ranges"] == 0).all()
+    bg = np.array((0.2, 0.1, 0.4), np.float32)[None, :, None, None]
+    assert np.array_equal(out["image"], np.broadcast_to(bg, out["image"].shape))
+    again = _run(p, D, cams, 0, capacity=full["ninst"], backward=False)
+    assert again["status"] == 0
+    _same({k: again[k] for k in ("image", "ranges", "keys", "ids", "gid")},
+          {k: full[k] for k in ("image", "ranges", "keys", "ids", "gid")})
+
+
+def test_binning_option_is_checked():
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd import _lib as L
+    ctx = G.Context(100, 1, 32, 32, 1 << 16)
+    with pytest.raises(L.GstaError):
+        ctx.set_option(L.OPT_BINNING, 2)

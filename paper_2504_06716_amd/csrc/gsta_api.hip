@@ -28,7 +28,8 @@ struct Slot {
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* ikey[2] = {nullptr, nullptr};
     uint32_t* ival[2] = {nullptr, nullptr};
-    uint32_t* inst_gid = nullptr;   // [cap] gid of each expansion index
+    uint32_t* inst_gid = nullptr;   // [cap] gid of each expansion index (sorted path)
+    uint32_t* gsort = nullptr;      // [cap] gid at each tile-list position
     uint32_t* inst_off = nullptr;   // [V][S] first expansion index of each Gaussian
     uint2* ranges = nullptr;
     float* T_final = nullptr;
@@ -190,7 +191,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.rect, V * S) && alloc(ctx, &s.dkey[0], V * S) && alloc(ctx, &s.dkey[1], V * S) &&
              alloc(ctx, &s.dval[0], V * S) && alloc(ctx, &s.dval[1], V * S) && alloc(ctx, &s.ikey[0], cap) &&
              alloc(ctx, &s.ikey[1], cap) && alloc(ctx, &s.ival[0], cap) && alloc(ctx, &s.ival[1], cap) &&
-             alloc(ctx, &s.inst_gid, cap) && alloc(ctx, &s.inst_off, V * S) &&
+             alloc(ctx, &s.inst_gid, cap) && alloc(ctx, &s.gsort, cap) && alloc(ctx, &s.inst_off, V * S) &&
              alloc(ctx, &s.ranges, V * ctx->tiles_max) && alloc(ctx, &s.T_final, V * HW) &&
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
              alloc(ctx, &s.n_count, 1) && alloc(ctx, &s.ck_idx, ((cap >> kMinSegShift) + 2) * kCkptGroups) &&
@@ -543,6 +544,12 @@ gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst
         if (st != GSTA_OK) return st;
         src = s.ikey[0];
     }
+    if (field == GSTA_STATE_INST_GID && s.placed) {
+        // placed lists are built without the per-expansion-index gids
+        launch_gid_by_index(s.ival[0], s.gsort, s.n_count, ctx->lim.instance_capacity, s.inst_gid, stream);
+        gsta_status st = hip_check(ctx, hipGetLastError(), "gids by index");
+        if (st != GSTA_OK) return st;
+    }
     if (rows == 1 || src_pitch == row_elems) {
         return hip_check(ctx, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, stream), "copy state");
     }
@@ -589,8 +596,8 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
         cl.count[0] = T * nv;
         cl.ptr[1] = s.ck_ctr;
         cl.count[1] = 1;
-        launch_place(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->place_cnt, ctx->tile_tot,
-                     ctx->partials, s.n_total, s.n_count, s.ival[0], s.inst_gid, s.inst_off, s.ranges,
+        launch_place(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, ca.c[0].nty, ctx->place_cnt, ctx->tile_tot,
+                     ctx->partials, s.n_total, s.n_count, s.ival[0], s.gsort, s.inst_off, s.ranges,
                      (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, cl, stream);
         s.inst_buf = 0;
     } else {
@@ -610,12 +617,13 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
         PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
         RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst, ctx->items_inst};
         s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
-        launch_ranges(s.ikey[s.inst_buf], s.n_count, ctx->lim.instance_capacity, s.ranges, stream);
+        launch_ranges(s.ikey[s.inst_buf], s.ival[s.inst_buf], s.inst_gid, s.n_count, ctx->lim.instance_capacity,
+                      s.ranges, s.gsort, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
         s.shift = ctx->fwd_waves == 0 ? 31u : ctx->seg_shift;    // no checkpoints in quadrant mode
-        launch_composite_fwd(ctx->fwd_waves, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col, s.rgb, S, ca,
+        launch_composite_fwd(ctx->fwd_waves, s.ranges, s.gsort, s.geo, s.col, s.rgb, S, ca,
                              nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, seg_ckpt(ctx, s),
                              pair_counter(ctx, 0), stream);
     }
@@ -661,7 +669,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     const int nv = n_views;
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
-        launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.inst_gid, s.geo, s.col,
+        launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.gsort, s.geo, s.col,
                              s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg, dL_dimage,
                              ctx->tile_grads, s.n_count, seg_ckpt(ctx, s), pair_counter(ctx, 1), stream);
     }

@@ -142,23 +142,28 @@ int64_t expand_blocks(int64_t elements);
 // Direct tile placement, the alternative to expansion + tile-key sort +
 // ranges for views of at most kPlaceMaxTiles tiles: writes ids (the
 // tile-major, depth-ordered list of expansion indices, as the stable sort
-// orders them), inst_gid, inst_off and the ranges of all nv*T tiles (empty
-// ones as {0, 0}), and zeroes the buffers named in `cl`.  Scratch: cnt
+// orders them), gsort (the gid at each list position), inst_off and the
+// ranges of all nv*T tiles (empty ones as {0, 0}), and zeroes the buffers
+// named in `cl`.  inst_gid is not written.  Scratch: cnt
 // [nv][place_blocks(n)][T], tile_tot [nv][T], partials [nv*place_blocks(n)].
 // On overflow (instances > capacity) nothing is placed and every range is
 // empty; the overflow is reported as by launch_expand.
-constexpr int kPlaceMaxTiles = 1536;
+constexpr int kPlaceMaxTiles = 1408;
 int64_t place_blocks(int64_t n);
-void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int T,
+void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int nty,
                   uint32_t* cnt, uint32_t* tile_tot, uint64_t* partials, uint64_t* d_total, uint32_t* d_count,
-                  uint32_t* ids, uint32_t* inst_gid, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
+                  uint32_t* ids, uint32_t* gsort, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
                   uint32_t* flags, uint64_t* max_inst, const Clears& cl, hipStream_t s);
+// inst_gid[ids[i]] = gsort[i] for the d_count positions of placed lists.
+void launch_gid_by_index(const uint32_t* ids, const uint32_t* gsort, const uint32_t* d_count, int64_t capacity,
+                         uint32_t* inst_gid, hipStream_t s);
 // keys[i] = tile index of list position i, from the ranges of ntiles tiles.
 void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys, hipStream_t s);
 
-// Tile ranges of the sorted keys; `ranges` must hold zeros beforehand.
-void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
-                   hipStream_t s);
+// Tile ranges of the sorted keys (`ranges` must hold zeros beforehand), and
+// gsort[i] = inst_gid[ids[i]], the gid at each list position.
+void launch_ranges(const uint32_t* keys, const uint32_t* ids, const uint32_t* inst_gid, const uint32_t* d_count,
+                   int64_t capacity, uint2* ranges, uint32_t* gsort, hipStream_t s);
 
 // Splat-segment checkpoints of the forward compositing, read by the
 // backward.  Every tile's depth-ordered list is cut into segments of K
@@ -193,9 +198,9 @@ struct SegCkpt {
     const uint32_t* gen;     // [1] current backward generation
     uint32_t* flags;         // flags[3]: the pool ran out
 };
-// Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  `ids` holds,
-// per sorted instance, its index in the depth-ordered expansion; inst_gid
-// maps that index to the Gaussian.  The backward writes each (tile, splat)
+// Compositing with `waves` (1, 2 or 4) waves per 16x16 tile.  gsort holds
+// the Gaussian at each position of the tile lists, `ids` (backward only) its
+// index in the depth-ordered expansion.  The backward writes each (tile, splat)
 // 2-D gradient into partials[expansion index][9] without atomics; it is a
 // persistent kernel of `blocks` workgroups over the (tile, segment) items.
 // It writes each non-zero per-tile total together with the call's
@@ -204,12 +209,11 @@ struct SegCkpt {
 // cleared.  The preprocess backward's last kernel advances the device-side
 // generation once every reader of it has finished (stream-ordered, so a
 // captured graph replays it too).
-void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
-                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
                           hipStream_t s);
-void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
                           const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,

@@ -124,7 +124,7 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
 
 template <int W, bool QUAD, bool CNT>
 __global__ __launch_bounds__(64 * W) void k_composite_fwd(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ gsort,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg, SegCkpt sc,
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     uint32_t gid_nxt = 0;
     {
         const uint32_t j = rg.x + tid;
-        if (j < rg.y) cur = fetch_rec(geo, col, rgbv, vs, inst_gid[ids[j]]);
-        if (j + B < rg.y) gid_nxt = inst_gid[ids[j + B]];
+        if (j < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gsort[j]);
+        if (j + B < rg.y) gid_nxt = gsort[j + B];
     }
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         if (__syncthreads_count(!alldone) == 0) break;
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         {
             const uint32_t jn = base + B + tid;
             if (jn < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
-            if (jn + B < rg.y) gid_nxt = inst_gid[ids[jn + B]];
+            if (jn + B < rg.y) gid_nxt = gsort[jn + B];
         }
         const int cnt = (int)min((uint32_t)B, rg.y - base);
         // Each lane leaves the walk as soon as its pixels are done; the
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
 
 template <int W, bool CNT>
 __global__ __launch_bounds__(64 * W) void k_composite_bwd(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ inst_gid,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ gsort,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, const uint8_t* __restrict__ frozen, CamArray cams, int nv, float bg0, float bg1, float bg2,
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in, const double* __restrict__ cfg,
@@ -445,13 +445,13 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
             const uint32_t j = beg + tid;
             if (j < end) {
                 idx_cur = ids[j];
-                const uint32_t gid = inst_gid[idx_cur];
+                const uint32_t gid = gsort[j];
                 cur = fetch_rec(geo, col, rgbv, vs, gid);
                 frz_cur = frozen ? (uint32_t)frozen[gid] : 0u;
             }
             if (j + B < end) {
                 idx_nxt = ids[j + B];
-                gid_nxt = inst_gid[idx_nxt];
+                gid_nxt = gsort[j + B];
             }
         }
         for (uint32_t base = beg; base < end; base += B) {
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                 }
                 if (jn + B < end) {
                     idx_nxt = ids[jn + B];
-                    gid_nxt = inst_gid[idx_nxt];
+                    gid_nxt = gsort[jn + B];
                 }
             }
             const int cnt = (int)min((uint32_t)B, end - base);
@@ -599,12 +599,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
 }  // namespace
 
 template <bool CNT>
-void fwd_launch(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid, const float4* geo,
+void fwd_launch(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo,
                 const float4* col, const float4* rgb, int64_t stride, const CamArray& cams, int nv, float bg0,
                 float bg1, float bg2, float* image, float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc,
                 unsigned long long* pairs, hipStream_t s) {
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-#define GSTA_FWD_ARGS ranges, ids, inst_gid, geo, col, rgb, stride, cams, bg0, bg1, bg2, image, T_final, last, cfg, sc, pairs
+#define GSTA_FWD_ARGS ranges, gsort, geo, col, rgb, stride, cams, bg0, bg1, bg2, image, T_final, last, cfg, sc, pairs
     if (waves == 0)   // one independent wave per 8x8 quarter of each tile
         k_composite_fwd<1, true, CNT><<<dim3(4 * tiles, nv), 64, 0, s>>>(GSTA_FWD_ARGS);
     else if (waves == 1)
@@ -617,12 +617,12 @@ void fwd_launch(int waves, const uint2* ranges, const uint32_t* ids, const uint3
 }
 
 template <bool CNT>
-void bwd_launch(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+void bwd_launch(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,
                 const float4* geo, const float4* col, const float4* rgb, int64_t stride, const uint8_t* frozen,
                 const CamArray& cams, int nv, float bg0, float bg1, float bg2, const float* T_final,
                 const uint32_t* last, const double* cfg, const float* dL_dimage, float* partials, const SegCkpt& sc,
                 unsigned long long* pairs, hipStream_t s) {
-#define GSTA_BWD_ARGS ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2, T_final, last, \
+#define GSTA_BWD_ARGS ranges, ids, gsort, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2, T_final, last, \
                       cfg, dL_dimage, partials, sc, pairs
     if (waves == 1)
         k_composite_bwd<1, CNT><<<blocks, 64, 0, s>>>(GSTA_BWD_ARGS);
@@ -633,24 +633,23 @@ void bwd_launch(int waves, int blocks, const uint2* ranges, const uint32_t* ids,
 #undef GSTA_BWD_ARGS
 }
 
-void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
-                          const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
                           hipStream_t s) {
     // sc.tile_last and sc.ctr arrive zeroed (cleared by the binning)
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
     if (pairs)
-        fwd_launch<true>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
+        fwd_launch<true>(waves, ranges, gsort, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
                          last, cfg, sc, pairs, s);
     else
-        fwd_launch<false>(waves, ranges, ids, inst_gid, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
+        fwd_launch<false>(waves, ranges, gsort, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
                           last, cfg, sc, pairs, s);
     // the backward's work items: ceil(tile_last / K) per tile
     k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off, sc.item_tile, sc.item_cap);
 }
 
-void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* inst_gid,
+void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
                           const float* T_final, const uint32_t* last, const double* cfg, const float* dL_dimage,
@@ -658,10 +657,10 @@ void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint
                           hipStream_t s) {
     (void)d_count;
     if (pairs)
-        bwd_launch<true>(waves, blocks, ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2,
+        bwd_launch<true>(waves, blocks, ranges, ids, gsort, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1, bg2,
                          T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
     else
-        bwd_launch<false>(waves, blocks, ranges, ids, inst_gid, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1,
+        bwd_launch<false>(waves, blocks, ranges, ids, gsort, geo, col, rgb, stride, frozen, cams, nv, bg0, bg1,
                           bg2, T_final, last, cfg, dL_dimage, partials, sc, pairs, s);
 }
 

@@ -369,11 +369,13 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
     }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* d_count,
-                         uint2* __restrict__ ranges) {
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ids,
+                         const uint32_t* __restrict__ inst_gid, const uint32_t* d_count,
+                         uint2* __restrict__ ranges, uint32_t* __restrict__ gsort) {
     const uint32_t count = *d_count;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
+        gsort[i] = inst_gid[ids[i]];
         const uint32_t k = keys[i];
         if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
         if (i + 1 == count || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
@@ -397,86 +399,148 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* d_co
 //   k_place_write  per block: masks, ranks, ids and inst_gid; the view's
 //                  first block writes the tile ranges
 // ---------------------------------------------------------------------------
-constexpr int kPlaceWin = 4096;   // instances per owner window of the placement
+constexpr int PL_THREADS = 1024;                  // threads per placement workgroup
+constexpr int PL_GAUSS = 256;                     // Gaussians per block (4 x 64-bit masks per tile)
+constexpr int PL_PARTS = PL_THREADS / PL_GAUSS;   // threads per Gaussian in per-Gaussian loops
+constexpr int PL_WAVES = PL_THREADS / 64;
 
-// The block's Gaussians (positions b*256 + tid of view v's depth order):
-// gid, rectangle and the exclusive scan of their tile counts.
-__device__ __forceinline__ void place_load(const ushort4* __restrict__ rect, const uint32_t* __restrict__ order,
-                                           int64_t stride, int64_t n, int v, int b, ushort4* s_rect,
-                                           uint32_t* s_gid, uint32_t* s_off, uint32_t* s_tmp, uint32_t& c,
-                                           uint32_t& ex, uint32_t& tot) {
-    const int tid = threadIdx.x;
-    const int64_t pos = (int64_t)b * EX_THREADS + tid;
-    c = 0;
-    uint32_t gid = 0;
-    ushort4 r = make_ushort4(0, 0, 0, 0);
-    if (pos < n) {
-        gid = order[(int64_t)v * stride + pos];
-        r = rect[(int64_t)v * stride + gid];
-        c = rect_tiles(r);
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    s_gid[tid] = gid;
-    s_rect[tid] = r;
-    ex = block_excl_scan_256(c, s_tmp, tot);
-    s_off[tid] = ex;
+    return x;
+}
+
+// Exclusive scan of one value per thread over a 1024-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t x, uint32_t* s_tmp, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) s_tmp[wid] = incl;
     __syncthreads();
-}
-
-// f(lo, t, j) for every instance j of the block (block-local Gaussian lo,
-// tile t of the view), in windows of kPlaceWin instances whose owners are
-// marked in s_owner.  Every thread of the block must call it.
-template <typename F>
-__device__ __forceinline__ void place_for_each(uint32_t c, uint32_t ex, uint32_t tot, const ushort4* s_rect,
-                                               const uint32_t* s_off, uint8_t* s_owner, int ntx, F&& f) {
-    for (uint32_t w0 = 0; w0 < tot; w0 += kPlaceWin) {
-        const uint32_t w1 = min(tot, w0 + (uint32_t)kPlaceWin);
-        if (c > 0) {
-            const uint32_t a = max(ex, w0), e = min(ex + c, w1);
-            for (uint32_t j = a; j < e; ++j) s_owner[j - w0] = (uint8_t)threadIdx.x;
-        }
-        __syncthreads();
-        for (uint32_t j = w0 + threadIdx.x; j < w1; j += EX_THREADS) {
-            const int lo = s_owner[j - w0];
-            const ushort4 r = s_rect[lo];
-            const uint32_t k = j - s_off[lo];
-            const uint32_t w = (uint32_t)(r.y - r.x);
-            f(lo, (r.z + k / w) * (uint32_t)ntx + r.x + k % w, j);
-        }
-        __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < PL_WAVES; ++w) {
+        const uint32_t t = s_tmp[w];
+        base += (w < wid) ? t : 0u;
+        tot += t;
     }
+    __syncthreads();
+    total = tot;
+    return base + incl - x;
 }
 
-__global__ __launch_bounds__(EX_THREADS) void k_place_count(const ushort4* __restrict__ rect,
+// k / w and k % w for k < 2^20, 1 <= w < 2^11: the float quotient is within
+// one of the true one, and one correction step makes it exact.
+__device__ __forceinline__ uint32_t divmod_small(uint32_t k, uint32_t w, uint32_t& r) {
+    uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
+    int rr = (int)k - (int)(q * w);
+    if (rr < 0) {
+        --q;
+        rr += (int)w;
+    } else if (rr >= (int)w) {
+        ++q;
+        rr -= (int)w;
+    }
+    r = (uint32_t)rr;
+    return q;
+}
+
+// The block's Gaussians (positions b*256 + i of view v's depth order, i < 256):
+// gid, rectangle and the exclusive scan of their tile counts (s_off[256] = total).
+__device__ __forceinline__ uint32_t place_load(const ushort4* __restrict__ rect, const uint32_t* __restrict__ order,
+                                               int64_t stride, int64_t n, int v, int b, ushort4* s_rect,
+                                               uint32_t* s_gid, uint32_t* s_off, uint32_t* s_tmp) {
+    const int tid = threadIdx.x;
+    const int64_t pos = (int64_t)b * PL_GAUSS + tid;
+    uint32_t c = 0;
+    if (tid < PL_GAUSS) {
+        uint32_t gid = 0;
+        ushort4 r = make_ushort4(0, 0, 0, 0);
+        if (pos < n) {
+            gid = order[(int64_t)v * stride + pos];
+            r = rect[(int64_t)v * stride + gid];
+            c = rect_tiles(r);
+        }
+        s_gid[tid] = gid;
+        s_rect[tid] = r;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_1024(c, s_tmp, tot);
+    if (tid < PL_GAUSS) s_off[tid] = ex;
+    if (tid == 0) s_off[PL_GAUSS] = tot;
+    __syncthreads();
+    return tot;
+}
+
+// Per block: cnt[v][b][t] = Gaussians of the block covering tile t, from a
+// 2-D difference array over the tile grid (four updates per rectangle, then
+// prefix sums along rows and columns); partials[v*nb + b] = instances.
+__global__ __launch_bounds__(PL_THREADS) void k_place_count(const ushort4* __restrict__ rect,
                                                             const uint32_t* __restrict__ order, int64_t stride,
-                                                            int64_t n, int nb, int ntx, int T,
+                                                            int64_t n, int nb, int ntx, int nty,
                                                             uint32_t* __restrict__ cnt,
                                                             uint64_t* __restrict__ partials, Clears cl) {
-    extern __shared__ uint32_t s_cnt[];     // [T]
-    __shared__ uint32_t s_tmp[RS_WAVES];
-    __shared__ uint32_t s_off[EX_THREADS];
-    __shared__ uint32_t s_gid[EX_THREADS];
-    __shared__ ushort4 s_rect[EX_THREADS];
-    __shared__ uint8_t s_owner[kPlaceWin];
-    static_assert(EX_THREADS <= 256, "block-local Gaussian indices are stored in bytes");
+    extern __shared__ uint32_t s_d[];     // [nty + 1][ntx + 1]
+    __shared__ uint32_t s_tmp[PL_WAVES];
+    __shared__ uint32_t s_off[PL_GAUSS + 1];
+    __shared__ uint32_t s_gid[PL_GAUSS];
+    __shared__ ushort4 s_rect[PL_GAUSS];
     {   // buffers the rest of the forward expects zeroed
-        const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * EX_THREADS;
-        const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * EX_THREADS + threadIdx.x;
+        const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * PL_THREADS;
+        const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * PL_THREADS + threadIdx.x;
         for (int k = 0; k < Clears::kMax; ++k)
             for (int64_t j = t0; j < cl.count[k]; j += nthreads) cl.ptr[k][j] = 0u;
     }
     const int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
-    for (int t = tid; t < T; t += EX_THREADS) s_cnt[t] = 0;
-    uint32_t c, ex, tot;
-    place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp, c, ex, tot);
+    const int lane = tid & 63, wid = tid >> 6;
+    const int pitch = ntx + 1, T = ntx * nty;
+    for (int i = tid; i < (nty + 1) * pitch; i += PL_THREADS) s_d[i] = 0;
+    const uint32_t tot = place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp);
     if (tid == 0) partials[(int64_t)v * nb + b] = tot;
-    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx,
-                   [&](int, uint32_t t, uint32_t) { atomicAdd(&s_cnt[t], 1u); });
+    if (tid < PL_GAUSS) {
+        const ushort4 r = s_rect[tid];
+        if (rect_tiles(r) > 0) {
+            atomicAdd(&s_d[r.z * pitch + r.x], 1u);
+            atomicAdd(&s_d[r.z * pitch + r.y], 0xFFFFFFFFu);
+            atomicAdd(&s_d[r.w * pitch + r.x], 0xFFFFFFFFu);
+            atomicAdd(&s_d[r.w * pitch + r.y], 1u);
+        }
+    }
+    __syncthreads();
+    for (int y = wid; y < nty; y += PL_WAVES) {          // along each row
+        uint32_t carry = 0;
+        for (int x0 = 0; x0 < ntx; x0 += 64) {
+            const int x = x0 + lane;
+            const uint32_t incl = wave_incl_scan(x < ntx ? s_d[y * pitch + x] : 0u) + carry;
+            if (x < ntx) s_d[y * pitch + x] = incl;
+            carry = __shfl(incl, 63, 64);
+        }
+    }
+    __syncthreads();
+    for (int x = wid; x < ntx; x += PL_WAVES) {          // down each column
+        uint32_t carry = 0;
+        for (int y0 = 0; y0 < nty; y0 += 64) {
+            const int y = y0 + lane;
+            const uint32_t incl = wave_incl_scan(y < nty ? s_d[y * pitch + x] : 0u) + carry;
+            if (y < nty) s_d[y * pitch + x] = incl;
+            carry = __shfl(incl, 63, 64);
+        }
+    }
+    __syncthreads();
     uint32_t* row = cnt + ((int64_t)v * nb + b) * T;
-    for (int t = tid; t < T; t += EX_THREADS) row[t] = s_cnt[t];
+    for (int t = tid; t < T; t += PL_THREADS) {
+        uint32_t x;
+        const uint32_t y = divmod_small((uint32_t)t, (uint32_t)ntx, x);
+        row[t] = s_d[y * pitch + x];
+    }
 }
 
 // Blocks x < ceil(T/64): 64 tiles of view y, 16 waves over the blocks b.
 // Block x == ceil(T/64) of view 0: the block totals.
+constexpr int PL_SCAN_REG = 32;   // column entries a wave keeps in registers
 __global__ __launch_bounds__(1024) void k_place_scan(uint32_t* __restrict__ cnt, int nb, int T,
                                                      uint32_t* __restrict__ tile_tot,
                                                      uint64_t* __restrict__ partials, int64_t nparts,
@@ -495,86 +559,190 @@ __global__ __launch_bounds__(1024) void k_place_scan(uint32_t* __restrict__ cnt,
     const int per = (nb + 15) / 16;
     const int b0 = min(nb, w * per), b1 = min(nb, b0 + per);
     uint32_t* col = cnt + (int64_t)v * nb * T + t;
+    const bool inreg = per <= PL_SCAN_REG;
+    uint32_t x[PL_SCAN_REG];
     uint32_t sum = 0;
-    if (t < T) {
+    if (inreg) {
+#pragma unroll
+        for (int i = 0; i < PL_SCAN_REG; ++i) {
+            x[i] = (t < T && b0 + i < b1) ? col[(int64_t)(b0 + i) * T] : 0u;
+            sum += x[i];
+        }
+    } else if (t < T) {
 #pragma unroll 8
-        for (int b = b0; b < b1; ++b) sum += col[(int64_t)b * T];
+        for (int bb = b0; bb < b1; ++bb) sum += col[(int64_t)bb * T];
     }
     s_part[w][lane] = sum;
     __syncthreads();
     uint32_t run = 0, tot = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const uint32_t x = s_part[k][lane];
-        run += (k < w) ? x : 0u;
-        tot += x;
+        const uint32_t y = s_part[k][lane];
+        run += (k < w) ? y : 0u;
+        tot += y;
     }
     if (t < T) {
+        if (inreg) {
+#pragma unroll
+            for (int i = 0; i < PL_SCAN_REG; ++i) {
+                if (b0 + i < b1) col[(int64_t)(b0 + i) * T] = run;
+                run += x[i];
+            }
+        } else {
 #pragma unroll 8
-        for (int b = b0; b < b1; ++b) {
-            const uint32_t x = col[(int64_t)b * T];
-            col[(int64_t)b * T] = run;
-            run += x;
+            for (int bb = b0; bb < b1; ++bb) {
+                const uint32_t y = col[(int64_t)bb * T];
+                col[(int64_t)bb * T] = run;
+                run += y;
+            }
         }
         if (w == 0) tile_tot[(int64_t)v * T + t] = tot;
     }
 }
 
-__global__ __launch_bounds__(EX_THREADS) void k_place_write(
+// The index (0..255) of the k-th set bit of a tile's 256-bit mask (k < its popcount).
+__device__ __forceinline__ uint32_t mask_select(const uint64_t* s_mask, int T, int t, uint32_t k) {
+    uint64_t m = s_mask[t];
+    uint32_t base = 0;
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+        const uint32_t pc = (uint32_t)__popcll(m);
+        if (k >= pc) {
+            k -= pc;
+            m = s_mask[q * T + t];
+            base += 64;
+        }
+    }
+    uint32_t x = (uint32_t)m, pc = (uint32_t)__popc(x);
+    if (k >= pc) {
+        k -= pc;
+        x = (uint32_t)(m >> 32);
+        base += 32;
+    }
+#pragma unroll
+    for (int h = 16; h >= 1; h >>= 1) {
+        pc = (uint32_t)__popc(x & ((1u << h) - 1u));
+        if (k >= pc) {
+            k -= pc;
+            x >>= h;
+            base += (uint32_t)h;
+        }
+    }
+    return base;
+}
+
+constexpr int64_t kPlaceStaticLds = 4352;
+static_assert(65536 - kPlaceStaticLds - (40 * (int64_t)kPlaceMaxTiles + 4) >= 2 * 2048,
+              "the largest placed view leaves an owner window of at least 2048 instances");
+
+// Dynamic LDS of k_place_write: masks [4][T] (u64), block starts [T] and
+// local starts [T + 1] (u32), tile owners [win] (u16).
+size_t place_write_lds(int T, int win) {
+    return (size_t)T * 4 * sizeof(uint64_t) + (size_t)(2 * T + 1) * sizeof(uint32_t) + (size_t)win * sizeof(uint16_t);
+}
+
+__global__ __launch_bounds__(PL_THREADS) void k_place_write(
     const ushort4* __restrict__ rect, const uint32_t* __restrict__ order, int64_t stride, int64_t n, int nb,
-    int ntx, int T, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tile_tot,
+    int ntx, int T, int win, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tile_tot,
     const uint64_t* __restrict__ partials, const uint64_t* __restrict__ d_total, uint32_t* __restrict__ ids,
-    uint32_t* __restrict__ inst_gid, uint32_t* __restrict__ inst_off, uint2* __restrict__ ranges,
-    uint64_t capacity) {
+    uint32_t* __restrict__ gsort, uint32_t* __restrict__ inst_off, uint2* __restrict__ ranges, uint64_t capacity) {
     extern __shared__ uint64_t s_dyn[];
-    uint64_t* s_mask = s_dyn;                                       // [4][T] covering Gaussians
-    uint32_t* s_base = reinterpret_cast<uint32_t*>(s_dyn + 4 * T);  // [T] the block's first place per tile
-    __shared__ uint32_t s_tmp[RS_WAVES];
-    __shared__ uint32_t s_off[EX_THREADS];
-    __shared__ uint32_t s_gid[EX_THREADS];
-    __shared__ ushort4 s_rect[EX_THREADS];
-    __shared__ uint8_t s_owner[kPlaceWin];
+    uint64_t* s_mask = s_dyn;                                         // [4][T] Gaussians covering each tile
+    uint32_t* s_base = reinterpret_cast<uint32_t*>(s_dyn + 4 * T);    // [T] list position of the block's first
+    uint32_t* s_ls = s_base + T;                                      // [T + 1] start among the block's instances
+    uint16_t* s_town = reinterpret_cast<uint16_t*>(s_ls + T + 1);    // [win] tile of each instance of a window
+    __shared__ uint32_t s_tmp[PL_WAVES];
+    __shared__ uint32_t s_off[PL_GAUSS + 1];
+    __shared__ uint32_t s_gid[PL_GAUSS];
+    __shared__ ushort4 s_rect[PL_GAUSS];
     const int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
-    uint32_t c, ex, tot;
-    place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp, c, ex, tot);
+    const uint32_t tot = place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp);
     const uint64_t base = partials[(int64_t)v * nb + b];   // expansion index of the block's first instance
     const uint64_t vbase = partials[(int64_t)v * nb];      // ... and of the view's
     const bool over = *d_total > capacity;
-    if ((int64_t)b * EX_THREADS + tid < n)
-        inst_off[(int64_t)v * stride + s_gid[tid]] = (uint32_t)min(base + ex, capacity);
+    if (tid < PL_GAUSS && (int64_t)b * PL_GAUSS + tid < n)
+        inst_off[(int64_t)v * stride + s_gid[tid]] = (uint32_t)min(base + s_off[tid], capacity);
     // tile starts: the view's first index + exclusive scan of its tile totals
-    const int per = (T + EX_THREADS - 1) / EX_THREADS;
+    const int per = (T + PL_THREADS - 1) / PL_THREADS;
     const int ta = min(T, tid * per), tb = min(T, ta + per);
     const uint32_t* tt = tile_tot + (int64_t)v * T;
-    uint32_t loc = 0;
-    for (int t = ta; t < tb; ++t) loc += tt[t];
-    uint32_t all;
-    uint64_t start = vbase + block_excl_scan_256(loc, s_tmp, all);
     const uint32_t* crow = cnt + ((int64_t)v * nb + b) * T;
-    for (int t = ta; t < tb; ++t) {
-        const uint32_t rt = tt[t];
-        s_base[t] = (uint32_t)(start + crow[t]);
-        if (b == 0)
-            ranges[(int64_t)v * T + t] = (over || rt == 0) ? make_uint2(0u, 0u)
-                                                             : make_uint2((uint32_t)start, (uint32_t)(start + rt));
-        start += rt;
+    {
+        uint32_t loc = 0, all;
+        for (int t = ta; t < tb; ++t) loc += tt[t];
+        uint64_t start = vbase + block_excl_scan_1024(loc, s_tmp, all);
+        for (int t = ta; t < tb; ++t) {
+            const uint32_t rt = tt[t];
+            s_base[t] = (uint32_t)(start + crow[t]);
+            if (b == 0)
+                ranges[(int64_t)v * T + t] = (over || rt == 0) ? make_uint2(0u, 0u)
+                                                                 : make_uint2((uint32_t)start, (uint32_t)(start + rt));
+            start += rt;
+        }
     }
     if (over) return;   // nothing placed; the overflow is reported
-    for (int i = tid; i < 4 * T; i += EX_THREADS) s_mask[i] = 0ull;
+    for (int i = tid; i < 4 * T; i += PL_THREADS) s_mask[i] = 0ull;
     __syncthreads();
-    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx, [&](int lo, uint32_t t, uint32_t) {
-        atomicOr(reinterpret_cast<unsigned long long*>(&s_mask[(lo >> 6) * T + t]), 1ull << (lo & 63));
-    });
-    place_for_each(c, ex, tot, s_rect, s_off, s_owner, ntx, [&](int lo, uint32_t t, uint32_t j) {
-        const int q = lo >> 6;
-        uint32_t rank = (uint32_t)__popcll(s_mask[q * T + t] & ((1ull << (lo & 63)) - 1ull));
-        for (int k = 0; k < q; ++k) rank += (uint32_t)__popcll(s_mask[k * T + t]);
-        const uint64_t p = (uint64_t)s_base[t] + rank, e = base + j;
-        if (p < capacity && e < capacity) {
-            ids[p] = (uint32_t)e;
-            inst_gid[e] = s_gid[lo];
+    {   // masks: PL_PARTS threads per Gaussian walk its rectangle
+        const int g = tid % PL_GAUSS, part = tid / PL_GAUSS;
+        const ushort4 r = s_rect[g];
+        const uint32_t c = rect_tiles(r);
+        if ((uint32_t)part < c) {
+            const uint32_t w = (uint32_t)(r.y - r.x);
+            unsigned long long* mq = reinterpret_cast<unsigned long long*>(s_mask + (g >> 6) * T);
+            const unsigned long long bit = 1ull << (g & 63);
+            uint32_t x;
+            uint32_t y = r.z + divmod_small((uint32_t)part, w, x);
+            x += r.x;
+            for (uint32_t k = (uint32_t)part; k < c; k += PL_PARTS) {
+                atomicOr(&mq[y * (uint32_t)ntx + x], bit);
+                x += PL_PARTS;
+                while (x >= r.y) {
+                    x -= w;
+                    ++y;
+                }
+            }
         }
-    });
+    }
+    __syncthreads();
+    {   // the block's instances per tile and where each tile's run starts
+        uint32_t loc = 0, all;
+        for (int t = ta; t < tb; ++t)
+            loc += (uint32_t)(__popcll(s_mask[t]) + __popcll(s_mask[T + t]) + __popcll(s_mask[2 * T + t]) +
+                              __popcll(s_mask[3 * T + t]));
+        uint32_t st = block_excl_scan_1024(loc, s_tmp, all);
+        for (int t = ta; t < tb; ++t) {
+            s_ls[t] = st;
+            st += (uint32_t)(__popcll(s_mask[t]) + __popcll(s_mask[T + t]) + __popcll(s_mask[2 * T + t]) +
+                             __popcll(s_mask[3 * T + t]));
+        }
+        if (tid == 0) s_ls[T] = all;
+    }
+    // Tile-major walk over the block's instances in windows of `win`:
+    // consecutive threads write consecutive list positions of a tile.
+    for (uint32_t w0 = 0; w0 < tot; w0 += (uint32_t)win) {
+        const uint32_t w1 = min(tot, w0 + (uint32_t)win);
+        __syncthreads();
+        for (int t = ta; t < tb; ++t) {
+            const uint32_t a = max(s_ls[t], w0), e = min(s_ls[t + 1], w1);
+            for (uint32_t q = a; q < e; ++q) s_town[q - w0] = (uint16_t)t;
+        }
+        __syncthreads();
+        for (uint32_t q = w0 + tid; q < w1; q += PL_THREADS) {
+            const int t = s_town[q - w0];
+            const uint32_t rank = q - s_ls[t];
+            const uint32_t g = mask_select(s_mask, T, t, rank);
+            const ushort4 r = s_rect[g];
+            uint32_t tx;
+            const uint32_t ty = divmod_small((uint32_t)t, (uint32_t)ntx, tx);
+            const uint64_t e = base + s_off[g] + (ty - r.z) * (uint32_t)(r.y - r.x) + (tx - r.x);
+            const uint64_t p = (uint64_t)s_base[t] + rank;
+            if (p < capacity && e < capacity) {
+                ids[p] = (uint32_t)e;
+                gsort[p] = s_gid[g];
+            }
+        }
+    }
 }
 
 // keys[i] = tile of list position i, from the tile ranges (state export of
@@ -652,21 +820,26 @@ void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, i
                                                     partials, keys, vals, inst_gid, inst_off, capacity);
 }
 
-int64_t place_blocks(int64_t n) { return n > 0 ? (n + EX_THREADS - 1) / EX_THREADS : 1; }
+int64_t place_blocks(int64_t n) { return n > 0 ? (n + PL_GAUSS - 1) / PL_GAUSS : 1; }
 
-void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int T,
+void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv, int ntx, int nty,
                   uint32_t* cnt, uint32_t* tile_tot, uint64_t* partials, uint64_t* d_total, uint32_t* d_count,
-                  uint32_t* ids, uint32_t* inst_gid, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
+                  uint32_t* ids, uint32_t* gsort, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
                   uint32_t* flags, uint64_t* max_inst, const Clears& cl, hipStream_t s) {
     const int nb = (int)place_blocks(n);
+    const int T = ntx * nty;
     const dim3 grid((unsigned)nb, (unsigned)nv);
-    k_place_count<<<grid, EX_THREADS, (size_t)T * sizeof(uint32_t), s>>>(rect, order, stride, n, nb, ntx, T, cnt,
-                                                                         partials, cl);
+    // owner window: what is left of 64 KiB of LDS after the static part
+    // (< kPlaceStaticLds) and the per-tile arrays, at most 16384 instances
+    const int win = std::min<int>(
+        16384, (int)((65536 - kPlaceStaticLds - (int64_t)place_write_lds(T, 0)) / (int64_t)sizeof(uint16_t)) & ~255);
+    k_place_count<<<grid, PL_THREADS, (size_t)(nty + 1) * (ntx + 1) * sizeof(uint32_t), s>>>(
+        rect, order, stride, n, nb, ntx, nty, cnt, partials, cl);
     k_place_scan<<<dim3((unsigned)((T + 63) / 64 + 1), (unsigned)nv), 1024, 0, s>>>(
         cnt, nb, T, tile_tot, partials, (int64_t)nb * nv, d_total, d_count, capacity, flags, max_inst);
-    k_place_write<<<grid, EX_THREADS, (size_t)T * (4 * sizeof(uint64_t) + sizeof(uint32_t)), s>>>(
-        rect, order, stride, n, nb, ntx, T, cnt, tile_tot, partials, d_total, ids, inst_gid, inst_off, ranges,
-        capacity);
+    k_place_write<<<grid, PL_THREADS, place_write_lds(T, win), s>>>(rect, order, stride, n, nb, ntx, T, win, cnt,
+                                                                    tile_tot, partials, d_total, ids, gsort,
+                                                                    inst_off, ranges, capacity);
 }
 
 void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys, hipStream_t s) {
@@ -674,12 +847,28 @@ void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys
     k_keys_from_ranges<<<(unsigned)g, 256, 0, s>>>(ranges, ntiles, keys);
 }
 
-void launch_ranges(const uint32_t* keys, const uint32_t* d_count, int64_t capacity, uint2* ranges,
-                   hipStream_t s) {
+void launch_ranges(const uint32_t* keys, const uint32_t* ids, const uint32_t* inst_gid, const uint32_t* d_count,
+                   int64_t capacity, uint2* ranges, uint32_t* gsort, hipStream_t s) {
     int64_t blocks = (capacity + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_ranges<<<(unsigned)blocks, 256, 0, s>>>(keys, d_count, ranges);
+    k_ranges<<<(unsigned)blocks, 256, 0, s>>>(keys, ids, inst_gid, d_count, ranges, gsort);
+}
+
+// inst_gid[ids[i]] = gsort[i] for the d_count list positions (state export
+// of the placed lists, which are built without inst_gid).
+__global__ void k_gid_by_index(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ gsort,
+                               const uint32_t* d_count, uint32_t* __restrict__ inst_gid) {
+    const uint32_t count = *d_count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        inst_gid[ids[i]] = gsort[i];
+}
+
+void launch_gid_by_index(const uint32_t* ids, const uint32_t* gsort, const uint32_t* d_count, int64_t capacity,
+                         uint32_t* inst_gid, hipStream_t s) {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, 8192));
+    k_gid_by_index<<<(unsigned)blocks, 256, 0, s>>>(ids, gsort, d_count, inst_gid);
 }
 
 }  // namespace gsta

@@ -64,12 +64,20 @@ def _case(kind):
     if kind == "c2view":
         c = S.CONFIGS["c2"]
         return S.make_scene(c["n"], 3), 3, S.config_cameras("c2")[:1]
-    if kind == "tiles1536":   # 48x32 tiles: the largest view placed directly
+    if kind == "tiles1408":   # 44x32 tiles: the largest view placed directly
         p = S.make_scene(20000, 1, seed=9)
-        return p, 1, [S.look_at(15.0, 30.0, 768, 512)]
-    if kind == "tiles1560":   # 40x39 tiles: beyond placement, both options sort
+        return p, 1, [S.look_at(15.0, 30.0, 704, 512)]
+    if kind == "tiles1440":   # 48x30 tiles: beyond placement, both options sort
         p = S.make_scene(20000, 1, seed=9)
-        return p, 1, [S.look_at(15.0, 30.0, 640, 610)]
+        return p, 1, [S.look_at(15.0, 30.0, 768, 480)]
+    if kind == "wide":        # one row of 96 tiles
+        p = S.make_scene(3000, 2, seed=12)
+        p[3:6] += 0.4
+        return p, 2, [S.look_at(5.0, 40.0, 1536, 16)]
+    if kind == "tall":        # one column of 64 tiles
+        p = S.make_scene(3000, 2, seed=13)
+        p[3:6] += 0.4
+        return p, 2, [S.look_at(5.0, 40.0, 16, 1024)]
     if kind == "big":         # a few Gaussians covering hundreds of tiles each
         p = S.make_scene(600, 0, seed=10)
         p[3:6, :8] += 3.0
@@ -77,7 +85,7 @@ def _case(kind):
     raise KeyError(kind)
 
 
-@pytest.mark.parametrize("kind", ["tiny", "ragged", "views8", "c2view", "tiles1536", "tiles1560", "big"])
+@pytest.mark.parametrize("kind", ["tiny", "ragged", "views8", "c2view", "tiles1408", "tiles1440", "wide", "tall", "big"])
 def test_placement_equals_sorted_lists(kind):
     p, D, cams = _case(kind)
     print(f"binning {kind}: n={p.shape[1]} views={len(cams)} {cams[0].width}x{cams[0].height}", flush=True)

@@ -577,14 +577,17 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     const int ntx = ca.c[0].ntx;
     const int64_t T = (int64_t)ca.c[0].ntx * ca.c[0].nty;
 
+    // chunks of 256 keys: the preprocess writes the depth sort's first-pass
+    // histograms (its blocks are the sort's first chunks)
+    const bool hist_given = ctx->items_depth == 1;
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
-                              s.dkey[0], s.dval[0], S, stream);
+                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
-        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth};
+        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth, hist_given};
         s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
     }
     s.placed = ctx->binning == 0 && nv <= ctx->place_views && T <= kPlaceMaxTiles;

@@ -90,9 +90,12 @@ __device__ __forceinline__ float wave_sum(float x) {
 // Host launchers (all asynchronous on `s`).
 // -------------------------------------------------------------------------
 
+// hist0 (optional, [nv][256][ceil(n/256)]): the depth sort's first-pass
+// chunk histograms (chunks of 256 keys), for radix_sort_pairs with
+// first_hist_given.
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, hipStream_t s);
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, hipStream_t s);
 
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
 // expansion offsets inst_off[v][gid], in tile order, taking a slot only if
@@ -110,11 +113,16 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
 // seg_stride elements; element count per segment from d_count (device, if
 // not null) or h_count.  Sorts `bits` low-order key bits.  Returns which
 // buffer (0 or 1) holds the result.
+// first_hist_given (items 1, host count, 8-bit digits): the producer of the
+// keys has written the first pass's chunk histograms into `hist` (chunk =
+// 256 keys, row pitch ceil(h_count/256)), so that pass needs no histogram
+// kernel.
 struct RadixScratch {
     uint32_t* hist;          // [nseg][256][nchunks_cap]
     uint32_t* digit_tot;     // [nseg][256]
     int64_t nchunks_cap;     // chunks reserved per segment (device-count sorts)
     int items;               // keys per thread per chunk: 1, 4, 8 or 16
+    bool first_hist_given = false;
 };
 int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg,
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,

@@ -182,81 +182,101 @@ __device__ __forceinline__ void load_core(const float* __restrict__ P, int64_t l
 }
 
 template <int D>
+// hist0 (optional): the depth sort's first-pass (low 8 bits) digit counts of
+// the block's keys -- its 256 Gaussians are the sort's first chunk --
+// written to hist0[v][digit][blockIdx.x] with row pitch hpitch.
 __global__ __launch_bounds__(256) void k_preprocess_fwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     float4* __restrict__ geo, float4* __restrict__ col, float4* __restrict__ rgbo,
     ushort4* __restrict__ rect, uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-    int64_t stride) {
+    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch) {
     constexpr int K = (D + 1) * (D + 1);
+    __shared__ uint32_t s_h[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const bool valid = i < n;
+    if (!valid && !hist0) return;    // with hist0 every thread reaches the barriers
     float mu[3], s[3], qn[4], Rq[9], qinv, o;
-    load_core(P, ld, i, mu, s, qn, Rq, qinv, o);
     float f[K][3];
+    if (valid) {
+        load_core(P, ld, i, mu, s, qn, Rq, qinv, o);
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) f[k][ch] = P[(11 + 3 * k + ch) * ld + i];
+            for (int ch = 0; ch < 3; ++ch) f[k][ch] = P[(11 + 3 * k + ch) * ld + i];
+    }
 
     for (int v = 0; v < nv; ++v) {
-        const DevCam& cm = cams.c[v];
-        const int64_t o_idx = (int64_t)v * stride + i;
-        Geo g;
-        bool vis = project_geo(cm, mu, Rq, s, g);
-        ushort4 r = make_ushort4(0, 0, 0, 0);
-        float4 rg = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (vis) {
-            float ex = 3.0f * sqrtf(g.a), ey = 3.0f * sqrtf(g.c);
-            float x0 = ceilf((g.u - ex - (float)(kTile - 1)) * (1.0f / kTile));
-            float x1 = floorf((g.u + ex) * (1.0f / kTile)) + 1.0f;
-            float y0 = ceilf((g.v - ey - (float)(kTile - 1)) * (1.0f / kTile));
-            float y1 = floorf((g.v + ey) * (1.0f / kTile)) + 1.0f;
-            int tx0 = (int)fminf(fmaxf(x0, 0.f), (float)cm.ntx);
-            int tx1 = (int)fminf(fmaxf(x1, 0.f), (float)cm.ntx);
-            int ty0 = (int)fminf(fmaxf(y0, 0.f), (float)cm.nty);
-            int ty1 = (int)fminf(fmaxf(y1, 0.f), (float)cm.nty);
-            vis = (tx0 < tx1) && (ty0 < ty1);
+        if (hist0) {
+            s_h[threadIdx.x] = 0;
+            __syncthreads();
+        }
+        if (valid) {
+            const DevCam& cm = cams.c[v];
+            const int64_t o_idx = (int64_t)v * stride + i;
+            Geo g;
+            bool vis = project_geo(cm, mu, Rq, s, g);
+            ushort4 r = make_ushort4(0, 0, 0, 0);
+            float4 rg = make_float4(0.f, 0.f, 0.f, 0.f);
             if (vis) {
-                r = make_ushort4((unsigned short)tx0, (unsigned short)tx1, (unsigned short)ty0,
-                                 (unsigned short)ty1);
-                // SH colour with the unit direction from the camera centre.
-                float d[3] = {mu[0] - cm.pos[0], mu[1] - cm.pos[1], mu[2] - cm.pos[2]};
-                float il = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                float B[16];
-                sh_eval<D>(d[0] * il, d[1] * il, d[2] * il, B);
-                float cc[3];
+                float ex = 3.0f * sqrtf(g.a), ey = 3.0f * sqrtf(g.c);
+                float x0 = ceilf((g.u - ex - (float)(kTile - 1)) * (1.0f / kTile));
+                float x1 = floorf((g.u + ex) * (1.0f / kTile)) + 1.0f;
+                float y0 = ceilf((g.v - ey - (float)(kTile - 1)) * (1.0f / kTile));
+                float y1 = floorf((g.v + ey) * (1.0f / kTile)) + 1.0f;
+                int tx0 = (int)fminf(fmaxf(x0, 0.f), (float)cm.ntx);
+                int tx1 = (int)fminf(fmaxf(x1, 0.f), (float)cm.ntx);
+                int ty0 = (int)fminf(fmaxf(y0, 0.f), (float)cm.nty);
+                int ty1 = (int)fminf(fmaxf(y1, 0.f), (float)cm.nty);
+                vis = (tx0 < tx1) && (ty0 < ty1);
+                if (vis) {
+                    r = make_ushort4((unsigned short)tx0, (unsigned short)tx1, (unsigned short)ty0,
+                                     (unsigned short)ty1);
+                    // SH colour with the unit direction from the camera centre.
+                    float d[3] = {mu[0] - cm.pos[0], mu[1] - cm.pos[1], mu[2] - cm.pos[2]};
+                    float il = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    float B[16];
+                    sh_eval<D>(d[0] * il, d[1] * il, d[2] * il, B);
+                    float cc[3];
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    float acc = 0.f;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        float acc = 0.f;
 #pragma unroll
-                    for (int k = 0; k < K; ++k) acc += f[k][ch] * B[k];
-                    cc[ch] = fmaxf(acc + 0.5f, 0.f);
+                        for (int k = 0; k < K; ++k) acc += f[k][ch] * B[k];
+                        cc[ch] = fmaxf(acc + 0.5f, 0.f);
+                    }
+                    rg = make_float4(cc[0], cc[1], cc[2], g.xc[2]);
+                    geo[o_idx] = make_float4(g.u, g.v, g.c * g.inv, -g.b * g.inv);
+                    // Screen half-extent outside which no pixel can be a member:
+                    // power >= -4.5 and o exp(power) >= 1/255 bound d^T conic d by
+                    // 2 min(4.5, ln(255 o)).  Inflated by 1% + 0.5 px so float32
+                    // rounding never makes a skipped splat a member.
+                    const float lo = logf(255.0f * o);
+                    float ex2 = -1e30f, ey2 = -1e30f;
+                    if (lo > 0.f) {
+                        const float kf = sqrtf(2.0f * fminf(4.5f, lo));
+                        ex2 = kf * sqrtf(g.a) * 1.01f + 0.5f;
+                        ey2 = kf * sqrtf(g.c) * 1.01f + 0.5f;
+                    }
+                    col[o_idx] = make_float4(g.a * g.inv, o, ex2, ey2);
                 }
-                rg = make_float4(cc[0], cc[1], cc[2], g.xc[2]);
-                geo[o_idx] = make_float4(g.u, g.v, g.c * g.inv, -g.b * g.inv);
-                // Screen half-extent outside which no pixel can be a member:
-                // power >= -4.5 and o exp(power) >= 1/255 bound d^T conic d by
-                // 2 min(4.5, ln(255 o)).  Inflated by 1% + 0.5 px so float32
-                // rounding never makes a skipped splat a member.
-                const float lo = logf(255.0f * o);
-                float ex2 = -1e30f, ey2 = -1e30f;
-                if (lo > 0.f) {
-                    const float kf = sqrtf(2.0f * fminf(4.5f, lo));
-                    ex2 = kf * sqrtf(g.a) * 1.01f + 0.5f;
-                    ey2 = kf * sqrtf(g.c) * 1.01f + 0.5f;
-                }
-                col[o_idx] = make_float4(g.a * g.inv, o, ex2, ey2);
             }
+            if (!vis) {
+                geo[o_idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+                col[o_idx] = make_float4(0.f, 0.f, -1e30f, -1e30f);
+                if (g.xc[2] > cm.near_z) rg.w = g.xc[2];
+            }
+            rgbo[o_idx] = rg;
+            rect[o_idx] = r;
+            const uint32_t key = vis ? __float_as_uint(g.xc[2]) : 0xFFFFFFFFu;
+            dkey[o_idx] = key;
+            dval[o_idx] = (uint32_t)i;
+            if (hist0) atomicAdd(&s_h[key & 0xFFu], 1u);
         }
-        if (!vis) {
-            geo[o_idx] = make_float4(0.f, 0.f, 0.f, 0.f);
-            col[o_idx] = make_float4(0.f, 0.f, -1e30f, -1e30f);
-            if (g.xc[2] > cm.near_z) rg.w = g.xc[2];
+        if (hist0) {
+            __syncthreads();
+            hist0[((int64_t)v * 256 + threadIdx.x) * hpitch + blockIdx.x] = s_h[threadIdx.x];
+            __syncthreads();
         }
-        rgbo[o_idx] = rg;
-        rect[o_idx] = r;
-        dkey[o_idx] = vis ? __float_as_uint(g.xc[2]) : 0xFFFFFFFFu;
-        dval[o_idx] = (uint32_t)i;
     }
 }
 
@@ -527,14 +547,17 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, hipStream_t s) {
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const int64_t hp = (n + 255) / 256;
+#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp
     switch (degree) {
-        case 0: k_preprocess_fwd<0><<<grid, block, 0, s>>>(P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride); break;
-        case 1: k_preprocess_fwd<1><<<grid, block, 0, s>>>(P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride); break;
-        case 2: k_preprocess_fwd<2><<<grid, block, 0, s>>>(P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride); break;
-        default: k_preprocess_fwd<3><<<grid, block, 0, s>>>(P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride); break;
+        case 0: k_preprocess_fwd<0><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
+        case 1: k_preprocess_fwd<1><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
+        case 2: k_preprocess_fwd<2><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
+        default: k_preprocess_fwd<3><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
     }
+#undef GSTA_PRE_ARGS
 }
 
 void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,

@@ -771,11 +771,15 @@ int radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int n
     if (bits <= 0) return cur;
     const int passes = (bits + 7) / 8;
     const int per = (bits + passes - 1) / passes;
+    // first_hist_given: the producer of the keys wrote the first pass's
+    // histograms (chunks of 256 keys, host count)
+    const bool given = rs.first_hist_given && ITEMS == 1 && !d_count && per == 8;
     for (int shift = 0; shift < bits; shift += per) {
         const int pass_bits = (bits - shift) < per ? (bits - shift) : per;
-        k_radix_hist<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
-                                                                       shift, (1u << pass_bits) - 1u, rs.hist,
-                                                                       nchunks_cap);
+        if (!(given && shift == 0))
+            k_radix_hist<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(keys[cur], seg_stride, d_count, h_count,
+                                                                           shift, (1u << pass_bits) - 1u, rs.hist,
+                                                                           nchunks_cap);
         k_radix_scan<ITEMS><<<dim3(RS_BINS, nseg), RS_THREADS, 0, s>>>(rs.hist, rs.digit_tot, d_count, h_count,
                                                                         nchunks_cap);
         k_radix_scatter<ITEMS><<<dim3(grid_x, nseg), RS_THREADS, 0, s>>>(

@@ -1,13 +1,16 @@
 // Depth sort, tile binning and tile ranges.
 //
-// The paper blends Gaussians "in a sorted order" (Section 3.1).  Here the
-// order is (float32 camera depth, gid) per view, made in two stages:
+// The paper blends Gaussians in depth order (Section 3.1).  Here the order
+// is (float32 camera depth, gid) per view, made in two stages:
 //   1. a stable LSD radix sort of the N depth keys of every view (the
 //      culled ones carry the largest key and sort last);
-//   2. a depth-ordered expansion of each Gaussian into one (view*T + tile,
-//      gid) instance per tile of its 3-sigma rectangle, followed by a stable
-//      radix sort of those 16-bit-or-less tile keys.  Stability keeps the
-//      depth order inside every tile.
+//   2. per tile, the list of the Gaussians whose 3-sigma rectangle covers
+//      it, in that order: either placed directly (views of at most
+//      kPlaceMaxTiles tiles, see "Direct tile placement" below), or through
+//      a depth-ordered expansion of each Gaussian into one (view*T + tile,
+//      gid) instance per tile of its rectangle, followed by a stable radix
+//      sort of those 16-bit-or-less tile keys (stability keeps the depth
+//      order inside every tile).
 //
 // Radix sort: 8-bit digits, chunks of 256, 1024 or 4096 keys per workgroup
 // iteration (small, mid-size and large sorts).
@@ -396,8 +399,8 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __re
 //                  (+ the clears of the forward)
 //   k_place_scan   per 64 tiles: exclusive scan of cnt down the blocks and
 //                  tile totals; one extra workgroup scans the block totals
-//   k_place_write  per block: masks, ranks, ids and inst_gid; the view's
-//                  first block writes the tile ranges
+//   k_place_write  per block: masks, ranks, ids and gsort (gid per list
+//                  position); the view's first block writes the tile ranges
 // ---------------------------------------------------------------------------
 constexpr int PL_THREADS = 1024;                  // threads per placement workgroup
 constexpr int PL_GAUSS = 256;                     // Gaussians per block (4 x 64-bit masks per tile)

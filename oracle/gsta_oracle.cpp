@@ -279,8 +279,8 @@ void project(const double* P, int64_t n, int64_t ld, int degree, int64_t g, cons
     p.visible = (p.tx0 < p.tx1) && (p.ty0 < p.ty1);
 }
 
-// Visible Gaussians in ascending (float32 depth, gid) order: "sorted order"
-// of Section 3.1; equal depths keep ascending gid (stable sort).
+// Visible Gaussians in ascending (float32 depth, gid) order, the blending
+// order of Section 3.1; equal depths keep ascending gid (stable sort).
 std::vector<int64_t> depth_order(const std::vector<Proj>& pr) {
     std::vector<int64_t> ids;
     for (int64_t g = 0; g < (int64_t)pr.size(); ++g)

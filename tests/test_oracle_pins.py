@@ -212,7 +212,7 @@ def test_ellipse_bounding_box_is_tight():
 
 
 # ---------------------------------------------------------------------------
-# Binning, order, brute force, invariants (eq. 2, "sorted order")
+# Binning, order, brute force, invariants (eq. 2, depth-ordered blending)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("degree,n,size", [(0, 400, 48), (3, 300, 40)])

@@ -89,8 +89,11 @@ typedef struct {
 
 /* Fields readable with gsta_get_state (after gsta_render_forward). */
 typedef enum {
-    GSTA_STATE_REC_GEO = 0,     /* float4 [V][N]: u, v, conic_a, conic_b           */
-    GSTA_STATE_REC_COL = 1,     /* float4 [V][N]: conic_c, opacity, conservative screen half-extents x, y */
+    GSTA_STATE_REC_GEO = 0,     /* float4 [V][N]: u, v, A, B: the conic (a, b) scaled so that the
+                                   base-2 exponent is A dx^2 + B dx dy + C dy^2
+                                   (A = -a log2(e)/2, B = -b log2(e))          */
+    GSTA_STATE_REC_COL = 1,     /* float4 [V][N]: C = -c log2(e)/2, opacity, conservative screen
+                                   half-extents x, y */
     GSTA_STATE_REC_RGB = 2,     /* float4 [V][N]: r, g, b (clamped colour), camera depth z */
     GSTA_STATE_RECT = 3,        /* uint16x4 [V][N]: tile x0, x1, y0, y1 (exclusive ends); all 0 if culled */
     GSTA_STATE_DEPTH_ORDER = 4, /* uint32 [V][N]: gid in ascending (float32 depth, gid) order, culled last */

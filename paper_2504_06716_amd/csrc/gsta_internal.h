@@ -19,6 +19,13 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+// The splat records hold the conic pre-scaled so that one pixel's exponent
+// comes out in base 2: A = -log2(e)/2 a, B = -log2(e) b, C = -log2(e)/2 c,
+// power2 = A dx^2 + B dx dy + C dy^2 = log2(e) (-(a dx^2 + c dy^2)/2 - b dx dy).
+constexpr float kConicScaleAC = -0.5f * kLog2e;
+constexpr float kConicScaleB = -kLog2e;
+constexpr float kPower2Floor = kPowerFloor * kLog2e;   // the 3-sigma floor in base-2 units
 
 struct DevCam {
     int width, height;
@@ -44,33 +51,36 @@ inline __host__ __device__ int n_rows(int degree) { return 11 + 3 * (degree + 1)
 // -------------------------------------------------------------------------
 // Splat evaluation shared by the forward and backward compositing kernels.
 // Both kernels must take bit-identical membership/termination decisions and
-// transmittance values, so the arithmetic lives in one place with
-// floating-point contraction disabled.
+// transmittance values, so the arithmetic lives in one place, written with
+// explicit fused multiply-adds and floating-point contraction disabled.
 // -------------------------------------------------------------------------
 struct SplatEval {
-    float dx, dy, power, G, oG, alpha;
+    float dx, dy, power2, G, oG, alpha;   // power2: the exponent in base 2 (power * log2 e)
 };
 
 // Split in two so that a wave can skip the exponential when none of its
-// pixels lies inside the splat's 3-sigma ellipse.
-__device__ __forceinline__ void eval_power(float u, float v, float ca, float cb, float cc, float px, float py,
+// pixels lies inside the splat's 3-sigma ellipse.  A, B, C: the scaled conic
+// of the record (kConicScaleAC, kConicScaleB).
+__device__ __forceinline__ void eval_power(float u, float v, float A, float B, float C, float px, float py,
                                            SplatEval& e) {
 #pragma clang fp contract(off)
     e.dx = u - px;
     e.dy = v - py;
-    e.power = -0.5f * (ca * e.dx * e.dx + cc * e.dy * e.dy) - cb * e.dx * e.dy;
+    float t = (A * e.dx) * e.dx;
+    t = fmaf(C * e.dy, e.dy, t);
+    e.power2 = fmaf(B * e.dx, e.dy, t);
 }
 
 __device__ __forceinline__ void eval_alpha(float o, SplatEval& e) {
 #pragma clang fp contract(off)
-    e.G = __builtin_amdgcn_exp2f(e.power * kLog2e);
+    e.G = __builtin_amdgcn_exp2f(e.power2);
     e.oG = o * e.G;
     e.alpha = fminf(kAlphaMax, e.oG);
 }
 
-__device__ __forceinline__ void eval_splat(float u, float v, float ca, float cb, float cc, float o,
+__device__ __forceinline__ void eval_splat(float u, float v, float A, float B, float C, float o,
                                            float px, float py, SplatEval& e) {
-    eval_power(u, v, ca, cb, cc, px, py, e);
+    eval_power(u, v, A, B, C, px, py, e);
     eval_alpha(o, e);
 }
 

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
                         cc[ch] = fmaxf(acc + 0.5f, 0.f);
                     }
                     rg = make_float4(cc[0], cc[1], cc[2], g.xc[2]);
-                    geo[o_idx] = make_float4(g.u, g.v, g.c * g.inv, -g.b * g.inv);
+                    // conic (a, b, c) = (c', -b', a') / det, stored pre-scaled (kConicScale*)
+                    geo[o_idx] = make_float4(g.u, g.v, (g.c * g.inv) * kConicScaleAC, (-g.b * g.inv) * kConicScaleB);
                     // Screen half-extent outside which no pixel can be a member:
                     // power >= -4.5 and o exp(power) >= 1/255 bound d^T conic d by
                     // 2 min(4.5, ln(255 o)).  Inflated by 1% + 0.5 px so float32
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
                         ex2 = kf * sqrtf(g.a) * 1.01f + 0.5f;
                         ey2 = kf * sqrtf(g.c) * 1.01f + 0.5f;
                     }
-                    col[o_idx] = make_float4(g.a * g.inv, o, ex2, ey2);
+                    col[o_idx] = make_float4((g.a * g.inv) * kConicScaleAC, o, ex2, ey2);
                 }
             }
             if (!vis) {

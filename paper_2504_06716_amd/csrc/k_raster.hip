@@ -41,11 +41,11 @@ __device__ __forceinline__ float row_sum(float v) {
     return v;
 }
 
-// One splat record as staged in LDS: mean + conic (a, b), conic c +
-// opacity, colour.
+// One splat record as staged in LDS: mean + scaled conic (A, B), scaled
+// conic C + opacity, colour.
 struct Rec {
-    float4 g;    // u, v, conic a, conic b
-    float4 co;   // conic c, opacity, half-extent x, half-extent y
+    float4 g;    // u, v, A, B (conic scaled by kConicScaleAC, kConicScaleB)
+    float4 co;   // C, opacity, half-extent x, half-extent y
     float4 c;    // r, g, b
 };
 
@@ -233,8 +233,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                     SplatEval e0, e1;
                     eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
                     eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
-                    const bool m0 = e0.power >= kPowerFloor && e0.alpha >= kAlphaMin;
-                    const bool m1 = two && e1.power >= kPowerFloor && e1.alpha >= kAlphaMin;
+                    const bool m0 = e0.power2 >= kPower2Floor && e0.alpha >= kAlphaMin;
+                    const bool m1 = two && e1.power2 >= kPower2Floor && e1.alpha >= kAlphaMin;
                     const float T0 = T[p];
                     const float Tn0 = next_T(T0, e0.alpha);
                     const bool t0 = m0 && Tn0 < kTMin;
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                         const bool act = pos < last[p];
                         if (CNT) evals += act ? 1u : 0u;
                         eval_power(g.x, g.y, g.z, g.w, co.x, fpx[p], fpy[p], e[p]);
-                        mem[p] = act && (e[p].power >= kPowerFloor);
+                        mem[p] = act && (e[p].power2 >= kPower2Floor);
                         any = any || mem[p];
                     }
                     bool contrib = false;
@@ -527,10 +527,13 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                                 g9[7] += dC[p][1] * w;
                                 g9[8] += dC[p][2] * w;
                                 if (e[p].oG <= kAlphaMax) {
+                                    // d power / d(u, v) = -(a dx + b dy, b dx + c dy)
+                                    //                   = ln 2 (2 A dx + B dy, B dx + 2 C dy)
                                     const float dpow = dalpha * e[p].alpha;
+                                    const float dpl = dpow * kLn2;
                                     g9[5] += dalpha * e[p].G;
-                                    g9[0] -= dpow * (g.z * e[p].dx + g.w * e[p].dy);
-                                    g9[1] -= dpow * (g.w * e[p].dx + co.x * e[p].dy);
+                                    g9[0] += dpl * (2.0f * g.z * e[p].dx + g.w * e[p].dy);
+                                    g9[1] += dpl * (g.w * e[p].dx + 2.0f * co.x * e[p].dy);
                                     g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
                                     g9[3] -= dpow * e[p].dx * e[p].dy;
                                     g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;

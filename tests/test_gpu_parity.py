@@ -87,10 +87,13 @@ def test_preprocess_records(kind):
         assert (col[v, both, 3][can] >= kf * np.sqrt(rb[can, 7]) - 1e-3).all()
         np.testing.assert_allclose(geo[v, both, 0], r[both, 1], atol=2e-4, rtol=1e-6)
         np.testing.assert_allclose(geo[v, both, 1], r[both, 2], atol=2e-4, rtol=1e-6)
+        # the records hold the conic scaled for a base-2 exponent:
+        # (A, B, C) = (-a/2, -b, -c/2) * log2(e)
+        l2e = np.log2(np.e)
+        conic = [geo[v, both, 2] / (-0.5 * l2e), geo[v, both, 3] / -l2e, col[v, both, 0] / (-0.5 * l2e)]
         cmax = np.maximum(np.abs(r[both, 9]), np.abs(r[both, 11]))
-        for k, j in ((2, 9), (3, 10)):
-            assert (np.abs(geo[v, both, k] - r[both, j]) <= 1e-4 * cmax).all()
-        assert (np.abs(col[v, both, 0] - r[both, 11]) <= 1e-4 * cmax).all()
+        for got, j in zip(conic, (9, 10, 11)):
+            assert (np.abs(got - r[both, j]) <= 1e-4 * cmax).all()
         np.testing.assert_allclose(col[v, both, 1], r[both, 24], atol=1e-6)
         np.testing.assert_allclose(rgb[v, both, :3], r[both, 18:21], atol=2e-5)
         ok = ~marg

@@ -196,6 +196,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             s_geo[tid] = cur.g;
             s_co[tid] = cur.co;
             s_rgb[tid] = cur.c;
+        } else if (base + tid == rg.y) {
+            // a zero-opacity record after the list's last splat: a two-splat
+            // step that reaches past the end evaluates it and it is never a member
+            s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (ckpt && tid == 0) {
             s_ckbase = ck_next;
@@ -217,48 +223,57 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         // exponentials overlap; the transmittance then advances through them
         // in list order with selects (the same operations on the same values
         // as one splat at a time), and one branch adds the colour.
-        for (int k = 0; k < cnt && !alldone; k += 2) {
-            const uint32_t pos = base - rg.x + (uint32_t)k;     // even: segment boundaries fall here
-            if (!QUAD && pos != 0u && (pos & kmask) == 0u)
-                fwd_checkpoint<W, P, B>(sc, base + (uint32_t)k, k, s_ckbase, tid, done, T, C);
-            const bool two = k + 1 < cnt;
-            const int k1 = two ? k + 1 : k;
-            const float4 g0 = s_geo[k], g1 = s_geo[k1];
-            const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
-            bool all = true;
-            if (CNT) witer += two ? 2u : 1u;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (!done[p]) {
-                    SplatEval e0, e1;
-                    eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
-                    eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
-                    const bool m0 = e0.power2 >= kPower2Floor && e0.alpha >= kAlphaMin;
-                    const bool m1 = two && e1.power2 >= kPower2Floor && e1.alpha >= kAlphaMin;
-                    const float T0 = T[p];
-                    const float Tn0 = next_T(T0, e0.alpha);
-                    const bool t0 = m0 && Tn0 < kTMin;
-                    const bool c0 = m0 && !t0;
-                    const float T1 = c0 ? Tn0 : T0;
-                    const float Tn1 = next_T(T1, e1.alpha);
-                    const bool t1 = !t0 && m1 && Tn1 < kTMin;
-                    const bool c1 = !t0 && m1 && !t1;
-                    if (c0 || c1) {
-                        const float4 ca = s_rgb[k], cb = s_rgb[k1];
-                        const double w0 = c0 ? (double)(e0.alpha * T0) : 0.0;
-                        const double w1 = c1 ? (double)(e1.alpha * T1) : 0.0;
-                        C[p][0] = fma((double)cb.x, w1, fma((double)ca.x, w0, C[p][0]));
-                        C[p][1] = fma((double)cb.y, w1, fma((double)ca.y, w0, C[p][1]));
-                        C[p][2] = fma((double)cb.z, w1, fma((double)ca.z, w0, C[p][2]));
-                        last[p] = c1 ? pos + 2u : pos + 1u;
-                    }
-                    T[p] = c1 ? Tn1 : T1;
-                    done[p] = t0 || t1;
-                    if (CNT) evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
-                }
-                all = all && done[p];
+        // Checkpoints fall on chunk starts: chunks of K splats (of the batch
+        // when K is longer), so the steps inside a chunk test nothing.
+        const int L = ckpt ? min(B, 1 << sc.shift) : B;
+        for (int kc = 0; kc < cnt && !alldone; kc += L) {
+            {
+                const uint32_t pos0 = base - rg.x + (uint32_t)kc;
+                if (ckpt && pos0 != 0u && (pos0 & kmask) == 0u)
+                    fwd_checkpoint<W, P, B>(sc, base + (uint32_t)kc, kc, s_ckbase, tid, done, T, C);
             }
-            alldone = all;
+            const int kend = min(cnt, kc + L);
+            for (int k = kc; k < kend && !alldone; k += 2) {
+                const uint32_t pos = base - rg.x + (uint32_t)k;
+                const int k1 = k + 1;                  // k1 == cnt: the zero-opacity record
+                const bool two = k1 < cnt;             // (counted by the counting variant only)
+                const float4 g0 = s_geo[k], g1 = s_geo[k1];
+                const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
+                bool all = true;
+                if (CNT) witer += two ? 2u : 1u;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (!done[p]) {
+                        SplatEval e0, e1;
+                        eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
+                        eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
+                        const bool m0 = e0.power2 >= kPower2Floor && e0.alpha >= kAlphaMin;
+                        const bool m1 = e1.power2 >= kPower2Floor && e1.alpha >= kAlphaMin;
+                        const float T0 = T[p];
+                        const float Tn0 = next_T(T0, e0.alpha);
+                        const bool t0 = m0 && Tn0 < kTMin;
+                        const bool c0 = m0 && !t0;
+                        const float T1 = c0 ? Tn0 : T0;
+                        const float Tn1 = next_T(T1, e1.alpha);
+                        const bool t1 = !t0 && m1 && Tn1 < kTMin;
+                        const bool c1 = !t0 && m1 && !t1;
+                        if (c0 || c1) {
+                            const float4 ca = s_rgb[k], cb = s_rgb[k1];
+                            const double w0 = c0 ? (double)(e0.alpha * T0) : 0.0;
+                            const double w1 = c1 ? (double)(e1.alpha * T1) : 0.0;
+                            C[p][0] = fma((double)cb.x, w1, fma((double)ca.x, w0, C[p][0]));
+                            C[p][1] = fma((double)cb.y, w1, fma((double)ca.y, w0, C[p][1]));
+                            C[p][2] = fma((double)cb.z, w1, fma((double)ca.z, w0, C[p][2]));
+                            last[p] = c1 ? pos + 2u : pos + 1u;
+                        }
+                        T[p] = c1 ? Tn1 : T1;
+                        done[p] = t0 || t1;
+                        if (CNT) evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
+                    }
+                    all = all && done[p];
+                }
+                alldone = all;
+            }
         }
     }
     if (CNT) {

@@ -388,6 +388,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
         s_pairs = 0;
         s_grad = 0;
     }
+    // row totals start at zero; only steps with gradient work write theirs,
+    // and each flush clears what it has read
+    for (int i = tid; i < 4 * W * 9 * kChunk; i += NT) (&s_part[0][0][0])[i] = 0.f;
+    __syncthreads();
 
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int gt = (int)sc.item_tile[item];     // the item's tile
@@ -564,12 +568,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
 #pragma unroll
                                 for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = g9[q];
                             }
-                            continue;
                         }
-                    }
-                    if ((lane & 15) == 0) {
-#pragma unroll
-                        for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = 0.f;
                     }
                 }
                 {
@@ -583,8 +582,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
 #pragma unroll
                             for (int q = 0; q < 9; ++q) {
                                 float acc = s_part[0][q][tid];
+                                s_part[0][q][tid] = 0.f;
 #pragma unroll
-                                for (int w = 1; w < 4 * W; ++w) acc += s_part[w][q][tid];
+                                for (int w = 1; w < 4 * W; ++w) {
+                                    acc += s_part[w][q][tid];
+                                    s_part[w][q][tid] = 0.f;
+                                }
                                 sum[q] = acc;
                                 nz = nz || (acc != 0.f);
                             }

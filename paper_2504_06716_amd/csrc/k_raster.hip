@@ -58,19 +58,16 @@ __device__ __forceinline__ Rec fetch_rec(const float4* __restrict__ geo, const f
     return r;
 }
 
-// Pixel p of thread tid.  Tile mode: 4/W pixels per thread, rows interleaved
-// by the block size.  Quadrant mode (one wave per 8x8 quarter of the tile,
-// blockIdx.x = 4 * tile + quarter): one pixel per lane.
+// Pixel p of thread tid.  Every 64-pixel group (the unit of the checkpoints)
+// is an 8x8 quarter of the tile, lane l at (l % 8, l / 8) in it.  Tile mode:
+// 4/W pixels per thread, group wave + p W.  Quadrant mode (one wave per
+// quarter, blockIdx.x = 4 * tile + quarter): one pixel per lane.
 template <int W, bool QUAD>
 __device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, int ty0, int& px, int& py) {
-    if (QUAD) {
-        px = tx0 + (quarter & 1) * 8 + (tid & 7);
-        py = ty0 + (quarter >> 1) * 8 + (tid >> 3);
-    } else {
-        const int pix = tid + p * 64 * W;
-        px = tx0 + (pix & (kTile - 1));
-        py = ty0 + pix / kTile;
-    }
+    const int lane = tid & 63;
+    const int g = QUAD ? quarter : (tid >> 6) + p * W;
+    px = tx0 + (g & 1) * 8 + (lane & 7);
+    py = ty0 + (g >> 1) * 8 + (lane >> 3);
 }
 
 // Pool slots a batch of B list positions reserves for its segment

@@ -625,7 +625,7 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
-        s.shift = ctx->fwd_waves == 0 ? 31u : ctx->seg_shift;    // no checkpoints in quadrant mode
+        s.shift = ctx->seg_shift;
         launch_composite_fwd(ctx->fwd_waves, s.ranges, s.gsort, s.geo, s.col, s.rgb, S, ca,
                              nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, seg_ckpt(ctx, s),
                              pair_counter(ctx, 0), stream);

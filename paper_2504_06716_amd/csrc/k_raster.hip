@@ -70,11 +70,12 @@ __device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, i
     py = ty0 + (g >> 1) * 8 + (lane >> 3);
 }
 
-// Pool slots a batch of B list positions reserves for its segment
-// boundaries: one per 64-pixel group and boundary.
-template <int B>
+// Pool slots a workgroup reserves per batch of B list positions for its
+// segment boundaries: one per boundary and 64-pixel group it holds (all four
+// in tile mode, its own quarter in quadrant mode).
+template <int B, bool QUAD>
 __device__ __forceinline__ uint32_t batch_slots(uint32_t shift) {
-    return (uint32_t)kCkptGroups * ((uint32_t)(B - 1) / (1u << shift) + 1u);
+    return (QUAD ? 1u : (uint32_t)kCkptGroups) * ((uint32_t)(B - 1) / (1u << shift) + 1u);
 }
 
 // Whether the batch at list offset b0 (a multiple of B) of a list of len
@@ -91,9 +92,10 @@ __device__ __forceinline__ bool batch_has_boundary(uint32_t b0, uint32_t len, ui
 // pixels.  Called with the lanes that are still walking; done lanes are
 // inactive.  The group's pool slot is fixed by the batch's block of slots
 // (ckbase, reserved by the workgroup a batch ahead): no counter on the walk.
-template <int W, int P, int B>
+template <int W, int P, int B, bool QUAD>
 __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, int k, uint32_t ckbase, int tid,
-                                               const bool* done, const float* T, const double (*C)[3]) {
+                                               int quarter, const bool* done, const float* T,
+                                               const double (*C)[3]) {
     const int lane = tid & 63, wid = tid >> 6;
     const size_t bucket = (size_t)(gpos >> sc.shift);
 #pragma unroll
@@ -101,8 +103,10 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
         const uint64_t m = __ballot(!done[p]);
         if (m == 0ull) continue;
         const int first = __builtin_ctzll(m);
-        const int g = wid + p * W;                    // 64-pixel group of pixel p
-        const uint64_t slot64 = (uint64_t)ckbase + (uint64_t)kCkptGroups * ((uint32_t)k >> sc.shift) + (uint64_t)g;
+        const int g = QUAD ? quarter : wid + p * W;   // 64-pixel group of pixel p
+        const uint64_t slot64 = QUAD ? (uint64_t)ckbase + ((uint32_t)k >> sc.shift)
+                                     : (uint64_t)ckbase + (uint64_t)kCkptGroups * ((uint32_t)k >> sc.shift) +
+                                           (uint64_t)g;
         const bool ok = ckbase != kNoSlot && slot64 < (uint64_t)sc.pool_cap;
         const uint32_t slot = (uint32_t)slot64;
         if (lane == first) {
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         s_last = 0;
     }
     // checkpoints at list positions that are multiples of K (none in quadrant mode)
-    const uint32_t kmask = (QUAD || sc.shift >= 31u) ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
+    const uint32_t kmask = sc.shift >= 31u ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
     const bool ckpt = kmask != 0xFFFFFFFFu;
     const uint32_t len = rg.y - rg.x;
     // The first batch's boundary slots are the tile's own; thread 0 reserves
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     // reserved block unused).
     uint32_t ck_next = kNoSlot;
     if (ckpt && tid == 0 && batch_has_boundary<B>(0u, len, sc.shift))
-        ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax;
+        ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax + (QUAD ? (uint32_t)quarter * batch_slots<B, QUAD>(sc.shift) : 0u);
 
     // Two-stage software pipeline: while a batch is composited, the records
     // of the next batch and the ids of the one after are in flight.
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             s_ckbase = ck_next;
             const uint32_t b1 = base - rg.x + (uint32_t)B;
             ck_next = batch_has_boundary<B>(b1, len, sc.shift)
-                          ? sc.first_slots + atomicAdd(sc.ctr, batch_slots<B>(sc.shift)) : kNoSlot;
+                          ? sc.first_slots + atomicAdd(sc.ctr, batch_slots<B, QUAD>(sc.shift)) : kNoSlot;
         }
         __syncthreads();
         {
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             {
                 const uint32_t pos0 = base - rg.x + (uint32_t)kc;
                 if (ckpt && pos0 != 0u && (pos0 & kmask) == 0u)
-                    fwd_checkpoint<W, P, B>(sc, base + (uint32_t)kc, kc, s_ckbase, tid, done, T, C);
+                    fwd_checkpoint<W, P, B, QUAD>(sc, base + (uint32_t)kc, kc, s_ckbase, tid, quarter, done, T, C);
             }
             const int kend = min(cnt, kc + L);
             for (int k = kc; k < kend && !alldone; k += 2) {

@@ -424,6 +424,32 @@ def test_waves_per_tile_options(fwd, bwd):
 
 
 @pytest.mark.parametrize("kind", ["ragged", "c2view"])
+def test_quadrant_forward_checkpoints_equal_tile_mode(kind):
+    """The quadrant-mode forward (one workgroup per 8x8 quarter) takes the
+    same per-pixel steps as the tile mode and writes its own quarter's
+    checkpoints: image, final state and segmented-backward gradients are
+    bit-identical."""
+    import torch
+    from paper_2504_06716_amd import _lib as L
+    p, D, cams = scene(kind)
+    H, W = cams[0].height, cams[0].width
+    dL = np.random.default_rng(5).standard_normal((len(cams), 3, H, W)).astype(np.float32)
+    out = []
+    for fwd in (4, 0):
+        print(f"quadrant checkpoints {kind}: forward waves {fwd}", flush=True)
+        g = GpuScene(p, D, cams)
+        g.ctx.set_waves(fwd=fwd, bwd=2)
+        img = g.forward()
+        last = g.state(L.STATE_LAST, torch.int32, (len(cams), H, W))
+        grad, g2, _ = g.backward(dL)
+        assert g.ctx.check()[0] == 0
+        out.append((img, last, grad, g2))
+    assert int(out[0][1].max()) > 64          # several segments per tile
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kind", ["ragged", "c2view"])
 def test_backward_segments_are_bit_identical(kind):
     """Splitting each tile's backward walk into segments that resume from
     the forward's checkpoints changes the schedule only: images, per-view

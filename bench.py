@@ -33,7 +33,7 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 # no-freeze run, quantile q = 0.4: the largest of 0.1, 0.2, 0.3, 0.4, 0.45,
 # 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
 C2_EPS0 = (1.0214666633002803e-06, 2.4916703086761885e-08)
-FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 4, 2, 64    # launch shape (the library defaults)
+FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 0, 2, 64    # launch shape (the library defaults; forward 0 = per quarter)
 COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_compositing_pmc.md")
 FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)
@@ -325,7 +325,7 @@ def main():
         "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],
         "bwd_grad_pairs_per_iter": pairs_all[5] / steps,
         # pairs per (wave iteration x 64 lanes x pixels per lane)
-        "lane_utilisation": [round(pairs_all[0] / max(64 * (4 // FWD_WAVES) * pairs_all[2], 1), 4),
+        "lane_utilisation": [round(pairs_all[0] / max(64 * (4 // FWD_WAVES if FWD_WAVES else 1) * pairs_all[2], 1), 4),
                              round(pairs_all[1] / max(64 * (4 // BWD_WAVES) * pairs_all[3], 1), 4)],
         "max_instances": max_inst,
     }

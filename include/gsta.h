@@ -109,9 +109,9 @@ typedef enum {
 
 /* Execution options (gsta_set_option).  They change speed, never results. */
 typedef enum {
-    GSTA_OPT_FWD_WAVES = 0,     /* waves per 16x16 tile in forward compositing: 1, 2 or 4 (default 4),
-                                   or 0: one independent wave per 8x8 quarter of each tile (each
-                                   writes its quarter's backward checkpoints) */
+    GSTA_OPT_FWD_WAVES = 0,     /* forward compositing: 0 (default): one independent wave per 8x8
+                                   quarter of each tile, each writing its quarter's backward
+                                   checkpoints; or 1, 2 or 4 waves per 16x16 tile */
     GSTA_OPT_BWD_WAVES = 1,     /* waves per tile in backward compositing: 1, 2 or 4 (default 2) */
     GSTA_OPT_BWD_SEGMENT = 2,   /* splats per backward work item: 0 (one item per tile) or a power of
                                    two in [64, 65536] (default 64).  The forward checkpoints every

@@ -16,9 +16,9 @@ import torch
 
 from .train import Trainer, TrainConfig
 
-CANDIDATES = [dict(fwd=4, bwd=4, graph=False), dict(fwd=0, bwd=4, graph=False),
-              dict(fwd=4, bwd=2, graph=False), dict(fwd=2, bwd=2, graph=False),
-              dict(fwd=4, bwd=4, graph=True), dict(fwd=0, bwd=4, graph=True)]
+CANDIDATES = [dict(fwd=0, bwd=2, graph=False), dict(fwd=0, bwd=4, graph=False),
+              dict(fwd=4, bwd=2, graph=False), dict(fwd=4, bwd=4, graph=False),
+              dict(fwd=0, bwd=2, graph=True), dict(fwd=4, bwd=2, graph=True)]
 
 _DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gsta_autotune.json")
 

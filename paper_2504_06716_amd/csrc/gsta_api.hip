@@ -79,7 +79,7 @@ struct gsta_ctx {
     uint32_t* gen = nullptr;       // [1] backward generation (starts at 1; stamps start at 0)
     float* d2sum = nullptr;        // [V][9][stride] per-view 2-D gradient of each Gaussian
     double2* loss_part = nullptr;  // [kL1Blocks] loss partial sums
-    int fwd_waves = 4, bwd_waves = 2;
+    int fwd_waves = 0, bwd_waves = 2;   // forward: one workgroup per 8x8 quarter
     uint32_t seg_shift = 6;        // backward segments of 64 splats (31: off)
     uint32_t pool_cap = 0;         // checkpoint slots per state slot
     uint32_t first_slots = 0;      // of which the tiles' first batches own the first ones

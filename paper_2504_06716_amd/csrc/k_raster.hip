@@ -70,13 +70,16 @@ __device__ __forceinline__ void pixel_of(int tid, int p, int quarter, int tx0, i
     py = ty0 + (g >> 1) * 8 + (lane >> 3);
 }
 
-// Pool slots a workgroup reserves per batch of B list positions for its
-// segment boundaries: one per boundary and 64-pixel group it holds (all four
-// in tile mode, its own quarter in quadrant mode).
-template <int B, bool QUAD>
+// Pool slots a tile-mode workgroup reserves per batch of B list positions for
+// its segment boundaries: one per boundary and 64-pixel group.
+template <int B>
 __device__ __forceinline__ uint32_t batch_slots(uint32_t shift) {
-    return (QUAD ? 1u : (uint32_t)kCkptGroups) * ((uint32_t)(B - 1) / (1u << shift) + 1u);
+    return (uint32_t)kCkptGroups * ((uint32_t)(B - 1) / (1u << shift) + 1u);
 }
+
+// Quadrant mode (batches of 64): a quarter reserves its slots per block of
+// S = max(256, K) list positions, S / K of them, one batch ahead.
+__device__ __forceinline__ uint32_t quad_block(uint32_t shift) { return max(256u, 1u << shift); }
 
 // Whether the batch at list offset b0 (a multiple of B) of a list of len
 // positions holds a segment boundary (a positive multiple of K).
@@ -92,9 +95,11 @@ __device__ __forceinline__ bool batch_has_boundary(uint32_t b0, uint32_t len, ui
 // pixels.  Called with the lanes that are still walking; done lanes are
 // inactive.  The group's pool slot is fixed by the batch's block of slots
 // (ckbase, reserved by the workgroup a batch ahead): no counter on the walk.
+// sub: the boundary's index within the reserved block (tile mode: within
+// the batch; quadrant mode: within the S-position block).
 template <int W, int P, int B, bool QUAD>
-__device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, int k, uint32_t ckbase, int tid,
-                                               int quarter, const bool* done, const float* T,
+__device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos, uint32_t sub, uint32_t ckbase,
+                                               int tid, int quarter, const bool* done, const float* T,
                                                const double (*C)[3]) {
     const int lane = tid & 63, wid = tid >> 6;
     const size_t bucket = (size_t)(gpos >> sc.shift);
@@ -104,9 +109,8 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
         if (m == 0ull) continue;
         const int first = __builtin_ctzll(m);
         const int g = QUAD ? quarter : wid + p * W;   // 64-pixel group of pixel p
-        const uint64_t slot64 = QUAD ? (uint64_t)ckbase + ((uint32_t)k >> sc.shift)
-                                     : (uint64_t)ckbase + (uint64_t)kCkptGroups * ((uint32_t)k >> sc.shift) +
-                                           (uint64_t)g;
+        const uint64_t slot64 = QUAD ? (uint64_t)ckbase + sub
+                                     : (uint64_t)ckbase + (uint64_t)kCkptGroups * sub + (uint64_t)g;
         const bool ok = ckbase != kNoSlot && slot64 < (uint64_t)sc.pool_cap;
         const uint32_t slot = (uint32_t)slot64;
         if (lane == first) {
@@ -178,9 +182,14 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     // each later batch's block from the counter one batch ahead, so the
     // counter's latency stays off the walk (a walk that ends early leaves one
     // reserved block unused).
-    uint32_t ck_next = kNoSlot;
-    if (ckpt && tid == 0 && batch_has_boundary<B>(0u, len, sc.shift))
-        ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax + (QUAD ? (uint32_t)quarter * batch_slots<B, QUAD>(sc.shift) : 0u);
+    uint32_t ck_next = kNoSlot, ck_cur = kNoSlot;
+    if (ckpt && tid == 0) {
+        if (QUAD)   // the first S positions: the quarter's part of the tile's own block
+            ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax +
+                      (uint32_t)quarter * (quad_block(sc.shift) >> sc.shift);
+        else if (batch_has_boundary<B>(0u, len, sc.shift))
+            ck_next = (uint32_t)(v * tiles + tile) * kBatchSlotsMax;
+    }
 
     // Two-stage software pipeline: while a batch is composited, the records
     // of the next batch and the ids of the one after are in flight.
@@ -205,10 +214,18 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (ckpt && tid == 0) {
-            s_ckbase = ck_next;
             const uint32_t b1 = base - rg.x + (uint32_t)B;
-            ck_next = batch_has_boundary<B>(b1, len, sc.shift)
-                          ? sc.first_slots + atomicAdd(sc.ctr, batch_slots<B, QUAD>(sc.shift)) : kNoSlot;
+            if (QUAD) {
+                const uint32_t S = quad_block(sc.shift);
+                if ((base - rg.x) % S == 0u) ck_cur = ck_next;          // a new block of S positions
+                if (b1 % S == 0u)                                      // its last batch: reserve the next
+                    ck_next = b1 < len ? sc.first_slots + atomicAdd(sc.ctr, S >> sc.shift) : kNoSlot;
+                s_ckbase = ck_cur;
+            } else {
+                s_ckbase = ck_next;
+                ck_next = batch_has_boundary<B>(b1, len, sc.shift)
+                              ? sc.first_slots + atomicAdd(sc.ctr, batch_slots<B>(sc.shift)) : kNoSlot;
+            }
         }
         __syncthreads();
         {
@@ -231,7 +248,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             {
                 const uint32_t pos0 = base - rg.x + (uint32_t)kc;
                 if (ckpt && pos0 != 0u && (pos0 & kmask) == 0u)
-                    fwd_checkpoint<W, P, B, QUAD>(sc, base + (uint32_t)kc, kc, s_ckbase, tid, quarter, done, T, C);
+                    fwd_checkpoint<W, P, B, QUAD>(sc, base + (uint32_t)kc,
+                                                  QUAD ? (pos0 % quad_block(sc.shift)) >> sc.shift
+                                                       : (uint32_t)kc >> sc.shift,
+                                                  s_ckbase, tid, quarter, done, T, C);
             }
             const int kend = min(cnt, kc + L);
             for (int k = kc; k < kend && !alldone; k += 2) {

@@ -141,6 +141,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     __shared__ unsigned int s_pairs;
     __shared__ uint32_t s_last;
     __shared__ uint32_t s_ckbase;      // pool slots of the current batch's segment boundaries
+    __shared__ uint8_t s_pos[QUAD ? B : 1];   // quadrant mode: batch offset of each kept record
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
@@ -200,18 +201,46 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         if (j < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gsort[j]);
         if (j + B < rg.y) gid_nxt = gsort[j + B];
     }
+    // quadrant mode: the quarter's pixel box
+    const float qx0 = (float)(tx0 + (quarter & 1) * 8), qy0 = (float)(ty0 + (quarter >> 1) * 8);
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         if (__syncthreads_count(!alldone) == 0) break;
-        if (base + tid < rg.y) {
-            s_geo[tid] = cur.g;
-            s_co[tid] = cur.co;
-            s_rgb[tid] = cur.c;
-        } else if (base + tid == rg.y) {
-            // a zero-opacity record after the list's last splat: a two-splat
-            // step that reaches past the end evaluates it and it is never a member
-            s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-            s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-            s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+        int cnt;
+        if (QUAD) {
+            // Keep only the splats whose member extent (col.z, col.w: half-widths
+            // beyond which no pixel can be a member) reaches the quarter: the
+            // others are non-members of every pixel here and would leave T and
+            // the colour as they are.  The kept records stay in list order.
+            const bool hit = base + tid < rg.y && cur.g.x + cur.co.z >= qx0 && cur.g.x - cur.co.z <= qx0 + 7.0f &&
+                             cur.g.y + cur.co.w >= qy0 && cur.g.y - cur.co.w <= qy0 + 7.0f;
+            const uint64_t hm = __ballot(hit);
+            const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+            cnt = __popcll(hm);
+            if (hit) {
+                s_geo[r] = cur.g;
+                s_co[r] = cur.co;
+                s_rgb[r] = cur.c;
+                s_pos[r] = (uint8_t)tid;
+            }
+            if (tid == cnt) {          // the zero-opacity record after the kept ones
+                s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
+            cnt = (int)min((uint32_t)B, rg.y - base);
+            if (base + tid < rg.y) {
+                s_geo[tid] = cur.g;
+                s_co[tid] = cur.co;
+                s_rgb[tid] = cur.c;
+            } else if (base + tid == rg.y) {
+                // a zero-opacity record after the list's last splat: a two-splat
+                // step that reaches past the end evaluates it and it is never a member
+                s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         if (ckpt && tid == 0) {
             const uint32_t b1 = base - rg.x + (uint32_t)B;
@@ -233,7 +262,6 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             if (jn < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
             if (jn + B < rg.y) gid_nxt = gsort[jn + B];
         }
-        const int cnt = (int)min((uint32_t)B, rg.y - base);
         // Each lane leaves the walk as soon as its pixels are done; the
         // exponential and the accumulation run under the lanes' own
         // membership tests.
@@ -243,8 +271,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         // as one splat at a time), and one branch adds the colour.
         // Checkpoints fall on chunk starts: chunks of K splats (of the batch
         // when K is longer), so the steps inside a chunk test nothing.
+        // (Quadrant mode: one chunk per batch, the batch start checkpointed
+        // even when no record of the batch was kept.)
         const int L = ckpt ? min(B, 1 << sc.shift) : B;
-        for (int kc = 0; kc < cnt && !alldone; kc += L) {
+        for (int kc = 0; (QUAD ? kc == 0 : kc < cnt) && !alldone; kc += L) {
             {
                 const uint32_t pos0 = base - rg.x + (uint32_t)kc;
                 if (ckpt && pos0 != 0u && (pos0 & kmask) == 0u)
@@ -255,8 +285,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             }
             const int kend = min(cnt, kc + L);
             for (int k = kc; k < kend && !alldone; k += 2) {
-                const uint32_t pos = base - rg.x + (uint32_t)k;
+                // list positions of the two records (kept records: their batch offsets)
+                const uint32_t pos = base - rg.x + (QUAD ? (uint32_t)s_pos[k] : (uint32_t)k);
                 const int k1 = k + 1;                  // k1 == cnt: the zero-opacity record
+                const uint32_t pos1 = QUAD ? base - rg.x + (uint32_t)s_pos[k1] : pos + 1u;
                 const bool two = k1 < cnt;             // (counted by the counting variant only)
                 const float4 g0 = s_geo[k], g1 = s_geo[k1];
                 const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
@@ -285,7 +317,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                             C[p][0] = fma((double)cb.x, w1, fma((double)ca.x, w0, C[p][0]));
                             C[p][1] = fma((double)cb.y, w1, fma((double)ca.y, w0, C[p][1]));
                             C[p][2] = fma((double)cb.z, w1, fma((double)ca.z, w0, C[p][2]));
-                            last[p] = c1 ? pos + 2u : pos + 1u;
+                            last[p] = c1 ? pos1 + 1u : pos + 1u;
                         }
                         T[p] = c1 ? Tn1 : T1;
                         done[p] = t0 || t1;

@@ -1,15 +1,19 @@
 // Tile compositing, forward and backward.
 //
-// Forward (Section 3.1, eq. 2): one workgroup of W waves per 16x16 tile;
-// each thread owns 4/W pixels.  The tile's depth-ordered splats are staged
-// in LDS in batches of one record per thread (a gather by gid), then every
-// pixel walks the batch front to back.  The workgroup stops fetching batches
-// once all its pixels have terminated (__syncthreads_count).  Colour is
-// accumulated in double precision and kept per pixel for the backward.
+// Forward (Section 3.1, eq. 2): by default one 64-thread workgroup per 8x8
+// quarter of a 16x16 tile (one pixel per lane); optionally one workgroup of
+// W waves per tile, each thread owning 4/W pixels.  The tile's depth-ordered
+// splats are staged in LDS in batches of one record per thread (a gather by
+// gid) -- in quarter mode only those whose member extent reaches the
+// quarter -- then every pixel walks the batch front to back.  The workgroup
+// stops fetching batches once all its pixels have terminated
+// (__syncthreads_count), and at every K-th list position it checkpoints its
+// still-active pixels' state for the backward.  Colour is accumulated in
+// double precision and kept per pixel for the backward.
 //
-// Backward (Section 3.2.4): same workgroup shape, one workgroup per
-// (tile, segment of K splats) work item, starting from the state the
-// forward checkpointed at the segment boundary.  Each pixel re-walks the
+// Backward (Section 3.2.4): W waves (default 2) per work item, one item per
+// (tile, segment of K splats), starting from the state the forward
+// checkpointed at the segment boundary.  Each pixel re-walks the
 // segment up to its last member and recomputes the transmittance with the
 // same instructions as the forward (shared eval_splat / next_T), so every
 // membership and termination decision is identical.  The colour behind a
@@ -17,7 +21,7 @@
 // Frozen splats still attenuate the pixels behind them but get no gradient
 // work.  Per splat, a thread sums its pixels' 9 partial derivatives, each
 // row of 16 lanes sums them with DPP operations, the rows' totals (4 per
-// wave) are added through LDS in a fixed order every 64 splats, and the
+// wave) are added through LDS in a fixed order every kChunk splats, and the
 // tile's total is written to the splat's own
 // slot (its position in the depth-ordered expansion) -- no atomics, so the
 // backward is deterministic.  The per-Gaussian sum over tiles happens in the

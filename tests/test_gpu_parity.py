@@ -467,7 +467,8 @@ def test_backward_segments_are_bit_identical(kind):
     import torch
     tl = g.state(L.STATE_LAST, torch.int32, (len(cams), H, W))
     print(kind, "largest last", int(tl.max()))
-    for seg, fwd, bwd in [(64, 4, 2), (128, 4, 2), (4096, 4, 2), (64, 1, 2), (128, 2, 1), (64, 0, 4), (128, 4, 4)]:
+    for seg, fwd, bwd in [(64, 4, 2), (128, 4, 2), (4096, 4, 2), (64, 1, 2), (128, 2, 1), (64, 0, 4), (128, 4, 4),
+                          (64, 0, 2), (128, 0, 2), (512, 0, 2), (4096, 0, 2)]:
         g.ctx.set_option(L.OPT_BWD_SEGMENT, seg)
         g.ctx.set_waves(fwd=fwd, bwd=bwd)
         img = g.forward()

@@ -5,7 +5,7 @@
  *
  * One training iteration of the paper's Algorithm 1 maps to:
  *   rasterize(G, freeze_map, cam_pose)           -> gsta_render_forward + gsta_render_backward
- *   loss_fcn(gt_image, render_image)             -> gsta_l1_loss
+ *   loss_fcn(gt_image, render_image)             -> gsta_l1_loss (or fused: gsta_render_forward_l1)
  *   optimizer_step(G, lr, loss, freeze_map)      -> gsta_adam_masked
  *   update_freeze_map / reset_freeze_map         -> gsta_update_freeze_mask
  *   adaptive_densification(G)                    -> gsta_densify_prune, gsta_opacity_reset
@@ -201,6 +201,18 @@ gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int6
 gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
                                 int32_t n_views, const float* bg, float* image, int32_t state_slot,
                                 hipStream_t stream);
+
+/* Algorithm 1, rasterize + loss_fcn in one pass: gsta_render_forward, and
+ * the L1 loss of its image against `target` computed by the compositing
+ * kernel as it writes each pixel.  dL_dimage and sums are those of
+ * gsta_l1_loss(image, target, n_views*3*H*W) -- dL_dimage bit for bit, sums
+ * up to the order of their double additions.
+ *   target, dL_dimage [n_views][3][H][W] float32 (device); sums device double [2].
+ * Same errors as gsta_render_forward; NULL target, dL_dimage or sums is
+ * GSTA_ERR_INVALID. */
+gsta_status gsta_render_forward_l1(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                   int32_t n_views, const float* bg, const float* target, float* image,
+                                   float* dL_dimage, double* sums, int32_t state_slot, hipStream_t stream);
 
 /* Section 3.2.4.  Backward of gsta_render_forward for the same g, cams,
  * n_views, bg and state_slot (checked).  dL_dimage [n_views][3][H][W].

@@ -63,7 +63,7 @@ class GstaError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gsta_check",
-           "gsta_get_state", "gsta_render_forward", "gsta_render_backward", "gsta_adam_masked",
+           "gsta_get_state", "gsta_render_forward", "gsta_render_forward_l1", "gsta_render_backward", "gsta_adam_masked",
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.gsta_check.argtypes = [P, P, ctypes.POINTER(i64)]
     L.gsta_get_state.argtypes = [P, i32, i32, P, i64, P]
     L.gsta_render_forward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, i32, P]
+    L.gsta_render_forward_l1.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, P, P, P, i32, P]
     L.gsta_render_backward.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), i32, P, P,
                                        PP, P, P, f32, P, P]
     L.gsta_densify_prune.argtypes = [P, PP, PP, PP, P, P, P, P, ctypes.POINTER(DensifyCfg), PP, PP, PP, P, P, P, P]

@@ -169,6 +169,17 @@ class Context:
                                                   _arr(image, shape, torch.float32, "image"), slot,
                                                   _stream(stream)))
 
+    def render_forward_l1(self, params, degree, cams, bg, target, image, dL_dimage, sums, slot=0, stream=None):
+        """render_forward with the L1 loss against `target` fused into the
+        compositing: dL_dimage and sums as l1_loss gives them."""
+        ps = params_struct(params, degree)
+        ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        shape = (len(ca), 3, ca[0].height, ca[0].width)
+        check(self.h, self.L.gsta_render_forward_l1(
+            self.h, ctypes.byref(ps), ca, len(ca), _f3(bg), _arr(target, shape, torch.float32, "target"),
+            _arr(image, shape, torch.float32, "image"), _arr(dL_dimage, shape, torch.float32, "dL_dimage"),
+            _arr(sums, (2,), torch.float64, "sums"), slot, _stream(stream)))
+
     def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
                         grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None):
         ps = params_struct(params, degree)

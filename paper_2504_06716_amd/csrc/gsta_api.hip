@@ -70,6 +70,7 @@ struct gsta_ctx {
     int64_t chunks_depth = 0, chunks_inst = 0;
     int items_depth = 16, items_inst = 16;
     uint64_t* partials = nullptr;
+    double2* fwd_lpart = nullptr;    // [V][tiles_max][4] fused-loss sums per forward workgroup
     uint32_t* place_cnt = nullptr;   // [place_views][ceil(stride/256)][tiles_max] placement counts
     uint32_t* tile_tot = nullptr;    // [place_views][tiles_max] instances per tile
     int place_views = 0;             // views the placement scratch holds (0: always sort)
@@ -213,7 +214,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ok = ok && alloc(ctx, &ctx->hist, hist_words) && alloc(ctx, &ctx->digit_tot, V * 256) &&
          alloc(ctx, &ctx->partials, std::max(expand_blocks(V * S), V * place_blocks(S)) + 1) &&
          alloc(ctx, &ctx->place_cnt, ctx->place_views > 0 ? pv * place_view_words : 1) &&
-         alloc(ctx, &ctx->tile_tot, pv * ctx->tiles_max) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
+         alloc(ctx, &ctx->tile_tot, pv * ctx->tiles_max) && alloc(ctx, &ctx->fwd_lpart, V * ctx->tiles_max * 4) && alloc(ctx, &ctx->tile_grads, 9 * cap + 4) &&
          alloc(ctx, &ctx->stamps, cap) && alloc(ctx, &ctx->gen, 1) && alloc(ctx, &ctx->d2sum, 9 * V * S) &&
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
@@ -559,9 +560,12 @@ gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst
                      "copy state");
 }
 
-gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
-                                int32_t n_views, const float* bg, float* image, int32_t state_slot,
-                                hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams, int32_t n_views,
+                           const float* bg, float* image, int32_t state_slot, FusedL1 l1, hipStream_t stream) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     gsta_status st;
     if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
@@ -626,9 +630,13 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);
         s.shift = ctx->seg_shift;
+        if (l1.target) {
+            l1.part = ctx->fwd_lpart;
+            l1.inv = 1.0f / (float)(nv * 3 * (int64_t)ca.c[0].width * ca.c[0].height);
+        }
         launch_composite_fwd(ctx->fwd_waves, s.ranges, s.gsort, s.geo, s.col, s.rgb, S, ca,
                              nv, bg[0], bg[1], bg[2], image, s.T_final, s.last, s.cfg, seg_ckpt(ctx, s),
-                             pair_counter(ctx, 0), stream);
+                             pair_counter(ctx, 0), l1, stream);
     }
     if ((st = hip_check(ctx, hipGetLastError(), "render_forward launch")) != GSTA_OK) {
         s.valid = false;
@@ -643,6 +651,28 @@ gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_
     for (int v = 0; v < nv; ++v) s.cams[v] = cams[v];
     for (int c = 0; c < 3; ++c) s.bg[c] = bg[c];
     return GSTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsta_status gsta_render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                int32_t n_views, const float* bg, float* image, int32_t state_slot,
+                                hipStream_t stream) {
+    return render_forward(ctx, g, cams, n_views, bg, image, state_slot, FusedL1{}, stream);
+}
+
+gsta_status gsta_render_forward_l1(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,
+                                   int32_t n_views, const float* bg, const float* target, float* image,
+                                   float* dL_dimage, double* sums, int32_t state_slot, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (!target || !dL_dimage || !sums) return fail(ctx, GSTA_ERR_INVALID, "NULL target, dL_dimage or sums");
+    FusedL1 l1;
+    l1.target = target;
+    l1.dL = dL_dimage;
+    l1.sums = sums;
+    return render_forward(ctx, g, cams, n_views, bg, image, state_slot, l1, stream);
 }
 
 gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams,

@@ -227,10 +227,23 @@ struct SegCkpt {
 // cleared.  The preprocess backward's last kernel advances the device-side
 // generation once every reader of it has finished (stream-ordered, so a
 // captured graph replays it too).
+// The L1 loss of the rendered image fused into the forward compositing
+// (target null: none).  Per pixel and channel, d = image - target gives
+// dL[i] = sign(d) * inv (0 at d = 0), and each workgroup adds |d| and
+// (clamp(image, 0, 1) - target)^2 (double) into part[workgroup]; the
+// work-item scan after the forward adds the parts in a fixed order into
+// sums[0], sums[1] (as gsta_l1_loss).  part: one double2 per forward workgroup.
+struct FusedL1 {
+    const float* target = nullptr;
+    float* dL = nullptr;
+    double2* part = nullptr;
+    double* sums = nullptr;
+    float inv = 0.f;          // 1 / (elements of the image)
+};
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
-                          hipStream_t s);
+                          const FusedL1& l1, hipStream_t s);
 void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,
                           const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,

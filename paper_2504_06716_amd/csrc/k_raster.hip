@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg, SegCkpt sc,
-    unsigned long long* __restrict__ pairs) {
+    unsigned long long* __restrict__ pairs, FusedL1 l1) {
     constexpr int NT = 64 * W, P = QUAD ? 1 : 4 / W, B = NT;
     __shared__ float4 s_geo[B];
     __shared__ float4 s_co[B];
@@ -353,6 +353,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         if (tid == 0 && s_last) atomicMax(sc.tile_last + (int64_t)v * tiles + tile, s_last);
     }
     const int64_t HW = (int64_t)cm.width * cm.height;
+    double la = 0.0, lb = 0.0;     // fused L1: sum |d| and sum of squared clamped errors
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (!inside[p]) continue;
@@ -360,15 +361,51 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         pixel_of<W, QUAD>(tid, p, quarter, tx0, ty0, px, py);
         const int64_t o = (int64_t)py * cm.width + px;
         float* img = image + (int64_t)v * 3 * HW + o;
-        img[0] = (float)(C[p][0] + (double)(T[p] * bg0));
-        img[HW] = (float)(C[p][1] + (double)(T[p] * bg1));
-        img[2 * HW] = (float)(C[p][2] + (double)(T[p] * bg2));
+        const float c3[3] = {(float)(C[p][0] + (double)(T[p] * bg0)), (float)(C[p][1] + (double)(T[p] * bg1)),
+                             (float)(C[p][2] + (double)(T[p] * bg2))};
+        img[0] = c3[0];
+        img[HW] = c3[1];
+        img[2 * HW] = c3[2];
         T_final[(int64_t)v * HW + o] = T[p];
         last_out[(int64_t)v * HW + o] = last[p];
         double* cf = cfg + (int64_t)v * 3 * HW + o;
         cf[0] = C[p][0];
         cf[HW] = C[p][1];
         cf[2 * HW] = C[p][2];
+        if (l1.target) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const int64_t i = (int64_t)v * 3 * HW + ch * HW + o;
+                const float t = l1.target[i];
+                const float d = c3[ch] - t;
+                l1.dL[i] = (d > 0.f) ? l1.inv : ((d < 0.f) ? -l1.inv : 0.f);
+                la += (double)fabsf(d);
+                const double e = (double)fminf(fmaxf(c3[ch], 0.f), 1.f) - (double)t;
+                lb += e * e;
+            }
+        }
+    }
+    if (l1.target) {   // uniform: every thread takes part
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            la += __shfl_xor(la, off, 64);
+            lb += __shfl_xor(lb, off, 64);
+        }
+        __shared__ double s_l1[W][2];
+        if ((tid & 63) == 0) {
+            s_l1[tid >> 6][0] = la;
+            s_l1[tid >> 6][1] = lb;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                a += s_l1[w][0];
+                b += s_l1[w][1];
+            }
+            l1.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(a, b);
+        }
     }
 }
 
@@ -379,9 +416,12 @@ constexpr int kChunk = 32;
 // Items per tile: ceil(tile_last / K) (one if segments are off), scanned by
 // one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total);
 // item_tile[i] names the tile of item i.
+// With a fused L1 loss (sums set) it also adds the forward's nparts
+// per-workgroup loss sums in a fixed order.
 __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__ tile_last, int nt, uint32_t shift,
                                                     uint32_t* __restrict__ item_off, uint32_t* __restrict__ item_tile,
-                                                    uint32_t item_cap) {
+                                                    uint32_t item_cap, const double2* __restrict__ lpart,
+                                                    int nparts, double* __restrict__ sums) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -415,6 +455,33 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) item_off[nt] = s_carry;
+    if (sums) {   // uniform
+        __shared__ double s_a[16], s_b[16];
+        double a = 0.0, b = 0.0;
+        for (int i = (int)threadIdx.x; i < nparts; i += 1024) {
+            a += lpart[i].x;
+            b += lpart[i].y;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            b += __shfl_xor(b, off, 64);
+        }
+        if (lane == 0) {
+            s_a[w] = a;
+            s_b[w] = b;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0;
+            for (int k = 0; k < 16; ++k) {
+                ta += s_a[k];
+                tb += s_b[k];
+            }
+            sums[0] = ta;
+            sums[1] = tb;
+        }
+    }
 }
 
 template <int W, bool CNT>
@@ -680,9 +747,9 @@ template <bool CNT>
 void fwd_launch(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo,
                 const float4* col, const float4* rgb, int64_t stride, const CamArray& cams, int nv, float bg0,
                 float bg1, float bg2, float* image, float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc,
-                unsigned long long* pairs, hipStream_t s) {
+                unsigned long long* pairs, const FusedL1& l1, hipStream_t s) {
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
-#define GSTA_FWD_ARGS ranges, gsort, geo, col, rgb, stride, cams, bg0, bg1, bg2, image, T_final, last, cfg, sc, pairs
+#define GSTA_FWD_ARGS ranges, gsort, geo, col, rgb, stride, cams, bg0, bg1, bg2, image, T_final, last, cfg, sc, pairs, l1
     if (waves == 0)   // one independent wave per 8x8 quarter of each tile
         k_composite_fwd<1, true, CNT><<<dim3(4 * tiles, nv), 64, 0, s>>>(GSTA_FWD_ARGS);
     else if (waves == 1)
@@ -714,17 +781,19 @@ void bwd_launch(int waves, int blocks, const uint2* ranges, const uint32_t* ids,
 void launch_composite_fwd(int waves, const uint2* ranges, const uint32_t* gsort, const float4* geo, const float4* col, const float4* rgb, int64_t stride,
                           const CamArray& cams, int nv, float bg0, float bg1, float bg2, float* image,
                           float* T_final, uint32_t* last, double* cfg, const SegCkpt& sc, unsigned long long* pairs,
-                          hipStream_t s) {
+                          const FusedL1& l1, hipStream_t s) {
     // sc.tile_last and sc.ctr arrive zeroed (cleared by the binning)
     const int tiles = cams.c[0].ntx * cams.c[0].nty;
     if (pairs)
         fwd_launch<true>(waves, ranges, gsort, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
-                         last, cfg, sc, pairs, s);
+                         last, cfg, sc, pairs, l1, s);
     else
         fwd_launch<false>(waves, ranges, gsort, geo, col, rgb, stride, cams, nv, bg0, bg1, bg2, image, T_final,
-                          last, cfg, sc, pairs, s);
-    // the backward's work items: ceil(tile_last / K) per tile
-    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off, sc.item_tile, sc.item_cap);
+                          last, cfg, sc, pairs, l1, s);
+    // the backward's work items: ceil(tile_last / K) per tile (and the fused loss's sums)
+    const int nparts = tiles * nv * (waves == 0 ? 4 : 1);
+    k_seg_items<<<1, 1024, 0, s>>>(sc.tile_last, tiles * nv, sc.shift, sc.item_off, sc.item_tile, sc.item_cap,
+                                   l1.part, nparts, l1.target ? l1.sums : nullptr);
 }
 
 void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,

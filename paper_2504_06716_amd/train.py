@@ -1,7 +1,7 @@
 """GSta training loop on top of libgsta (Algorithm 1).
 
 Per iteration: (densify / prune / opacity reset) -> (freeze-map update or
-reset) -> render_forward -> l1_loss -> render_backward (frozen skipped,
+reset) -> render_forward (+ fused L1 loss) -> render_backward (frozen skipped,
 gradient-norm EMAs, densification statistics) -> adam_masked (frozen
 skipped).  Everything per Gaussian or per pixel runs in the HIP library; this
 module keeps only host scalars (schedule, learning rates) and the device
@@ -54,6 +54,7 @@ class TrainConfig:
     proposer: object | None = None       # learned freeze proposer (proposer.Proposer), needs traj_every
     dataset: object | None = None        # proposer.ProposerDataset to record the rule's decisions into
     partition: bool = False              # after each freeze update, move the frozen columns behind the active ones
+    fused_loss: bool = True              # L1 loss computed by the forward compositing (else a separate pass)
 
 
 class Trainer:
@@ -258,8 +259,11 @@ class Trainer:
             idx = torch.as_tensor(view, device="cuda")
             torch.index_select(self.targets, 0, idx, out=self.tgt_batch)
             tgt = self.tgt_batch
-        self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
-        self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
+        if cfg.fused_loss:
+            self.ctx.render_forward_l1(self.P, self.degree, cam, cfg.bg, tgt, self.image, self.dL, self.sums, 0)
+        else:
+            self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
+            self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
                                  cfg.ema_beta, dstats=self.dstats)
         if self.use_sched:

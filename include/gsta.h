@@ -119,7 +119,7 @@ typedef enum {
                                    the backward of a long tile list is spread over several
                                    workgroups; the result does not depend on it. */
     GSTA_OPT_BINNING = 3        /* how the per-tile lists are built: 0 (default) places every tile
-                                   instance directly where views have at most 1536 tiles and the
+                                   instance directly where views have at most 1408 tiles and the
                                    placement scratch was reserved for the call's views, else sorts;
                                    1 always expands and sorts the tile keys (LSD radix).  Both give
                                    the same lists (Section 3.1: splats per tile in depth order). */

@@ -315,23 +315,39 @@ __global__ __launch_bounds__(256) void k_sum_partials(const ushort4* __restrict_
     const int l16 = threadIdx.x & 15;
     const int64_t i = (int64_t)blockIdx.x * kSumRows + (threadIdx.x >> 4);
     const int v = blockIdx.y;
-    // `work` is uniform over each row of 16 lanes
-    bool work = i < n && !(frozen && frozen[i]);
     const int64_t o_idx = (int64_t)v * stride + i;
-    ushort4 r = make_ushort4(0, 0, 0, 0);
-    if (work) {
-        r = rect[o_idx];
-        work = r.x < r.y;
-    }
+    // the independent loads first, so that their latencies overlap
+    const bool inb = i < n;
+    const bool fz = inb && frozen && frozen[i];
+    const ushort4 r = inb ? rect[o_idx] : make_ushort4(0, 0, 0, 0);
+    const uint64_t j0 = inb ? inst_off[o_idx] : 0ull;
+    // `work` is uniform over each row of 16 lanes
+    const bool work = inb && !fz && r.x < r.y;
     if (work) {
         const uint32_t cnt = (uint32_t)(r.y - r.x) * (uint32_t)(r.w - r.z);
-        const uint64_t j0 = inst_off[o_idx];
         const uint32_t gen = *genp;
         float d2[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) d2[k] = 0.f;
         if (j0 + cnt <= (uint64_t)(*d_count)) {
-            for (uint32_t base = 0; base < cnt; base += 16) {
+            // lane l adds slots l, l + 16, l + 32, ... in that order, two per step
+            uint32_t base = 0;
+            for (; base + 16u < cnt; base += 32u) {
+                const uint32_t t0 = base + (uint32_t)l16, t1 = t0 + 16u;
+                const bool s0 = stamps[j0 + t0] == gen;
+                const bool s1 = t1 < cnt && stamps[j0 + t1] == gen;
+                if (s0) {
+                    const float* src = partials + (j0 + t0) * 9;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) d2[k] += src[k];
+                }
+                if (s1) {
+                    const float* src = partials + (j0 + t1) * 9;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) d2[k] += src[k];
+                }
+            }
+            if (base < cnt) {
                 const uint32_t t = base + (uint32_t)l16;
                 if (t < cnt && stamps[j0 + t] == gen) {
                     const float* src = partials + (j0 + t) * 9;

@@ -458,6 +458,7 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
     if (sums) {   // uniform
         __shared__ double s_a[16], s_b[16];
         double a = 0.0, b = 0.0;
+#pragma unroll 4
         for (int i = (int)threadIdx.x; i < nparts; i += 1024) {
             a += lpart[i].x;
             b += lpart[i].y;

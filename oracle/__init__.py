@@ -50,6 +50,7 @@ def lib():
         L.oracle_render_backward.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P, P, P, P, P]
         L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_render_pixels.argtypes = [P, i64, i64, i32, P, P, P, i64, P, P, P]
         _lib = L
     return _lib
@@ -57,6 +58,11 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C++ oracle's parallel loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):
@@ -335,6 +341,110 @@ class PlateauLR:
             self.scale *= self.factor
             self.bad = 0
         return self.scale
+
+
+# ---------------------------------------------------------------------------
+# Freeze-map lifecycle and the end of training (Algorithm 1; Section 3.2.2;
+# Section 4.1 "GSta Details").  Written as the sets of iterations at which
+# something happens, so that a reader can check them against the text:
+#   * no freezing before the warm-up;
+#   * the freezing window closes at min(window_end, early-stop iteration);
+#     the map is then reset and every Gaussian trains for K_f more
+#     iterations (the finetune), after which training ends;
+#   * inside the window the map is updated every `every` iterations and
+#     accumulates; at every multiple of `reset_every` past the warm-up it is
+#     reset and not updated again for `wait` iterations.
+# Early stop (eq. 7) is tested on the PSNRs of the evaluations made every
+# `eval_every` iterations while the window is open.
+# ---------------------------------------------------------------------------
+
+ACT_NONE, ACT_UPDATE, ACT_RESET = 0, 1, 2
+
+
+def freeze_reset_iters(warmup, reset_every, close):
+    """Iterations before which the freeze map is reset: the multiples of
+    reset_every past the warm-up and before the window closes, and the
+    closing iteration itself (start of the finetune)."""
+    resets = [r for r in range(reset_every, close, reset_every) if r > warmup]
+    return resets + [close]
+
+
+def freeze_update_iters(warmup, every, reset_every, wait, close):
+    """Iterations before which the freeze map is updated: multiples of
+    `every` in [warmup, close) that are not a reset and do not fall within
+    `wait` iterations after a reset."""
+    resets = freeze_reset_iters(warmup, reset_every, close)
+    out = []
+    for k in range(0, close, every):
+        if k < warmup or k in resets:
+            continue
+        if any(r <= k < r + wait for r in resets):
+            continue
+        out.append(k)
+    return out
+
+
+def freeze_action(k, warmup, every, reset_every, wait, window_end, stop_iter=None):
+    """What happens to the freeze map before iteration k: ACT_NONE,
+    ACT_UPDATE or ACT_RESET."""
+    close = window_end if stop_iter is None else min(window_end, stop_iter)
+    if k in freeze_reset_iters(warmup, reset_every, close):
+        return ACT_RESET
+    if k in freeze_update_iters(warmup, every, reset_every, wait, close):
+        return ACT_UPDATE
+    return ACT_NONE
+
+
+def training_end(total_iters, window_end, stop_iter, finetune_iters):
+    """Number of training iterations.  When the freezing window closes
+    (early stop, or the forced stop at window_end) before total_iters, the
+    finetune of finetune_iters iterations follows and training ends; the
+    loop of Algorithm 1 keeps running while finetune iterations remain, so
+    the end may lie past total_iters.  A window that never closes before
+    total_iters ends training at total_iters."""
+    close = window_end if stop_iter is None else min(window_end, stop_iter)
+    if close >= total_iters:
+        return total_iters
+    return close + finetune_iters
+
+
+def densify_action(k, start, stop, every, reset_every, stop_iter=None):
+    """(densify, opacity_reset) before iteration k (Section 4.1): densify
+    and prune every `every` iterations in [start, min(stop, early stop));
+    opacity reset every reset_every iterations in [reset_every,
+    min(stop, early stop)]."""
+    end = stop if stop_iter is None else min(stop, stop_iter)
+    dens = k > 0 and start <= k < end and k % every == 0
+    reset = reset_every <= k <= end and k % reset_every == 0
+    return dens, reset
+
+
+def simulate_lifecycle(total_iters, warmup, every, reset_every, wait, window_end, finetune_iters,
+                       eval_every=None, psnr_at=None, es_eps=0.2, plateau=None):
+    """Run the host side of Algorithm 1 for a whole training: per iteration
+    the freeze action, evaluations every eval_every iterations while the
+    window is open (psnr_at(k) gives the PSNR measured after k iterations),
+    eq. 7 early stop and the plateau scale of the position learning rate.
+    Returns dict(actions [end], stop_iter, end, psnrs, pos_scale [end] (the
+    scale used by iteration k))."""
+    psnrs = []
+    stop_iter = None
+    actions = []
+    scales = []
+    scale = 1.0
+    k = 0
+    while k < training_end(total_iters, window_end, stop_iter, finetune_iters):
+        actions.append(freeze_action(k, warmup, every, reset_every, wait, window_end, stop_iter))
+        scales.append(scale)
+        k += 1
+        close = window_end if stop_iter is None else min(window_end, stop_iter)
+        if eval_every and k % eval_every == 0 and k < close and stop_iter is None:
+            psnrs.append(float(psnr_at(k)))
+            if plateau is not None:
+                scale = plateau.step(psnrs[-1])
+            if early_stop(psnrs, es_eps):
+                stop_iter = k
+    return dict(actions=actions, stop_iter=stop_iter, end=k, psnrs=psnrs, pos_scale=scales)
 
 
 # ---------------------------------------------------------------------------

@@ -501,6 +501,15 @@ int oracle_num_threads() {
 #endif
 }
 
+// Sets the threads of later OpenMP loops (timing at 1 thread and at all cores).
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 // Number of doubles per projected record written by oracle_project.
 int oracle_nrec() { return 40; }
 

@@ -56,14 +56,25 @@ class FreezeSchedule:
         end = self.window_close(stop_iter)
         if k == end:
             return RESET                                 # finetune: everyone trains again
-        if k < self.warmup or k > end or k % self.every != 0:
+        if k < self.warmup or k > end:
             return NONE
         if k > self.warmup and k % self.reset_every == 0:
             return RESET
+        if k % self.every != 0:
+            return NONE
         last_reset = (k // self.reset_every) * self.reset_every
         if last_reset > self.warmup and k - last_reset < self.wait:
             return NONE
         return UPDATE
+
+
+def training_end(total_iters: int, window_end: int, stop_iter: int | None, finetune_iters: int) -> int:
+    """Iterations of a whole training (Algorithm 1): when the freezing
+    window closes (early stop or window_end) before total_iters, K_f =
+    finetune_iters more iterations train every Gaussian and training ends
+    there, also past total_iters; otherwise it ends at total_iters."""
+    close = window_end if stop_iter is None else min(window_end, stop_iter)
+    return total_iters if close >= total_iters else close + finetune_iters
 
 
 @dataclass

@@ -119,6 +119,43 @@ def test_isotropic_on_axis_closed_form():
         np.testing.assert_allclose(r[9:12], [1 / sig2, 0.0, 1 / sig2], atol=1e-12)
 
 
+def test_ewa_off_axis_matches_pinhole_jacobian():
+    """Eq. 1 away from the optical axis: Sigma' - 0.3 I must equal D Sigma D^T
+    with D the Jacobian of the pinhole map (world point -> pixel) at the
+    mean, taken here by central differences of u = fx x/z + cx, v = fy y/z +
+    cy, and Sigma = R S^2 R^T with R from scipy's quaternion rotation.  A sign
+    or index slip in the perspective Jacobian's third column (zero on the
+    axis) or in the quaternion rotation fails this."""
+    from scipy.spatial.transform import Rotation
+    cam = S.look_at(25.0, 40.0, 96, 80)
+    rng = np.random.default_rng(11)
+    tested = 0
+    for _ in range(30):
+        mu = rng.uniform(-0.7, 0.7, 3)
+        log_s = rng.normal(-2.5, 0.5, 3)
+        q = rng.standard_normal(4)
+        p = _single(mu, log_s, q)
+        r = O.project(p, 0, cam)[0]
+        xc = cam.R @ mu + cam.t
+        if r[30] or r[31] or abs(xc[0] / xc[2]) < 0.05 or abs(xc[1] / xc[2]) < 0.05:
+            continue                      # tangent clamp active, or too close to the axis to matter
+
+        def pix(x):
+            c = cam.R @ x + cam.t
+            return np.array([cam.fx * c[0] / c[2] + cam.cx, cam.fy * c[1] / c[2] + cam.cy])
+
+        h = 1e-6
+        D = np.stack([(pix(mu + h * e) - pix(mu - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        Sig = Rm @ np.diag(np.exp(2 * log_s)) @ Rm.T
+        S2 = D @ Sig @ D.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose([r[5], r[6], r[7]], [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose([r[1], r[2]], pix(mu), rtol=0, atol=1e-9)
+        assert r[3] == pytest.approx(xc[2], rel=1e-14)
+        tested += 1
+    assert tested >= 10
+
+
 def test_near_plane_cull():
     cam = S.config_cameras("c1")[0]
     # camera at (3,0,0), forward -x: world x = 3 - z_cam
@@ -361,6 +398,29 @@ def test_backward_frozen_rows_untouched_and_active_unchanged():
 # ---------------------------------------------------------------------------
 # Adam (Section 3.2.4 optimizer restricted to non-frozen Gaussians)
 # ---------------------------------------------------------------------------
+
+def test_l1_loss_and_psnr_hand_values():
+    """Eq. 3 with lambda_SSIM = 0: L = mean |C - C*|, dL/dC = sign(C - C*) /
+    count with sign(0) = 0; the PSNR clamps the rendered image only."""
+    C = np.array([0.5, 1.2, -0.1, 0.3]).reshape(1, 1, 2, 2)
+    T = np.array([0.5, 1.1, 0.0, 0.6]).reshape(1, 1, 2, 2)
+    loss, dL, mse = O.l1_loss(C, T)
+    assert loss == pytest.approx((0.0 + 0.1 + 0.1 + 0.3) / 4, abs=1e-15)
+    np.testing.assert_array_equal(dL.reshape(-1), [0.0, 0.25, -0.25, -0.25])
+    # clamp(C) = (0.5, 1.0, 0.0, 0.3): errors (0, -0.1, 0, -0.3); a clamped target would give 0 at index 1
+    assert mse == pytest.approx((0.01 + 0.09) / 4, abs=1e-15)
+    assert O.psnr(mse) == pytest.approx(10.0 * math.log10(40.0), abs=1e-12)
+    assert O.psnr(0.01) == pytest.approx(20.0, abs=1e-12)
+    # the count is every value of every view and channel
+    C2 = np.zeros((2, 3, 4, 5))
+    T2 = np.zeros_like(C2)
+    C2[1, 2, 3, 4] = 0.6
+    loss2, dL2, mse2 = O.l1_loss(C2, T2)
+    assert loss2 == pytest.approx(0.6 / 120, abs=1e-15)
+    assert dL2[1, 2, 3, 4] == pytest.approx(1.0 / 120, abs=1e-15)
+    assert np.count_nonzero(dL2) == 1
+    assert mse2 == pytest.approx(0.36 / 120, abs=1e-15)
+
 
 def test_adam_matches_torch_optim():
     rng = np.random.default_rng(14)

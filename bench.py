@@ -3,12 +3,19 @@
 
 Workload (synthetic, seeded): 100k Gaussians with SH degree 3, 32 cameras
 (4 elevation rings x 8 azimuths) at 480x640, 16x16 tiles, one view per
-iteration, 2000 iterations; targets rendered from a seed-perturbed copy of
-the scene.  One step = freeze-map update (when scheduled) + forward render +
-L1 loss + backward + masked Adam.  The GSta run (freezing) and the plain run
-(no freezing) are timed on the same GPU from the same initial state; the
-PSNR of both over all 32 views is reported so the comparison can be checked
-at equal iteration count.
+iteration, a 2000-iteration schedule (freezing window [600, 1800), then a
+200-iteration finetune); targets rendered from a seed-perturbed copy of the
+scene.  One step = freeze-map update (when scheduled) + forward render + L1
+loss + backward + masked Adam.
+
+The GSta run (freezing) and the plain run (no freezing) start from the same
+state and view order.  Each is advanced untimed to the start of the timed
+window, which lies inside the freezing window when the step count allows
+(--steps <= 800: iterations [1000, 1000 + steps)), times exactly --steps
+iterations there, and then finishes the schedule untimed for the PSNR over
+all 32 views.  The PSNR difference is also taken over two more view orders
+(full schedules), so the equal-iteration accuracy check does not rest on one
+run.
 
 Prints one JSON line.  `--gpus` above 1 is refused: the library runs on one
 GPU.
@@ -99,7 +106,7 @@ def c2_setup(torch):
         sched = FreezeSchedule(total_iters=iters, warmup=600, every=50, reset_every=400, wait=100,
                                window_end=1800, eps_xyz0=C2_EPS0[0], eps_rgb0=C2_EPS0[1])
         return TrainConfig(iters=iters, freeze=freeze, schedule=sched if freeze else None,
-                           lrs=LearningRates(decay_iters=iters), partition=freeze)
+                           lrs=LearningRates(decay_iters=iters), partition=freeze, finetune_iters=200)
 
     return dict(p0=p0, pt=pt, cams=cams, ctx=ctx, targets=targets, order=order, cfg=cfg, n=n, D=D, H=H, W=W,
                 iters=iters, capacity=int(need * 1.5) + 4096)
@@ -120,10 +127,23 @@ def calibrate(torch, w, q):
     return thresholds_from_quantile(ema_snapshot(tr), sched, q)
 
 
-def run_trainer(torch, w, freeze, steps, profile_phases=None, counters=False):
+def window_start(steps, iters=2000, close=1800, start=1000):
+    """First timed iteration: inside the freezing window ([600, 1800) of the
+    schedule) when the timed steps fit after iteration 1000, else as late as
+    still ends at the window close, else 0 (whole schedule)."""
+    return max(0, min(start, close - steps))
+
+
+def run_trainer(torch, w, freeze, steps, profile_phases=None, counters=False, start=0, finish=False,
+                order=None):
+    """Advance a fresh trainer untimed to iteration `start`, time exactly
+    `steps` iterations (profiling only inside them), then (finish) train
+    untimed to the end of the schedule."""
     from paper_2504_06716_amd.train import Trainer
-    tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], w["cfg"](freeze), w["order"], ctx=w["ctx"])
+    tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], w["cfg"](freeze),
+                 w["order"] if order is None else order, ctx=w["ctx"])
     ctx = w["ctx"]
+    tr.run(start)
     ctx.set_profiling(None if profile_phases == "all" else (profile_phases or []), counters=counters)
     ctx.read_profile()
     torch.cuda.synchronize()
@@ -133,7 +153,21 @@ def run_trainer(torch, w, freeze, steps, profile_phases=None, counters=False):
     dt = time.perf_counter() - t0
     prof, pairs = ctx.read_profile()
     ctx.set_profiling([])
+    if finish:
+        tr.run()
     return tr, dt, prof, pairs
+
+
+def frozen_in_window(hist, k0, k1, n):
+    """Mean frozen fraction over iterations [k0, k1) from the freeze-map
+    history [(iteration, action, frozen count after it)]."""
+    cur, total = 0, 0
+    events = sorted((k, c) for k, _, c in hist)
+    for k in range(k0, k1):
+        while events and events[0][0] <= k:
+            cur = events.pop(0)[1]
+        total += cur
+    return total / max(k1 - k0, 1) / n
 
 
 def algorithmic_work(phase, w, steps, pairs, n_active_mean, inst_mean):
@@ -161,24 +195,25 @@ def algorithmic_work(phase, w, steps, pairs, n_active_mean, inst_mean):
     return steps * n, "byte", "hbm"
 
 
-def _mean_frozen(hist, steps):
-    """Frozen count averaged over the iterations of the run."""
-    total, cur, prev = 0, 0, 0
-    for k, _, c in hist:
-        k = min(k, steps)
-        total += cur * (k - prev)
-        cur, prev = c, k
-    total += cur * max(steps - prev, 0)
-    return total / max(steps, 1)
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(w, max_seconds=20.0):
-    """The FP64 oracle timed on the host for a bounded sample of the same
-    workload: consecutive training iterations (1 view each) from the
-    initial state."""
+def oracle_iteration_seconds(w, threads, max_seconds, max_iters):
+    """Per-iteration times of the FP64 oracle running consecutive c2
+    training iterations (1 view each) from the initial state on `threads`
+    host threads: one untimed warm-up iteration, then iterations until
+    max_seconds or max_iters."""
     import numpy as np
     import oracle as O
-    import torch
+    O.set_threads(threads)
     targets = w["targets"].cpu().numpy().astype(np.float64)
     D = w["D"]
     p = w["p0"].astype(np.float64)
@@ -188,10 +223,12 @@ def cpu_baseline(w, max_seconds=20.0):
     ema = np.full((4, n), O.FLT_MAX)
     frozen = np.zeros(n, np.uint8)
     lrs = w["cfg"](True).lrs
-    iters = 0
-    t0 = time.perf_counter()
+    times = []
+    t_start = time.perf_counter()
+    it = 0
     while True:
-        view = int(w["order"][iters])
+        t0 = time.perf_counter()
+        view = int(w["order"][it])
         cam = w["cams"][view]
         img = O.render(p, D, cam)["image"]
         loss, dL, mse = O.l1_loss(img[None], targets[view:view + 1])
@@ -199,14 +236,33 @@ def cpu_baseline(w, max_seconds=20.0):
         sc = O.scores(g)
         for k in range(4):
             ema[k] = O.ema_update(ema[k], sc[k], vis.any(0), frozen, 0.9)
-        p, m, v = O.adam_masked(p, g, m, v, np.array(lrs.rows(iters, D)), 0.9, 0.999, 1e-15, iters + 1, frozen)
-        iters += 1
-        el = time.perf_counter() - t0
-        if el >= max_seconds or iters >= 50:
+        p, m, v = O.adam_masked(p, g, m, v, np.array(lrs.rows(it, D)), 0.9, 0.999, 1e-15, it + 1, frozen)
+        if it > 0:
+            times.append(time.perf_counter() - t0)
+        it += 1
+        if len(times) >= max_iters or (times and time.perf_counter() - t_start >= max_seconds):
             break
-    return {"value": iters / el, "unit": "iters/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{iters} consecutive c2 training iterations (1 view of 480x640, all 100k Gaussians, "
-                      f"SH degree 3, forward+L1+backward+EMA+Adam in FP64) in {el:.1f} s"}
+    return times, O.num_threads()
+
+
+def cpu_baseline(w, max_seconds=20.0):
+    """The FP64 oracle as it stands, timed on the host for a bounded sample
+    of the same workload: median seconds per training iteration on all of
+    the host's cores and on one thread."""
+    import numpy as np
+    import oracle as O
+    all_cores = os.cpu_count() or 1
+    t_all, used = oracle_iteration_seconds(w, all_cores, 0.6 * max_seconds, 40)
+    t_one, _ = oracle_iteration_seconds(w, 1, 0.4 * max_seconds, 3)
+    O.set_threads(all_cores)
+    med_all, med_one = float(np.median(t_all)), float(np.median(t_one))
+    return {"value": 1.0 / med_all, "unit": "iters/s", "cores": used, "kind": "oracle",
+            "sample": f"median of {len(t_all)} consecutive c2 training iterations after 1 warm-up (1 view of "
+                      f"480x640, all 100k Gaussians, SH degree 3, forward+L1+backward+EMA+Adam in FP64) on "
+                      f"{used} threads",
+            "cpu_model": cpu_model(), "host_cpus": all_cores,
+            "one_thread": {"value": 1.0 / med_one, "unit": "iters/s", "cores": 1,
+                           "sample": f"median of {len(t_one)} iterations after 1 warm-up, same workload"}}
 
 
 def log(msg):
@@ -247,36 +303,58 @@ def main():
         print(json.dumps({"q": args.calibrate, "eps0": calibrate(torch, w, args.calibrate)}))
         return
     steps = args.steps
-    log(f"instance capacity {w['capacity']}")
+    k0 = window_start(steps, w["iters"])
+    log(f"instance capacity {w['capacity']}; timed window [{k0}, {k0 + steps})")
 
     # untimed warm-up iterations (same schedule, discarded)
     if args.warmup > 0:
         run_trainer(torch, w, True, args.warmup)
 
-    # untimed profiling passes over the same schedule: one with the counting
+    # untimed profiling passes over the same window: one with the counting
     # kernel variants for the (pixel, splat) pair counts, one with the
     # production kernels for the per-phase times that pick the dominant phase
     log("counting pass")
-    _, _, _, pairs_all = run_trainer(torch, w, True, steps, profile_phases="all", counters=True)
+    _, _, _, pairs_all = run_trainer(torch, w, True, steps, profile_phases="all", counters=True, start=k0)
     log("profiling pass")
-    trp, _, prof_all, _ = run_trainer(torch, w, True, steps, profile_phases="all")
+    trp, _, prof_all, _ = run_trainer(torch, w, True, steps, profile_phases="all", start=k0)
     dominant = max(prof_all, key=lambda k: prof_all[k][0])
     log(f"dominant phase: {dominant}")
 
     # timed runs (events only around the dominant phase in the GSta run, no
     # counting kernels; the pair counts of the identical counting pass are used)
-    tr_f, dt_f, prof_f, pairs_f = run_trainer(torch, w, True, steps, profile_phases=[dominant])
+    tr_f, dt_f, prof_f, pairs_f = run_trainer(torch, w, True, steps, profile_phases=[dominant], start=k0,
+                                              finish=True)
     log(f"GSta run: {steps / dt_f:.1f} iters/s")
     psnr_f = tr_f.evaluate()
     hist = tr_f.freeze_history()
+    frozen_window = frozen_in_window(hist, k0, k0 + steps, w["n"])
     peak_frozen = max([c for _, _, c in hist], default=0) / w["n"]
-    mean_frozen = _mean_frozen(hist, steps) / w["n"]
-    tr_n, dt_n, _, _ = run_trainer(torch, w, False, steps)
+    mean_frozen = frozen_in_window(hist, 0, tr_f.k, w["n"])
+    tr_n, dt_n, _, _ = run_trainer(torch, w, False, steps, start=k0, finish=True)
     psnr_n = tr_n.evaluate()
-    log("no-freeze profiling pass")
-    _, _, prof_n, _ = run_trainer(torch, w, False, steps, profile_phases="all")
     log(f"no-freeze run: {steps / dt_n:.1f} iters/s; PSNR {psnr_f:.3f} vs {psnr_n:.3f}")
+    log("no-freeze profiling pass")
+    _, _, prof_n, _ = run_trainer(torch, w, False, steps, profile_phases="all", start=k0)
     st, max_inst = w["ctx"].check()
+    if st != 0:
+        raise RuntimeError(f"device flag raised during the benchmark (status {st})")
+
+    # whole schedules on two more view orders: the equal-iteration PSNR check
+    # over three orders, and the whole-schedule rates
+    import synthetic as S
+    deltas = [psnr_f - psnr_n]
+    whole = []
+    for seed in (12, 22):
+        order = S.view_order(len(w["cams"]), w["iters"], seed=seed)
+        rf, df, _, _ = run_trainer(torch, w, True, w["iters"], order=order, finish=True)
+        rn, dn, _, _ = run_trainer(torch, w, False, w["iters"], order=order, finish=True)
+        deltas.append(rf.evaluate() - rn.evaluate())
+        whole.append((w["iters"] / df, w["iters"] / dn))
+        log(f"view order {seed}: delta PSNR {deltas[-1]:+.3f} dB, whole schedule {whole[-1][0]:.1f} vs "
+            f"{whole[-1][1]:.1f} iters/s")
+    st, _ = w["ctx"].check()
+    if st != 0:
+        raise RuntimeError(f"device flag raised during the benchmark (status {st})")
 
     ms_dom, launches = prof_f[dominant]
     n_active_mean = w["n"]          # (refined below from the profiling pass)
@@ -305,17 +383,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 100k Gaussians SH3, 32 cams 480x640, 16x16 tiles, 1 view/iter, "
                                "2000-iteration GSta schedule (warm-up 600, update 50, reset 400 + wait 100, "
-                               "finetune from 1800)",
+                               "finetune from 1800); timed: iterations "
+                               f"[{k0}, {k0 + steps}) of the schedule",
                    "n_gaussians": w["n"], "sh_degree": w["D"], "views": len(w["cams"]), "height": w["H"],
-                   "width": w["W"], "schedule_iters": w["iters"]},
+                   "width": w["W"], "schedule_iters": w["iters"], "timed_window": [k0, k0 + steps]},
         "no_freeze": {"value": round(steps / dt_n, 3), "ms_per_step": round(1000.0 * dt_n / steps, 4),
                       "psnr_db": round(psnr_n, 4),
                       "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_n.items()}},
         "psnr_db": round(psnr_f, 4),
         "delta_psnr_db": round(psnr_f - psnr_n, 4),
+        "delta_psnr_db_view_orders": {"seeds": [2, 12, 22], "values": [round(d, 4) for d in deltas],
+                                      "mean": round(sum(deltas) / len(deltas), 4),
+                                      "min": round(min(deltas), 4), "max": round(max(deltas), 4)},
         "speedup_vs_no_freeze": round(dt_n / dt_f, 4),
+        "schedule_end_iters": [tr_f.k, tr_n.k],
+        "frozen_fraction_timed_window": round(frozen_window, 4),
         "frozen_fraction_peak": round(peak_frozen, 4),
         "frozen_fraction_mean": round(mean_frozen, 4),
+        "whole_schedule_iters_per_s": {"gsta": [round(a, 1) for a, _ in whole],
+                                       "no_freeze": [round(b, 1) for _, b in whole], "seeds": [12, 22]},
         "roofline": {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
                      "unit": unit_r, "frac": round(achieved / peak, 5),
                      "traffic": measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"),

@@ -6,6 +6,7 @@ contiguous in the layouts documented in include/gsta.h.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -89,6 +90,7 @@ class Context:
     def __init__(self, max_gaussians, max_views=1, max_height=64, max_width=64,
                  instance_capacity=1 << 20, n_slots=1):
         self.L = _lib.load()
+        self.segment = 64                     # GSTA_OPT_BWD_SEGMENT (the library default)
         self.limits = Limits(int(max_gaussians), int(max_views), int(max_height), int(max_width),
                              int(instance_capacity), 16, 16, int(n_slots))
         h = ctypes.c_void_p()
@@ -130,6 +132,20 @@ class Context:
 
     def set_option(self, option: int, value: int):
         check(self.h, self.L.gsta_set_option(self.h, int(option), int(value)))
+        if option == _lib.OPT_BWD_SEGMENT:
+            self.segment = int(value)
+
+    @contextlib.contextmanager
+    def forward_only(self):
+        """Renders inside this block are not followed by a backward: they
+        write no compositing checkpoints (segment option 0), so they cannot
+        use up the checkpoint pool; the option is restored afterwards."""
+        saved = self.segment
+        self.set_option(_lib.OPT_BWD_SEGMENT, 0)
+        try:
+            yield self
+        finally:
+            self.set_option(_lib.OPT_BWD_SEGMENT, saved)
 
     def set_waves(self, fwd: int | None = None, bwd: int | None = None):
         if fwd is not None:

@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from .core import Context, adam_sched_tensor, camera_array, n_rows, set_adam_sched_field
 from .schedule import (NONE, RESET, UPDATE, DensifySchedule, FreezeSchedule, LearningRates, PlateauLR,
-                       early_stop, scene_extent)
+                       early_stop, scene_extent, training_end)
 
 FLT_MAX = float(np.finfo(np.float32).max)
 
@@ -43,7 +43,7 @@ class TrainConfig:
     eval_every: int | None = None        # K_PSNR; None: no periodic validation
     early_stop_eps: float | None = None  # eq. 7 threshold (dB); None: no early stop
     plateau: PlateauLR | None = None
-    finetune_iters: int = 0              # K_f after an early stop
+    finetune_iters: int = 0              # K_f: iterations trained after the freezing window closes
     track_ema: bool = False              # keep gradient-norm EMAs even without freezing
     device_sched: bool = False           # Adam scalars from a device schedule (implied by graph)
     graph: bool = False                  # capture each view's iteration once in a HIP graph, then replay
@@ -109,6 +109,7 @@ class Trainer:
         self.psnrs: list[float] = []
         self.stop_iter: int | None = None
         self.pos_scale = 1.0
+        self.scale_log: list[tuple[int, float]] = []     # (first iteration using it, position-LR scale)
         self.frozen_log: list[tuple[int, int]] = []
         self.frozen_counts = torch.zeros(1024, dtype=torch.int64, device="cuda")
         self.use_sched = cfg.device_sched or cfg.graph
@@ -213,6 +214,17 @@ class Trainer:
         if i < self.frozen_counts.numel():
             self.frozen_counts[i:i + 1].copy_(self.n_frozen, non_blocking=True)
         self.frozen_log.append((k, act))
+        self.check_flags(f"freeze-map change before iteration {k}")
+
+    def check_flags(self, where: str):
+        """Synchronise and raise if a kernel raised a device flag since the
+        last check (tile instances or forward checkpoints beyond the reserved
+        capacity, a non-finite gradient): the iterations since then trained
+        on incomplete or wrong gradients."""
+        st, need = self.ctx.check()
+        if st != _lib.GSTA_OK:
+            raise _lib.GstaError(st, f"device flag raised by the iterations up to the {where} "
+                                     f"(instances needed: {need}, reserved: {self.ctx.limits.instance_capacity})")
 
     def _partition(self):
         """Permute every per-Gaussian array in place so that the active
@@ -301,23 +313,59 @@ class Trainer:
         else:
             self._body(view, k)
         self.k += 1
-        if cfg.eval_every and self.k % cfg.eval_every == 0 and self.stop_iter is None:
+        self._after_step()
+
+    def _after_step(self):
+        """Host bookkeeping after iteration k - 1: validation every K_PSNR
+        iterations while the freezing window is open, which feeds eq. 7 and
+        the plateau scheduler."""
+        cfg = self.cfg
+        if (cfg.eval_every and self.k % cfg.eval_every == 0 and self.stop_iter is None
+                and self.k < self.window_close()):
             self._validate()
 
     def _validate(self):
         p = self.evaluate(self.val_views)
+        self.check_flags(f"validation after iteration {self.k}")
         self.psnrs.append(p)
         if self.cfg.plateau is not None:
             scale = self.cfg.plateau.step(p)
-            if self.use_sched and scale != self.pos_scale:
-                set_adam_sched_field(self.sched, "pos_scale", scale)
+            if scale != self.pos_scale:
+                if self.use_sched:
+                    set_adam_sched_field(self.sched, "pos_scale", scale)
+                self.scale_log.append((self.k, scale))
             self.pos_scale = scale
         if self.cfg.early_stop_eps is not None and early_stop(self.psnrs, self.cfg.early_stop_eps):
             self.stop_iter = self.k
 
-    def run(self, iters: int):
-        for _ in range(iters):
-            self.step()
+    def window_close(self) -> int:
+        """Iteration at which the freezing window closes (the finetune starts):
+        the schedule's window end (the forced stop; the run's length without
+        a schedule) or the early-stop iteration, whichever comes first."""
+        s = self.cfg.schedule
+        end = s.window_end if s is not None else self.cfg.iters
+        return end if self.stop_iter is None else min(end, self.stop_iter)
+
+    def end_iter(self) -> int:
+        """Length of the whole training as known now (Algorithm 1): the
+        window close + K_f when the window closes before cfg.iters, else
+        cfg.iters."""
+        s = self.cfg.schedule
+        end = s.window_end if s is not None else self.cfg.iters
+        return training_end(self.cfg.iters, end, self.stop_iter, self.cfg.finetune_iters)
+
+    @property
+    def finished(self) -> bool:
+        return self.k >= self.end_iter()
+
+    def run(self, iters: int | None = None):
+        """Train `iters` iterations, or (None) to the end of training."""
+        if iters is None:
+            while not self.finished:
+                self.step()
+        else:
+            for _ in range(iters):
+                self.step()
 
     # ------------------------------------------------------------------
     def render_views(self, views, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -325,19 +373,31 @@ class Trainer:
         views = list(views)
         out = out if out is not None else torch.empty((len(views), 3, self.H, self.W), device="cuda")
         vmax = self.ctx.limits.max_views
-        for b in range(0, len(views), vmax):
-            vs = views[b:b + vmax]
-            self.ctx.render_forward(self.P, self.degree, [self.cams[v] for v in vs], self.cfg.bg,
-                                    out[b:b + len(vs)], 0)
+        with self.ctx.forward_only():
+            for b in range(0, len(views), vmax):
+                vs = views[b:b + vmax]
+                self.ctx.render_forward(self.P, self.degree, [self.cams[v] for v in vs], self.cfg.bg,
+                                        out[b:b + len(vs)], 0)
         return out
 
     def evaluate(self, views=None) -> float:
-        """Mean PSNR over views (images clamped to [0, 1])."""
+        """Mean over views of the PSNR 10 log10(count / SSE), the squared
+        error summed by gsta_l1_loss over the image clamped to [0, 1]."""
         views = self.val_views if views is None else list(views)
         img = self.render_views(views)
-        tgt = self.targets[views]
-        mse = ((img.clamp(0.0, 1.0) - tgt) ** 2).flatten(1).mean(1).double()
-        return float((10.0 * torch.log10(1.0 / mse)).mean())
+        sse = self.view_sse(img, views)
+        count = 3 * self.H * self.W
+        return float(np.mean([10.0 * np.log10(count / s) for s in sse]))
+
+    def view_sse(self, img: torch.Tensor, views) -> list[float]:
+        """Per view, the squared error of the clamped image against its
+        target, summed by the library's loss kernel (one readback)."""
+        views = list(views)
+        sums = torch.zeros((len(views), 2), dtype=torch.float64, device="cuda")
+        scratch = torch.empty((1, 3, self.H, self.W), device="cuda")
+        for i, v in enumerate(views):
+            self.ctx.l1_loss(img[i:i + 1], self.targets[v:v + 1], scratch, sums[i])
+        return sums[:, 1].cpu().tolist()
 
     def frozen_fraction(self) -> float:
         return float(self.frozen.float().mean()) if self.cfg.freeze else 0.0
@@ -351,9 +411,10 @@ def render_targets(ctx: Context, params: np.ndarray, degree: int, cams, bg=(0.0,
     H, W = cams[0].height, cams[0].width
     out = torch.empty((len(cams), 3, H, W), device="cuda")
     vmax = ctx.limits.max_views
-    for b in range(0, len(cams), vmax):
-        cs = cams[b:b + vmax]
-        ctx.render_forward(P, degree, cs, bg, out[b:b + len(cs)], 0)
+    with ctx.forward_only():
+        for b in range(0, len(cams), vmax):
+            cs = cams[b:b + vmax]
+            ctx.render_forward(P, degree, cs, bg, out[b:b + len(cs)], 0)
     return out
 
 

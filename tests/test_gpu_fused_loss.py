@@ -25,7 +25,7 @@ def _case(kind):
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged", "c2view"])
-@pytest.mark.parametrize("fwd", [0, 4])
+@pytest.mark.parametrize("fwd", [0, 1, 2, 4])
 def test_fused_l1_equals_separate_loss(kind, fwd):
     import torch
     p, D, cams = _case(kind)

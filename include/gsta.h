@@ -13,8 +13,8 @@
  * Conventions for every entry point:
  *   - Pointers are DEVICE pointers unless marked (host).  The caller owns
  *     every argument buffer; the library owns only the scratch held in the
- *     context, allocated by gsta_create / gsta_reserve.  No other call
- *     allocates device memory.
+ *     context, allocated by gsta_create / gsta_reserve, and the fixed device
+ *     array of gsta_l1_loss_noalloc.  No other call allocates device memory.
  *   - Work is enqueued on `stream` and the call returns without
  *     synchronising, except gsta_create, gsta_reserve, gsta_destroy and
  *     gsta_check.
@@ -132,7 +132,8 @@ gsta_status gsta_create(const gsta_limits* lim, gsta_ctx** out);
 /* Grows (never shrinks) the scratch; synchronises the device first. */
 gsta_status gsta_reserve(gsta_ctx* ctx, const gsta_limits* lim);
 void gsta_destroy(gsta_ctx* ctx);
-/* Message for the last non-OK status returned on this context ("" if none). */
+/* Message for the last non-OK status returned on this context ("" if none);
+ * with ctx NULL, that of the last failed context-free call on this thread. */
 const char* gsta_last_error(const gsta_ctx* ctx);
 /* Synchronises `stream`, then reports and clears the device flags:
  * GSTA_ERR_CAPACITY if a render overflowed the instance capacity,
@@ -325,6 +326,22 @@ gsta_status gsta_partition_frozen(gsta_ctx* ctx, int64_t n, uint8_t* frozen, con
  *   (the loss is sums[0] / count, the PSNR 10 log10(count / sums[1])). */
 gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,
                          float* dL_dimage, double* sums, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the L1
+ * loss of gsta_l1_loss without a context.  Same arguments, same kernels and
+ * the same fixed summation order, so dL_dimage and sums equal gsta_l1_loss's
+ * bit for bit.  Its partial sums live in a library-owned device array of
+ * 1024 double2 (16 KiB) per GPU, held until the process ends; the call
+ * allocates nothing.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (different streams, no ordering) race and must not be
+ * issued.  count in [1, GSTA_L1_NOALLOC_MAX_COUNT] (1024 workgroups x 256
+ * lanes x 4096 values per lane); beyond it, or with a NULL pointer, the call
+ * returns GSTA_ERR_INVALID, enqueues nothing and leaves a message for
+ * gsta_last_error(NULL). */
+#define GSTA_L1_NOALLOC_MAX_COUNT ((int64_t)1 << 30)
+gsta_status gsta_l1_loss_noalloc(const float* image, const float* target, int64_t count, float* dL_dimage,
+                                 double* sums, hipStream_t stream);
 
 /* Adaptive densification and pruning (Section 3.1: Gaussians are densified
  * by gradient norm and pruned by opacity; Section 4.1: run every 100

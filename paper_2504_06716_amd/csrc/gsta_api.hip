@@ -113,6 +113,8 @@ struct gsta_ctx {
 
 namespace {
 
+thread_local std::string g_noctx_err;   // last failure of a context-free call on this thread
+
 gsta_status fail(gsta_ctx* ctx, gsta_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -361,6 +363,15 @@ unsigned long long* pair_counter(gsta_ctx* ctx, int which) {
 
 }  // namespace
 
+void gsta::set_noctx_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_noctx_err = buf;
+}
+
 extern "C" {
 
 gsta_status gsta_create(const gsta_limits* lim, gsta_ctx** out) {
@@ -481,7 +492,7 @@ gsta_status gsta_read_profile(gsta_ctx* ctx, double* ms, int64_t* launches, int6
     return GSTA_OK;
 }
 
-const char* gsta_last_error(const gsta_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+const char* gsta_last_error(const gsta_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
 gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;

@@ -324,6 +324,9 @@ void launch_mlp_bf16_copy(const float* w, uint16_t* wb, hipStream_t s);
 void launch_mlp_propose(const float* z, const float* sx, const float* sr, int64_t n, float thr, float vx, float vr,
                         uint8_t* prop, hipStream_t s);
 constexpr int kL1Blocks = 1024;   // partial sums of the loss (fixed-order second pass)
+// Message for gsta_last_error(NULL): the last failure of a call that takes no
+// context, on this thread.
+void set_noctx_error(const char* fmt, ...);
 void launch_l1(const float* img, const float* tgt, int64_t count, float* dL, double* sums, double2* part,
                hipStream_t s);
 void launch_mlp_bce(const float* z, const uint8_t* y, int64_t n, float* dz, double* loss, double2* part,

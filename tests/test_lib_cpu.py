@@ -60,3 +60,17 @@ def test_product_path_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
     finally:
         _lib._lib = saved
+
+
+def test_noalloc_loss_validates_on_the_host():
+    """The context-free loss rejects counts beyond its stated maximum and
+    NULL pointers before touching the device, with a message for
+    gsta_last_error(NULL)."""
+    from paper_2504_06716_amd import _lib
+    L = _lib.load()
+    p = ctypes.c_void_p(16)          # never dereferenced: the call is rejected first
+    for count in (0, -1, _lib.L1_NOALLOC_MAX_COUNT + 1):
+        assert L.gsta_l1_loss_noalloc(p, p, count, p, p, None) == _lib.GSTA_ERR_INVALID
+        assert b"outside" in L.gsta_last_error(None)
+    assert L.gsta_l1_loss_noalloc(p, None, 10, p, p, None) == _lib.GSTA_ERR_INVALID
+    assert b"NULL" in L.gsta_last_error(None)

@@ -274,6 +274,78 @@ def freeze_update(frozen, s_xyz, s_rgb, eps_xyz, eps_rgb, mode, proposal=None):
     return new.astype(np.uint8)
 
 
+# ---------------------------------------------------------------------------
+# The ablation's naive freezing rules (Section 4.3, Table 3 rows "+mingrad"
+# and "+random"): freeze the Gaussians with the lowest 25% gradients, or a
+# random 25% of them, in place of the thresholds of eqs. 4-6.  The random
+# draws come from Philox4x64-10 (Salmon et al., "Parallel random numbers: as
+# easy as 1, 2, 3", SC 2011), written here from its published round
+# function; the GPU implements the same generator on its own.
+# ---------------------------------------------------------------------------
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_U64 = (1 << 64) - 1
+
+
+def philox4x64_10(counter, key):
+    """Philox4x64 with 10 rounds: counter = 4 uint64, key = 2 uint64 ->
+    4 uint64.  Each round multiplies words 0 and 2 by the two constants
+    (128-bit products), mixes the high halves with words 1 and 3 and the key,
+    and the key is bumped by the Weyl constants between rounds."""
+    c = [int(x) & _U64 for x in counter]
+    k = [int(x) & _U64 for x in key]
+    for r in range(10):
+        if r:
+            k = [(k[0] + _PHILOX_W[0]) & _U64, (k[1] + _PHILOX_W[1]) & _U64]
+        p0 = _PHILOX_M[0] * c[0]
+        p1 = _PHILOX_M[1] * c[2]
+        c = [(p1 >> 64) ^ c[1] ^ k[0], p1 & _U64, (p0 >> 64) ^ c[3] ^ k[1], p0 & _U64]
+    return c
+
+
+def random_threshold(fraction):
+    """Integer threshold t with P(u32 < t) = fraction for a uniform u32:
+    floor(fraction * 2^32), at most 2^32."""
+    import math
+    return min(int(math.floor(float(fraction) * 4294967296.0)), 1 << 32)
+
+
+def freeze_random(n, fraction, seed, draw):
+    """"+random": Gaussian i is proposed for freezing iff the top 32 bits of
+    the first word of Philox4x64-10(counter = (i, draw, 0, 0), key = (seed,
+    0)) are below floor(fraction * 2^32), so each Gaussian is drawn
+    independently with probability `fraction` and every freeze update
+    (draw) gets fresh draws."""
+    t = random_threshold(fraction)
+    return np.array([(philox4x64_10((i, draw, 0, 0), (seed, 0))[0] >> 32) < t for i in range(n)], np.uint8)
+
+
+def freeze_mingrad(score, fraction):
+    """"+mingrad": among the Gaussians with a finite average (s < FLT_MAX,
+    i.e. seen at least once), the m = floor(fraction * count) with the
+    smallest positional gradient-norm average, compared in float32, equal
+    values taken in ascending index order."""
+    import math
+    s = np.asarray(score, np.float32)
+    cand = [i for i in range(s.size) if s[i] < np.float32(FLT_MAX)]
+    m = int(math.floor(float(fraction) * float(len(cand))))
+    chosen = sorted(cand, key=lambda i: (float(s[i]), i))[:m]
+    out = np.zeros(s.size, np.uint8)
+    out[chosen] = 1
+    return out
+
+
+def apply_freeze(frozen, cond, mode):
+    """The freeze map after an update whose condition is `cond`: mode 0 ORs
+    it into the map (frozen Gaussians stay frozen), mode 1 resets the map,
+    mode 2 replaces it."""
+    old = np.asarray(frozen) != 0
+    c = np.asarray(cond) != 0
+    new = old | c if mode == 0 else (np.zeros_like(old) if mode == 1 else c)
+    return new.astype(np.uint8)
+
+
 def partition_order(frozen):
     """Column order that puts the Gaussians the optimizer still updates
     (Section 3.2.4: frozen ones are skipped) in front: the active columns in

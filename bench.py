@@ -265,6 +265,51 @@ def cpu_baseline(w, max_seconds=20.0):
                            "sample": f"median of {len(t_one)} iterations after 1 warm-up, same workload"}}
 
 
+def ablation(torch, w, seeds=(2, 12, 22)):
+    """Section 4.3 / Table 3 on this workload: whole 2000-iteration schedules
+    with the gradient rule (eqs. 4-6), "mingrad" and "random" at the paper's
+    25% (accumulated like the rule's map), the two naive rules at the rule's
+    own frozen fraction of each update (the map replaced at each update), and
+    no freezing; per view order the rate, PSNR and frozen fractions."""
+    import dataclasses
+    import synthetic as S
+    from paper_2504_06716_amd.train import Trainer
+    out = {}
+    for seed in seeds:
+        order = S.view_order(len(w["cams"]), w["iters"], seed=seed)
+
+        def run(label, freeze, **rule):
+            cfg = w["cfg"](freeze)
+            if rule:
+                cfg = dataclasses.replace(cfg, schedule=dataclasses.replace(cfg.schedule, **rule))
+            tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], cfg, order, ctx=w["ctx"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            hist = tr.freeze_history()
+            res = {"iters_per_s": round(tr.k / dt, 1), "psnr_db": round(tr.evaluate(), 4),
+                   "frozen_mean": round(frozen_in_window(hist, 0, tr.k, w["n"]), 4),
+                   "frozen_window": round(frozen_in_window(hist, 600, 1800, w["n"]), 4)}
+            out.setdefault(label, []).append(res)
+            log(f"ablation order {seed} {label}: {res}")
+            return tr, hist
+
+        _, hist = run("gradient", True)
+        matched = {k: c / w["n"] for k, a, c in hist if a == 1}
+        run("mingrad_25", True, rule="mingrad", fraction=0.25)
+        run("random_25", True, rule="random", fraction=0.25)
+        run("mingrad_matched", True, rule="mingrad", fraction_at=matched, accumulate=False)
+        run("random_matched", True, rule="random", fraction_at=matched, accumulate=False)
+        run("no_freeze", False)
+    st, _ = w["ctx"].check()
+    if st != 0:
+        raise RuntimeError(f"device flag raised during the ablation (status {st})")
+    return {"ablation": out, "seeds": list(seeds),
+            "workload": "c2, whole 2000-iteration schedules (freezing window [600, 1800), finetune 200)"}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -279,6 +324,8 @@ def main():
     ap.add_argument("--details", default=None, help="write the per-phase breakdown JSON here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB on the device (a plain copy of known size for counter scaling)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="compare the freezing rules of the paper's ablation on whole schedules and exit")
     ap.add_argument("--calibrate", type=float, default=None, metavar="Q",
                     help="print the initial freeze thresholds of the workload for quantile Q and exit")
     args = ap.parse_args()
@@ -301,6 +348,9 @@ def main():
     w = c2_setup(torch)
     if args.calibrate is not None:
         print(json.dumps({"q": args.calibrate, "eps0": calibrate(torch, w, args.calibrate)}))
+        return
+    if args.ablation:
+        print(json.dumps(ablation(torch, w)), flush=True)
         return
     steps = args.steps
     k0 = window_start(steps, w["iters"])

@@ -291,6 +291,25 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
                                     const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen,
                                     hipStream_t stream);
 
+/* The naive freezing rules of the paper's ablation (Section 4.3, Table 3
+ * rows "+mingrad" and "+random"), used in place of the thresholds of eqs. 4-6
+ * to show what the gradient rule gains over them:
+ *   GSTA_FREEZE_RULE_MINGRAD: among the Gaussians with score[i] < FLT_MAX
+ *     (the positional gradient-norm average; FLT_MAX = never seen), the
+ *     m = floor(fraction * count) with the smallest score (float32 order,
+ *     equal scores by ascending index) are chosen.  Exact (radix select).
+ *   GSTA_FREEZE_RULE_RANDOM: Gaussian i is chosen iff the top 32 bits of
+ *     word 0 of Philox4x64-10(counter = (i, draw, 0, 0), key = (seed, 0)) are
+ *     below floor(fraction * 2^32): independent Bernoulli(fraction) draws,
+ *     fresh for every `draw` (e.g. the iteration of the update).  score unused.
+ * The chosen Gaussians are applied with `mode` as in gsta_update_freeze_mask
+ * (0: OR into the map, 1: reset, 2: replace); n_frozen (device int64 [1], may
+ * be NULL) receives the frozen count.  fraction in [0, 1]; n <= max_gaussians. */
+typedef enum { GSTA_FREEZE_RULE_MINGRAD = 1, GSTA_FREEZE_RULE_RANDOM = 2 } gsta_freeze_rule;
+gsta_status gsta_update_freeze_mask_rule(gsta_ctx* ctx, int32_t rule, const float* score, int64_t n,
+                                         double fraction, uint64_t seed, uint64_t draw, int32_t mode,
+                                         uint8_t* frozen, int64_t* n_frozen, hipStream_t stream);
+
 /* One per-Gaussian array for gsta_partition_frozen: `rows` rows of n
  * elements of `elem_bytes` (1, 2 or 4) bytes, row r at base + r*ld elements
  * (ld >= n; rows of one column block, an EMA block [4][n], a bf16 ring

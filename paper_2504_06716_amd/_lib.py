@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NO
 (STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
  STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES, STATE_INST_GID) = range(12)
 OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT, OPT_BINNING = 0, 1, 2, 3
+FREEZE_RULE_MINGRAD, FREEZE_RULE_RANDOM = 1, 2
 
 
 class Limits(ctypes.Structure):
@@ -67,7 +68,7 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
-           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc"]
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
 L1_NOALLOC_MAX_COUNT = 1 << 30
@@ -116,6 +117,8 @@ def load(path: str = LIB_PATH):
     L.gsta_partition_frozen.argtypes = [P, i64, P, ctypes.POINTER(Columns), i32, P, i64, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
     L.gsta_l1_loss_noalloc.argtypes = [P, P, i64, P, P, P]
+    L.gsta_update_freeze_mask_rule.argtypes = [P, i32, P, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                               i32, P, P, P]
     L.gsta_set_profiling.argtypes = [P, i32]
     L.gsta_set_option.argtypes = [P, i32, i64]
     L.gsta_adam_masked_sched.argtypes = [P, PP, PP, PP, PP, P, P, P]

@@ -237,6 +237,17 @@ class Context:
                                                       _arr(n_frozen, (1,), torch.int64, "n_frozen"),
                                                       _stream(stream)))
 
+    def update_freeze_mask_rule(self, rule, score, fraction, seed, draw, mode, frozen, n_frozen=None,
+                                stream=None):
+        """The ablation's naive freezing rules: rule "mingrad" (the fraction of
+        Gaussians with the smallest score) or "random" (Philox draws)."""
+        r = {"mingrad": _lib.FREEZE_RULE_MINGRAD, "random": _lib.FREEZE_RULE_RANDOM}[rule]
+        n = frozen.numel()
+        check(self.h, self.L.gsta_update_freeze_mask_rule(
+            self.h, r, _arr(score, (n,), torch.float32, "score"), n, float(fraction), int(seed), int(draw),
+            int(mode), _arr(frozen, (n,), torch.uint8, "frozen"), _arr(n_frozen, (1,), torch.int64, "n_frozen"),
+            _stream(stream)))
+
     def partition_frozen(self, frozen, arrays, tmp, n_active=None, stream=None):
         """Stable partition of the columns by the freeze map (active first),
         in place.  frozen: uint8 [n]; arrays: device tensors [rows, n] (unit

@@ -92,6 +92,8 @@ struct gsta_ctx {
     uint32_t* dens_tot = nullptr;  // [4] kept, clones, splits, overflow
     uint32_t* part_src = nullptr;  // [max_gaussians] freeze partition gather list
     uint32_t* part_tot = nullptr;  // [1] active count of the partition
+    SelState* sel = nullptr;       // [1] radix-select state of the mingrad freezing rule
+    uint32_t* sel_blk = nullptr;   // [ceil(max_gaussians / 256)] equal-key counts per block
     float* mlp_part = nullptr;     // [kMlpBlocks][kMlpCount] proposer gradient partials
     double* mlp_stats = nullptr;   // [kMlpBlocks][64] feature-statistics partials
     uint64_t* max_inst = nullptr;
@@ -221,6 +223,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->loss_part, kL1Blocks) && alloc(ctx, &ctx->dens_code, l->max_gaussians) &&
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
          alloc(ctx, &ctx->part_src, l->max_gaussians) && alloc(ctx, &ctx->part_tot, 1) &&
+         alloc(ctx, &ctx->sel, 1) && alloc(ctx, &ctx->sel_blk, (l->max_gaussians + 255) / 256) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
@@ -789,6 +792,30 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
     PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
     launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
     return hip_check(ctx, hipGetLastError(), "freeze launch");
+}
+
+gsta_status gsta_update_freeze_mask_rule(gsta_ctx* ctx, int32_t rule, const float* score, int64_t n,
+                                         double fraction, uint64_t seed, uint64_t draw, int32_t mode,
+                                         uint8_t* frozen, int64_t* n_frozen, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (rule != GSTA_FREEZE_RULE_MINGRAD && rule != GSTA_FREEZE_RULE_RANDOM)
+        return fail(ctx, GSTA_ERR_INVALID, "rule must be GSTA_FREEZE_RULE_MINGRAD or GSTA_FREEZE_RULE_RANDOM");
+    if (mode < 0 || mode > 2) return fail(ctx, GSTA_ERR_INVALID, "mode must be 0, 1 or 2");
+    if (!(fraction >= 0.0 && fraction <= 1.0)) return fail(ctx, GSTA_ERR_INVALID, "fraction must be in [0, 1]");
+    if (n < 0 || n > ctx->lim.max_gaussians)
+        return fail(ctx, GSTA_ERR_INVALID, "n = %lld outside [0, max_gaussians = %lld]", (long long)n,
+                    (long long)ctx->lim.max_gaussians);
+    if (!frozen && n > 0) return fail(ctx, GSTA_ERR_INVALID, "frozen is NULL");
+    if (rule == GSTA_FREEZE_RULE_MINGRAD && !score && n > 0) return fail(ctx, GSTA_ERR_INVALID, "score is NULL");
+    PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
+    if (rule == GSTA_FREEZE_RULE_RANDOM) {
+        const double t = std::floor(fraction * 4294967296.0);
+        const uint64_t thr = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+        launch_freeze_random(n, thr, seed, draw, mode, frozen, n_frozen, stream);
+    } else {
+        launch_freeze_mingrad(score, n, fraction, mode, frozen, n_frozen, ctx->sel, ctx->sel_blk, stream);
+    }
+    return hip_check(ctx, hipGetLastError(), "freeze rule launch");
 }
 
 gsta_status gsta_partition_frozen(gsta_ctx* ctx, int64_t n, uint8_t* frozen, const gsta_columns* arrays,

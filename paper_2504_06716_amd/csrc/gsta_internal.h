@@ -268,6 +268,18 @@ void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float
                        int64_t vld, int64_t n, int rows, AdamSched* sched, const uint8_t* frozen, uint32_t* flags,
                        hipStream_t s);
 
+// State of the exact radix select of the "mingrad" freezing rule.
+struct SelState {
+    uint32_t hist[256];          // digit histogram of the current pass
+    unsigned long long count;    // Gaussians taking part (finite average)
+    unsigned long long rem;      // how many of the keys with the current prefix are still to choose
+    uint32_t prefix;             // digits of the threshold key found so far
+    uint32_t none;               // nothing to choose (m = 0)
+};
+void launch_freeze_random(int64_t n, uint64_t thr, uint64_t seed, uint64_t draw, int mode, uint8_t* frozen,
+                          int64_t* n_frozen, hipStream_t s);
+void launch_freeze_mingrad(const float* score, int64_t n, double fraction, int mode, uint8_t* frozen,
+                           int64_t* n_frozen, SelState* st, uint32_t* blk, hipStream_t s);
 void launch_freeze(const float* sx, const float* sr, int64_t n, float ex, float er, int mode,
                    const uint8_t* proposal, uint8_t* frozen, int64_t* n_frozen, hipStream_t s);
 

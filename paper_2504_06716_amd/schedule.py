@@ -23,7 +23,10 @@ class FreezeSchedule:
       and every Gaussian is trained again (finetune).
     Thresholds follow eq. 5 read as eps0 * clamp(lam1 + lam2 * k'/K, lam1,
     lam2) with k' = min(k, k_stop) (``linear``: eps0 * (lam1 + (lam2 - lam1)
-    * k'/K))."""
+    * k'/K)).  ``rule`` replaces the thresholds by one of the ablation's naive
+    rules (Section 4.3): "mingrad" freezes the ``fraction`` of Gaussians with
+    the lowest positional gradient average, "random" a random ``fraction``;
+    the lifecycle stays the same."""
 
     total_iters: int
     warmup: int = 3000
@@ -36,6 +39,16 @@ class FreezeSchedule:
     lam1: float = 0.5
     lam2: float = 1.5
     linear: bool = False
+    rule: str = "gradient"           # "gradient" (eqs. 4-6), or the ablation's "mingrad" / "random"
+    fraction: float = 0.25           # share the ablation rules freeze at each update
+    seed: int = 5                    # Philox key of the "random" rule
+    accumulate: bool = True          # ablation rules: OR into the map (else replace it at each update)
+    fraction_at: dict | None = None  # ablation rules: per-update fraction {iteration: fraction}
+
+    def rule_fraction(self, k: int) -> float:
+        if self.fraction_at is not None and k in self.fraction_at:
+            return self.fraction_at[k]
+        return self.fraction
 
     def factor(self, k: int, k_stop: int | None = None) -> float:
         kk = k if k_stop is None else min(k, k_stop)

@@ -127,6 +127,10 @@ class Trainer:
         elif cfg.proposer is not None or cfg.dataset is not None:
             raise ValueError("the proposer and its dataset need traj_every > 0")
         self.prop_buf = torch.zeros(self.n, dtype=torch.uint8, device="cuda") if cfg.proposer is not None else None
+        if cfg.schedule is not None and cfg.schedule.rule not in ("gradient", "mingrad", "random"):
+            raise ValueError(f"unknown freezing rule {cfg.schedule.rule!r}")
+        if cfg.schedule is not None and cfg.schedule.rule != "gradient" and (cfg.proposer or cfg.dataset):
+            raise ValueError("the learned proposer works with the gradient rule only")
         # Column permutation of the partitioned layout: column i holds the
         # Gaussian that started in column origin[i] (not tracked through
         # densification, which renumbers the set).
@@ -195,7 +199,13 @@ class Trainer:
         act = s.action(k, self.stop_iter)
         if act == NONE:
             return
-        if act == UPDATE:
+        if act == UPDATE and s.rule != "gradient":
+            # the ablation's naive rules; `draw` = the iteration keeps every update's draws fresh
+            self.ctx.update_freeze_mask_rule(s.rule, self.ema[0], s.rule_fraction(k), s.seed, k,
+                                             0 if s.accumulate else 2, self.frozen, n_frozen=self.n_frozen)
+            if self.cfg.partition:
+                self._partition()
+        elif act == UPDATE:
             ex, er = s.thresholds(k, s.window_close(self.stop_iter))
             prop = None
             if self.cfg.dataset is not None:

@@ -206,6 +206,94 @@ def psnr(mse):
 
 
 # ---------------------------------------------------------------------------
+# D-SSIM term of eq. 3 (lambda_SSIM = 0.2) and the loss of eq. 3.  SSIM is
+# the structural similarity of Wang et al. (2004) with the window that 3D
+# Gaussian splatting uses: an 11 x 11 Gaussian of standard deviation 1.5,
+# normalised, applied per channel as a zero-padded 'same' 2-D filter;
+# C1 = 0.01^2, C2 = 0.03^2.  L_D-SSIM = 1 - mean of the SSIM map over every
+# view, channel and pixel.
+# ---------------------------------------------------------------------------
+
+SSIM_C1, SSIM_C2 = 0.01 ** 2, 0.03 ** 2
+SSIM_RADIUS, SSIM_SIGMA = 5, 1.5
+
+
+def ssim_window_1d():
+    """The 11 taps exp(-(i - 5)^2 / (2 * 1.5^2)), normalised to sum 1."""
+    i = np.arange(2 * SSIM_RADIUS + 1, dtype=np.float64) - SSIM_RADIUS
+    g = np.exp(-(i * i) / (2.0 * SSIM_SIGMA * SSIM_SIGMA))
+    return g / g.sum()
+
+
+def filter2d_same(img, w1):
+    """out(y, x) = sum over a, b of w(a) w(b) img(y + a - r, x + b - r), with
+    img taken as zero outside the image: the 2-D window is the outer product
+    of the 1-D taps, written here as a plain sum over its 121 offsets.  img
+    is [..., H, W]."""
+    img = np.asarray(img, np.float64)
+    r = (len(w1) - 1) // 2
+    H, W = img.shape[-2], img.shape[-1]
+    pad = np.zeros(img.shape[:-2] + (H + 2 * r, W + 2 * r))
+    pad[..., r:r + H, r:r + W] = img
+    out = np.zeros_like(img)
+    for a in range(2 * r + 1):
+        for b in range(2 * r + 1):
+            out += w1[a] * w1[b] * pad[..., a:a + H, b:b + W]
+    return out
+
+
+def ssim_map(x, y):
+    """SSIM map of images x, y ([..., H, W], per channel): with mu = G*x,
+    sigma_x^2 = G*(x^2) - mu_x^2, sigma_xy = G*(x y) - mu_x mu_y,
+    S = (2 mu_x mu_y + C1)(2 sigma_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2))."""
+    w = ssim_window_1d()
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    mx, my = filter2d_same(x, w), filter2d_same(y, w)
+    sxx = filter2d_same(x * x, w) - mx * mx
+    syy = filter2d_same(y * y, w) - my * my
+    sxy = filter2d_same(x * y, w) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def dssim_loss(image, target):
+    """L_D-SSIM = 1 - mean SSIM over every value of image [V, 3, H, W], and its
+    gradient with respect to the image.  With m = G*x, s = G*(x^2), c =
+    G*(x y) the map S depends on x only through (m, s, c) at each pixel, so
+    dL/dx = G*(g_m) + 2 x G*(g_s) + y G*(g_c) with g_q = dL/dS * dS/dq:
+    dS/dm = S (2 mu_y / A - 2 mu_y / B - 2 mu_x / C + 2 mu_x / D),
+    dS/ds = -S / D, dS/dc = 2 S / B (A, B, C, D the four factors of S), and
+    the filter is its own adjoint (symmetric taps, zero padding)."""
+    w = ssim_window_1d()
+    x = np.asarray(image, np.float64)
+    y = np.asarray(target, np.float64)
+    mx, my = filter2d_same(x, w), filter2d_same(y, w)
+    sxx = filter2d_same(x * x, w) - mx * mx
+    syy = filter2d_same(y * y, w) - my * my
+    sxy = filter2d_same(x * y, w) - mx * my
+    A = 2 * mx * my + SSIM_C1
+    B = 2 * sxy + SSIM_C2
+    C = mx * mx + my * my + SSIM_C1
+    D = sxx + syy + SSIM_C2
+    S = (A * B) / (C * D)
+    count = S.size
+    loss = 1.0 - S.sum() / count
+    dS = -1.0 / count
+    gm = dS * S * (2 * my / A - 2 * my / B - 2 * mx / C + 2 * mx / D)
+    gs = dS * (-S / D)
+    gc = dS * (2 * S / B)
+    grad = filter2d_same(gm, w) + 2 * x * filter2d_same(gs, w) + y * filter2d_same(gc, w)
+    return loss, grad, S.sum()
+
+
+def total_loss(image, target, lam=0.2):
+    """Eq. 3: L = (1 - lambda) L1 + lambda L_D-SSIM, and dL/dimage."""
+    l1, g1, _ = l1_loss(image, target)
+    ld, gd, _ = dssim_loss(image, target)
+    return (1 - lam) * l1 + lam * ld, (1 - lam) * g1 + lam * gd
+
+
+# ---------------------------------------------------------------------------
 # Masked Adam (Section 3.2.4: frozen Gaussians are not updated)
 # ---------------------------------------------------------------------------
 

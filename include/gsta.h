@@ -346,6 +346,24 @@ gsta_status gsta_partition_frozen(gsta_ctx* ctx, int64_t n, uint8_t* frozen, con
 gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target, int64_t count,
                          float* dL_dimage, double* sums, hipStream_t stream);
 
+/* The D-SSIM term of eq. 3, L = (1 - lambda) L1 + lambda L_D-SSIM with
+ * lambda_SSIM = 0.2 in the paper.  SSIM per channel with an 11 x 11 Gaussian
+ * window (sigma 1.5, normalised, zero padding at the image border), C1 =
+ * 0.01^2, C2 = 0.03^2; L_D-SSIM = 1 - mean of the SSIM map over the
+ * n_views * 3 * height * width values.  The separable window runs as row and
+ * column passes over LDS tiles, fused with the map and its derivative
+ * (Section 3.3, accelerated SSIM).
+ *   image, target [n_views][3][height][width] float32.
+ *   dL_dimage in/out: on entry the L1 gradient (gsta_l1_loss or the fused
+ *     forward), on exit (1 - lambda) dL_dimage + lambda dL_D-SSIM/dimage,
+ *     the gradient of eq. 3.
+ *   ssim_sum (device double [1]) receives the sum of the SSIM map (the loss
+ *     is (1 - lambda) L1 + lambda (1 - ssim_sum / count)).
+ * Sizes must fit the reserved limits; lambda in [0, 1]. */
+gsta_status gsta_dssim_loss(gsta_ctx* ctx, const float* image, const float* target, int32_t n_views,
+                            int32_t height, int32_t width, float lambda, float* dL_dimage, double* ssim_sum,
+                            hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the L1
  * loss of gsta_l1_loss without a context.  Same arguments, same kernels and

@@ -68,7 +68,7 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
-           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule"]
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
 L1_NOALLOC_MAX_COUNT = 1 << 30
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
     L.gsta_partition_frozen.argtypes = [P, i64, P, ctypes.POINTER(Columns), i32, P, i64, P, P]
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
     L.gsta_l1_loss_noalloc.argtypes = [P, P, i64, P, P, P]
+    L.gsta_dssim_loss.argtypes = [P, P, P, i32, i32, i32, f32, P, P, P]
     L.gsta_update_freeze_mask_rule.argtypes = [P, i32, P, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                                i32, P, P, P]
     L.gsta_set_profiling.argtypes = [P, i32]

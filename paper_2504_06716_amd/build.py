@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsta.so")
-SOURCES = ["gsta_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_optim.hip", "k_densify.hip", "k_mlp.hip", "gsta_noalloc.hip", "k_freeze_rules.hip"]
+SOURCES = ["gsta_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_optim.hip", "k_densify.hip", "k_mlp.hip", "gsta_noalloc.hip", "k_freeze_rules.hip", "k_ssim.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -237,6 +237,18 @@ class Context:
                                                       _arr(n_frozen, (1,), torch.int64, "n_frozen"),
                                                       _stream(stream)))
 
+    def dssim_loss(self, image, target, lam, dL_dimage, ssim_sum, stream=None):
+        """Eq. 3's D-SSIM term: dL_dimage (the L1 gradient on entry) becomes
+        (1 - lam) dL_dimage + lam dL_D-SSIM/dimage; ssim_sum (device double
+        [1]) receives the sum of the SSIM map."""
+        sh = tuple(image.shape)
+        if len(sh) != 4 or sh[1] != 3:
+            raise ValueError("image: expected [views, 3, H, W]")
+        check(self.h, self.L.gsta_dssim_loss(self.h, _arr(image, sh, torch.float32, "image"),
+                                              _arr(target, sh, torch.float32, "target"), sh[0], sh[2], sh[3],
+                                              float(lam), _arr(dL_dimage, sh, torch.float32, "dL_dimage"),
+                                              _arr(ssim_sum, (1,), torch.float64, "ssim_sum"), _stream(stream)))
+
     def update_freeze_mask_rule(self, rule, score, fraction, seed, draw, mode, frozen, n_frozen=None,
                                 stream=None):
         """The ablation's naive freezing rules: rule "mingrad" (the fraction of

@@ -92,6 +92,8 @@ struct gsta_ctx {
     uint32_t* dens_tot = nullptr;  // [4] kept, clones, splits, overflow
     uint32_t* part_src = nullptr;  // [max_gaussians] freeze partition gather list
     uint32_t* part_tot = nullptr;  // [1] active count of the partition
+    float* ssim_g = nullptr;       // [3][max_views * 3 * H * W] D-SSIM partial-derivative maps
+    double* ssim_part = nullptr;   // [ssim_blocks] per-workgroup SSIM sums
     SelState* sel = nullptr;       // [1] radix-select state of the mingrad freezing rule
     uint32_t* sel_blk = nullptr;   // [ceil(max_gaussians / 256)] equal-key counts per block
     float* mlp_part = nullptr;     // [kMlpBlocks][kMlpCount] proposer gradient partials
@@ -224,6 +226,8 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->dens_boff, 3 * densify_blocks(l->max_gaussians)) && alloc(ctx, &ctx->dens_tot, 4) &&
          alloc(ctx, &ctx->part_src, l->max_gaussians) && alloc(ctx, &ctx->part_tot, 1) &&
          alloc(ctx, &ctx->sel, 1) && alloc(ctx, &ctx->sel_blk, (l->max_gaussians + 255) / 256) &&
+         alloc(ctx, &ctx->ssim_g, 3 * V * 3 * HW) &&
+         alloc(ctx, &ctx->ssim_part, ssim_blocks((int)V, l->max_height, l->max_width)) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
@@ -792,6 +796,22 @@ gsta_status gsta_update_freeze_mask(gsta_ctx* ctx, const float* score_xyz, const
     PhaseTimer pt(ctx, GSTA_PHASE_FREEZE, stream);
     launch_freeze(score_xyz, score_rgb, n, eps_xyz, eps_rgb, mode, proposal, frozen, n_frozen, stream);
     return hip_check(ctx, hipGetLastError(), "freeze launch");
+}
+
+gsta_status gsta_dssim_loss(gsta_ctx* ctx, const float* image, const float* target, int32_t n_views,
+                            int32_t height, int32_t width, float lambda, float* dL_dimage, double* ssim_sum,
+                            hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (n_views < 1 || n_views > ctx->lim.max_views || height < 1 || height > ctx->lim.max_height || width < 1 ||
+        width > ctx->lim.max_width)
+        return fail(ctx, GSTA_ERR_INVALID, "views x height x width = %d x %d x %d beyond the reserved %d x %d x %d",
+                    n_views, height, width, ctx->lim.max_views, ctx->lim.max_height, ctx->lim.max_width);
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(ctx, GSTA_ERR_INVALID, "lambda must be in [0, 1]");
+    if (!image || !target || !dL_dimage || !ssim_sum) return fail(ctx, GSTA_ERR_INVALID, "NULL pointer argument");
+    PhaseTimer pt(ctx, GSTA_PHASE_LOSS, stream);
+    launch_dssim(image, target, n_views, height, width, lambda, dL_dimage, ssim_sum, ctx->ssim_g, ctx->ssim_part,
+                 stream);
+    return hip_check(ctx, hipGetLastError(), "dssim launch");
 }
 
 gsta_status gsta_update_freeze_mask_rule(gsta_ctx* ctx, int32_t rule, const float* score, int64_t n,

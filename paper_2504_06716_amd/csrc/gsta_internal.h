@@ -268,6 +268,14 @@ void launch_adam_sched(float* p, int64_t pld, const float* g, int64_t gld, float
                        int64_t vld, int64_t n, int rows, AdamSched* sched, const uint8_t* frozen, uint32_t* flags,
                        hipStream_t s);
 
+// The 11 taps of the SSIM window (Gaussian, sigma 1.5, normalised).
+struct SsimTaps {
+    double w[11];
+};
+int64_t ssim_blocks(int nv, int H, int W);
+void launch_dssim(const float* img, const float* tgt, int nv, int H, int W, float lambda, float* dL, double* ssim_sum,
+                  float* gmap, double* part, hipStream_t s);
+
 // State of the exact radix select of the "mingrad" freezing rule.
 struct SelState {
     uint32_t hist[256];          // digit histogram of the current pass

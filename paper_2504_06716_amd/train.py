@@ -55,6 +55,7 @@ class TrainConfig:
     dataset: object | None = None        # proposer.ProposerDataset to record the rule's decisions into
     partition: bool = False              # after each freeze update, move the frozen columns behind the active ones
     fused_loss: bool = True              # L1 loss computed by the forward compositing (else a separate pass)
+    lambda_ssim: float = 0.0             # eq. 3: L = (1 - lambda) L1 + lambda D-SSIM (the paper uses 0.2)
 
 
 class Trainer:
@@ -104,6 +105,7 @@ class Trainer:
         self.dL = torch.empty_like(self.image)
         self.tgt_batch = torch.empty_like(self.image) if vb > 1 else None
         self.sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+        self.ssim_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.step_count = 0
         self.k = 0
         self.psnrs: list[float] = []
@@ -286,6 +288,8 @@ class Trainer:
         else:
             self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
             self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
+        if cfg.lambda_ssim > 0.0:
+            self.ctx.dssim_loss(self.image, tgt, cfg.lambda_ssim, self.dL, self.ssim_sum)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
                                  cfg.ema_beta, dstats=self.dstats)
         if self.use_sched:
@@ -408,6 +412,13 @@ class Trainer:
         for i, v in enumerate(views):
             self.ctx.l1_loss(img[i:i + 1], self.targets[v:v + 1], scratch, sums[i])
         return sums[:, 1].cpu().tolist()
+
+    def loss(self) -> float:
+        """Eq. 3 loss of the last iteration (synchronises)."""
+        count = self.image.numel()
+        l1 = float(self.sums[0]) / count
+        lam = self.cfg.lambda_ssim
+        return l1 if lam == 0.0 else (1.0 - lam) * l1 + lam * (1.0 - float(self.ssim_sum[0]) / count)
 
     def frozen_fraction(self) -> float:
         return float(self.frozen.float().mean()) if self.cfg.freeze else 0.0

@@ -51,6 +51,7 @@ def lib():
         L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_opacity_activation.argtypes = [ctypes.c_int]
         L.oracle_render_pixels.argtypes = [P, i64, i64, i32, P, P, P, i64, P, P, P]
         _lib = L
     return _lib
@@ -63,6 +64,36 @@ def num_threads() -> int:
 def set_threads(n: int) -> None:
     """Threads of the C++ oracle's parallel loops from now on."""
     lib().oracle_set_threads(int(n))
+
+
+class opacity_activation:
+    """Context in which the rasterizer reads row 10 as the opacity itself,
+    opacity = |x| (act 1, the finetune stage of Section 4.1), instead of
+    sigmoid(x) (act 0)."""
+
+    def __init__(self, act: int):
+        self.act = int(act)
+
+    def __enter__(self):
+        lib().oracle_set_opacity_activation(self.act)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_opacity_activation(0)
+        return False
+
+
+def opacity_to_absolute(params, m, v):
+    """The switch to the absolute activation when the finetune starts:
+    row 10 <- sigmoid(row 10) (every opacity unchanged) and the moments of
+    row 10 restart from zero."""
+    P = np.array(params, np.float64)
+    M = np.array(m, np.float64)
+    V = np.array(v, np.float64)
+    P[10] = 1.0 / (1.0 + np.exp(-P[10]))
+    M[10] = 0.0
+    V[10] = 0.0
+    return P, M, V
 
 
 def _ptr(a: np.ndarray):

@@ -159,6 +159,10 @@ struct Proj {
     double m_near, m_det, m_rect, m_tan, m_col;
 };
 
+// Opacity activation (Section 4.1): 0 sigmoid of the logit in row 10; 1 the
+// absolute value of row 10, used by the finetune stage.
+int g_opacity_act = 0;
+
 double frac_dist(double x) {   // distance of x to the nearest integer
     return std::fabs(x - std::nearbyint(x));
 }
@@ -198,8 +202,9 @@ void project(const double* P, int64_t n, int64_t ld, int degree, int64_t g, cons
             p.Sigma[i][j] = acc;                              // Sigma = M M^T
         }
 
-    // Opacity (sigmoid of the logit) and colour are defined for every Gaussian.
-    p.opacity = 1.0 / (1.0 + std::exp(-par(10)));
+    // Opacity (sigmoid of the logit, or |x| in the finetune stage) and colour
+    // are defined for every Gaussian.
+    p.opacity = g_opacity_act ? std::fabs(par(10)) : 1.0 / (1.0 + std::exp(-par(10)));
     for (int i = 0; i < 3; ++i) p.dir[i] = p.mu[i] - cam.pos[i];
     p.dlen = std::sqrt(p.dir[0] * p.dir[0] + p.dir[1] * p.dir[1] + p.dir[2] * p.dir[2]);
     for (int i = 0; i < 3; ++i) p.dn[i] = p.dir[i] / p.dlen;
@@ -390,8 +395,14 @@ void chain_to_params(const Proj& p, const Cam& cam, int degree, const double* P,
     double dot = ddn[0] * p.dn[0] + ddn[1] * p.dn[1] + ddn[2] * p.dn[2];
     for (int a = 0; a < 3; ++a) dmu[a] += (ddn[a] - p.dn[a] * dot) / p.dlen;
 
-    // Opacity: o = sigmoid(logit).
-    gsum[10] += d2[5] * p.opacity * (1.0 - p.opacity);
+    // Opacity: o = sigmoid(logit), do/dlogit = o (1 - o); or o = |x|,
+    // do/dx = sign(x) (0 at x = 0).
+    if (g_opacity_act) {
+        const double x = par(10);
+        gsum[10] += x > 0 ? d2[5] : (x < 0 ? -d2[5] : 0.0);
+    } else {
+        gsum[10] += d2[5] * p.opacity * (1.0 - p.opacity);
+    }
 
     // Conic K = A^-1 with A = [[a, b], [b, c]] (dilated).  Matrix gradient of
     // the symmetric K: GK = [[dL/dca, dL/dcb / 2], [dL/dcb / 2, dL/dcc]];
@@ -500,6 +511,9 @@ int oracle_num_threads() {
     return 1;
 #endif
 }
+
+// Selects the opacity activation of later calls (0 sigmoid, 1 absolute value).
+void oracle_set_opacity_activation(int act) { g_opacity_act = act ? 1 : 0; }
 
 // Sets the threads of later OpenMP loops (timing at 1 thread and at all cores).
 void oracle_set_threads(int n) {

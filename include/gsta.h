@@ -84,6 +84,9 @@ typedef struct {
     int64_t n;                  /* Gaussians */
     int64_t ld;                 /* row stride in elements, >= n */
     int32_t sh_degree;          /* 0..3 */
+    int32_t opacity_act;        /* row 10 -> opacity: 0 sigmoid(logit) (default); 1 |x|, the
+                                   "absolute" activation of the finetune stage (Section 4.1),
+                                   opacities above 1 allowed (alpha stays capped at 0.99) */
     float* block;               /* device, [R][ld] float32 */
 } gsta_params;
 
@@ -428,6 +431,15 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
                                gsta_params* g_out, gsta_params* m_out, gsta_params* v_out,
                                float* ema_out, uint8_t* frozen_out, int64_t* counts,
                                hipStream_t stream);
+
+/* Switch to the finetune stage's absolute opacity activation (Section 4.1:
+ * when the finetune starts, opacity = sigmoid(x) becomes opacity = |x|).
+ * For every column of g (opacity_act 0 on entry): x <- sigmoid(x), so each
+ * opacity is unchanged, and the Adam moments of row 10 are zeroed (they were
+ * taken in logit units).  The caller renders g with opacity_act = 1 from
+ * then on.  g, m, v share n. */
+gsta_status gsta_opacity_to_absolute(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gsta_params* v,
+                                     hipStream_t stream);
 
 /* Opacity reset (Section 4.1, every 3K iterations): for every active
  * Gaussian logit <- min(logit, logit_cap) (opacity capped at

@@ -35,7 +35,7 @@ class Camera(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
-                ("block", ctypes.c_void_p)]
+                ("opacity_act", ctypes.c_int32), ("block", ctypes.c_void_p)]
 
 
 class AdamSched(ctypes.Structure):
@@ -68,7 +68,7 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
-           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss"]
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss", "gsta_opacity_to_absolute"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
 L1_NOALLOC_MAX_COUNT = 1 << 30
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
                                        PP, P, P, f32, P, P]
     L.gsta_densify_prune.argtypes = [P, PP, PP, PP, P, P, P, P, ctypes.POINTER(DensifyCfg), PP, PP, PP, P, P, P, P]
     L.gsta_opacity_reset.argtypes = [P, PP, PP, PP, P, f32, P]
+    L.gsta_opacity_to_absolute.argtypes = [P, PP, PP, PP, P]
     L.gsta_traj_push.argtypes = [P, P, i64, P, i32, P]
     L.gsta_mlp_feature_stats.argtypes = [P, P, i64, i32, P, P]
     L.gsta_mlp_features.argtypes = [P, P, i64, i32, P, P, P, P]

@@ -47,18 +47,19 @@ def _arr(t, shape, dtype, name):
     return _ptr(t)
 
 
-def params_struct(block: torch.Tensor, degree: int) -> Params:
-    """[R, n] float32 device tensor (row stride = block.stride(0))."""
+def params_struct(block: torch.Tensor, degree: int, opacity_act: int = 0) -> Params:
+    """[R, n] float32 device tensor (row stride = block.stride(0)); opacity_act
+    1 selects the finetune stage's absolute opacity activation."""
     if block.dtype != torch.float32 or block.dim() != 2:
         raise ValueError("parameter blocks are [R, n] float32")
     if block.shape[0] != n_rows(degree):
         raise ValueError(f"expected {n_rows(degree)} rows for SH degree {degree}, got {block.shape[0]}")
     n = block.shape[1]
     if n == 0:
-        return Params(0, 1, degree, block.data_ptr() or None)
+        return Params(n=0, ld=1, sh_degree=degree, opacity_act=opacity_act, block=block.data_ptr() or None)
     if block.stride(1) != 1 or block.stride(0) < n:
         raise ValueError("parameter blocks need unit column stride and row stride >= n")
-    return Params(n, block.stride(0), degree, block.data_ptr())
+    return Params(n=n, ld=block.stride(0), sh_degree=degree, opacity_act=opacity_act, block=block.data_ptr())
 
 
 def camera_struct(cam) -> Camera:
@@ -177,18 +178,19 @@ class Context:
         return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, tuple(pr)
 
     # ---- hot path --------------------------------------------------------
-    def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None):
-        ps = params_struct(params, degree)
+    def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None, opacity_act=0):
+        ps = params_struct(params, degree, opacity_act)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         shape = (len(ca), 3, ca[0].height, ca[0].width)
         check(self.h, self.L.gsta_render_forward(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
                                                   _arr(image, shape, torch.float32, "image"), slot,
                                                   _stream(stream)))
 
-    def render_forward_l1(self, params, degree, cams, bg, target, image, dL_dimage, sums, slot=0, stream=None):
+    def render_forward_l1(self, params, degree, cams, bg, target, image, dL_dimage, sums, slot=0, stream=None,
+                          opacity_act=0):
         """render_forward with the L1 loss against `target` fused into the
         compositing: dL_dimage and sums as l1_loss gives them."""
-        ps = params_struct(params, degree)
+        ps = params_struct(params, degree, opacity_act)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         shape = (len(ca), 3, ca[0].height, ca[0].width)
         check(self.h, self.L.gsta_render_forward_l1(
@@ -197,8 +199,8 @@ class Context:
             _arr(sums, (2,), torch.float64, "sums"), slot, _stream(stream)))
 
     def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
-                        grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None):
-        ps = params_struct(params, degree)
+                        grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None, opacity_act=0):
+        ps = params_struct(params, degree, opacity_act)
         gs = params_struct(grad, degree)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         V, n = len(ca), ps.n
@@ -311,6 +313,13 @@ class Context:
             _arr(dstats, (4, n), torch.float32, "dstats"), _arr(noise, (6, n), torch.float32, "noise"),
             ctypes.byref(cfg), ctypes.byref(so), ctypes.byref(smo), ctypes.byref(svo),
             _ptr(ema_out), _ptr(frozen_out), _arr(counts, (4,), torch.int64, "counts"), _stream(stream)))
+
+    def opacity_to_absolute(self, p, m, v, degree, stream=None):
+        """Finetune switch to the absolute opacity activation: row 10 <-
+        sigmoid(row 10), its Adam moments zeroed."""
+        sp, sm, sv = (params_struct(x, degree) for x in (p, m, v))
+        check(self.h, self.L.gsta_opacity_to_absolute(self.h, ctypes.byref(sp), ctypes.byref(sm), ctypes.byref(sv),
+                                                       _stream(stream)))
 
     def opacity_reset(self, p, m, v, degree, frozen, logit_cap, stream=None):
         sp, sm, sv = (params_struct(x, degree) for x in (p, m, v))

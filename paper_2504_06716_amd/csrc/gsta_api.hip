@@ -305,6 +305,8 @@ gsta_status check_params(gsta_ctx* ctx, const gsta_params* g, const char* name) 
                     (long long)g->n, (long long)ctx->lim.max_gaussians);
     if (g->ld < g->n || g->ld < 1) return fail(ctx, GSTA_ERR_INVALID, "%s.ld < n", name);
     if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GSTA_ERR_INVALID, "%s.sh_degree not in 0..3", name);
+    if (g->opacity_act != 0 && g->opacity_act != 1)
+        return fail(ctx, GSTA_ERR_INVALID, "%s.opacity_act must be 0 (sigmoid) or 1 (absolute)", name);
     return GSTA_OK;
 }
 
@@ -605,7 +607,7 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
-                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, stream);
+                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, g->opacity_act, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
@@ -730,7 +732,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
                               ctx->stamps, ctx->gen, s.n_count, frozen, ctx->d2sum, grad->block,
                               grad->ld, ema,
                               ema_beta, grad2d,
-                              dstats, stream);
+                              dstats, g->opacity_act, stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }
@@ -901,6 +903,8 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
     }
     const int64_t n = g->n, cap = g_out->n;
     const int D = g->sh_degree;
+    if (g->opacity_act != 0)
+        return fail(ctx, GSTA_ERR_INVALID, "densification prunes by the opacity logit: g.opacity_act must be 0");
     for (int k = 0; k < 3; ++k) {
         if (in[k]->n != n || in[k]->sh_degree != D || out[k]->sh_degree != D || out[k]->n != cap)
             return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n; outputs share the capacity; one sh_degree");
@@ -952,9 +956,24 @@ gsta_status gsta_opacity_reset(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gs
     if ((st = check_params(ctx, v, "v")) != GSTA_OK) return st;
     if (m->n != g->n || v->n != g->n) return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n");
     if (!std::isfinite(logit_cap)) return fail(ctx, GSTA_ERR_INVALID, "logit_cap must be finite");
+    if (g->opacity_act != 0) return fail(ctx, GSTA_ERR_INVALID, "the opacity reset caps the logit: g.opacity_act must be 0");
     PhaseTimer pt(ctx, GSTA_PHASE_DENSIFY, stream);
     launch_opacity_reset(g->block, g->ld, m->block, m->ld, v->block, v->ld, g->n, frozen, logit_cap, stream);
     return hip_check(ctx, hipGetLastError(), "opacity reset launch");
+}
+
+gsta_status gsta_opacity_to_absolute(gsta_ctx* ctx, gsta_params* g, gsta_params* m, gsta_params* v,
+                                     hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    gsta_status st;
+    if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, m, "m")) != GSTA_OK) return st;
+    if ((st = check_params(ctx, v, "v")) != GSTA_OK) return st;
+    if (m->n != g->n || v->n != g->n) return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n");
+    if (g->opacity_act != 0) return fail(ctx, GSTA_ERR_INVALID, "g already uses the absolute activation");
+    PhaseTimer pt(ctx, GSTA_PHASE_DENSIFY, stream);
+    launch_opacity_to_abs(g->block, g->ld, m->block, m->ld, v->block, v->ld, g->n, stream);
+    return hip_check(ctx, hipGetLastError(), "opacity activation switch launch");
 }
 
 // ---- learned freeze proposer ----------------------------------------------

@@ -105,7 +105,8 @@ __device__ __forceinline__ float wave_sum(float x) {
 // first_hist_given.
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, hipStream_t s);
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
+                           hipStream_t s);
 
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
 // expansion offsets inst_off[v][gid], in tile order, taking a slot only if
@@ -117,7 +118,8 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
-                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s);
+                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, int opact,
+                           hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
 // seg_stride elements; element count per segment from d_count (device, if
@@ -313,6 +315,8 @@ struct DensIO {
 int64_t densify_blocks(int64_t n);
 void launch_densify(const DensIO& io, const DensCfg& cfg, uint8_t* code, uint32_t* boff, uint32_t* tot,
                     int64_t* counts, uint32_t* flags, hipStream_t s);
+void launch_opacity_to_abs(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
+                           hipStream_t s);
 void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
                           const uint8_t* frozen, float cap, hipStream_t s);
 // Stable partition of the columns by the freeze map (active first), applied

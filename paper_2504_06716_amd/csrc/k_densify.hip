@@ -220,6 +220,16 @@ __global__ __launch_bounds__(256) void k_opacity_reset(float* __restrict__ P, in
     V[10 * vld + i] = 0.f;
 }
 
+// Finetune switch to the absolute opacity activation: the parameter becomes
+// the opacity itself (sigmoid of the logit) and the row's moments restart.
+__global__ __launch_bounds__(256) void k_opacity_to_abs(float* __restrict__ P, int64_t ld, float* __restrict__ M,
+                                                        int64_t mld, float* __restrict__ V, int64_t vld, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    P[10 * ld + i] = 1.0f / (1.0f + expf(-P[10 * ld + i]));
+    M[10 * mld + i] = 0.f;
+    V[10 * vld + i] = 0.f;
+}
 
 // ---- stable partition by the freeze map --------------------------------
 // Active (frozen == 0) columns move to [0, A) and frozen ones to [A, n), each
@@ -347,6 +357,12 @@ void launch_opacity_reset(float* P, int64_t ld, float* M, int64_t mld, float* V,
                           const uint8_t* frozen, float cap, hipStream_t s) {
     if (n <= 0) return;
     k_opacity_reset<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, ld, M, mld, V, vld, n, frozen, cap);
+}
+
+void launch_opacity_to_abs(float* P, int64_t ld, float* M, int64_t mld, float* V, int64_t vld, int64_t n,
+                           hipStream_t s) {
+    if (n <= 0) return;
+    k_opacity_to_abs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, ld, M, mld, V, vld, n);
 }
 
 void launch_partition(int64_t n, uint8_t* frozen, const PartArray* arrays, int count, void* tmp,

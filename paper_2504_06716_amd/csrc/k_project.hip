@@ -164,8 +164,12 @@ __device__ __forceinline__ bool project_geo(const DevCam& cm, const float* mu, c
     return true;
 }
 
+// Opacity activation: sigmoid of the logit (opact 0), or the absolute value
+// of the parameter (opact 1), which the finetune stage switches to
+// (Section 4.1: the "absolute" activation of Taming 3DGS; opacities above 1
+// then make high-opacity Gaussians, alpha still capped at 0.99).
 __device__ __forceinline__ void load_core(const float* __restrict__ P, int64_t ld, int64_t i, float* mu,
-                                          float* s, float* qn, float* Rq, float& qinv, float& o) {
+                                          float* s, float* qn, float* Rq, float& qinv, float& o, int opact) {
     mu[0] = P[i];
     mu[1] = P[ld + i];
     mu[2] = P[2 * ld + i];
@@ -178,7 +182,8 @@ __device__ __forceinline__ void load_core(const float* __restrict__ P, int64_t l
 #pragma unroll
     for (int k = 0; k < 4; ++k) qn[k] = q[k] * qinv;
     quat_rot(qn, Rq);
-    o = 1.0f / (1.0f + expf(-P[10 * ld + i]));
+    const float x = P[10 * ld + i];
+    o = opact ? fabsf(x) : 1.0f / (1.0f + expf(-x));
 }
 
 template <int D>
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     float4* __restrict__ geo, float4* __restrict__ col, float4* __restrict__ rgbo,
     ushort4* __restrict__ rect, uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch) {
+    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch, int opact) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ uint32_t s_h[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
     float mu[3], s[3], qn[4], Rq[9], qinv, o;
     float f[K][3];
     if (valid) {
-        load_core(P, ld, i, mu, s, qn, Rq, qinv, o);
+        load_core(P, ld, i, mu, s, qn, Rq, qinv, o, opact);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const ushort4* __restrict__ rect, int64_t stride, const float* __restrict__ d2sum,
     const uint8_t* __restrict__ frozen,
     float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
-    float* __restrict__ dstats, uint32_t* __restrict__ genp) {
+    float* __restrict__ dstats, uint32_t* __restrict__ genp, int opact) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // Every reader of this backward's generation (the compositing backward
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     if (i >= n) return;
     if (frozen && frozen[i]) return;
     float mu[3], s[3], qn[4], Rq[9], qinv, o;
-    load_core(P, ld, i, mu, s, qn, Rq, qinv, o);
+    load_core(P, ld, i, mu, s, qn, Rq, qinv, o, opact);
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -452,7 +457,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         }
 
         // ---- opacity ----
-        glogit += d2[5] * o * (1.f - o);
+        if (opact) {   // d|x|/dx = sign(x), 0 at x = 0
+            const float x = P[10 * ld + i];
+            glogit += x > 0.f ? d2[5] : (x < 0.f ? -d2[5] : 0.f);
+        } else {
+            glogit += d2[5] * o * (1.f - o);
+        }
 
         // ---- conic = A^-1:  GA = -K GK K with GK = [[dca, dcb/2], [dcb/2, dcc]] ----
         float pk = g.c * g.inv, qk = -g.b * g.inv, rk = g.a * g.inv;
@@ -564,10 +574,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, hipStream_t s) {
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
+                           hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     const int64_t hp = (n + 255) / 256;
-#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp
+#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp, opact
     switch (degree) {
         case 0: k_preprocess_fwd<0><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
         case 1: k_preprocess_fwd<1><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
@@ -581,11 +592,12 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
                            int nv, const ushort4* rect, const uint32_t* inst_off, int64_t stride,
                            const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
-                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, hipStream_t s) {
+                           int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, int opact,
+                           hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     k_sum_partials<<<dim3((unsigned)((n + kSumRows - 1) / kSumRows), (unsigned)nv), block, 0, s>>>(
         rect, inst_off, stride, n, partials, stamps, gen, d_count, frozen, d2sum);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats, gen
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats, gen, opact
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -56,6 +56,7 @@ class TrainConfig:
     partition: bool = False              # after each freeze update, move the frozen columns behind the active ones
     fused_loss: bool = True              # L1 loss computed by the forward compositing (else a separate pass)
     lambda_ssim: float = 0.0             # eq. 3: L = (1 - lambda) L1 + lambda D-SSIM (the paper uses 0.2)
+    abs_opacity_finetune: bool = False   # Section 4.1: opacity = |x| instead of sigmoid once the finetune starts
 
 
 class Trainer:
@@ -106,6 +107,7 @@ class Trainer:
         self.tgt_batch = torch.empty_like(self.image) if vb > 1 else None
         self.sums = torch.zeros(2, dtype=torch.float64, device="cuda")
         self.ssim_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.opacity_act = 0                 # 1 after the finetune's switch to the absolute activation
         self.step_count = 0
         self.k = 0
         self.psnrs: list[float] = []
@@ -283,15 +285,17 @@ class Trainer:
             idx = torch.as_tensor(view, device="cuda")
             torch.index_select(self.targets, 0, idx, out=self.tgt_batch)
             tgt = self.tgt_batch
+        act = self.opacity_act
         if cfg.fused_loss:
-            self.ctx.render_forward_l1(self.P, self.degree, cam, cfg.bg, tgt, self.image, self.dL, self.sums, 0)
+            self.ctx.render_forward_l1(self.P, self.degree, cam, cfg.bg, tgt, self.image, self.dL, self.sums, 0,
+                                       opacity_act=act)
         else:
-            self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0)
+            self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0, opacity_act=act)
             self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
         if cfg.lambda_ssim > 0.0:
             self.ctx.dssim_loss(self.image, tgt, cfg.lambda_ssim, self.dL, self.ssim_sum)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
-                                 cfg.ema_beta, dstats=self.dstats)
+                                 cfg.ema_beta, dstats=self.dstats, opacity_act=act)
         if self.use_sched:
             self.ctx.adam_masked_sched(self.P, self.G, self.M, self.Vm, self.degree, self.sched, frz)
         else:
@@ -304,6 +308,11 @@ class Trainer:
         k = self.k
         cfg = self.cfg
         self._densify_step(k)
+        if cfg.abs_opacity_finetune and self.opacity_act == 0 and k >= self.window_close():
+            # the finetune starts: opacity = |x| from now on, x = the current opacity
+            self.ctx.opacity_to_absolute(self.P, self.M, self.Vm, self.degree)
+            self.opacity_act = 1
+            self.graphs.clear()                      # the captured calls carry the old activation
         if self.traj is not None:
             self.traj.maybe_push(k, self.ema)
         self._freeze_step(k)
@@ -391,7 +400,7 @@ class Trainer:
             for b in range(0, len(views), vmax):
                 vs = views[b:b + vmax]
                 self.ctx.render_forward(self.P, self.degree, [self.cams[v] for v in vs], self.cfg.bg,
-                                        out[b:b + len(vs)], 0)
+                                        out[b:b + len(vs)], 0, opacity_act=self.opacity_act)
         return out
 
     def evaluate(self, views=None) -> float:

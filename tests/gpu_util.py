@@ -25,7 +25,7 @@ def dev(a):
 class GpuScene:
     """One parameter block + cameras rendered through libgsta."""
 
-    def __init__(self, params, degree, cams, bg=(0.0, 0.0, 0.0), capacity=1 << 22, ctx=None):
+    def __init__(self, params, degree, cams, bg=(0.0, 0.0, 0.0), capacity=1 << 22, ctx=None, opacity_act=0):
         import torch
         import paper_2504_06716_amd as G
         self.torch = torch
@@ -39,11 +39,12 @@ class GpuScene:
         self.P = dev(params.astype(np.float32))
         self.carr = G.camera_array(cams)
         self.R = params.shape[0]
+        self.opacity_act = opacity_act
 
     def forward(self):
         t = self.torch
         img = t.empty((self.V, 3, self.H, self.W), dtype=t.float32, device="cuda")
-        self.ctx.render_forward(self.P, self.degree, self.carr, self.bg, img, 0)
+        self.ctx.render_forward(self.P, self.degree, self.carr, self.bg, img, 0, opacity_act=self.opacity_act)
         t.cuda.synchronize()
         self.image = img
         return img.cpu().numpy()
@@ -63,7 +64,7 @@ class GpuScene:
         fz = None if frozen is None else dev(frozen.astype(np.uint8))
         em = None if ema is None else dev(ema.astype(np.float32))
         self.ctx.render_backward(self.P, self.degree, self.carr, self.bg, 0, dev(dL.astype(np.float32)),
-                                 fz, grad, g2, em, beta)
+                                 fz, grad, g2, em, beta, opacity_act=self.opacity_act)
         t.cuda.synchronize()
         return grad.cpu().numpy(), g2.cpu().numpy(), (None if em is None else em.cpu().numpy())
 

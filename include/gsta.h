@@ -110,7 +110,11 @@ typedef enum {
                                    each one's tiles contiguous in row-major order) */
 } gsta_state_field;
 
-/* Execution options (gsta_set_option).  They change speed, never results. */
+/* Execution options (gsta_set_option).  They change speed, not what is
+ * computed: images, states and forward decisions are bit-identical for every
+ * setting, and so are gradients except across GSTA_OPT_BWD_WAVES, which
+ * changes the order of the backward's float additions (agreement to
+ * rounding). */
 typedef enum {
     GSTA_OPT_FWD_WAVES = 0,     /* forward compositing: 0 (default): one independent wave per 8x8
                                    quarter of each tile, each writing its quarter's backward
@@ -516,6 +520,50 @@ gsta_status gsta_mlp_sync_bf16(gsta_ctx* ctx, const float* w, uint16_t* w_bf16, 
 gsta_status gsta_mlp_propose(gsta_ctx* ctx, const float* logits, const float* score_xyz, const float* score_rgb,
                              int64_t n, float logit_threshold, float veto_xyz, float veto_rgb, uint8_t* proposal,
                              hipStream_t stream);
+
+/* ---- captured iterations and the autotuner --------------------------------
+ * Several views per launch, whole iterations captured in a HIP graph and an
+ * autotuner over launch options are project extensions (not in the paper)
+ * for the many small launches of one training iteration. */
+
+/* A captured sequence of library calls (a training iteration), replayed
+ * with gsta_graph_launch.  A graph keeps the pointers, sizes, cameras and
+ * options of its capture: it is invalid after gsta_reserve, after any buffer
+ * it uses is freed, or for other cameras.  Host-side scalars (e.g. Adam's
+ * step) must come from device memory (gsta_adam_masked_sched). */
+typedef struct gsta_graph gsta_graph;
+/* Starts capturing `stream` (not the null stream): the library calls issued
+ * on it until gsta_graph_end are recorded, not run.  Profiling must be off;
+ * gsta_check, gsta_reserve and gsta_autotune are refused meanwhile. */
+gsta_status gsta_graph_begin(gsta_ctx* ctx, hipStream_t stream);
+/* Ends the capture and instantiates it into *out (release with
+ * gsta_graph_destroy). */
+gsta_status gsta_graph_end(gsta_ctx* ctx, hipStream_t stream, gsta_graph** out);
+/* Replays a captured graph on `stream` (stream-ordered, no synchronisation). */
+gsta_status gsta_graph_launch(gsta_graph* graph, hipStream_t stream);
+void gsta_graph_destroy(gsta_graph* graph);
+
+/* Result of gsta_autotune (host struct). */
+typedef struct {
+    int32_t fwd_waves;      /* GSTA_OPT_FWD_WAVES chosen */
+    int32_t bwd_waves;      /* GSTA_OPT_BWD_WAVES chosen */
+    int32_t bwd_segment;    /* GSTA_OPT_BWD_SEGMENT chosen (0: one work item per tile) */
+    int32_t candidates;     /* settings timed */
+    float fwd_ms;           /* forward per call with the chosen forward shape */
+    float step_ms;          /* forward + backward per call with the chosen options */
+} gsta_tuning;
+
+/* Times the execution options that do not change results on the caller's
+ * own workload -- forward waves {0, 1, 2, 4} (forward calls), then backward
+ * waves {1, 2, 4} x segment length {64, 128, 256, one item per tile}
+ * (forward + backward calls) -- `repeats` calls each after one untimed call,
+ * and sets the fastest on the context (profiling is suspended meanwhile).
+ * Synchronises.  image [n_views][3][H][W], dL_dimage (same shape; any
+ * values) and grad (shaped like g) are the caller's scratch; their contents
+ * afterwards are unspecified.  out (host) may be NULL. */
+gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams, int32_t n_views,
+                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, int32_t repeats,
+                          gsta_tuning* out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,11 @@ class Columns(ctypes.Structure):
                 ("elem_bytes", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("fwd_waves", ctypes.c_int32), ("bwd_waves", ctypes.c_int32), ("bwd_segment", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("fwd_ms", ctypes.c_float), ("step_ms", ctypes.c_float)]
+
+
 class GstaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"gsta error {STATUS_NAMES.get(status, status)}: {msg}")
@@ -68,7 +73,8 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
-           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss", "gsta_opacity_to_absolute"]
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss", "gsta_opacity_to_absolute",
+           "gsta_graph_begin", "gsta_graph_end", "gsta_graph_launch", "gsta_graph_destroy", "gsta_autotune"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
 L1_NOALLOC_MAX_COUNT = 1 << 30
@@ -104,6 +110,13 @@ def load(path: str = LIB_PATH):
     L.gsta_densify_prune.argtypes = [P, PP, PP, PP, P, P, P, P, ctypes.POINTER(DensifyCfg), PP, PP, PP, P, P, P, P]
     L.gsta_opacity_reset.argtypes = [P, PP, PP, PP, P, f32, P]
     L.gsta_opacity_to_absolute.argtypes = [P, PP, PP, PP, P]
+    L.gsta_graph_begin.argtypes = [P, P]
+    L.gsta_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
+    L.gsta_graph_launch.argtypes = [P, P]
+    L.gsta_graph_destroy.argtypes = [P]
+    L.gsta_graph_destroy.restype = None
+    L.gsta_autotune.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, P, PP, i32,
+                                ctypes.POINTER(Tuning), P]
     L.gsta_traj_push.argtypes = [P, P, i64, P, i32, P]
     L.gsta_mlp_feature_stats.argtypes = [P, P, i64, i32, P, P]
     L.gsta_mlp_features.argtypes = [P, P, i64, i32, P, P, P, P]
@@ -126,7 +139,7 @@ def load(path: str = LIB_PATH):
     L.gsta_adam_masked_sched.argtypes = [P, PP, PP, PP, PP, P, P, P]
     L.gsta_read_profile.argtypes = [P, P, P, P]
     for name in EXPORTS:
-        if name not in ("gsta_destroy", "gsta_last_error"):
+        if name not in ("gsta_destroy", "gsta_last_error", "gsta_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -85,6 +85,29 @@ def _f3(bg):
     return (ctypes.c_float * 3)(*[float(x) for x in bg])
 
 
+class Graph:
+    """A captured sequence of library calls (gsta_graph), replayed with launch()."""
+
+    def __init__(self, L, handle):
+        self.L, self.h = L, handle
+
+    def launch(self, stream=None):
+        st = self.L.gsta_graph_launch(self.h, _stream(stream))
+        if st != _lib.GSTA_OK:
+            raise _lib.GstaError(st, "gsta_graph_launch failed")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gsta_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """Owns a libgsta context (all scratch is allocated here, once)."""
 
@@ -147,6 +170,34 @@ class Context:
             yield self
         finally:
             self.set_option(_lib.OPT_BWD_SEGMENT, saved)
+
+    def capture(self, fn, stream=None) -> Graph:
+        """Capture the library calls fn() issues on `stream` (a created
+        stream, not the null stream; default: the current stream) into a
+        graph.  fn must issue only library calls (no torch work)."""
+        s = _stream(stream)
+        check(self.h, self.L.gsta_graph_begin(self.h, s))
+        try:
+            fn()
+        finally:
+            out = ctypes.c_void_p()
+            st = self.L.gsta_graph_end(self.h, s, ctypes.byref(out))
+        check(self.h, st)
+        return Graph(self.L, out)
+
+    def autotune(self, params, degree, cams, bg, image, dL_dimage, grad, repeats=3, stream=None):
+        """Time the result-neutral launch options on this workload and keep
+        the fastest (gsta_autotune); returns the gsta_tuning fields."""
+        ps, gs = params_struct(params, degree), params_struct(grad, degree)
+        ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
+        shape = (len(ca), 3, ca[0].height, ca[0].width)
+        t = _lib.Tuning()
+        check(self.h, self.L.gsta_autotune(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
+                                            _arr(image, shape, torch.float32, "image"),
+                                            _arr(dL_dimage, shape, torch.float32, "dL_dimage"), ctypes.byref(gs),
+                                            int(repeats), ctypes.byref(t), _stream(stream)))
+        self.segment = int(t.bwd_segment)
+        return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
 
     def set_waves(self, fwd: int | None = None, bwd: int | None = None):
         if fwd is not None:

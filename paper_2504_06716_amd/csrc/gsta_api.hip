@@ -102,6 +102,7 @@ struct gsta_ctx {
     std::string err;
     // profiling
     uint32_t profiling = 0;                   // phase mask
+    bool capturing = false;                   // between gsta_graph_begin and gsta_graph_end
     // profiling counters: [0] fwd pairs, [1] bwd pairs, [2] fwd wave iterations,
     // [3] bwd wave iterations, [4] bwd wave reductions
     unsigned long long* pairs = nullptr;
@@ -399,6 +400,7 @@ gsta_status gsta_create(const gsta_limits* lim, gsta_ctx** out) {
 }
 
 gsta_status gsta_reserve(gsta_ctx* ctx, const gsta_limits* lim) {
+    if (ctx && ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "gsta_reserve synchronises: not while a graph is captured");
     if (!ctx) return GSTA_ERR_INVALID;
     gsta_status st = check_limits(ctx, lim);
     if (st != GSTA_OK) return st;
@@ -466,6 +468,7 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
 
 gsta_status gsta_set_profiling(gsta_ctx* ctx, int32_t phase_mask) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (ctx->capturing && phase_mask) return fail(ctx, GSTA_ERR_INVALID, "no profiling while a graph is captured");
     ctx->profiling = (uint32_t)phase_mask & (((1u << GSTA_N_PHASES) - 1u) | GSTA_PROFILE_COUNTERS);
     return GSTA_OK;
 }
@@ -505,6 +508,7 @@ const char* gsta_last_error(const gsta_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "gsta_check synchronises: not while a graph is captured");
     gsta_status st;
     if ((st = hip_check(ctx, hipStreamSynchronize(stream), "hipStreamSynchronize")) != GSTA_OK) return st;
     uint32_t flags[4] = {0, 0, 0, 0};
@@ -1083,6 +1087,151 @@ gsta_status gsta_l1_loss(gsta_ctx* ctx, const float* image, const float* target,
     PhaseTimer pt(ctx, GSTA_PHASE_LOSS, stream);
     launch_l1(image, target, count, dL_dimage, sums, ctx->loss_part, stream);
     return hip_check(ctx, hipGetLastError(), "l1 launch");
+}
+
+// ---- captured iterations and the autotuner ---------------------------------
+
+struct gsta_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+gsta_status gsta_graph_begin(gsta_ctx* ctx, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (!stream) return fail(ctx, GSTA_ERR_INVALID, "the null stream cannot be captured; use a created stream");
+    if (ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "a capture is already open on this context");
+    if (ctx->profiling) return fail(ctx, GSTA_ERR_INVALID, "switch profiling off before capturing");
+    gsta_status st = hip_check(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal),
+                               "hipStreamBeginCapture");
+    if (st == GSTA_OK) ctx->capturing = true;
+    return st;
+}
+
+gsta_status gsta_graph_end(gsta_ctx* ctx, hipStream_t stream, gsta_graph** out) {
+    if (!ctx || ctx->allocs.empty() || !out) return GSTA_ERR_INVALID;
+    *out = nullptr;
+    if (!ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "no capture is open on this context");
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    gsta_status st = hip_check(ctx, hipStreamEndCapture(stream, &g), "hipStreamEndCapture");
+    if (st != GSTA_OK) return st;
+    hipGraphExec_t e = nullptr;
+    st = hip_check(ctx, hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (st != GSTA_OK) {
+        (void)hipGraphDestroy(g);
+        return st;
+    }
+    gsta_graph* gr = new gsta_graph();
+    gr->graph = g;
+    gr->exec = e;
+    *out = gr;
+    return GSTA_OK;
+}
+
+gsta_status gsta_graph_launch(gsta_graph* graph, hipStream_t stream) {
+    if (!graph || !graph->exec) return GSTA_ERR_INVALID;
+    return hipGraphLaunch(graph->exec, stream) == hipSuccess ? GSTA_OK : GSTA_ERR_HIP;
+}
+
+void gsta_graph_destroy(gsta_graph* graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams, int32_t n_views,
+                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, int32_t repeats,
+                          gsta_tuning* out, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "the autotuner synchronises: not while a graph is captured");
+    if (repeats < 1 || repeats > 1000) return fail(ctx, GSTA_ERR_INVALID, "repeats must be in [1, 1000]");
+    if (!image || !dL_dimage || !grad) return fail(ctx, GSTA_ERR_INVALID, "NULL scratch argument");
+    const int fwd0 = ctx->fwd_waves, bwd0 = ctx->bwd_waves;
+    const uint32_t seg0 = ctx->seg_shift;
+    const uint32_t prof0 = ctx->profiling;
+    ctx->profiling = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    gsta_status st = hip_check(ctx, hipEventCreate(&e0), "hipEventCreate");
+    if (st == GSTA_OK) st = hip_check(ctx, hipEventCreate(&e1), "hipEventCreate");
+    auto restore = [&](gsta_status s) {
+        ctx->fwd_waves = fwd0;
+        ctx->bwd_waves = bwd0;
+        ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(bwd0);
+        ctx->seg_shift = seg0;
+        ctx->profiling = prof0;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return s;
+    };
+    if (st != GSTA_OK) return restore(st);
+    // ms per call of `fn` over `repeats` calls after one untimed call
+    auto timed = [&](auto fn, float* ms) -> gsta_status {
+        gsta_status s = fn();
+        if (s != GSTA_OK) return s;
+        if ((s = hip_check(ctx, hipEventRecord(e0, stream), "hipEventRecord")) != GSTA_OK) return s;
+        for (int r = 0; r < repeats; ++r)
+            if ((s = fn()) != GSTA_OK) return s;
+        if ((s = hip_check(ctx, hipEventRecord(e1, stream), "hipEventRecord")) != GSTA_OK) return s;
+        if ((s = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize")) != GSTA_OK) return s;
+        float t = 0.f;
+        if ((s = hip_check(ctx, hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime")) != GSTA_OK) return s;
+        *ms = t / (float)repeats;
+        return GSTA_OK;
+    };
+    auto forward = [&]() { return gsta_render_forward(ctx, g, cams, n_views, bg, image, 0, stream); };
+    auto step = [&]() {
+        gsta_status s = gsta_render_forward(ctx, g, cams, n_views, bg, image, 0, stream);
+        if (s == GSTA_OK)
+            s = gsta_render_backward(ctx, g, cams, n_views, bg, 0, dL_dimage, nullptr, grad, nullptr, nullptr, 0.9f,
+                                     nullptr, stream);
+        return s;
+    };
+    gsta_tuning best{};
+    int cands = 0;
+    // forward launch shape first (it does not depend on the backward's)
+    float best_f = 3.0e38f;
+    const int fwd_c[4] = {0, 1, 2, 4};
+    for (int f : fwd_c) {
+        ctx->fwd_waves = f;
+        float ms = 0.f;
+        if ((st = timed(forward, &ms)) != GSTA_OK) return restore(st);
+        ++cands;
+        if (ms < best_f) {
+            best_f = ms;
+            best.fwd_waves = f;
+            best.fwd_ms = ms;
+        }
+    }
+    ctx->fwd_waves = best.fwd_waves;
+    // then backward waves x segment length, timed as forward + backward
+    // (the segment length also sets the forward's checkpoints)
+    float best_s = 3.0e38f;
+    const int bwd_c[3] = {1, 2, 4};
+    const uint32_t seg_c[4] = {6, 7, 8, 31};
+    for (int b : bwd_c)
+        for (uint32_t sh : seg_c) {
+            ctx->bwd_waves = b;
+            ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(b);
+            ctx->seg_shift = sh;
+            float ms = 0.f;
+            if ((st = timed(step, &ms)) != GSTA_OK) return restore(st);
+            ++cands;
+            if (ms < best_s) {
+                best_s = ms;
+                best.bwd_waves = b;
+                best.bwd_segment = sh >= 31 ? 0 : (1 << sh);
+                best.step_ms = ms;
+            }
+        }
+    best.candidates = cands;
+    restore(GSTA_OK);
+    ctx->fwd_waves = best.fwd_waves;
+    ctx->bwd_waves = best.bwd_waves;
+    ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(best.bwd_waves);
+    ctx->seg_shift = best.bwd_segment == 0 ? 31u : (uint32_t)__builtin_ctz((unsigned)best.bwd_segment);
+    if (out) *out = best;
+    return GSTA_OK;
 }
 
 }  // extern "C"

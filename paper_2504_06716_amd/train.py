@@ -48,6 +48,8 @@ class TrainConfig:
     device_sched: bool = False           # Adam scalars from a device schedule (implied by graph)
     graph: bool = False                  # capture each view's iteration once in a HIP graph, then replay
     views_per_step: int = 1              # V_b views rendered per library call; the loss averages them
+    batches: list | None = None          # fixed groups of views (then the view order lists group ids); needed
+                                         # for graph capture with several views per step
     densify: DensifySchedule | None = None   # adaptive densification (the number of Gaussians changes)
     max_gaussians: int | None = None     # capacity of the parameter blocks (default: the initial count)
     traj_every: int = 0                  # push the gradient-norm averages to the 8-deep ring every k iterations
@@ -72,6 +74,7 @@ class Trainer:
         self.cams = cams
         self.H, self.W = cams[0].height, cams[0].width
         self.cam1 = [camera_array([c]) for c in cams]
+        self.batch_cams = None if cfg.batches is None else [camera_array([cams[v] for v in b]) for b in cfg.batches]
         self.targets = targets
         self.order = view_order
         self.val_views = list(range(len(cams))) if val_views is None else list(val_views)
@@ -99,9 +102,17 @@ class Trainer:
             self.noise_gen = torch.Generator(device="cuda")
             self.noise_gen.manual_seed(ds.seed)
         self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
+        if cfg.batches is not None:
+            sizes = {len(b) for b in cfg.batches}
+            if len(sizes) != 1 or min(sizes) < 1 or min(sizes) > self.ctx.limits.max_views:
+                raise ValueError("batches must be non-empty groups of equal size within the context's views")
+            cfg.views_per_step = sizes.pop()
         vb = cfg.views_per_step
-        if vb > 1 and cfg.graph:
-            raise ValueError("graph capture is per view; use views_per_step = 1 with graph=True")
+        if vb > 1 and cfg.graph and cfg.batches is None:
+            raise ValueError("graph capture with several views per step needs fixed batches (cfg.batches)")
+        # each fixed batch's targets, contiguous, gathered once
+        self.batch_targets = None if cfg.batches is None else [
+            torch.index_select(targets, 0, torch.as_tensor(b, device="cuda")).contiguous() for b in cfg.batches]
         self.image = torch.empty((vb, 3, self.H, self.W), device="cuda")
         self.dL = torch.empty_like(self.image)
         self.tgt_batch = torch.empty_like(self.image) if vb > 1 else None
@@ -121,7 +132,7 @@ class Trainer:
             l = cfg.lrs
             self.sched = adam_sched_tensor(1, cfg.beta1, cfg.beta2, cfg.adam_eps, l.rows(0, degree),
                                            l.extent * l.pos_init, l.extent * l.pos_final, l.decay_iters)
-        self.graphs: dict[int, torch.cuda.CUDAGraph] = {}
+        self.graphs: dict = {}                # view (or batch id) -> library graph (core.Graph)
         self.traj = None
         if cfg.traj_every:
             if cfg.densify is not None:
@@ -186,7 +197,7 @@ class Trainer:
             self.cur = 1 - self.cur
             self._bind(n_out)
             self.dstats.zero_()
-            self.graphs.clear()                       # pointers and sizes changed: capture again
+            self._drop_graphs()                       # pointers and sizes changed: capture again
             self.n_history.append((k, n_out))
             # keep the tile-instance capacity ahead of the growth
             need = int(max_inst * max(1.0, n_out / max(n_in, 1)) * 1.3) + 1024
@@ -240,6 +251,12 @@ class Trainer:
             raise _lib.GstaError(st, f"device flag raised by the iterations up to the {where} "
                                      f"(instances needed: {need}, reserved: {self.ctx.limits.instance_capacity})")
 
+    def _drop_graphs(self):
+        """Forget the captured graphs (after the stream has finished them)."""
+        if self.graphs:
+            torch.cuda.current_stream().synchronize()
+            self.graphs.clear()
+
     def _partition(self):
         """Permute every per-Gaussian array in place so that the active
         Gaussians form the prefix [0, n_active): the backward's per-Gaussian
@@ -277,7 +294,11 @@ class Trainer:
         cfg = self.cfg
         frz = self.frozen if cfg.freeze else None
         ema = self.ema if (cfg.freeze or cfg.track_ema) else None
-        if isinstance(view, int):
+        if isinstance(view, tuple):             # a fixed batch: ("batch", id)
+            b = view[1]
+            cam = self.batch_cams[b]
+            tgt = self.batch_targets[b]
+        elif isinstance(view, int):
             cam = self.cam1[view]
             tgt = self.targets[view:view + 1]
         else:
@@ -312,12 +333,14 @@ class Trainer:
             # the finetune starts: opacity = |x| from now on, x = the current opacity
             self.ctx.opacity_to_absolute(self.P, self.M, self.Vm, self.degree)
             self.opacity_act = 1
-            self.graphs.clear()                      # the captured calls carry the old activation
+            self._drop_graphs()                      # the captured calls carry the old activation
         if self.traj is not None:
             self.traj.maybe_push(k, self.ema)
         self._freeze_step(k)
         vb = cfg.views_per_step
-        if vb == 1:
+        if cfg.batches is not None:
+            view = ("batch", int(self.order[k % len(self.order)]))
+        elif vb == 1:
             view = int(self.order[k % len(self.order)])
         else:
             view = [int(self.order[(k * vb + i) % len(self.order)]) for i in range(vb)]
@@ -325,14 +348,14 @@ class Trainer:
         if cfg.graph:
             g = self.graphs.get(view)
             if g is None:
-                g = torch.cuda.CUDAGraph()
+                # captured by the library on a side stream (the null stream cannot be captured)
                 side = torch.cuda.Stream()
                 side.wait_stream(torch.cuda.current_stream())
-                with torch.cuda.graph(g, stream=side):
-                    self._body(view, k)
+                with torch.cuda.stream(side):
+                    g = self.ctx.capture(lambda: self._body(view, k))
                 torch.cuda.current_stream().wait_stream(side)
                 self.graphs[view] = g
-            g.replay()
+            g.launch()
         else:
             self._body(view, k)
         self.k += 1

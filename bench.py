@@ -265,6 +265,55 @@ def cpu_baseline(w, max_seconds=20.0):
                            "sample": f"median of {len(t_one)} iterations after 1 warm-up, same workload"}}
 
 
+def c3_throughput(torch, steps, vb=4):
+    """Batched views at the c3 size: 1M Gaussians (SH degree 3), 100 cameras
+    at 1080x1600, 4 views per step in fixed batches, each batch's iteration
+    captured once in a HIP graph; iterations/s and views/s over `steps`
+    timed steps after one pass over the 25 batches (which captures them),
+    with the launch options chosen by gsta_autotune on the first batch."""
+    import synthetic as S
+    from paper_2504_06716_amd import _lib
+    from paper_2504_06716_amd.autotune import tune_options
+    from paper_2504_06716_amd.core import Context
+    from paper_2504_06716_amd.schedule import LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
+    c = S.CONFIGS["c3"]
+    n, D, H, W = c["n"], c["degree"], c["height"], c["width"]
+    p0 = S.make_scene(n, D)
+    cams = S.config_cameras("c3")
+    log("c3: sizing the instance capacity, rendering targets")
+    from paper_2504_06716_amd.train import required_capacity
+    ctx = Context(n, vb, H, W, instance_capacity=(1 << 28), n_slots=1)
+    pt = S.perturb_scene(p0, D)
+    need = max(required_capacity(ctx, p0, D, cams), required_capacity(ctx, pt, D, cams))
+    ctx.reserve(instance_capacity=min(int(need * 1.5) + 4096, (1 << 32) - 1))
+    targets = render_targets(ctx, pt, D, cams)
+    st, need = ctx.check()
+    if st != 0:
+        raise RuntimeError(f"c3 targets: status {st}, instances {need}")
+    perm = list(S.view_order(len(cams), len(cams), seed=3))
+    batches = [perm[i:i + vb] for i in range(0, len(cams), vb)]
+    tuned = tune_options(p0, D, [cams[v] for v in batches[0]], ctx, views=vb, repeats=2)
+    log(f"c3: launch options {tuned}")
+    order = S.view_order(len(batches), len(batches) + steps, seed=5)
+    cfg = TrainConfig(iters=len(order), freeze=False, lrs=LearningRates(decay_iters=len(order)), graph=True,
+                      batches=batches)
+    tr = Trainer(p0, D, cams, targets, cfg, order, ctx=ctx)
+    tr.run(len(batches))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st, need = ctx.check()
+    if st != 0:
+        raise RuntimeError(f"c3 training: status {st}, instances {need}")
+    return {"workload": "c3: 1M Gaussians SH3, 100 cams 1080x1600, 4 views per graph-captured step "
+                        "(25 fixed batches), L1 loss, Adam, no freezing",
+            "steps": steps, "iters_per_s": round(steps / dt, 2), "views_per_s": round(steps * vb / dt, 2),
+            "ms_per_step": round(1e3 * dt / steps, 3), "launch_options": tuned, "max_instances_per_call": need}
+
+
 def ablation(torch, w, seeds=(2, 12, 22)):
     """Section 4.3 / Table 3 on this workload: whole 2000-iteration schedules
     with the gradient rule (eqs. 4-6), "mingrad" and "random" at the paper's
@@ -324,6 +373,8 @@ def main():
     ap.add_argument("--details", default=None, help="write the per-phase breakdown JSON here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB on the device (a plain copy of known size for counter scaling)")
+    ap.add_argument("--c3", action="store_true",
+                    help="time the c3 workload's graph-captured 4-view steps (1M Gaussians, 1080x1600) and exit")
     ap.add_argument("--ablation", action="store_true",
                     help="compare the freezing rules of the paper's ablation on whole schedules and exit")
     ap.add_argument("--calibrate", type=float, default=None, metavar="Q",
@@ -344,6 +395,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.c3:
+        print(json.dumps(c3_throughput(torch, args.steps if args.steps != 2000 else 20)), flush=True)
+        return
     log("setting up the c2 workload")
     w = c2_setup(torch)
     if args.calibrate is not None:

@@ -407,6 +407,11 @@ typedef struct {
     float split_log_scale;         /* ln(0.01 * scene extent) */
     float prune_logit;             /* ln(0.005 / 0.995) */
     float child_log_scale_shift;   /* ln(1.6): children's scales are the parent's / 1.6 */
+    uint64_t noise_seed;           /* with noise NULL: the children's normals come from Philox4x64-10 */
+    int64_t noise_draw;            /* (counter (column, noise_draw, child, 0), key (noise_seed, 1)), Box-Muller
+                                      on its four words u = (w >> 11 + 0.5) 2^-53: r = sqrt(-2 ln u0),
+                                      n = (r cos 2 pi u1, r sin 2 pi u1, sqrt(-2 ln u2) cos 2 pi u3), in double;
+                                      e.g. noise_draw = the iteration */
 } gsta_densify_cfg;
 
 /* One densify-and-prune step: a stream compaction of every per-Gaussian
@@ -422,7 +427,8 @@ typedef struct {
  *   g, m, v   [R][ld] inputs (shared n and sh_degree).
  *   ema [4][n] or NULL (then survivors get FLT_MAX); frozen [n] or NULL.
  *   dstats [4][n] as accumulated by gsta_render_backward.
- *   noise [6][n] float32 standard-normal draws (rows 3c..3c+2 for child c).
+ *   noise [6][n] float32 standard-normal draws (rows 3c..3c+2 for child c),
+ *         or NULL to draw them in the kernel (cfg->noise_seed, noise_draw).
  *   g_out, m_out, v_out: the n field is the output capacity (columns).
  *   ema_out [4][n_out] contiguous (room for 4 * capacity floats) or NULL;
  *   frozen_out [n_out] (room for capacity) or NULL.

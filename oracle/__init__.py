@@ -708,6 +708,24 @@ def densify_decisions(stats, params, frozen, grad_threshold, rgb_threshold, use_
     return sel & ~big, sel & big, live
 
 
+def densify_noise(n, seed, draw):
+    """Standard normals for the split children (noise [6][n], rows 3c..3c+2
+    for child c of column i), from Philox4x64-10 with counter (i, draw, c, 0)
+    and key (seed, 1): its four words become uniforms u = (floor(w / 2^11) +
+    0.5) / 2^53 in (0, 1), and the Box-Muller transform gives r = sqrt(-2 ln
+    u0), (r cos 2 pi u1, r sin 2 pi u1) and sqrt(-2 ln u2) cos 2 pi u3."""
+    out = np.zeros((6, n))
+    for i in range(n):
+        for c in range(2):
+            w = philox4x64_10((i, draw, c, 0), (seed, 1))
+            u = [((x >> 11) + 0.5) / 2.0 ** 53 for x in w]
+            r0 = np.sqrt(-2.0 * np.log(u[0]))
+            r1 = np.sqrt(-2.0 * np.log(u[2]))
+            out[3 * c:3 * c + 3, i] = [r0 * np.cos(2 * np.pi * u[1]), r0 * np.sin(2 * np.pi * u[1]),
+                                       r1 * np.cos(2 * np.pi * u[3])]
+    return out
+
+
 def densify_prune(params, m, v, ema, frozen, stats, noise, grad_threshold, rgb_threshold, use_rgb,
                   split_log_scale, prune_logit, child_log_scale_shift):
     """One densify-and-prune step.  Output columns, in this order: the

@@ -47,7 +47,8 @@ class AdamSched(ctypes.Structure):
 class DensifyCfg(ctypes.Structure):
     _fields_ = [("grad_threshold", ctypes.c_float), ("rgb_threshold", ctypes.c_float),
                 ("use_rgb", ctypes.c_int32), ("split_log_scale", ctypes.c_float),
-                ("prune_logit", ctypes.c_float), ("child_log_scale_shift", ctypes.c_float)]
+                ("prune_logit", ctypes.c_float), ("child_log_scale_shift", ctypes.c_float),
+                ("noise_seed", ctypes.c_uint64), ("noise_draw", ctypes.c_int64)]
 
 
 class Columns(ctypes.Structure):

@@ -915,7 +915,7 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
         if (n > 0 && !out[k]->block) return fail(ctx, GSTA_ERR_INVALID, "%s.block is NULL", names[3 + k]);
     }
     if (!cfg || !counts) return fail(ctx, GSTA_ERR_INVALID, "cfg or counts is NULL");
-    if (n > 0 && (!dstats || !noise)) return fail(ctx, GSTA_ERR_INVALID, "dstats or noise is NULL");
+    if (n > 0 && !dstats) return fail(ctx, GSTA_ERR_INVALID, "dstats is NULL");
     if (!std::isfinite(cfg->split_log_scale) || !std::isfinite(cfg->prune_logit) ||
         !std::isfinite(cfg->child_log_scale_shift) || std::isnan(cfg->grad_threshold) ||
         std::isnan(cfg->rgb_threshold))
@@ -936,6 +936,7 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
     io.P = g->block; io.M = m->block; io.V = v->block;
     io.ld = g->ld; io.mld = m->ld; io.vld = v->ld; io.n = n; io.degree = D;
     io.ema = ema; io.frozen = frozen; io.stats = dstats; io.noise = noise;
+    io.seed = cfg->noise_seed; io.draw = cfg->noise_draw;
     io.Po = g_out->block; io.Mo = m_out->block; io.Vo = v_out->block;
     io.old_ = g_out->ld; io.mold = m_out->ld; io.vold = v_out->ld; io.cap = cap;
     io.ema_o = ema_out; io.frozen_o = frozen_out;

@@ -278,6 +278,30 @@ int64_t ssim_blocks(int nv, int H, int W);
 void launch_dssim(const float* img, const float* tgt, int nv, int H, int W, float lambda, float* dL, double* ssim_sum,
                   float* gmap, double* part, hipStream_t s);
 
+// Philox4x64-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2,
+// 3", SC 2011): counter c (4 words) -> 4 random words, key (k0, k1).  Ten
+// rounds, each multiplying words 0 and 2 by two constants into 128-bit
+// products and mixing their high halves with words 1 and 3 and the key; the
+// key advances by two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
 // State of the exact radix select of the "mingrad" freezing rule.
 struct SelState {
     uint32_t hist[256];          // digit histogram of the current pass
@@ -306,7 +330,9 @@ struct DensIO {
     const float* ema;                // [4][n] or null
     const uint8_t* frozen;           // [n] or null
     const float* stats;              // [4][n]
-    const float* noise;              // [6][n]
+    const float* noise;              // [6][n], or null: drawn in the kernel from Philox (seed, draw)
+    uint64_t seed;
+    int64_t draw;
     float *Po, *Mo, *Vo;             // [R][old_] ...
     int64_t old_, mold, vold, cap;   // cap: output columns available
     float* ema_o;                    // [4][n_out] or null

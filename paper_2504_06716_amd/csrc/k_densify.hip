@@ -133,7 +133,8 @@ __global__ __launch_bounds__(kDB) void k_dens_scatter(
     const float* __restrict__ P, int64_t ld, const float* __restrict__ M, int64_t mld, const float* __restrict__ V,
     int64_t vld, const float* __restrict__ ema, const uint8_t* __restrict__ frozen, const float* __restrict__ noise,
     int64_t n, const uint8_t* __restrict__ code, const uint32_t* __restrict__ boff, int64_t nb,
-    const uint32_t* __restrict__ tot, float child_shift, float* __restrict__ Po, int64_t old_, float* __restrict__ Mo,
+    const uint32_t* __restrict__ tot, float child_shift, uint64_t seed, int64_t draw, float* __restrict__ Po,
+    int64_t old_, float* __restrict__ Mo,
     int64_t mold, float* __restrict__ Vo, int64_t vold, float* __restrict__ ema_o, uint8_t* __restrict__ frozen_o) {
     constexpr int R = 11 + 3 * (D + 1) * (D + 1);
     __shared__ uint32_t s_w[kDB / 64][3];
@@ -187,8 +188,23 @@ __global__ __launch_bounds__(kDB) void k_dens_scatter(
         for (int ch = 0; ch < 2; ++ch) {
             const int64_t o = (int64_t)K + C + (int64_t)ch * S + s;
             float e[3];
+            if (noise) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) e[a] = sc[a] * noise[(3 * ch + a) * n + i];
+                for (int a = 0; a < 3; ++a) e[a] = sc[a] * noise[(3 * ch + a) * n + i];
+            } else {
+                // child ch of Gaussian i: three standard normals by Box-Muller from the
+                // four words of Philox4x64-10(counter (i, draw, ch, 0), key (seed, 1))
+                uint64_t w4[4] = {(uint64_t)i, (uint64_t)draw, (uint64_t)ch, 0ull};
+                philox4x64_10(w4, seed, 1ull);
+                double u[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) u[a] = ((double)(w4[a] >> 11) + 0.5) * 0x1.0p-53;
+                const double two_pi = 6.283185307179586476925286766559;
+                const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+                const double nz[3] = {r0 * cos(two_pi * u[1]), r0 * sin(two_pi * u[1]), r1 * cos(two_pi * u[3])};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) e[a] = sc[a] * (float)nz[a];
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 Po[a * old_ + o] = P[a * ld + i] + (Rm[3 * a] * e[0] + Rm[3 * a + 1] * e[1] + Rm[3 * a + 2] * e[2]);
@@ -343,7 +359,8 @@ void launch_densify(const DensIO& io, const DensCfg& cfg, uint8_t* code, uint32_
     if (nb == 0) return;
 #define GSTA_DENS_ARGS                                                                                          \
     io.P, io.ld, io.M, io.mld, io.V, io.vld, io.ema, io.frozen, io.noise, io.n, code, boff, nb, tot,            \
-        cfg.child_log_scale_shift, io.Po, io.old_, io.Mo, io.mold, io.Vo, io.vold, io.ema_o, io.frozen_o
+        cfg.child_log_scale_shift, io.seed, io.draw, io.Po, io.old_, io.Mo, io.mold, io.Vo, io.vold, io.ema_o,  \
+        io.frozen_o
     switch (io.degree) {
         case 0: k_dens_scatter<0><<<(unsigned)nb, kDB, 0, s>>>(GSTA_DENS_ARGS); break;
         case 1: k_dens_scatter<1><<<(unsigned)nb, kDB, 0, s>>>(GSTA_DENS_ARGS); break;

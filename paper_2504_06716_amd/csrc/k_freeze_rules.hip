@@ -26,25 +26,6 @@ constexpr float kFltMax = 3.402823466e+38f;
 
 __global__ void k_zero_count(unsigned long long* p) { *p = 0ull; }
 
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
 // freeze map update with condition `cond` (mode 0: OR, 1: reset, 2: replace)
 // and the frozen count by ballot
 __device__ __forceinline__ void apply_and_count(bool in, int64_t i, bool cond, int mode, uint8_t* frozen,

@@ -99,8 +99,6 @@ class Trainer:
             ds = cfg.densify
             self.extent = scene_extent([c.campos for c in cams])
             self.dens_rng = np.random.Generator(np.random.Philox(ds.seed))
-            self.noise_gen = torch.Generator(device="cuda")
-            self.noise_gen.manual_seed(ds.seed)
         self.n_frozen = torch.zeros(1, dtype=torch.int64, device="cuda")
         if cfg.batches is not None:
             sizes = {len(b) for b in cfg.batches}
@@ -180,9 +178,10 @@ class Trainer:
         if ds.densify_now(k, self.stop_iter):
             ex, er = ds.thresholds(k, ds.end(self.stop_iter))
             use_rgb = bool(self.dens_rng.random() < ds.rgb_prob)
+            # the split children's normals are drawn in the kernel from Philox (seed, iteration, column)
             cfg = _lib.DensifyCfg(ex, er, int(use_rgb), ds.split_log_scale(self.extent), ds.prune_logit(),
-                                  float(np.log(ds.split_div)))
-            noise = torch.randn((6, self.n), device="cuda", generator=self.noise_gen)
+                                  float(np.log(ds.split_div)), ds.seed, k)
+            noise = None
             out = self.sets[1 - self.cur]
             frz = self.frozen if self.cfg.freeze else None
             ema = self.ema if (self.cfg.freeze or self.cfg.track_ema) else None

@@ -82,3 +82,21 @@ def test_apply_freeze_modes():
     assert list(O.apply_freeze(old, cond, 0)) == [1, 0, 1, 1]
     assert list(O.apply_freeze(old, cond, 1)) == [0, 0, 0, 0]
     assert list(O.apply_freeze(old, cond, 2)) == [0, 0, 1, 1]
+
+
+def test_densify_noise_box_muller_hand_values_and_moments():
+    """The split children's normals (Section 4.1 densification with the 3DGS
+    split rule): the Box-Muller transform of Philox words, checked by hand
+    for one column and by its moments over many."""
+    w = O.philox4x64_10((3, 7, 1, 0), (11, 1))
+    u = [((x >> 11) + 0.5) / 2.0 ** 53 for x in w]
+    nz = O.densify_noise(4, 11, 7)[3:6, 3]
+    r = math.sqrt(-2 * math.log(u[0]))
+    assert nz[0] == pytest.approx(r * math.cos(2 * math.pi * u[1]), rel=1e-15)
+    assert nz[1] == pytest.approx(r * math.sin(2 * math.pi * u[1]), rel=1e-15)
+    assert nz[2] == pytest.approx(math.sqrt(-2 * math.log(u[2])) * math.cos(2 * math.pi * u[3]), rel=1e-15)
+    z = O.densify_noise(4000, 5, 100)
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / z.size)
+    assert abs(np.corrcoef(z[0], z[1])[0, 1]) < 5 / math.sqrt(4000)
+    assert not np.array_equal(z, O.densify_noise(4000, 5, 101))

@@ -42,6 +42,7 @@ def _cfg(thr=2e-4, rgb=1e-6, use_rgb=False):
 
 
 def _run(ctx, degree, p, M, V, ema, frozen, st, noise, cfg, cap, pad=0):
+    """noise None: the kernel draws the children's normals (cfg.noise_seed, noise_draw)."""
     import torch
     R, n = p.shape
     ld = cap + pad
@@ -51,7 +52,7 @@ def _run(ctx, degree, p, M, V, ema, frozen, st, noise, cfg, cap, pad=0):
     counts = torch.zeros(4, dtype=torch.int64, device="cuda")
     ins = [dev(x)[:, :n] if x.ndim == 2 else dev(x) for x in (p, M, V)]
     ctx.densify_prune(ins[0], ins[1], ins[2], degree, None if ema is None else dev(ema),
-                      None if frozen is None else dev(frozen), dev(st), dev(noise), cfg,
+                      None if frozen is None else dev(frozen), dev(st), None if noise is None else dev(noise), cfg,
                       outs[0], outs[1], outs[2], ema_o, fz_o, counts)
     torch.cuda.synchronize()
     c = tuple(int(x) for x in counts.cpu())
@@ -92,6 +93,35 @@ def test_densify_prune_matches_oracle(n, degree, use_rgb, with_state):
     np.testing.assert_allclose(ch[3:6], oc_[3:6], rtol=1e-6, atol=1e-6)
     # untouched tail of the outputs
     assert (gP[:, n_out:] == -7.0).all() and (gF[n_out:] == 9).all()
+
+
+@pytest.mark.parametrize("draw", [0, 1234])
+def test_densify_noise_drawn_in_kernel_matches_oracle(draw):
+    """With noise NULL the split children's normals come from
+    Philox4x64-10 (seed, draw, column) + Box-Muller in the kernel: children
+    equal the oracle's, given the oracle's draws, to float32 rounding."""
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd._lib import DensifyCfg
+    n = 1500
+    p, M, V, ema, frozen, st, _ = _case(n, 3, seed=7)
+    ctx = G.Context(3 * n + 64, 1, 16, 16, 16)
+    cfg = DensifyCfg(2e-4, 1e-6, 0, SPLIT_LS, PRUNE_LG, SHIFT, 2 ** 40 + 9, draw)
+    cap = 3 * n + 5
+    counts, (gP, _, _), _, _ = _run(ctx, 3, p, M, V, ema, frozen, st, None, cfg, cap)
+    noise = O.densify_noise(n, 2 ** 40 + 9, draw)
+    oP, _, _, _, _, oc = O.densify_prune(p, M, V, ema, frozen, st, noise, 2e-4, 1e-6, False, SPLIT_LS, PRUNE_LG,
+                                         SHIFT)
+    assert counts == oc and oc[3] > 20
+    n_out, K, C, _ = oc
+    ch, oc_ = gP[:, K + C:n_out].astype(np.float64), oP[:, K + C:]
+    np.testing.assert_array_equal(gP[:, :K + C], oP[:, :K + C].astype(np.float32))
+    assert np.all(np.abs(ch[0:3] - oc_[0:3]) <= 1e-6 * (np.abs(oc_[0:3]) + 1.0))
+    np.testing.assert_array_equal(ch[6:], oc_[6:])
+    # the children moved away from their parents (non-trivial draws)
+    _, split, live = O.densify_decisions(st, p, frozen, 2e-4, 1e-6, False, SPLIT_LS, PRUNE_LG)
+    parents = p[0:3, np.flatnonzero(split & live)].astype(np.float64)
+    S_ = parents.shape[1]
+    assert np.abs(ch[0:3, :S_] - parents).max() > 1e-4 and np.abs(ch[0:3, S_:2 * S_] - parents).max() > 1e-4
 
 
 def test_densify_capacity_overflow_writes_nothing_and_is_reported():

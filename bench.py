@@ -314,6 +314,103 @@ def c3_throughput(torch, steps, vb=4):
             "ms_per_step": round(1e3 * dt / steps, 3), "launch_options": tuned, "max_instances_per_call": need}
 
 
+class FalseFreezeAudit:
+    """Counts the proposer's false freezes (a measurement, not part of
+    training): a Gaussian frozen by an accepted proposal alone (the rule's
+    own condition false at that update) is a false freeze when, at the first
+    update after the next reset (its averages have been updated again during
+    the wait), either average is at or above the rule's thresholds."""
+
+    def __init__(self, torch, sched):
+        self.torch, self.sched = torch, sched
+        self.tracked = None
+        self.pending_check = False
+        self.accepted = self.false = self.checked = 0
+        self.last_reset = None
+
+    def __call__(self, tr, k, ex, er, prop, before):
+        t = self.torch
+        sx, sr = tr.ema[0], tr.ema[1]
+        rule = (sx < ex) & (sr < er)
+        if before:
+            if self.tracked is not None and self.pending_check:
+                bad = self.tracked & ((sx >= ex) | (sr >= er))
+                self.false += int(bad.sum())
+                self.checked += int(self.tracked.sum())
+                self.tracked = None
+                self.pending_check = False
+            self._frozen_before = tr.frozen.clone()
+            return
+        if prop is None:
+            return
+        only = (prop != 0) & ~rule & (self._frozen_before == 0)
+        self.accepted += int(only.sum())
+        self.tracked = only if self.tracked is None else (self.tracked | only)
+
+    def on_reset(self):
+        if self.tracked is not None:
+            self.pending_check = True
+
+
+def proposer_gain(torch, w, epochs=400):
+    """The learned freeze proposer on c2: a rule-only run logs the trajectory
+    ring and the rule's future decisions; the MLP is trained on them (fit
+    time at the workload's sample count); then whole schedules with the rule
+    alone and with the rule + proposer (same view order, no partition) give
+    the frozen count at each update, the rate, the PSNR and the proposer's
+    false freezes."""
+    import dataclasses
+    from paper_2504_06716_amd.proposer import Proposer, ProposerDataset
+    from paper_2504_06716_amd.schedule import RESET
+    from paper_2504_06716_amd.train import Trainer
+    base = dataclasses.replace(w["cfg"](True), partition=False, traj_every=10)
+    ds = ProposerDataset(w["ctx"], w["n"])
+    tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], dataclasses.replace(base, dataset=ds), w["order"],
+                 ctx=w["ctx"])
+    tr.run()
+    prop = Proposer(w["ctx"])
+    x, y = ds.build(prop)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = prop.fit(x, y, epochs=epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    log(f"proposer: {x.shape[0]} samples, {y.float().mean().item():.3f} positive, fit {fit_s:.2f} s, bce {hist}")
+    out = {"samples": int(x.shape[0]), "positive_fraction": round(float(y.float().mean()), 4), "epochs": epochs,
+           "fit_seconds": round(fit_s, 3), "bce_first_last": [hist[0][1], hist[-1][1]]}
+    runs = {}
+    # timed runs without any measurement hook, then an untimed audited run of the proposer
+    for label in ("rule", "rule_plus_proposer", "audit"):
+        audit = FalseFreezeAudit(torch, base.schedule) if label == "audit" else None
+        cfg = dataclasses.replace(base, proposer=prop if label != "rule" else None, update_hook=audit)
+        t = Trainer(w["p0"], w["D"], w["cams"], w["targets"], cfg, w["order"], ctx=w["ctx"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while not t.finished:
+            if audit is not None and base.schedule.action(t.k, t.stop_iter) == RESET:
+                audit.on_reset()
+            t.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h = t.freeze_history()
+        runs[label] = {"iters_per_s": round(t.k / dt, 1), "psnr_db": round(t.evaluate(), 4),
+                       "frozen_at_updates": [(k, c) for k, a, c in h if a == 1],
+                       "frozen_mean": round(frozen_in_window(h, 0, t.k, w["n"]), 4)}
+        if audit is not None:
+            runs["rule_plus_proposer"]["proposal_only_freezes"] = audit.accepted
+            runs["rule_plus_proposer"]["false_freezes"] = audit.false
+            runs["rule_plus_proposer"]["false_freeze_checked"] = audit.checked
+            del runs[label]
+        else:
+            log(f"proposer {label}: {runs[label]['iters_per_s']} it/s, PSNR {runs[label]['psnr_db']}")
+    out["runs"] = runs
+    out["delta_psnr_db"] = round(runs["rule_plus_proposer"]["psnr_db"] - runs["rule"]["psnr_db"], 4)
+    st, _ = w["ctx"].check()
+    if st != 0:
+        raise RuntimeError(f"device flag raised during the proposer runs (status {st})")
+    return out
+
+
 def ablation(torch, w, seeds=(2, 12, 22)):
     """Section 4.3 / Table 3 on this workload: whole 2000-iteration schedules
     with the gradient rule (eqs. 4-6), "mingrad" and "random" at the paper's
@@ -375,6 +472,8 @@ def main():
                     help="first copy 256 MiB on the device (a plain copy of known size for counter scaling)")
     ap.add_argument("--c3", action="store_true",
                     help="time the c3 workload's graph-captured 4-view steps (1M Gaussians, 1080x1600) and exit")
+    ap.add_argument("--proposer", action="store_true",
+                    help="train the learned freeze proposer on a logged c2 run and compare it with the rule alone")
     ap.add_argument("--ablation", action="store_true",
                     help="compare the freezing rules of the paper's ablation on whole schedules and exit")
     ap.add_argument("--calibrate", type=float, default=None, metavar="Q",
@@ -405,6 +504,9 @@ def main():
         return
     if args.ablation:
         print(json.dumps(ablation(torch, w)), flush=True)
+        return
+    if args.proposer:
+        print(json.dumps(proposer_gain(torch, w)), flush=True)
         return
     steps = args.steps
     k0 = window_start(steps, w["iters"])

@@ -12,8 +12,9 @@
 //                   first hidden layer re-rounded to bf16 through LDS, the
 //                   output unit as a float32 dot product
 //   K11e bce:       dL/dz = (sigmoid(z) - y) / n and the loss (fixed order)
-//   K11f backward:  weight gradients, per-block partials summed in block
-//                   order (deterministic)
+//   K11f backward:  weight gradients on bf16 matrix cores (split-bf16 for
+//                   the derivative operands), per-block partials summed in
+//                   block order (deterministic)
 //   K11g adam:      float32 master weights, bf16 copies of W1 and W2
 //   K11h propose:   z > threshold and not vetoed
 #include "gsta_internal.h"
@@ -220,88 +221,158 @@ __global__ __launch_bounds__(64) void k_mlp_bce_final(const double2* __restrict_
     loss[0] = t / (double)n;
 }
 
-// Weight gradients of sum_i dz_i z_i.  Each block takes batches of 16
-// samples (batch b = block + k * grid) and accumulates in a fixed order:
-// thread t owns W2[t/4][16 (t%4) ..], W1[t/4][8 (t%4) ..] and, for t%4 = 0,
-// b1, b2, w3 of unit t/4; thread 0 owns b3.
+// Weight gradients of sum_i dz_i z_i on the matrix cores.  Each block takes
+// batches of 32 samples (batch b = block + k * grid) and accumulates in a
+// fixed order.  With d2 = dz w3 [h2 > 0] and d1 = (d2 W2) [h1 > 0]:
+//   gW2 = d2^T h1   [64 x 64],  gW1 = d1^T x   [64 x 32],  d1 = d2 W2  [32 x 64],
+// each a 16x16x32 bf16 MFMA chain with float32 accumulation.  x, h1 and W2
+// are bf16 values already (the forward's operands); d2 and d1 are not, so
+// each is split into hi = bf16(d) and lo = bf16(d - hi) and both halves are
+// multiplied (error ~2^-17 of d instead of the 2^-9 of a single bf16).  The
+// bias and w3 gradients are float32 sums on the vector units.
+// LDS is [row][32 samples] transposed for the MFMA operands that run over
+// samples.  Lane l of an MFMA reads A row l & 15, k 8 (l >> 4) .. +7 and B
+// column l & 15, k 8 (l >> 4) .. +7, and holds C rows 4 (l >> 4) .. +3 of
+// column l & 15.
 __global__ __launch_bounds__(256) void k_mlp_backward(const uint16_t* __restrict__ wb, const float* __restrict__ wf,
                                                       const uint16_t* __restrict__ x, const uint16_t* __restrict__ h1,
                                                       const float* __restrict__ h2, const float* __restrict__ dz,
                                                       int64_t n, float* __restrict__ part) {
-    __shared__ float s_x[16][32], s_h1[16][64], s_d2[16][64], s_d1[16][64], s_dz[16];
-    __shared__ float s_w2[64][65];
-    __shared__ float s_w3[64];
-    const int tid = threadIdx.x;
-    for (int k = tid; k < 4096; k += 256) s_w2[k >> 6][k & 63] = from_bf16(wb[2048 + k]);
+    __shared__ __attribute__((aligned(16))) uint16_t s_w2t[64][64];     // W2^T: [input v][output u]
+    __shared__ __attribute__((aligned(16))) uint16_t s_xt[32][32];      // x^T: [feature][sample]
+    __shared__ __attribute__((aligned(16))) uint16_t s_h1t[64][32];     // h1^T: [unit][sample]
+    __shared__ __attribute__((aligned(16))) uint16_t s_d2[2][32][64];   // d2 hi / lo: [sample][unit]
+    __shared__ __attribute__((aligned(16))) uint16_t s_d2t[2][64][32];  // d2^T hi / lo: [unit][sample]
+    __shared__ __attribute__((aligned(16))) uint16_t s_d1t[2][64][32];  // d1^T hi / lo: [unit][sample]
+    __shared__ float s_dz[32], s_w3[64];
+    __shared__ float s_bias[3][64][4];                                   // b2, w3, b1 partials per quarter
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    for (int k = tid; k < 4096; k += 256) s_w2t[k & 63][k >> 6] = wb[2048 + k];   // W2[u][v] -> [v][u]
     if (tid < 64) s_w3[tid] = wf[kMlpW3 + tid];
-    const int u = tid >> 2, q = tid & 3;
-    float gW2[16], gW1[8];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) gW2[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) gW1[k] = 0.f;
+    // vector-unit ownership: unit u = tid / 4, samples 8 (tid % 4) .. +7 of each batch
+    const int vu = tid >> 2, vq = tid & 3;
     float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f;
-    const int64_t nbat = (n + 15) / 16;
+    f32x4 accW2[4], accW1[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accW2[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) accW1[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t nbat = (n + 31) / 32;
     for (int64_t bt = blockIdx.x; bt < nbat; bt += gridDim.x) {
-        const int64_t s0 = bt * 16;
-        __syncthreads();
-        // stage the batch: features, first hidden layer, dz, and d2 = dz w3 [h2 > 0]
-        for (int k = tid; k < 16 * 32; k += 256) {
-            const int s = k >> 5, f = k & 31;
-            s_x[s][f] = (s0 + s < n) ? from_bf16(x[(s0 + s) * 32 + f]) : 0.f;
-        }
-        if (tid < 16) s_dz[tid] = (s0 + tid < n) ? dz[s0 + tid] : 0.f;
-        __syncthreads();
-        for (int k = tid; k < 16 * 64; k += 256) {
-            const int s = k >> 6, v = k & 63;
-            const bool ok = s0 + s < n;
-            s_h1[s][v] = ok ? from_bf16(h1[(s0 + s) * 64 + v]) : 0.f;
-            const float hv = ok ? h2[(s0 + s) * 64 + v] : 0.f;
-            s_d2[s][v] = hv > 0.f ? s_dz[s] * s_w3[v] : 0.f;
-            // reuse s_d1 to hold h2 for the w3 gradient
-            s_d1[s][v] = hv;
+        const int64_t s0 = bt * 32;
+        __syncthreads();    // the previous batch's operands are consumed
+        if (tid < 32) s_dz[tid] = (s0 + tid < n) ? dz[s0 + tid] : 0.f;
+        {   // x^T: feature f = tid % 32, samples 4 (tid / 32) .. +3
+            const int f = tid & 31, g4 = (tid >> 5) * 4;
+            uint16_t v4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v4[k] = (s0 + g4 + k < n) ? x[(s0 + g4 + k) * 32 + f] : (uint16_t)0;
+            *reinterpret_cast<uint2*>(&s_xt[f][g4]) =
+                make_uint2((uint32_t)v4[0] | ((uint32_t)v4[1] << 16), (uint32_t)v4[2] | ((uint32_t)v4[3] << 16));
         }
         __syncthreads();
-        if (q == 0) {
-            for (int s = 0; s < 16; ++s) {
-                gw3 += s_dz[s] * s_d1[s][u];
-                gb2 += s_d2[s][u];
+        {   // h1^T, d2 (split), and the b2 / w3 sums: unit vu, samples 8 vq .. +7
+            uint16_t hv[8], dh[8], dl[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int s = 8 * vq + k;
+                const bool ok = s0 + s < n;
+                hv[k] = ok ? h1[(s0 + s) * 64 + vu] : (uint16_t)0;
+                const float h2v = ok ? h2[(s0 + s) * 64 + vu] : 0.f;
+                const float d2 = h2v > 0.f ? s_dz[s] * s_w3[vu] : 0.f;
+                gb2 += d2;
+                gw3 += s_dz[s] * h2v;
+                dh[k] = to_bf16(d2);
+                dl[k] = to_bf16(d2 - from_bf16(dh[k]));
+                s_d2[0][s][vu] = dh[k];
+                s_d2[1][s][vu] = dl[k];
             }
+            uint4 ph, pd, pl;
+            ph = make_uint4(hv[0] | (hv[1] << 16), hv[2] | (hv[3] << 16), hv[4] | (hv[5] << 16), hv[6] | (hv[7] << 16));
+            pd = make_uint4(dh[0] | (dh[1] << 16), dh[2] | (dh[3] << 16), dh[4] | (dh[5] << 16), dh[6] | (dh[7] << 16));
+            pl = make_uint4(dl[0] | (dl[1] << 16), dl[2] | (dl[3] << 16), dl[4] | (dl[5] << 16), dl[6] | (dl[7] << 16));
+            *reinterpret_cast<uint4*>(&s_h1t[vu][8 * vq]) = ph;
+            *reinterpret_cast<uint4*>(&s_d2t[0][vu][8 * vq]) = pd;
+            *reinterpret_cast<uint4*>(&s_d2t[1][vu][8 * vq]) = pl;
         }
         if (tid == 0)
-            for (int s = 0; s < 16; ++s) gb3 += s_dz[s];
+            for (int s = 0; s < 32; ++s) gb3 += s_dz[s];
         __syncthreads();
-        // d1[s][v] = sum_u d2[s][u] W2[u][v], masked by h1 > 0: thread -> (s = tid / 16, v = 4 (tid % 16) ..)
-        {
-            const int s = tid >> 4, v0 = (tid & 15) * 4;
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            for (int uu = 0; uu < 64; ++uu) {
-                const float d = s_d2[s][uu];
+        // d1 = d2 W2 masked by h1 > 0: 8 output tiles (2 sample tiles x 4 unit tiles), 2 per wave
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] += d * s_w2[uu][v0 + k];
+        for (int tt = 0; tt < 2; ++tt) {
+            const int tau = 2 * wid + tt, St = tau & 1, Vt = tau >> 1;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int Kt = 0; Kt < 2; ++Kt) {
+                const bf16x8 b = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4*>(&s_w2t[16 * Vt + row][32 * Kt + 8 * grp]));
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 a = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const uint4*>(&s_d2[h][16 * St + row][32 * Kt + 8 * grp]));
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+                }
+            }
+            const int v = 16 * Vt + row;
+            uint16_t dh[4], dl[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s = 16 * St + 4 * grp + r;
+                const float d1 = from_bf16(s_h1t[v][s]) > 0.f ? acc[r] : 0.f;
+                dh[r] = to_bf16(d1);
+                dl[r] = to_bf16(d1 - from_bf16(dh[r]));
+            }
+            *reinterpret_cast<uint2*>(&s_d1t[0][v][16 * St + 4 * grp]) =
+                make_uint2((uint32_t)dh[0] | ((uint32_t)dh[1] << 16), (uint32_t)dh[2] | ((uint32_t)dh[3] << 16));
+            *reinterpret_cast<uint2*>(&s_d1t[1][v][16 * St + 4 * grp]) =
+                make_uint2((uint32_t)dl[0] | ((uint32_t)dl[1] << 16), (uint32_t)dl[2] | ((uint32_t)dl[3] << 16));
+        }
+        // gW2 tiles (unit tile wid, input tiles 0..3): K = the batch's 32 samples
+        {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_d2t[0][16 * wid + row][8 * grp]));
+            const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_d2t[1][16 * wid + row][8 * grp]));
+#pragma unroll
+            for (int Vt = 0; Vt < 4; ++Vt) {
+                const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_h1t[16 * Vt + row][8 * grp]));
+                accW2[Vt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, accW2[Vt], 0, 0, 0);
+                accW2[Vt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, accW2[Vt], 0, 0, 0);
+            }
+        }
+        __syncthreads();    // d1^T complete
+        {   // gW1 tiles (unit tile wid, feature tiles 0..1) and the b1 sums
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_d1t[0][16 * wid + row][8 * grp]));
+            const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_d1t[1][16 * wid + row][8 * grp]));
+#pragma unroll
+            for (int Ft = 0; Ft < 2; ++Ft) {
+                const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&s_xt[16 * Ft + row][8 * grp]));
+                accW1[Ft] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, accW1[Ft], 0, 0, 0);
+                accW1[Ft] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, accW1[Ft], 0, 0, 0);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s_d1[s][v0 + k] = s_h1[s][v0 + k] > 0.f ? acc[k] : 0.f;
-        }
-        __syncthreads();
-        for (int s = 0; s < 16; ++s) {
-            const float d2 = s_d2[s][u], d1 = s_d1[s][u];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) gW2[k] += d2 * s_h1[s][16 * q + k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) gW1[k] += d1 * s_x[s][8 * q + k];
-            if (q == 0) gb1 += d1;
+            for (int k = 0; k < 8; ++k)
+                gb1 += from_bf16(s_d1t[0][vu][8 * vq + k]) + from_bf16(s_d1t[1][vu][8 * vq + k]);
         }
     }
     float* p = part + (int64_t)blockIdx.x * kMlpCount;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) p[kMlpW2 + u * 64 + 16 * q + k] = gW2[k];
+    for (int Vt = 0; Vt < 4; ++Vt)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) p[kMlpW1 + u * 32 + 8 * q + k] = gW1[k];
-    if (q == 0) {
-        p[kMlpB1 + u] = gb1;
-        p[kMlpB2 + u] = gb2;
-        p[kMlpW3 + u] = gw3;
+        for (int r = 0; r < 4; ++r) p[kMlpW2 + (16 * wid + 4 * grp + r) * 64 + 16 * Vt + row] = accW2[Vt][r];
+#pragma unroll
+    for (int Ft = 0; Ft < 2; ++Ft)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[kMlpW1 + (16 * wid + 4 * grp + r) * 32 + 16 * Ft + row] = accW1[Ft][r];
+    // bias and w3 sums: the four sample quarters of each unit added in a fixed order
+    s_bias[0][vu][vq] = gb2;
+    s_bias[1][vu][vq] = gw3;
+    s_bias[2][vu][vq] = gb1;
+    __syncthreads();
+    if (tid < 64) {
+        p[kMlpB2 + tid] = ((s_bias[0][tid][0] + s_bias[0][tid][1]) + s_bias[0][tid][2]) + s_bias[0][tid][3];
+        p[kMlpW3 + tid] = ((s_bias[1][tid][0] + s_bias[1][tid][1]) + s_bias[1][tid][2]) + s_bias[1][tid][3];
+        p[kMlpB1 + tid] = ((s_bias[2][tid][0] + s_bias[2][tid][1]) + s_bias[2][tid][2]) + s_bias[2][tid][3];
     }
     if (tid == 0) p[kMlpB3] = gb3;
 }

@@ -55,6 +55,8 @@ class TrainConfig:
     traj_every: int = 0                  # push the gradient-norm averages to the 8-deep ring every k iterations
     proposer: object | None = None       # learned freeze proposer (proposer.Proposer), needs traj_every
     dataset: object | None = None        # proposer.ProposerDataset to record the rule's decisions into
+    update_hook: object | None = None    # called as hook(trainer, k, eps_xyz, eps_rgb, accepted proposals or None)
+                                         # after every freeze-map update (measurement, e.g. false-freeze counts)
     partition: bool = False              # after each freeze update, move the frozen columns behind the active ones
     fused_loss: bool = True              # L1 loss computed by the forward compositing (else a separate pass)
     lambda_ssim: float = 0.0             # eq. 3: L = (1 - lambda) L1 + lambda D-SSIM (the paper uses 0.2)
@@ -226,8 +228,12 @@ class Trainer:
                 self.cfg.dataset.record(self.traj, self.ema, ex, er)
             if self.cfg.proposer is not None:
                 prop = self.cfg.proposer.propose(self.traj.ring, self.traj.head, self.ema, ex, er, self.prop_buf)
+            if self.cfg.update_hook is not None:
+                self.cfg.update_hook(self, k, ex, er, prop, before=True)
             self.ctx.update_freeze_mask(self.ema[0], self.ema[1], ex, er, 0, self.frozen, proposal=prop,
                                         n_frozen=self.n_frozen)
+            if self.cfg.update_hook is not None:
+                self.cfg.update_hook(self, k, ex, er, prop, before=False)
             if self.cfg.partition:
                 self._partition()
         elif act == RESET:

@@ -156,7 +156,7 @@ def test_mlp_bce_matches_oracle():
     assert (np.abs(dz.cpu().numpy() - odz) <= 1e-6 * np.abs(odz) + 2e-7 / n).all()
 
 
-@pytest.mark.parametrize("n", [5, 5000])
+@pytest.mark.parametrize("n", [5, 5000, 33, 200_000])
 def test_mlp_backward_matches_oracle(n):
     import torch
     ctx = _ctx()

@@ -456,6 +456,42 @@ def ablation(torch, w, seeds=(2, 12, 22)):
             "workload": "c2, whole 2000-iteration schedules (freezing window [600, 1800), finetune 200)"}
 
 
+PROBES = {0: ("hbm_copy", "GB/s", 1e9), 1: ("fp32_fma", "TFLOP/s", 1e12), 2: ("v_exp_f32", "Gexp/s", 1e9),
+          3: ("lds_read_b128", "TB/s", 1e12), 4: ("bf16_mfma_16x16x32", "TFLOP/s", 1e12),
+          5: ("fp32_atomic_distinct", "Gop/s", 1e9), 6: ("fp32_atomic_contended_64", "Gop/s", 1e9)}
+NOMINAL = {"hbm_copy": 8000.0, "fp32_fma": 157.3, "bf16_mfma_16x16x32": 2500.0}
+
+
+def measure_peaks(torch, kinds=(0, 1, 2, 3, 4, 5, 6), reps=10):
+    """The peak microbenchmarks (libgsta_micro.so): rate of each probe on this
+    GPU, next to the nominal figure where one is published."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2504_06716_amd", "libgsta_micro.so"))
+    lib.gsta_micro_probe.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(ctypes.c_double)]
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    st = torch.cuda.current_stream().cuda_stream
+    for k in kinds:
+        ms, work = ctypes.c_float(0), ctypes.c_double(0)
+        size = nbytes if k == 0 else (64 << 20)
+        rc = lib.gsta_micro_probe(k, a.data_ptr(), b.data_ptr(), size, reps if k != 6 else 2, st, ctypes.byref(ms),
+                                  ctypes.byref(work))
+        if rc != 0:
+            raise RuntimeError(f"microbenchmark {k} failed: {rc}")
+        name, unit, scale = PROBES[k]
+        rate = work.value / (ms.value * 1e-3) / scale
+        out[name] = {"value": round(rate, 2), "unit": unit}
+        if name in NOMINAL:
+            out[name]["nominal"] = NOMINAL[name]
+            out[name]["of_nominal"] = round(rate / NOMINAL[name], 4)
+    del a, b
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -472,6 +508,10 @@ def main():
                     help="first copy 256 MiB on the device (a plain copy of known size for counter scaling)")
     ap.add_argument("--c3", action="store_true",
                     help="time the c3 workload's graph-captured 4-view steps (1M Gaussians, 1080x1600) and exit")
+    ap.add_argument("--peaks", action="store_true", help="run the peak microbenchmarks and exit")
+    ap.add_argument("--profile-window", type=int, default=None, metavar="K",
+                    help="for counter collection: advance the c2 GSta run untimed to iteration 1000, run K "
+                         "iterations, exit")
     ap.add_argument("--proposer", action="store_true",
                     help="train the learned freeze proposer on a logged c2 run and compare it with the rule alone")
     ap.add_argument("--ablation", action="store_true",
@@ -497,8 +537,22 @@ def main():
     if args.c3:
         print(json.dumps(c3_throughput(torch, args.steps if args.steps != 2000 else 20)), flush=True)
         return
+    if args.peaks:
+        print(json.dumps(measure_peaks(torch)), flush=True)
+        return
     log("setting up the c2 workload")
     w = c2_setup(torch)
+    if args.profile_window is not None:
+        from paper_2504_06716_amd.train import Trainer
+        tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], w["cfg"](True), w["order"], ctx=w["ctx"])
+        tr.run(1000)
+        torch.cuda.synchronize()
+        log(f"profile window: iterations [1000, {1000 + args.profile_window})")
+        tr.run(args.profile_window)
+        torch.cuda.synchronize()
+        st, _ = w["ctx"].check()
+        print(json.dumps({"profile_window": [1000, 1000 + args.profile_window], "status": st}), flush=True)
+        return
     if args.calibrate is not None:
         print(json.dumps({"q": args.calibrate, "eps0": calibrate(torch, w, args.calibrate)}))
         return
@@ -573,6 +627,8 @@ def main():
         achieved = amount / (ms_dom * 1e-3) / 1e9
         peak, unit_r = HBM_PEAK_GBS, "GB/s"
 
+    measured = measure_peaks(torch, kinds=(0, 1))
+    peak_meas = measured["fp32_fma"]["value"] if unit_r == "TFLOP/s" else measured["hbm_copy"]["value"]
     value = steps / dt_f
     out = {
         "metric": "train iters/sec (fwd+bwd+Adam), GSta freeze vs no-freeze at equal iterations",
@@ -612,7 +668,9 @@ def main():
                      "unit": unit_r, "frac": round(achieved / peak, 5),
                      "traffic": measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"),
                                                  dominant),
-                     "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches},
+                     "avg_launch_ms": round(ms_dom / max(launches, 1), 5), "launches": launches,
+                     "measured_peak": peak_meas, "frac_of_measured": round(achieved / peak_meas, 5)},
+        "measured_peaks": measured,
         "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_all.items()},
         "pairs_per_iter": [pairs_all[0] / steps, pairs_all[1] / steps],
         "bwd_grad_pairs_per_iter": pairs_all[5] / steps,

@@ -125,11 +125,15 @@ typedef enum {
                                    pixel's transmittance and colour prefix at each multiple of it, so
                                    the backward of a long tile list is spread over several
                                    workgroups; the result does not depend on it. */
-    GSTA_OPT_BINNING = 3        /* how the per-tile lists are built: 0 (default) places every tile
+    GSTA_OPT_BINNING = 3,       /* how the per-tile lists are built: 0 (default) places every tile
                                    instance directly where views have at most 1408 tiles and the
                                    placement scratch was reserved for the call's views, else sorts;
                                    1 always expands and sorts the tile keys (LSD radix).  Both give
                                    the same lists (Section 3.1: splats per tile in depth order). */
+    GSTA_OPT_DEPTH_SORT = 4     /* the per-view depth sort: 0 (default) histogram / scan / scatter
+                                   kernels per 8-bit pass, 1 onesweep (a global digit histogram,
+                                   then one kernel per pass with decoupled look-back).  Both are the
+                                   same stable sort: identical order. */
 } gsta_option;
 
 /* ---- context ------------------------------------------------------------ */

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NO
 
 (STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
  STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES, STATE_INST_GID) = range(12)
-OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT, OPT_BINNING = 0, 1, 2, 3
+OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT, OPT_BINNING, OPT_DEPTH_SORT = 0, 1, 2, 3, 4
 FREEZE_RULE_MINGRAD, FREEZE_RULE_RANDOM = 1, 2
 
 

@@ -75,6 +75,10 @@ struct gsta_ctx {
     uint32_t* tile_tot = nullptr;    // [place_views][tiles_max] instances per tile
     int place_views = 0;             // views the placement scratch holds (0: always sort)
     int binning = 0;                 // GSTA_OPT_BINNING
+    int depth_sort = 0;              // GSTA_OPT_DEPTH_SORT
+    uint32_t* os_tot = nullptr;      // onesweep depth sort: [V][4][256] digit totals
+    uint32_t* os_status = nullptr;   // [V][4][chunks][256] look-back words
+    uint32_t* os_tickets = nullptr;  // [V][4] chunk tickets
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
     uint32_t* gen = nullptr;       // [1] backward generation (starts at 1; stamps start at 0)
@@ -231,7 +235,9 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->ssim_part, ssim_blocks((int)V, l->max_height, l->max_width)) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
-         alloc(ctx, &ctx->flags, 4) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
+         alloc(ctx, &ctx->os_tot, V * 4 * 256) && alloc(ctx, &ctx->os_tickets, V * 4) &&
+         alloc(ctx, &ctx->os_status, V * 4 * onesweep_chunks(S) * 256) &&
+         alloc(ctx, &ctx->flags, 8) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
     if (!ok) {
         free_all(ctx);
         return fail(ctx, GSTA_ERR_OOM, "device allocation failed");
@@ -241,7 +247,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         ctx->cus = 1;
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
-    if (hipMemset(ctx->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
+    if (hipMemset(ctx->flags, 0, 8 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->stamps, 0, (size_t)std::max<int64_t>(cap, 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMemcpy(ctx->gen, &kGen0, sizeof(kGen0), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
@@ -461,6 +467,10 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
             if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "binning must be 0 or 1");
             ctx->binning = (int)value;
             return GSTA_OK;
+        case GSTA_OPT_DEPTH_SORT:
+            if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "depth sort must be 0 or 1");
+            ctx->depth_sort = (int)value;
+            return GSTA_OK;
         default:
             return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
     }
@@ -511,13 +521,13 @@ gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances
     if (ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "gsta_check synchronises: not while a graph is captured");
     gsta_status st;
     if ((st = hip_check(ctx, hipStreamSynchronize(stream), "hipStreamSynchronize")) != GSTA_OK) return st;
-    uint32_t flags[4] = {0, 0, 0, 0};
+    uint32_t flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t mi = 0;
     if ((st = hip_check(ctx, hipMemcpy(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost), "read flags")) != GSTA_OK)
         return st;
     if ((st = hip_check(ctx, hipMemcpy(&mi, ctx->max_inst, sizeof(mi), hipMemcpyDeviceToHost), "read counts")) != GSTA_OK)
         return st;
-    const uint32_t zeros[4] = {0, 0, 0, 0};
+    const uint32_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint64_t z64 = 0;
     if ((st = hip_check(ctx, hipMemcpy(ctx->flags, zeros, sizeof(zeros), hipMemcpyHostToDevice), "clear flags")) != GSTA_OK)
         return st;
@@ -529,6 +539,7 @@ gsta_status gsta_check(gsta_ctx* ctx, hipStream_t stream, int64_t* max_instances
     if (flags[2]) return fail(ctx, GSTA_ERR_CAPACITY, "densified set exceeded the output capacity");
     if (flags[3]) return fail(ctx, GSTA_ERR_CAPACITY, "compositing checkpoints exceeded their pool (%u slots)",
                               ctx->pool_cap);
+    if (flags[4]) return fail(ctx, GSTA_ERR_HIP, "the depth sort's look-back did not complete (spin bound reached)");
     if (flags[1]) return fail(ctx, GSTA_ERR_NONFINITE, "non-finite gradient met by the optimizer");
     return GSTA_OK;
 }
@@ -605,9 +616,10 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     const int ntx = ca.c[0].ntx;
     const int64_t T = (int64_t)ca.c[0].ntx * ca.c[0].nty;
 
-    // chunks of 256 keys: the preprocess writes the depth sort's first-pass
-    // histograms (its blocks are the sort's first chunks)
-    const bool hist_given = ctx->items_depth == 1;
+    // onesweep depth sort (default), or the hist / scan / scatter passes, whose
+    // first-pass histograms the preprocess writes when its chunks are 256 keys
+    const bool onesweep = ctx->depth_sort == 1 && n < ((int64_t)1 << 30);
+    const bool hist_given = !onesweep && ctx->items_depth == 1;
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
@@ -615,8 +627,15 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
-        RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth, hist_given};
-        s.depth_buf = (n > 0) ? radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream) : 0;
+        if (n == 0) {
+            s.depth_buf = 0;
+        } else if (onesweep) {
+            OnesweepScratch os{ctx->os_tot, ctx->os_status, ctx->os_tickets};
+            s.depth_buf = radix_sort_onesweep(s.dkey, s.dval, S, nv, (uint32_t)n, os, ctx->flags, stream);
+        } else {
+            RadixScratch rd{ctx->hist, ctx->digit_tot, ctx->chunks_depth, ctx->items_depth, hist_given};
+            s.depth_buf = radix_sort_pairs(s.dkey, s.dval, S, nv, nullptr, (uint32_t)n, 32, rd, stream);
+        }
     }
     s.placed = ctx->binning == 0 && nv <= ctx->place_views && T <= kPlaceMaxTiles;
     if (s.placed) {

@@ -140,6 +140,16 @@ int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
                      const uint32_t* d_count, uint32_t h_count, int bits, const RadixScratch& rs,
                      hipStream_t s);
 int64_t radix_chunks(int64_t count, int items);
+// Onesweep variant for host-known counts (the per-view depth sort): a
+// global-histogram kernel and one decoupled-look-back kernel per 8-bit pass.
+struct OnesweepScratch {
+    uint32_t* tot;           // [nseg][4][256] digit totals of each pass
+    uint32_t* status;        // [nseg][4][chunks][256] look-back words
+    uint32_t* tickets;       // [nseg][4] chunk tickets
+};
+int64_t onesweep_chunks(int64_t count);
+int radix_sort_onesweep(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, uint32_t count,
+                        const OnesweepScratch& os, uint32_t* flags, hipStream_t s);
 
 // Depth-ordered tile-instance expansion: counts per Gaussian in depth
 // order, exclusive scan, write (view*T + tile, gid) for every touched tile.

@@ -499,7 +499,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     __shared__ float4 s_rgb[B];
     __shared__ uint32_t s_idx[B];
     __shared__ uint32_t s_frz[B];
-    __shared__ float s_part[4 * W][9][kChunk];
+    // row totals; the chunk dimension is padded to kChunk + 1 words so that the
+    // four row writers of a wave (rows 4 wid .. +3, stride 9 (kChunk + 1))
+    // fall into different LDS banks
+    __shared__ float s_part[4 * W][9][kChunk + 1];
     __shared__ unsigned int s_pairs, s_grad;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     }
     // row totals start at zero; only steps with gradient work write theirs,
     // and each flush clears what it has read
-    for (int i = tid; i < 4 * W * 9 * kChunk; i += NT) (&s_part[0][0][0])[i] = 0.f;
+    for (int i = tid; i < 4 * W * 9 * (kChunk + 1); i += NT) (&s_part[0][0][0])[i] = 0.f;
     __syncthreads();
 
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {

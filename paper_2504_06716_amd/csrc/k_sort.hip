@@ -227,6 +227,201 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------------
+// Onesweep radix sort (one kernel per pass) for sorts whose key count is
+// known on the host, used for the per-view depth sort.  A first kernel
+// counts the digits of every pass over all keys (global histograms) and
+// clears the pass state; then each pass is one kernel in which every
+// workgroup takes the next chunk by ticket, ranks its keys stably (as the
+// scatter above), publishes its per-digit counts, and finds how many keys of
+// each digit the earlier chunks hold by decoupled look-back: the status word
+// of (chunk, digit) carries the chunk's own count (flag AGG) or the count of
+// every chunk up to and including it (flag INC), and a workgroup sums its
+// predecessors' words backwards, eight at a time, until it meets an INC.
+// Tickets make every predecessor's workgroup resident before its successor
+// starts, and each publishes its AGG words before looking back, so every
+// wait ends; a spin bound turns a wait that does not into a device flag.
+// ---------------------------------------------------------------------------
+constexpr int OS_ITEMS = 8;
+constexpr int OS_CHUNK = RS_THREADS * OS_ITEMS;      // 2048 keys per workgroup
+constexpr uint32_t OS_AGG = 1u << 30, OS_INC = 2u << 30, OS_CNT = (1u << 30) - 1u;
+constexpr uint32_t OS_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint32_t os_load(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void os_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Global digit counts of every pass (tot[seg][pass][256], cleared with the
+// tickets by k_os_clear), and this chunk's look-back words of every pass
+// cleared: status[seg][pass][chunk][256].
+__global__ __launch_bounds__(RS_THREADS) void k_os_totals(const uint32_t* __restrict__ keys, int64_t seg_stride,
+                                                          uint32_t count, int passes, int per,
+                                                          uint32_t* __restrict__ tot, uint32_t* __restrict__ status,
+                                                          uint32_t* __restrict__ tickets, int64_t nchunks) {
+    __shared__ uint32_t s_h[4][RS_BINS];
+    const int seg = blockIdx.y, tid = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) s_h[p][tid] = 0u;
+    // this chunk's status words of every pass, and (first chunk) the tickets and totals
+    for (int p = 0; p < passes; ++p) status[(((int64_t)seg * 4 + p) * nchunks + chunk) * RS_BINS + tid] = 0u;
+    __syncthreads();
+    const uint32_t* k = keys + seg * seg_stride;
+    const uint32_t dmask = (1u << per) - 1u;
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const int64_t idx = chunk * OS_CHUNK + (int64_t)it * RS_THREADS + tid;
+        if (idx < count) {
+            const uint32_t key = k[idx];
+            for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(key >> (p * per)) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        if (s_h[p][tid]) atomicAdd(&tot[((int64_t)seg * 4 + p) * RS_BINS + tid], s_h[p][tid]);
+}
+
+__global__ void k_os_clear(uint32_t* __restrict__ tot, uint32_t* __restrict__ tickets, int nseg) {
+    for (int i = threadIdx.x; i < nseg * 4 * RS_BINS; i += blockDim.x) tot[i] = 0u;
+    for (int i = threadIdx.x; i < nseg * 4; i += blockDim.x) tickets[i] = 0u;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_os_pass(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t seg_stride, uint32_t count, int pass, int shift, int bits,
+    const uint32_t* __restrict__ tot, uint32_t* __restrict__ status, uint32_t* __restrict__ tickets,
+    int64_t nchunks, uint32_t* __restrict__ flags) {
+    constexpr int WSPAN = 64 * OS_ITEMS;
+    const uint32_t dmask = (1u << bits) - 1u;
+    __shared__ uint32_t s_keys[OS_CHUNK];
+    __shared__ uint32_t s_vals[OS_CHUNK];
+    __shared__ uint32_t s_cnt[RS_WAVES][RS_BINS];
+    __shared__ uint32_t s_local_start[RS_BINS];
+    __shared__ uint32_t s_gbase[RS_BINS];
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint32_t s_chunk;
+    const int seg = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) s_chunk = atomicAdd(&tickets[seg * 4 + pass], 1u);
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) s_cnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t chunk = s_chunk;
+    uint32_t* st = status + ((int64_t)seg * 4 + pass) * nchunks * RS_BINS;
+    const uint32_t* ki = kin + seg * seg_stride;
+    const uint32_t* vi = vin + seg * seg_stride;
+    uint32_t* ko = kout + seg * seg_stride;
+    uint32_t* vo = vout + seg * seg_stride;
+    const int64_t base = chunk * OS_CHUNK;
+    const int n_valid = (int)min((int64_t)OS_CHUNK, (int64_t)count - base);
+    uint32_t key[OS_ITEMS], val[OS_ITEMS], rank[OS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const int j = wid * WSPAN + it * 64 + lane;
+        const bool ok = j < n_valid;
+        key[it] = ok ? ki[base + j] : 0u;
+        val[it] = ok ? vi[base + j] : 0u;
+    }
+    // stable ranks inside each wave (ballots) with the wave's digit counters in LDS
+#pragma unroll
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const int j = wid * WSPAN + it * 64 + lane;
+        const bool ok = j < n_valid;
+        const uint32_t d = (key[it] >> shift) & dmask;
+        uint64_t match = __ballot(ok);
+        for (int b = 0; b < bits; ++b) {
+            const uint64_t bal = __ballot(ok && ((d >> b) & 1u));
+            match &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(match >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)match, 0u));
+        const uint32_t before = ok ? s_cnt[wid][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == 0) s_cnt[wid][d] = before + (uint32_t)__popcll(match);
+        __builtin_amdgcn_wave_barrier();
+        rank[it] = before + below;
+    }
+    __syncthreads();
+    uint32_t dtot = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+        const uint32_t c = s_cnt[w][tid];
+        s_cnt[w][tid] = dtot;
+        dtot += c;
+    }
+    // publish this chunk's count of digit tid, then look back for the earlier chunks'
+    if (chunk == 0) {
+        os_store(&st[tid], OS_INC | dtot);
+    } else {
+        os_store(&st[chunk * RS_BINS + tid], OS_AGG | dtot);
+    }
+    uint32_t excl = 0;
+    if (chunk > 0) {
+        int64_t j = chunk - 1;
+        uint32_t spins = 0;
+        bool done = false;
+        while (!done && j >= 0) {
+            uint32_t v[8];
+            const int m = (int)min((int64_t)8, j + 1);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = t < m ? os_load(&st[(j - t) * RS_BINS + tid]) : 0u;
+            int t = 0;
+            for (; t < m; ++t) {
+                const uint32_t f = v[t] & ~OS_CNT;
+                if (f == 0u) break;
+                excl += v[t] & OS_CNT;
+                if (f == OS_INC) {
+                    done = true;
+                    ++t;
+                    break;
+                }
+            }
+            j -= t;
+            if (t == 0 && ++spins > OS_SPIN_LIMIT) {
+                atomicOr(&flags[4], 1u);
+                done = true;
+            }
+        }
+        os_store(&st[chunk * RS_BINS + tid], OS_INC | (excl + dtot));
+    }
+    {
+        uint32_t total_all;
+        const uint32_t dbase = block_excl_scan_256(tot[((int64_t)seg * 4 + pass) * RS_BINS + tid], s_tmp, total_all);
+        uint32_t t2;
+        const uint32_t ls = block_excl_scan_256(dtot, s_tmp, t2);
+        s_local_start[tid] = ls;
+        s_gbase[tid] = dbase + excl - ls;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const int j = wid * WSPAN + it * 64 + lane;
+        if (j < n_valid) {
+            const uint32_t d = (key[it] >> shift) & dmask;
+            const uint32_t pos = s_local_start[d] + s_cnt[wid][d] + rank[it];
+            if (pos < (uint32_t)OS_CHUNK) {
+                s_keys[pos] = key[it];
+                s_vals[pos] = val[it];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const int p = it * RS_THREADS + tid;
+        if (p < n_valid) {
+            const uint32_t k = s_keys[p];
+            const uint32_t g = s_gbase[(k >> shift) & dmask] + (uint32_t)p;
+            if (g < count) {
+                ko[g] = k;
+                vo[g] = s_vals[p];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Depth-ordered expansion into tile instances.
 // Element e = v*n + pos is the pos-th Gaussian of view v in depth order.
 // ---------------------------------------------------------------------------
@@ -809,6 +1004,28 @@ int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
     if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 8) return radix_passes<8>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+}
+
+int64_t onesweep_chunks(int64_t count) { return (count + OS_CHUNK - 1) / OS_CHUNK; }
+
+int radix_sort_onesweep(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, uint32_t count,
+                        const OnesweepScratch& os, uint32_t* flags, hipStream_t s) {
+    // 32-bit keys in 4 passes of 8 bits
+    constexpr int passes = 4, per = 8;
+    const int64_t nchunks = onesweep_chunks(count);
+    if (nchunks == 0) return 0;
+    k_os_clear<<<1, 256, 0, s>>>(os.tot, os.tickets, nseg);
+    k_os_totals<<<dim3((unsigned)nchunks, nseg), RS_THREADS, 0, s>>>(keys[0], seg_stride, count, passes, per, os.tot,
+                                                                    os.status, os.tickets, nchunks);
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+        k_os_pass<<<dim3((unsigned)nchunks, nseg), RS_THREADS, 0, s>>>(keys[cur], vals[cur], keys[1 - cur],
+                                                                      vals[1 - cur], seg_stride, count, p, p * per,
+                                                                      per, os.tot, os.status, os.tickets, nchunks,
+                                                                      flags);
+        cur = 1 - cur;
+    }
+    return cur;
 }
 
 int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / EX_THREADS; }

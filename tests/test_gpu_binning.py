@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synthetic as S
-from tests.gpu_util import GpuScene
+from tests.gpu_util import GpuScene, dev
 
 pytestmark = pytest.mark.gpu
 
@@ -117,3 +117,34 @@ def test_binning_option_is_checked():
     ctx = G.Context(100, 1, 32, 32, 1 << 16)
     with pytest.raises(L.GstaError):
         ctx.set_option(L.OPT_BINNING, 2)
+
+
+@pytest.mark.parametrize("n,views", [(1, 1), (2049, 1), (100_000, 1), (4097, 8), (300_001, 2)])
+def test_onesweep_depth_sort_equals_pass_sort(n, views):
+    """The onesweep depth sort (GSTA_OPT_DEPTH_SORT 1) and the histogram /
+    scan / scatter passes (0) give the same stable order, bit for bit, and
+    the same images (the default path's order against the oracle is in
+    test_gpu_parity)."""
+    import torch
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd import _lib as L
+    print(f"depth sort n={n} views={views}", flush=True)
+    p = S.make_scene(n, 0, seed=n % 97)
+    cams = [S.look_at(10.0 * v, 40.0 * v, 48, 32) for v in range(views)]
+    out = []
+    for mode in (0, 1):
+        ctx = G.Context(n, views, 32, 48, 1 << 22)
+        ctx.set_option(L.OPT_DEPTH_SORT, mode)
+        P = dev(p)
+        img = torch.empty((views, 3, 32, 48), device="cuda")
+        with ctx.forward_only():        # no backward follows: no checkpoints for the very long tile lists
+            ctx.render_forward(P, 0, cams, (0, 0, 0), img, 0)
+        order = torch.empty((views, n), dtype=torch.int32, device="cuda")
+        ctx.get_state(0, L.STATE_DEPTH_ORDER, order)
+        torch.cuda.synchronize()
+        assert ctx.check()[0] == 0
+        out.append((order.cpu().numpy(), img.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    for v in range(views):                       # a permutation of the Gaussians
+        assert np.array_equal(np.sort(out[0][0][v]), np.arange(n, dtype=np.int32))

@@ -269,3 +269,38 @@ def test_proposer_end_to_end_training_run():
     print("rule froze", int(rule.sum()), "proposals added", int(extra.sum()))
     t2.run(iters - sched.warmup - 1)
     assert np.isfinite(t2.evaluate())
+
+
+def test_proposer_inference_at_c5_scale():
+    """The c5 workload's proposer step at its size: features of 3M Gaussians
+    from an 8-deep ring and logits on the matrix cores, against the oracle
+    on 4000 sampled Gaussians (features within one bf16 step, logits to the
+    forward test's bound)."""
+    import time
+    import torch
+    n = 3_000_000
+    ctx = _ctx()
+    rng = np.random.default_rng(17)
+    ring_v = O.bf16_round(np.exp(rng.normal(-9.0, 2.0, (8, 4, n))))
+    ring = dev(bits(ring_v))
+    mean_np = rng.normal(-4.0, 0.1, 32).astype(np.float32)
+    std_np = rng.uniform(0.5, 1.5, 32).astype(np.float32)
+    wf = _weights(7)
+    w, wb = _dev_weights(ctx, wf)
+    x = torch.empty((n, 32), dtype=torch.int16, device="cuda")
+    z = torch.empty(n, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.mlp_features(ring, 5, dev(mean_np), dev(std_np), x)
+    ctx.mlp_forward(wb, w, x, z)
+    torch.cuda.synchronize()
+    print(f"c5 proposer inference: {n} Gaussians in {(time.perf_counter() - t0) * 1e3:.2f} ms", flush=True)
+    idx = rng.choice(n, 4000, replace=False)
+    xo = O.traj_features(ring_v[:, :, idx], 5, mean_np.astype(np.float64), std_np.astype(np.float64))
+    xg = from_bits(x.cpu().numpy()[idx])
+    assert (np.abs(xg - xo) <= np.maximum(np.abs(xo) * 2.0 ** -7, 1e-5)).all()
+    oz, oh1, oh2 = O.mlp_forward(xg, wf.astype(np.float64))
+    W1, b1, W2, b2, w3, b3 = O.mlp_unpack(wf)
+    flip = 2.0 ** -8 * (np.abs(oh1) * (np.abs(w3) @ np.abs(O.bf16_round(W2)))[None, :]).max(1)
+    tol = 1e-5 * (1.0 + np.abs(oh2) @ np.abs(w3)) + flip
+    assert (np.abs(z.cpu().numpy()[idx] - oz) <= tol).all()

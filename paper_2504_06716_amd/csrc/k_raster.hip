@@ -31,17 +31,19 @@
 namespace gsta {
 namespace {
 
-// Sum over each row of 16 lanes with DPP (pairs, quads, then rotations by
-// 4 and 8 within the row); every lane of a row holds its row's total.
+// Sum over each row of 16 lanes with DPP: pairs, quads, then the mirror
+// within each half-row (lane i and 7 - i) and within the row (i and 15 - i),
+// permutations under which every lane has a source.  Every lane of a row
+// holds its row's total, (q0 + q1) + (q2 + q3) over its quads.
 __device__ __forceinline__ float row_sum(float v) {
     int x = __builtin_bit_cast(int, v);
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));
     x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, true));
     return v;
 }
 
@@ -534,8 +536,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
         const uint32_t p0 = seg ? (sgi << sc.shift) : 0u;                       // first position of the item
         const uint32_t p1 = seg ? min(tl, (sgi + 1u) << sc.shift) : tl;          // one past its last
 
-        float fpx[P], fpy[P], dC[P][3], Tf[P], T[P];
-        double F[P][3], A[P][3];
+        float fpx[P], fpy[P], dC[P][3], T[P];
+        // FB: the pixel's final colour, background term included (the
+        // forward's double colour + T_final bg); FB - A is then what lies
+        // behind the current splat
+        double FB[P][3], A[P][3];
         uint32_t last[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -546,8 +551,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
             T[p] = 1.0f;
             A[p][0] = A[p][1] = A[p][2] = 0.0;
             dC[p][0] = dC[p][1] = dC[p][2] = 0.f;
-            F[p][0] = F[p][1] = F[p][2] = 0.0;
-            Tf[p] = 1.f;
+            FB[p][0] = FB[p][1] = FB[p][2] = 0.0;
             last[p] = 0;
             if (px < cm.width && py < cm.height) {
                 const int64_t o = (int64_t)py * cm.width + px;
@@ -557,11 +561,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                     dC[p][0] = dl[0];
                     dC[p][1] = dl[HW];
                     dC[p][2] = dl[2 * HW];
-                    Tf[p] = T_final[(int64_t)v * HW + o];
+                    const float tf = T_final[(int64_t)v * HW + o];
                     const double* cf = cfg + (int64_t)v * 3 * HW + o;
-                    F[p][0] = cf[0];
-                    F[p][1] = cf[HW];
-                    F[p][2] = cf[2 * HW];
+                    FB[p][0] = cf[0] + (double)(tf * bg0);
+                    FB[p][1] = cf[HW] + (double)(tf * bg1);
+                    FB[p][2] = cf[2 * HW] + (double)(tf * bg2);
                 }
             }
         }
@@ -644,49 +648,52 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                         mem[p] = act && (e[p].power2 >= kPower2Floor);
                         any = any || mem[p];
                     }
-                    bool contrib = false;
                     if (__ballot(any) != 0ull) {
+                        // Straight-line over the pixels: a non-member gets weight
+                        // 0 and a zero dalpha, so it adds exact zeros and keeps
+                        // its T and accumulated colour, without divergent branches.
                         const float4 c = s_rgb[k];
+                        const double cx = (double)c.x, cy = (double)c.y, cz = (double)c.z;
+                        bool contrib = false;
                         float g9[9];
 #pragma unroll
                         for (int q = 0; q < 9; ++q) g9[q] = 0.f;
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             eval_alpha(co.y, e[p]);
-                            mem[p] = mem[p] && (e[p].alpha >= kAlphaMin);
-                            if (!mem[p]) continue;
-                            const float w = e[p].alpha * T[p];
+                            const bool m = mem[p] && (e[p].alpha >= kAlphaMin);
+                            const float w = m ? e[p].alpha * T[p] : 0.f;
                             const double wd = (double)w;
-                            A[p][0] = fma((double)c.x, wd, A[p][0]);
-                            A[p][1] = fma((double)c.y, wd, A[p][1]);
-                            A[p][2] = fma((double)c.z, wd, A[p][2]);
-                            if (!frz) {
-                                contrib = true;
-                                if (CNT) ++ngrad;
+                            A[p][0] = fma(cx, wd, A[p][0]);
+                            A[p][1] = fma(cy, wd, A[p][1]);
+                            A[p][2] = fma(cz, wd, A[p][2]);
+                            if (!frz) {   // uniform
+                                contrib = contrib || m;
+                                if (CNT) ngrad += m ? 1u : 0u;
                                 const float inv1m = __builtin_amdgcn_rcpf(1.0f - e[p].alpha);
-                                const float b0 = (float)(F[p][0] - A[p][0]) + Tf[p] * bg0;
-                                const float b1 = (float)(F[p][1] - A[p][1]) + Tf[p] * bg1;
-                                const float b2 = (float)(F[p][2] - A[p][2]) + Tf[p] * bg2;
-                                const float dalpha = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
-                                                     dC[p][1] * (c.y * T[p] - b1 * inv1m) +
-                                                     dC[p][2] * (c.z * T[p] - b2 * inv1m);
+                                const float b0 = (float)(FB[p][0] - A[p][0]);
+                                const float b1 = (float)(FB[p][1] - A[p][1]);
+                                const float b2 = (float)(FB[p][2] - A[p][2]);
+                                const float da = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
+                                                 dC[p][1] * (c.y * T[p] - b1 * inv1m) +
+                                                 dC[p][2] * (c.z * T[p] - b2 * inv1m);
                                 g9[6] += dC[p][0] * w;
                                 g9[7] += dC[p][1] * w;
                                 g9[8] += dC[p][2] * w;
-                                if (e[p].oG <= kAlphaMax) {
-                                    // d power / d(u, v) = -(a dx + b dy, b dx + c dy)
-                                    //                   = ln 2 (2 A dx + B dy, B dx + 2 C dy)
-                                    const float dpow = dalpha * e[p].alpha;
-                                    const float dpl = dpow * kLn2;
-                                    g9[5] += dalpha * e[p].G;
-                                    g9[0] += dpl * (2.0f * g.z * e[p].dx + g.w * e[p].dy);
-                                    g9[1] += dpl * (g.w * e[p].dx + 2.0f * co.x * e[p].dy);
-                                    g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
-                                    g9[3] -= dpow * e[p].dx * e[p].dy;
-                                    g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
-                                }
+                                // alpha clamped at kAlphaMax: no gradient to opacity or power
+                                const float dalpha = (m && e[p].oG <= kAlphaMax) ? da : 0.f;
+                                // d power / d(u, v) = -(a dx + b dy, b dx + c dy)
+                                //                   = ln 2 (2 A dx + B dy, B dx + 2 C dy)
+                                const float dpow = dalpha * e[p].alpha;
+                                const float dpl = dpow * kLn2;
+                                g9[5] += dalpha * e[p].G;
+                                g9[0] += dpl * (2.0f * g.z * e[p].dx + g.w * e[p].dy);
+                                g9[1] += dpl * (g.w * e[p].dx + 2.0f * co.x * e[p].dy);
+                                g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
+                                g9[3] -= dpow * e[p].dx * e[p].dy;
+                                g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
                             }
-                            T[p] = next_T(T[p], e[p].alpha);
+                            T[p] = m ? next_T(T[p], e[p].alpha) : T[p];
                         }
                         if (!frz && __ballot(contrib) != 0ull) {
                             if (CNT) wred += 1u;

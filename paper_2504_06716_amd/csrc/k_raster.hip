@@ -133,6 +133,10 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
     }
 }
 
+// Records per step of the forward walk (a multiple of which every chunk
+// length is).
+constexpr int kStep = 4;
+
 template <int W, bool QUAD, bool CNT>
 __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ gsort,
@@ -141,13 +145,15 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     float* __restrict__ T_final, uint32_t* __restrict__ last_out, double* __restrict__ cfg, SegCkpt sc,
     unsigned long long* __restrict__ pairs, FusedL1 l1) {
     constexpr int NT = 64 * W, P = QUAD ? 1 : 4 / W, B = NT;
-    __shared__ float4 s_geo[B];
-    __shared__ float4 s_co[B];
-    __shared__ float4 s_rgb[B];
+    // kStep - 1 slots past the batch hold zero-opacity records, which a
+    // step reaching past the last staged record evaluates as non-members
+    __shared__ float4 s_geo[B + kStep - 1];
+    __shared__ float4 s_co[B + kStep - 1];
+    __shared__ float4 s_rgb[B + kStep - 1];
     __shared__ unsigned int s_pairs;
     __shared__ uint32_t s_last;
     __shared__ uint32_t s_ckbase;      // pool slots of the current batch's segment boundaries
-    __shared__ uint8_t s_pos[QUAD ? B : 1];   // quadrant mode: batch offset of each kept record
+    __shared__ uint8_t s_pos[QUAD ? B + kStep - 1 : 1];   // quadrant mode: batch offset of each kept record
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
@@ -181,6 +187,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         s_pairs = 0;
         s_last = 0;
     }
+    if (tid < kStep - 1) {
+        s_geo[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_co[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_rgb[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     // checkpoints at list positions that are multiples of K (none in quadrant mode)
     const uint32_t kmask = sc.shift >= 31u ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
     const bool ckpt = kmask != 0xFFFFFFFFu;
@@ -199,13 +210,16 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     }
 
     // Two-stage software pipeline: while a batch is composited, the records
-    // of the next batch and the ids of the one after are in flight.
+    // of the next batch and the ids of the one after are in flight.  The
+    // loads are unconditional, from positions inside the list (a lane past
+    // its end reads the last entry, which the staging ignores): loads under
+    // a lane mask would make the compiler wait for them before the walk.
     Rec cur;
     uint32_t gid_nxt = 0;
-    {
-        const uint32_t j = rg.x + tid;
-        if (j < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gsort[j]);
-        if (j + B < rg.y) gid_nxt = gsort[j + B];
+    if (rg.y > rg.x) {   // uniform
+        const uint32_t j = rg.x + tid, jl = rg.y - 1u;
+        cur = fetch_rec(geo, col, rgbv, vs, gsort[min(j, jl)]);
+        gid_nxt = gsort[min(j + B, jl)];
     }
     // quadrant mode: the quarter's pixel box
     const float qx0 = (float)(tx0 + (quarter & 1) * 8), qy0 = (float)(ty0 + (quarter >> 1) * 8);
@@ -229,7 +243,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                 s_rgb[r] = cur.c;
                 s_pos[r] = (uint8_t)tid;
             }
-            if (tid == cnt) {          // the zero-opacity record after the kept ones
+            if (tid >= cnt && tid < cnt + kStep - 1) {   // zero-opacity records after the kept ones
                 s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -240,9 +254,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                 s_geo[tid] = cur.g;
                 s_co[tid] = cur.co;
                 s_rgb[tid] = cur.c;
-            } else if (base + tid == rg.y) {
-                // a zero-opacity record after the list's last splat: a two-splat
-                // step that reaches past the end evaluates it and it is never a member
+            } else if (base + tid < rg.y + (uint32_t)(kStep - 1)) {
+                // zero-opacity records after the list's last splat: a step that
+                // reaches past the end evaluates them and they are never members
                 s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -265,16 +279,15 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         __syncthreads();
         {
             const uint32_t jn = base + B + tid;
-            if (jn < rg.y) cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
-            if (jn + B < rg.y) gid_nxt = gsort[jn + B];
+            cur = fetch_rec(geo, col, rgbv, vs, gid_nxt);
+            gid_nxt = gsort[min(jn + B, rg.y - 1u)];
         }
-        // Each lane leaves the walk as soon as its pixels are done; the
-        // exponential and the accumulation run under the lanes' own
-        // membership tests.
-        // Two splats per step, both evaluated unconditionally so that their
-        // exponentials overlap; the transmittance then advances through them
-        // in list order with selects (the same operations on the same values
-        // as one splat at a time), and one branch adds the colour.
+        // Each lane leaves the walk as soon as its pixels are done.  kStep
+        // records per step, all evaluated unconditionally so that their
+        // exponentials and LDS reads overlap; the transmittance then advances
+        // through them in list order with selects (the same operations on the
+        // same values as one splat at a time), and the colour takes them in
+        // the same order.
         // Checkpoints fall on chunk starts: chunks of K splats (of the batch
         // when K is longer), so the steps inside a chunk test nothing.
         // (Quadrant mode: one chunk per batch, the batch start checkpointed
@@ -290,44 +303,63 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                                                   s_ckbase, tid, quarter, done, T, C);
             }
             const int kend = min(cnt, kc + L);
-            for (int k = kc; k < kend && !alldone; k += 2) {
-                // list positions of the two records (kept records: their batch offsets)
-                const uint32_t pos = base - rg.x + (QUAD ? (uint32_t)s_pos[k] : (uint32_t)k);
-                const int k1 = k + 1;                  // k1 == cnt: the zero-opacity record
-                const uint32_t pos1 = QUAD ? base - rg.x + (uint32_t)s_pos[k1] : pos + 1u;
-                const bool two = k1 < cnt;             // (counted by the counting variant only)
-                const float4 g0 = s_geo[k], g1 = s_geo[k1];
-                const float2 o0 = make_float2(s_co[k].x, s_co[k].y), o1 = make_float2(s_co[k1].x, s_co[k1].y);
+            for (int k = kc; k < kend && !alldone; k += kStep) {
+                // offsets k .. k + kStep - 1 (past cnt: the zero-opacity records)
+                float4 g[kStep], rgb[kStep];
+                float2 o[kStep];
+                uint32_t pos[kStep];     // list positions (kept records: their batch offsets)
+#pragma unroll
+                for (int i = 0; i < kStep; ++i) {
+                    g[i] = s_geo[k + i];
+                    const float4 t = s_co[k + i];
+                    o[i] = make_float2(t.x, t.y);
+                    rgb[i] = s_rgb[k + i];
+                    pos[i] = base - rg.x + (QUAD ? (uint32_t)s_pos[k + i] : (uint32_t)(k + i));
+                }
+                const int nreal = min(kStep, cnt - k);   // (counted by the counting variant only)
                 bool all = true;
-                if (CNT) witer += two ? 2u : 1u;
+                if (CNT) witer += (uint32_t)nreal;
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     if (!done[p]) {
-                        SplatEval e0, e1;
-                        eval_splat(g0.x, g0.y, g0.z, g0.w, o0.x, o0.y, fpx[p], fpy[p], e0);
-                        eval_splat(g1.x, g1.y, g1.z, g1.w, o1.x, o1.y, fpx[p], fpy[p], e1);
-                        const bool m0 = e0.power2 >= kPower2Floor && e0.alpha >= kAlphaMin;
-                        const bool m1 = e1.power2 >= kPower2Floor && e1.alpha >= kAlphaMin;
-                        const float T0 = T[p];
-                        const float Tn0 = next_T(T0, e0.alpha);
-                        const bool t0 = m0 && Tn0 < kTMin;
-                        const bool c0 = m0 && !t0;
-                        const float T1 = c0 ? Tn0 : T0;
-                        const float Tn1 = next_T(T1, e1.alpha);
-                        const bool t1 = !t0 && m1 && Tn1 < kTMin;
-                        const bool c1 = !t0 && m1 && !t1;
-                        if (c0 || c1) {
-                            const float4 ca = s_rgb[k], cb = s_rgb[k1];
-                            const double w0 = c0 ? (double)(e0.alpha * T0) : 0.0;
-                            const double w1 = c1 ? (double)(e1.alpha * T1) : 0.0;
-                            C[p][0] = fma((double)cb.x, w1, fma((double)ca.x, w0, C[p][0]));
-                            C[p][1] = fma((double)cb.y, w1, fma((double)ca.y, w0, C[p][1]));
-                            C[p][2] = fma((double)cb.z, w1, fma((double)ca.z, w0, C[p][2]));
-                            last[p] = c1 ? pos1 + 1u : pos + 1u;
+                        SplatEval e[kStep];
+                        bool mem[kStep];
+#pragma unroll
+                        for (int i = 0; i < kStep; ++i) {
+                            eval_splat(g[i].x, g[i].y, g[i].z, g[i].w, o[i].x, o[i].y, fpx[p], fpy[p], e[i]);
+                            mem[i] = e[i].power2 >= kPower2Floor && e[i].alpha >= kAlphaMin;
                         }
-                        T[p] = c1 ? Tn1 : T1;
-                        done[p] = t0 || t1;
-                        if (CNT) evals += (two && !t0) ? 2u : 1u;     // the pairs a one-at-a-time walk evaluates
+                        // Transmittance after each record: a non-member's factor is
+                        // exactly 1, so Tp[i + 1] is the one-at-a-time walk's T
+                        // after record i (the same product T (1 - alpha)) as long as
+                        // that walk has not stopped.  T never rises, so the records
+                        // before the first Tp[i + 1] < kTMin are the ones the walk
+                        // takes and it stops at that record: one multiply per record
+                        // is the only chain.
+                        float om[kStep];
+#pragma unroll
+                        for (int i = 0; i < kStep; ++i) om[i] = mem[i] ? 1.0f - e[i].alpha : 1.0f;
+                        float Tp[kStep + 1];
+                        Tp[0] = T[p];
+#pragma unroll
+                        for (int i = 0; i < kStep; ++i) Tp[i + 1] = Tp[i] * om[i];
+                        float Tc = Tp[0];
+#pragma unroll
+                        for (int i = 0; i < kStep; ++i) {
+                            if (CNT) evals += (Tp[i] >= kTMin && i < nreal) ? 1u : 0u;   // a one-at-a-time walk's pairs
+                            const bool ok = Tp[i + 1] >= kTMin;
+                            const bool c = mem[i] && ok;                    // contributes
+                            const double wd = c ? (double)(e[i].alpha * Tp[i]) : 0.0;
+                            // a zero weight leaves the colour unchanged
+                            C[p][0] = fma((double)rgb[i].x, wd, C[p][0]);
+                            C[p][1] = fma((double)rgb[i].y, wd, C[p][1]);
+                            C[p][2] = fma((double)rgb[i].z, wd, C[p][2]);
+                            last[p] = c ? pos[i] + 1u : last[p];
+                            Tc = ok ? Tp[i + 1] : Tc;
+                        }
+                        const bool stop = Tp[kStep] < kTMin;
+                        T[p] = Tc;
+                        done[p] = stop;
                     }
                     all = all && done[p];
                 }

@@ -52,6 +52,7 @@ def lib():
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_opacity_activation.argtypes = [ctypes.c_int]
+        L.oracle_set_sh_mask.argtypes = [P, i64, ctypes.c_double, P]
         L.oracle_render_pixels.argtypes = [P, i64, i64, i32, P, P, P, i64, P, P, P]
         _lib = L
     return _lib
@@ -81,6 +82,45 @@ class opacity_activation:
     def __exit__(self, *exc):
         lib().oracle_set_opacity_activation(0)
         return False
+
+
+class sh_mask:
+    """Context in which the rasterizer gates SH bands 1..3 of every Gaussian
+    with the hard masks of Section 3.3: M_l = 1 if sigmoid(logit_l) exceeds
+    `threshold`, else 0, multiplying each coefficient of band l (band 0 is
+    never masked).  render_backward inside the context also writes the
+    straight-through gradient dL/dlogit = dL/dM sigmoid'(logit) into
+    ``self.grad`` ([3, n]; frozen columns keep zero)."""
+
+    def __init__(self, logits, threshold):
+        self.logits = np.ascontiguousarray(logits, dtype=np.float64)
+        assert self.logits.ndim == 2 and self.logits.shape[0] == 3
+        self.threshold = float(threshold)
+        self.grad = np.zeros_like(self.logits)
+
+    def __enter__(self):
+        n = self.logits.shape[1]
+        lib().oracle_set_sh_mask(_ptr(self.logits), n, self.threshold,
+                                 _ptr(self.grad))
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_sh_mask(None, 0, 0.0, None)
+        return False
+
+
+def sh_band_gates(logits, threshold):
+    """Hard band gates M [3, n] (Section 3.3): 1 where sigmoid(logit) > threshold."""
+    return (1.0 / (1.0 + np.exp(-np.asarray(logits, np.float64))) > threshold).astype(np.float64)
+
+
+def sh_mask_reg(logits, lam):
+    """Sparsity term on the band masks, lam times the mean of sigmoid(logit)
+    over every Gaussian and band, and its gradient with respect to the
+    logits."""
+    x = np.asarray(logits, np.float64)
+    sg = 1.0 / (1.0 + np.exp(-x))
+    return lam * sg.mean(), lam * sg * (1.0 - sg) / x.size
 
 
 def opacity_to_absolute(params, m, v):

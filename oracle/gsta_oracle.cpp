@@ -163,6 +163,27 @@ struct Proj {
 // absolute value of row 10, used by the finetune stage.
 int g_opacity_act = 0;
 
+// SH-band masking (Section 3.3; learned only in the finetune stage): three
+// mask logits per Gaussian, one per SH band l = 1..3 (row l - 1 of a [3][ld]
+// block).  The forward uses the hard gate M_l = 1 if sigmoid(logit) > the
+// threshold, else 0, as a factor on every coefficient of band l (band 0 is
+// never masked); the backward takes the straight-through estimate
+// dL/dlogit = dL/dM_l sigmoid'(logit).  Off (nullptr) by default.
+const double* g_shm = nullptr;
+int64_t g_shm_ld = 0;
+double g_shm_threshold = 0.0;
+double* g_shm_grad = nullptr;      // [3][ld] output of the backward, or nullptr
+
+int sh_band(int k) { return k < 1 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3)); }
+
+double sigmoid(double x) { return 1.0 / (1.0 + std::exp(-x)); }
+
+// Gate of band l of Gaussian g.
+double band_gate(int64_t g, int l) {
+    if (!g_shm || l == 0) return 1.0;
+    return sigmoid(g_shm[(int64_t)(l - 1) * g_shm_ld + g]) > g_shm_threshold ? 1.0 : 0.0;
+}
+
 double frac_dist(double x) {   // distance of x to the nearest integer
     return std::fabs(x - std::nearbyint(x));
 }
@@ -212,7 +233,7 @@ void project(const double* P, int64_t n, int64_t ld, int degree, int64_t g, cons
     int K = (degree + 1) * (degree + 1);
     for (int ch = 0; ch < 3; ++ch) {
         double acc = 0;
-        for (int k = 0; k < K; ++k) acc += par(11 + 3 * k + ch) * p.B[k];
+        for (int k = 0; k < K; ++k) acc += band_gate(g, sh_band(k)) * par(11 + 3 * k + ch) * p.B[k];
         p.raw[ch] = acc + 0.5;
         p.clamped[ch] = p.raw[ch] < 0;
         p.rgb[ch] = p.clamped[ch] ? 0.0 : p.raw[ch];
@@ -374,7 +395,8 @@ void walk_pixel(const std::vector<Proj>& pr, const std::vector<int64_t>& list, d
 }
 
 // Chain rule from the 2-D quantities (u, v, conic, opacity, rgb) of one view
-// to every parameter of the Gaussian; adds into gsum[R].
+// to every parameter of the Gaussian; adds into gsum[R] (and, with band
+// masks, dL/dM of bands 1..3 into gsum[R .. R + 2]).
 void chain_to_params(const Proj& p, const Cam& cam, int degree, const double* P, int64_t ld, int64_t g,
                      const double* d2, double* gsum) {
     auto par = [&](int row) { return P[(int64_t)row * ld + g]; };
@@ -386,12 +408,20 @@ void chain_to_params(const Proj& p, const Cam& cam, int degree, const double* P,
     for (int ch = 0; ch < 3; ++ch) draw[ch] = p.clamped[ch] ? 0.0 : d2[6 + ch];
     double B[16], dB[16][3];
     sh_basis(degree, p.dn[0], p.dn[1], p.dn[2], B, dB);
+    // With band masks the coefficient is M_l f; gsum[R + l - 1] collects
+    // dL/dM_l = sum over band l's coefficients of dL/d(M_l f) f.
+    const int R = 11 + 3 * K;
     double ddn[3] = {0, 0, 0};
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+        const int l = sh_band(k);
+        const double M = band_gate(g, l);
         for (int ch = 0; ch < 3; ++ch) {
-            gsum[11 + 3 * k + ch] += draw[ch] * B[k];
-            for (int a = 0; a < 3; ++a) ddn[a] += draw[ch] * par(11 + 3 * k + ch) * dB[k][a];
+            const double f = par(11 + 3 * k + ch);
+            gsum[11 + 3 * k + ch] += M * draw[ch] * B[k];
+            if (g_shm && l > 0) gsum[R + l - 1] += draw[ch] * B[k] * f;
+            for (int a = 0; a < 3; ++a) ddn[a] += draw[ch] * M * f * dB[k][a];
         }
+    }
     double dot = ddn[0] * p.dn[0] + ddn[1] * p.dn[1] + ddn[2] * p.dn[2];
     for (int a = 0; a < 3; ++a) dmu[a] += (ddn[a] - p.dn[a] * dot) / p.dlen;
 
@@ -514,6 +544,16 @@ int oracle_num_threads() {
 
 // Selects the opacity activation of later calls (0 sigmoid, 1 absolute value).
 void oracle_set_opacity_activation(int act) { g_opacity_act = act ? 1 : 0; }
+
+// SH-band masks of later calls: logits [3][ld] (nullptr: off), the gate
+// threshold on sigmoid(logit), and where the backward writes dL/dlogit
+// ([3][ld], or nullptr).  The arrays must outlive the calls that use them.
+void oracle_set_sh_mask(const double* logits, int64_t ld, double threshold, double* grad_out) {
+    g_shm = logits;
+    g_shm_ld = ld;
+    g_shm_threshold = threshold;
+    g_shm_grad = grad_out;
+}
 
 // Sets the threads of later OpenMP loops (timing at 1 thread and at all cores).
 void oracle_set_threads(int n) {
@@ -653,7 +693,8 @@ int oracle_render_backward(const double* params, int64_t n, int64_t ld, int32_t 
                            const double* bg, const double* dL_dimage, const uint8_t* frozen,
                            double* grads, double* grad2d, uint8_t* visible_out) {
     const int R = 11 + 3 * (degree + 1) * (degree + 1);
-    std::vector<double> total((size_t)R * n, 0.0);
+    const int RX = R + 3;    // + the three band-mask gradients dL/dM_l
+    std::vector<double> total((size_t)RX * n, 0.0);
     std::vector<uint8_t> any_visible((size_t)n, 0);
     int64_t img_off = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -733,14 +774,19 @@ int oracle_render_backward(const double* params, int64_t n, int64_t ld, int32_t 
             if (frozen && frozen[g]) continue;
             double d[9], gs[64];
             for (int k = 0; k < 9; ++k) d[k] = d2[(size_t)k * n + g];
-            for (int k = 0; k < R; ++k) gs[k] = 0;
+            for (int k = 0; k < RX; ++k) gs[k] = 0;
             chain_to_params(pr[g], cam, degree, params, ld, g, d, gs);
-            for (int k = 0; k < R; ++k) total[(size_t)k * n + g] += gs[k];
+            for (int k = 0; k < RX; ++k) total[(size_t)k * n + g] += gs[k];
         }
     }
     for (int64_t g = 0; g < n; ++g) {
         if (frozen && frozen[g]) continue;
         for (int k = 0; k < R; ++k) grads[(size_t)k * ld + g] = total[(size_t)k * n + g];
+        if (g_shm && g_shm_grad)
+            for (int l = 1; l <= 3; ++l) {   // straight-through: dL/dlogit = dL/dM sigmoid'(logit)
+                const double sg = sigmoid(g_shm[(int64_t)(l - 1) * g_shm_ld + g]);
+                g_shm_grad[(int64_t)(l - 1) * g_shm_ld + g] = total[(size_t)(R + l - 1) * n + g] * sg * (1.0 - sg);
+            }
     }
     return 0;
 }

@@ -88,6 +88,18 @@ typedef struct {
                                    "absolute" activation of the finetune stage (Section 4.1),
                                    opacities above 1 allowed (alpha stays capped at 0.99) */
     float* block;               /* device, [R][ld] float32 */
+    float* sh_mask;             /* device, [3][ld] float32, or NULL (no masking).  SH-band masking of
+                                   the finetune stage (Section 3.3): in the parameters of a render
+                                   call, one logit per Gaussian and SH band l = 1..3 (row l - 1); band
+                                   l's coefficients are used where sigmoid(logit) > sh_mask_threshold
+                                   (decided as logit > ln(t / (1 - t)) rounded to float32) and count
+                                   as zero elsewhere; band 0 is never masked, bands above sh_degree
+                                   are ignored.  In the gradient block of gsta_render_backward (g
+                                   masked): receives dL/dlogit = dL/dM sigmoid'(logit), the
+                                   straight-through estimate of the hard mask M, for the Gaussians
+                                   whose parameter gradients it writes (NULL: not written).
+                                   Densification rejects masked parameters. */
+    float sh_mask_threshold;    /* gate threshold t on sigmoid(logit), in (0, 1); read with sh_mask */
 } gsta_params;
 
 /* Fields readable with gsta_get_state (after gsta_render_forward). */
@@ -288,6 +300,27 @@ typedef struct {
 gsta_status gsta_adam_masked_sched(gsta_ctx* ctx, gsta_params* p, const gsta_params* grad, gsta_params* m,
                                    gsta_params* v, gsta_adam_sched* sched, const uint8_t* frozen,
                                    hipStream_t stream);
+
+/* The same masked Adam step (Section 3.2.4) over any [rows][ld] float32 block
+ * of n columns, all four arrays with the same ld: the optimizer of the
+ * SH-band mask logits of the finetune stage (Section 3.3; rows = 3).  p,
+ * grad, m, v device; lr_per_row host [rows], rows in [1, 64]; frozen [n] or
+ * NULL (frozen columns bit-unchanged); step >= 1. */
+gsta_status gsta_adam_rows(gsta_ctx* ctx, float* p, const float* grad, float* m, float* v, int64_t n,
+                           int64_t ld, int32_t rows, const float* lr_per_row, float beta1, float beta2, float eps,
+                           int32_t step, const uint8_t* frozen, hipStream_t stream);
+
+/* Sparsity term of the SH-band masks (Section 3.3; the paper defers its
+ * form to the masking methods it adopts; this library takes their mean
+ * sigmoid): for logits [3][ld] (device) of n >= 1 Gaussians,
+ *   out[0] = lambda * mean over the 3n logits of sigmoid(logit),
+ *   out[1..3] = number of open gates of bands 1..3 (sigmoid(logit) > threshold,
+ *               decided as for rendering),
+ * and, if grad (device [3][ld]) is not NULL, grad += lambda sigmoid'(logit) /
+ * (3n) for every column with frozen[i] == 0 (frozen [n] or NULL).  out:
+ * device double [4].  Sums in a fixed order (deterministic). */
+gsta_status gsta_sh_mask_reg(gsta_ctx* ctx, const float* logits, int64_t n, int64_t ld, float threshold,
+                             float lambda, const uint8_t* frozen, float* grad, double* out, hipStream_t stream);
 
 /* Section 3.2.1, eqs. 4 and 6, with the accumulation and reset of the freeze
  * map.  cond_i = (score_xyz[i] < eps_xyz) && (score_rgb[i] < eps_rgb)

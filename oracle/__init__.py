@@ -14,6 +14,7 @@ section or equation it follows.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -110,8 +111,11 @@ class sh_mask:
 
 
 def sh_band_gates(logits, threshold):
-    """Hard band gates M [3, n] (Section 3.3): 1 where sigmoid(logit) > threshold."""
-    return (1.0 / (1.0 + np.exp(-np.asarray(logits, np.float64))) > threshold).astype(np.float64)
+    """Hard band gates M [3, n] (Section 3.3): 1 where sigmoid(logit) >
+    threshold, decided as the rasterizer does, float32 logit > float32
+    ln(t / (1 - t))."""
+    xt = np.float32(math.log(threshold / (1.0 - threshold)))
+    return (np.asarray(logits, np.float64).astype(np.float32) > xt).astype(np.float64)
 
 
 def sh_mask_reg(logits, lam):

@@ -178,10 +178,14 @@ int sh_band(int k) { return k < 1 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3)); }
 
 double sigmoid(double x) { return 1.0 / (1.0 + std::exp(-x)); }
 
-// Gate of band l of Gaussian g.
+// Gate of band l of Gaussian g.  sigmoid(logit) > t is the same test as
+// logit > ln(t / (1 - t)); the decision is taken in the rasterizer's
+// precision, the float32 logit against the float32-rounded threshold logit.
 double band_gate(int64_t g, int l) {
     if (!g_shm || l == 0) return 1.0;
-    return sigmoid(g_shm[(int64_t)(l - 1) * g_shm_ld + g]) > g_shm_threshold ? 1.0 : 0.0;
+    const float x = (float)g_shm[(int64_t)(l - 1) * g_shm_ld + g];
+    const float xt = (float)std::log(g_shm_threshold / (1.0 - g_shm_threshold));
+    return x > xt ? 1.0 : 0.0;
 }
 
 double frac_dist(double x) {   // distance of x to the nearest integer

@@ -35,7 +35,8 @@ class Camera(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
-                ("opacity_act", ctypes.c_int32), ("block", ctypes.c_void_p)]
+                ("opacity_act", ctypes.c_int32), ("block", ctypes.c_void_p), ("sh_mask", ctypes.c_void_p),
+                ("sh_mask_threshold", ctypes.c_float)]
 
 
 class AdamSched(ctypes.Structure):
@@ -74,7 +75,7 @@ EXPORTS = ["gsta_create", "gsta_reserve", "gsta_destroy", "gsta_last_error", "gs
            "gsta_update_freeze_mask", "gsta_partition_frozen", "gsta_l1_loss", "gsta_set_profiling", "gsta_read_profile", "gsta_set_option", "gsta_adam_masked_sched",
            "gsta_densify_prune", "gsta_opacity_reset", "gsta_traj_push", "gsta_mlp_feature_stats",
            "gsta_mlp_features", "gsta_mlp_forward", "gsta_mlp_bce", "gsta_mlp_backward", "gsta_mlp_adam",
-           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss", "gsta_opacity_to_absolute",
+           "gsta_mlp_sync_bf16", "gsta_mlp_propose", "gsta_l1_loss_noalloc", "gsta_update_freeze_mask_rule", "gsta_dssim_loss", "gsta_opacity_to_absolute", "gsta_adam_rows", "gsta_sh_mask_reg",
            "gsta_graph_begin", "gsta_graph_end", "gsta_graph_launch", "gsta_graph_destroy", "gsta_autotune"]
 
 MLP_PARAMS, MLP_BF16 = 6337, 6144
@@ -133,6 +134,8 @@ def load(path: str = LIB_PATH):
     L.gsta_l1_loss.argtypes = [P, P, P, i64, P, P, P]
     L.gsta_l1_loss_noalloc.argtypes = [P, P, i64, P, P, P]
     L.gsta_dssim_loss.argtypes = [P, P, P, i32, i32, i32, f32, P, P, P]
+    L.gsta_adam_rows.argtypes = [P, P, P, P, P, i64, i64, i32, ctypes.POINTER(f32), f32, f32, f32, i32, P, P]
+    L.gsta_sh_mask_reg.argtypes = [P, P, i64, i64, f32, f32, P, P, P, P]
     L.gsta_update_freeze_mask_rule.argtypes = [P, i32, P, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                                i32, P, P, P]
     L.gsta_set_profiling.argtypes = [P, i32]

@@ -47,9 +47,12 @@ def _arr(t, shape, dtype, name):
     return _ptr(t)
 
 
-def params_struct(block: torch.Tensor, degree: int, opacity_act: int = 0) -> Params:
+def params_struct(block: torch.Tensor, degree: int, opacity_act: int = 0, sh_mask: torch.Tensor | None = None,
+                  sh_mask_threshold: float = 0.0) -> Params:
     """[R, n] float32 device tensor (row stride = block.stride(0)); opacity_act
-    1 selects the finetune stage's absolute opacity activation."""
+    1 selects the finetune stage's absolute opacity activation.  sh_mask: the
+    [3, n] float32 SH-band mask logits (or, for a gradient block, where their
+    gradient goes), with the block's row stride; sh_mask_threshold in (0, 1)."""
     if block.dtype != torch.float32 or block.dim() != 2:
         raise ValueError("parameter blocks are [R, n] float32")
     if block.shape[0] != n_rows(degree):
@@ -59,7 +62,14 @@ def params_struct(block: torch.Tensor, degree: int, opacity_act: int = 0) -> Par
         return Params(n=0, ld=1, sh_degree=degree, opacity_act=opacity_act, block=block.data_ptr() or None)
     if block.stride(1) != 1 or block.stride(0) < n:
         raise ValueError("parameter blocks need unit column stride and row stride >= n")
-    return Params(n=n, ld=block.stride(0), sh_degree=degree, opacity_act=opacity_act, block=block.data_ptr())
+    ps = Params(n=n, ld=block.stride(0), sh_degree=degree, opacity_act=opacity_act, block=block.data_ptr())
+    if sh_mask is not None:
+        if (sh_mask.dtype != torch.float32 or sh_mask.dim() != 2 or tuple(sh_mask.shape) != (3, n)
+                or sh_mask.stride(1) != 1 or sh_mask.stride(0) != block.stride(0) or sh_mask.device != block.device):
+            raise ValueError("SH-band masks are [3, n] float32 with the parameter block's row stride")
+        ps.sh_mask = sh_mask.data_ptr()
+        ps.sh_mask_threshold = float(sh_mask_threshold)
+    return ps
 
 
 def camera_struct(cam) -> Camera:
@@ -229,8 +239,9 @@ class Context:
         return {name: (ms[i], ln[i]) for i, name in enumerate(_lib.PHASES)}, tuple(pr)
 
     # ---- hot path --------------------------------------------------------
-    def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None, opacity_act=0):
-        ps = params_struct(params, degree, opacity_act)
+    def render_forward(self, params, degree, cams, bg, image, slot=0, stream=None, opacity_act=0, sh_mask=None,
+                       sh_mask_threshold=0.0):
+        ps = params_struct(params, degree, opacity_act, sh_mask, sh_mask_threshold)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         shape = (len(ca), 3, ca[0].height, ca[0].width)
         check(self.h, self.L.gsta_render_forward(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
@@ -238,10 +249,10 @@ class Context:
                                                   _stream(stream)))
 
     def render_forward_l1(self, params, degree, cams, bg, target, image, dL_dimage, sums, slot=0, stream=None,
-                          opacity_act=0):
+                          opacity_act=0, sh_mask=None, sh_mask_threshold=0.0):
         """render_forward with the L1 loss against `target` fused into the
         compositing: dL_dimage and sums as l1_loss gives them."""
-        ps = params_struct(params, degree, opacity_act)
+        ps = params_struct(params, degree, opacity_act, sh_mask, sh_mask_threshold)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         shape = (len(ca), 3, ca[0].height, ca[0].width)
         check(self.h, self.L.gsta_render_forward_l1(
@@ -250,9 +261,12 @@ class Context:
             _arr(sums, (2,), torch.float64, "sums"), slot, _stream(stream)))
 
     def render_backward(self, params, degree, cams, bg, slot, dL_dimage, frozen, grad,
-                        grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None, opacity_act=0):
-        ps = params_struct(params, degree, opacity_act)
-        gs = params_struct(grad, degree)
+                        grad2d=None, ema=None, ema_beta=0.9, dstats=None, stream=None, opacity_act=0,
+                        sh_mask=None, sh_mask_threshold=0.0, sh_mask_grad=None):
+        """sh_mask (the forward's band-mask logits) also writes dL/dlogit into
+        sh_mask_grad ([3, n], the gradient block's row stride) when given."""
+        ps = params_struct(params, degree, opacity_act, sh_mask, sh_mask_threshold)
+        gs = params_struct(grad, degree, 0, sh_mask_grad)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         V, n = len(ca), ps.n
         check(self.h, self.L.gsta_render_backward(
@@ -261,6 +275,34 @@ class Context:
             _arr(frozen, (n,), torch.uint8, "frozen"), ctypes.byref(gs),
             _arr(grad2d, (V, 9, n), torch.float32, "grad2d"), _arr(ema, (4, n), torch.float32, "ema"),
             float(ema_beta), _arr(dstats, (4, n), torch.float32, "dstats"), _stream(stream)))
+
+    def adam_rows(self, p, g, m, v, lr_rows, beta1, beta2, eps, step, frozen=None, stream=None):
+        """Masked Adam over a [rows, n] float32 block (p, g, m, v alike), e.g.
+        the SH-band mask logits."""
+        rows, n = p.shape
+        for x, nm in ((g, "grad"), (m, "m"), (v, "v")):
+            if tuple(x.shape) != (rows, n) or x.stride() != p.stride() or x.dtype != torch.float32:
+                raise ValueError(f"{nm} must match p in shape, strides and dtype")
+        if p.stride(1) != 1:
+            raise ValueError("p needs unit column stride")
+        lr = (ctypes.c_float * rows)(*[float(x) for x in lr_rows])
+        check(self.h, self.L.gsta_adam_rows(self.h, p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), n,
+                                            p.stride(0), rows, lr, float(beta1), float(beta2), float(eps),
+                                            int(step), _arr(frozen, (n,), torch.uint8, "frozen"),
+                                            _stream(stream)))
+
+    def sh_mask_reg(self, logits, threshold, lam, out, frozen=None, grad=None, stream=None):
+        """Sparsity term of the SH-band masks: out (float64 [4]) <- [lam *
+        mean sigmoid, open gates of bands 1..3]; grad += its gradient."""
+        rows, n = logits.shape
+        if rows != 3 or logits.dtype != torch.float32 or logits.stride(1) != 1:
+            raise ValueError("logits are [3, n] float32 with unit column stride")
+        if grad is not None and (grad.shape != logits.shape or grad.stride() != logits.stride()):
+            raise ValueError("grad must match logits in shape and strides")
+        check(self.h, self.L.gsta_sh_mask_reg(self.h, logits.data_ptr(), n, logits.stride(0), float(threshold),
+                                              float(lam), _arr(frozen, (n,), torch.uint8, "frozen"),
+                                              None if grad is None else grad.data_ptr(),
+                                              _arr(out, (4,), torch.float64, "out"), _stream(stream)))
 
     def adam_masked(self, p, g, m, v, degree, lr_rows, beta1, beta2, eps, step, frozen=None, stream=None):
         R = n_rows(degree)

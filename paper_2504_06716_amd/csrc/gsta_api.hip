@@ -52,6 +52,8 @@ struct Slot {
     int64_t n = 0, ld = 0;
     int degree = 0;
     const float* block = nullptr;
+    const float* sh_mask = nullptr;
+    float sh_mask_threshold = 0.f;
     int nv = 0;
     gsta_camera cams[kMaxViews];
     float bg[3] = {0.f, 0.f, 0.f};
@@ -98,6 +100,7 @@ struct gsta_ctx {
     uint32_t* part_tot = nullptr;  // [1] active count of the partition
     float* ssim_g = nullptr;       // [3][max_views * 3 * H * W] D-SSIM partial-derivative maps
     double* ssim_part = nullptr;   // [ssim_blocks] per-workgroup SSIM sums
+    double* shm_part = nullptr;    // [4][ceil(max_gaussians / 256)] SH-mask term partials
     SelState* sel = nullptr;       // [1] radix-select state of the mingrad freezing rule
     uint32_t* sel_blk = nullptr;   // [ceil(max_gaussians / 256)] equal-key counts per block
     float* mlp_part = nullptr;     // [kMlpBlocks][kMlpCount] proposer gradient partials
@@ -233,6 +236,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->sel, 1) && alloc(ctx, &ctx->sel_blk, (l->max_gaussians + 255) / 256) &&
          alloc(ctx, &ctx->ssim_g, 3 * V * 3 * HW) &&
          alloc(ctx, &ctx->ssim_part, ssim_blocks((int)V, l->max_height, l->max_width)) &&
+         alloc(ctx, &ctx->shm_part, 4 * ((l->max_gaussians + 255) / 256) + 4) &&
          alloc(ctx, &ctx->mlp_part, (int64_t)kMlpBlocks * kMlpCount) &&
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->os_tot, V * 4 * 256) && alloc(ctx, &ctx->os_tickets, V * 4) &&
@@ -315,6 +319,26 @@ gsta_status check_params(gsta_ctx* ctx, const gsta_params* g, const char* name) 
     if (g->opacity_act != 0 && g->opacity_act != 1)
         return fail(ctx, GSTA_ERR_INVALID, "%s.opacity_act must be 0 (sigmoid) or 1 (absolute)", name);
     return GSTA_OK;
+}
+
+// The SH-band masks of the parameters of a render call.
+gsta_status check_sh_mask(gsta_ctx* ctx, const gsta_params* g) {
+    if (g->sh_mask && !(g->sh_mask_threshold > 0.f && g->sh_mask_threshold < 1.f))
+        return fail(ctx, GSTA_ERR_INVALID, "g.sh_mask_threshold must be in (0, 1)");
+    return GSTA_OK;
+}
+
+// The band gates of g: sigmoid(logit) > t taken as logit > ln(t / (1 - t)),
+// the threshold's logit rounded once to float32.
+ShMask sh_mask_of(const gsta_params* g, float* grad_out) {
+    ShMask m;
+    if (g->sh_mask) {
+        const double t = (double)g->sh_mask_threshold;
+        m.logit = g->sh_mask;
+        m.thr_logit = (float)std::log(t / (1.0 - t));
+        m.grad = grad_out;
+    }
+    return m;
 }
 
 gsta_status check_views(gsta_ctx* ctx, const gsta_camera* cams, int32_t nv, CamArray& ca) {
@@ -604,6 +628,7 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     gsta_status st;
     if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    if ((st = check_sh_mask(ctx, g)) != GSTA_OK) return st;
     CamArray ca;
     if ((st = check_views(ctx, cams, n_views, ca)) != GSTA_OK) return st;
     if (!bg) return fail(ctx, GSTA_ERR_INVALID, "bg is NULL");
@@ -623,7 +648,8 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
-                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, g->opacity_act, stream);
+                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, g->opacity_act,
+                              sh_mask_of(g, nullptr), stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
@@ -690,6 +716,8 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     s.ld = g->ld;
     s.degree = g->sh_degree;
     s.block = g->block;
+    s.sh_mask = g->sh_mask;
+    s.sh_mask_threshold = g->sh_mask_threshold;
     s.nv = nv;
     for (int v = 0; v < nv; ++v) s.cams[v] = cams[v];
     for (int c = 0; c < 3; ++c) s.bg[c] = bg[c];
@@ -726,6 +754,7 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     gsta_status st;
     if ((st = check_params(ctx, g, "g")) != GSTA_OK) return st;
+    if ((st = check_sh_mask(ctx, g)) != GSTA_OK) return st;
     if ((st = check_params(ctx, grad, "grad")) != GSTA_OK) return st;
     CamArray ca;
     if ((st = check_views(ctx, cams, n_views, ca)) != GSTA_OK) return st;
@@ -739,7 +768,8 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     if (!s.valid) return fail(ctx, GSTA_ERR_INVALID, "state_slot %d holds no forward state", state_slot);
     bool same = s.n == g->n && s.ld == g->ld && s.degree == g->sh_degree && s.block == g->block && s.nv == n_views &&
                 memcmp(s.cams, cams, sizeof(gsta_camera) * n_views) == 0 && s.bg[0] == bg[0] && s.bg[1] == bg[1] &&
-                s.bg[2] == bg[2];
+                s.bg[2] == bg[2] && s.sh_mask == g->sh_mask &&
+                (!g->sh_mask || s.sh_mask_threshold == g->sh_mask_threshold);
     if (!same) return fail(ctx, GSTA_ERR_INVALID, "backward arguments differ from the forward in slot %d", state_slot);
     const int64_t n = g->n, S = ctx->stride;
     const int nv = n_views;
@@ -753,9 +783,8 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
         launch_preprocess_bwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.rect, s.inst_off, S, ctx->tile_grads,
                               ctx->stamps, ctx->gen, s.n_count, frozen, ctx->d2sum, grad->block,
-                              grad->ld, ema,
-                              ema_beta, grad2d,
-                              dstats, g->opacity_act, stream);
+                              grad->ld, ema, ema_beta, grad2d, dstats, g->opacity_act,
+                              sh_mask_of(g, grad->sh_mask), stream);
     }
     return hip_check(ctx, hipGetLastError(), "render_backward launch");
 }
@@ -837,6 +866,46 @@ gsta_status gsta_dssim_loss(gsta_ctx* ctx, const float* image, const float* targ
     launch_dssim(image, target, n_views, height, width, lambda, dL_dimage, ssim_sum, ctx->ssim_g, ctx->ssim_part,
                  stream);
     return hip_check(ctx, hipGetLastError(), "dssim launch");
+}
+
+gsta_status gsta_adam_rows(gsta_ctx* ctx, float* p, const float* grad, float* m, float* v, int64_t n,
+                           int64_t ld, int32_t rows, const float* lr_per_row, float beta1, float beta2, float eps,
+                           int32_t step, const uint8_t* frozen, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (n < 0 || n > ctx->lim.max_gaussians)
+        return fail(ctx, GSTA_ERR_INVALID, "n = %lld outside [0, max_gaussians = %lld]", (long long)n,
+                    (long long)ctx->lim.max_gaussians);
+    if (ld < n || ld < 1) return fail(ctx, GSTA_ERR_INVALID, "ld < n");
+    if (rows < 1 || rows > 64) return fail(ctx, GSTA_ERR_INVALID, "rows must be in [1, 64]");
+    if (n > 0 && (!p || !grad || !m || !v)) return fail(ctx, GSTA_ERR_INVALID, "NULL p, grad, m or v");
+    if (!lr_per_row) return fail(ctx, GSTA_ERR_INVALID, "lr_per_row is NULL");
+    if (step < 1) return fail(ctx, GSTA_ERR_INVALID, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(ctx, GSTA_ERR_INVALID, "betas must be in [0, 1) and eps >= 0");
+    LrArray lr;
+    for (int r = 0; r < 64; ++r) lr.lr[r] = r < rows ? lr_per_row[r] : 0.f;
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    PhaseTimer pt(ctx, GSTA_PHASE_ADAM, stream);
+    if (n > 0) launch_adam(p, ld, grad, ld, m, ld, v, ld, n, rows, lr, beta1, beta2, eps, bc1, bc2, frozen, ctx->flags, stream);
+    return hip_check(ctx, hipGetLastError(), "adam_rows launch");
+}
+
+gsta_status gsta_sh_mask_reg(gsta_ctx* ctx, const float* logits, int64_t n, int64_t ld, float threshold,
+                             float lambda, const uint8_t* frozen, float* grad, double* out, hipStream_t stream) {
+    if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
+    if (n < 1 || n > ctx->lim.max_gaussians)
+        return fail(ctx, GSTA_ERR_INVALID, "n = %lld outside [1, max_gaussians = %lld]", (long long)n,
+                    (long long)ctx->lim.max_gaussians);
+    if (ld < n) return fail(ctx, GSTA_ERR_INVALID, "ld < n");
+    if (!(threshold > 0.f && threshold < 1.f)) return fail(ctx, GSTA_ERR_INVALID, "threshold must be in (0, 1)");
+    if (!(lambda >= 0.f)) return fail(ctx, GSTA_ERR_INVALID, "lambda must be >= 0");
+    if (!logits || !out) return fail(ctx, GSTA_ERR_INVALID, "NULL logits or out");
+    const double t = (double)threshold;
+    PhaseTimer pt(ctx, GSTA_PHASE_LOSS, stream);
+    launch_sh_mask_reg(logits, n, ld, (float)std::log(t / (1.0 - t)), lambda, frozen, grad, ctx->shm_part, out,
+                       stream);
+    return hip_check(ctx, hipGetLastError(), "sh_mask_reg launch");
 }
 
 gsta_status gsta_update_freeze_mask_rule(gsta_ctx* ctx, int32_t rule, const float* score, int64_t n,
@@ -928,6 +997,8 @@ gsta_status gsta_densify_prune(gsta_ctx* ctx, const gsta_params* g, const gsta_p
     const int D = g->sh_degree;
     if (g->opacity_act != 0)
         return fail(ctx, GSTA_ERR_INVALID, "densification prunes by the opacity logit: g.opacity_act must be 0");
+    if (g->sh_mask)
+        return fail(ctx, GSTA_ERR_INVALID, "densification does not carry SH-band masks (a finetune-stage parameter)");
     for (int k = 0; k < 3; ++k) {
         if (in[k]->n != n || in[k]->sh_degree != D || out[k]->sh_degree != D || out[k]->n != cap)
             return fail(ctx, GSTA_ERR_INVALID, "g, m, v must share n; outputs share the capacity; one sh_degree");

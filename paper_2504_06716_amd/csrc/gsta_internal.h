@@ -103,10 +103,26 @@ __device__ __forceinline__ float wave_sum(float x) {
 // hist0 (optional, [nv][256][ceil(n/256)]): the depth sort's first-pass
 // chunk histograms (chunks of 256 keys), for radix_sort_pairs with
 // first_hist_given.
+// SH-band masks of the finetune stage (Section 3.3): logits [3][ld] (same
+// ld as the parameters) or null, the gate threshold as a logit, and the
+// backward's output dL/dlogit ([3][gld], or null).
+struct ShMask {
+    const float* logit = nullptr;
+    float thr_logit = 0.f;
+    float* grad = nullptr;
+};
+
+// The sparsity term of the SH-band masks (Section 3.3): out[0] = lambda *
+// mean sigmoid(logit) over the 3 n logits, out[1..3] = open gates of bands
+// 1..3 (logit > thr_logit); grad (if not null) += lambda sigmoid'(logit) /
+// (3 n) for every non-frozen column.  part: [4][ceil(n / 256)] scratch.
+void launch_sh_mask_reg(const float* logits, int64_t n, int64_t ld, float thr_logit, float lambda,
+                        const uint8_t* frozen, float* grad, double* part, double* out, hipStream_t s);
+
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
                            uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
-                           hipStream_t s);
+                           const ShMask& sm, hipStream_t s);
 
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
 // expansion offsets inst_off[v][gid], in tile order, taking a slot only if
@@ -119,7 +135,7 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
                            const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, int opact,
-                           hipStream_t s);
+                           const ShMask& sm, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs, `nseg` independent segments of
 // seg_stride elements; element count per segment from d_count (device, if

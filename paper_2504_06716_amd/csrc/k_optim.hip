@@ -191,7 +191,71 @@ __global__ __launch_bounds__(256) void k_l1_final(const double2* __restrict__ pa
     }
 }
 
+// SH-band mask sparsity (Section 3.3): per Gaussian its three logits' sigmoid
+// sum and open-gate counts, block totals in LDS, one partial per block.
+__global__ __launch_bounds__(256) void k_shm_reg(const float* __restrict__ logits, int64_t n, int64_t ld,
+                                                 float thr, float scale, const uint8_t* __restrict__ frozen,
+                                                 float* __restrict__ grad, double* __restrict__ part, int nb) {
+    __shared__ double s_v[4][256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n) {
+        const bool upd = grad && !(frozen && frozen[i]);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const float x = logits[l * ld + i];
+            const float sg = 1.0f / (1.0f + expf(-x));
+            acc[0] += (double)sg;
+            acc[1 + l] = x > thr ? 1.0 : 0.0;
+            if (upd) grad[l * ld + i] += scale * (sg * (1.0f - sg));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {   // fixed-order tree
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] += s_v[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[(int64_t)threadIdx.x * nb + blockIdx.x] = s_v[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_shm_reg_final(const double* __restrict__ part, int nb, double scale,
+                                                       double* __restrict__ out) {
+    __shared__ double s_v[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = (int)threadIdx.x; b < nb; b += 256)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += part[(int64_t)q * nb + b];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] += s_v[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = scale * s_v[0][0];
+        out[1] = s_v[1][0];
+        out[2] = s_v[2][0];
+        out[3] = s_v[3][0];
+    }
+}
+
 }  // namespace
+
+void launch_sh_mask_reg(const float* logits, int64_t n, int64_t ld, float thr_logit, float lambda,
+                        const uint8_t* frozen, float* grad, double* part, double* out, hipStream_t s) {
+    const int nb = (int)((n + 255) / 256);
+    const double mean = 1.0 / (3.0 * (double)n);
+    k_shm_reg<<<(unsigned)nb, 256, 0, s>>>(logits, n, ld, thr_logit, (float)((double)lambda * mean), frozen, grad,
+                                           part, nb);
+    k_shm_reg_final<<<1, 256, 0, s>>>(part, nb, (double)lambda * mean, out);
+}
 
 void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                  int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,

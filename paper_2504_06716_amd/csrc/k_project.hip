@@ -186,6 +186,18 @@ __device__ __forceinline__ void load_core(const float* __restrict__ P, int64_t l
     o = opact ? fabsf(x) : 1.0f / (1.0f + expf(-x));
 }
 
+// SH-band masks (Section 3.3): band l = 1..D of Gaussian i is kept where its
+// logit exceeds the threshold's logit (sigmoid(logit) > threshold), else its
+// coefficients count as zero.  gate[l] is 1 or 0 (gate[0] = 1).
+template <int D>
+__device__ __forceinline__ void band_gates(const ShMask& sm, int64_t ld, int64_t i, float* gate) {
+    gate[0] = 1.f;
+#pragma unroll
+    for (int l = 1; l <= D; ++l) gate[l] = (sm.logit && !(sm.logit[(l - 1) * ld + i] > sm.thr_logit)) ? 0.f : 1.f;
+}
+
+__device__ __forceinline__ constexpr int sh_band(int k) { return k < 1 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3)); }
+
 template <int D>
 // hist0 (optional): the depth sort's first-pass (low 8 bits) digit counts of
 // the block's keys -- its 256 Gaussians are the sort's first chunk --
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     float4* __restrict__ geo, float4* __restrict__ col, float4* __restrict__ rgbo,
     ushort4* __restrict__ rect, uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch, int opact) {
+    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch, int opact, ShMask sm) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ uint32_t s_h[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,10 +216,12 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
     float f[K][3];
     if (valid) {
         load_core(P, ld, i, mu, s, qn, Rq, qinv, o, opact);
+        float gate[D + 1];
+        band_gates<D>(sm, ld, i, gate);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) f[k][ch] = P[(11 + 3 * k + ch) * ld + i];
+            for (int ch = 0; ch < 3; ++ch) f[k][ch] = gate[sh_band(k)] * P[(11 + 3 * k + ch) * ld + i];
     }
 
     for (int v = 0; v < nv; ++v) {
@@ -377,7 +391,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const ushort4* __restrict__ rect, int64_t stride, const float* __restrict__ d2sum,
     const uint8_t* __restrict__ frozen,
     float* __restrict__ G, int64_t gld, float* __restrict__ ema, float beta, float* __restrict__ grad2d_out,
-    float* __restrict__ dstats, uint32_t* __restrict__ genp, int opact) {
+    float* __restrict__ dstats, uint32_t* __restrict__ genp, int opact, ShMask sm) {
     constexpr int K = (D + 1) * (D + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // Every reader of this backward's generation (the compositing backward
@@ -388,11 +402,17 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     if (frozen && frozen[i]) return;
     float mu[3], s[3], qn[4], Rq[9], qinv, o;
     load_core(P, ld, i, mu, s, qn, Rq, qinv, o, opact);
-    float f[K][3];
+    // f: the coefficients as used (a closed band's are zero); fr: as stored
+    float gate[D + 1];
+    band_gates<D>(sm, ld, i, gate);
+    float f[K][3], fr[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) f[k][ch] = P[(11 + 3 * k + ch) * ld + i];
+        for (int ch = 0; ch < 3; ++ch) {
+            fr[k][ch] = P[(11 + 3 * k + ch) * ld + i];
+            f[k][ch] = gate[sh_band(k)] * fr[k][ch];
+        }
 
     float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gqn[4] = {0.f, 0.f, 0.f, 0.f};
     float glogit = 0.f;
@@ -545,10 +565,25 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
     for (int k = 0; k < 4; ++k) G[(6 + k) * gld + i] = (gqn[k] - qn[k] * qd) * qinv;
     G[10 * gld + i] = glogit;
+    // gsh is dL/d(gate f): a stored coefficient gets it times its gate, and
+    // each band's logit the straight-through dL/dgate sigmoid'(logit)
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) G[(11 + 3 * k + ch) * gld + i] = gsh[k][ch];
+        for (int ch = 0; ch < 3; ++ch) G[(11 + 3 * k + ch) * gld + i] = gate[sh_band(k)] * gsh[k][ch];
+    if (sm.logit && sm.grad) {
+#pragma unroll
+        for (int l = 1; l <= D; ++l) {
+            float dM = 0.f;
+#pragma unroll
+            for (int k = l * l; k < (l + 1) * (l + 1); ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dM += gsh[k][ch] * fr[k][ch];
+            const float x = sm.logit[(l - 1) * ld + i];
+            const float sg = 1.0f / (1.0f + expf(-x));
+            sm.grad[(l - 1) * gld + i] = dM * (sg * (1.0f - sg));
+        }
+    }
 
     if (dstats && any_vis) {
         dstats[i] += dsum;
@@ -575,10 +610,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
                            uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
-                           hipStream_t s) {
+                           const ShMask& sm, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     const int64_t hp = (n + 255) / 256;
-#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp, opact
+#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp, opact, sm
     switch (degree) {
         case 0: k_preprocess_fwd<0><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
         case 1: k_preprocess_fwd<1><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
@@ -593,11 +628,11 @@ void launch_preprocess_bwd(const float* P, int64_t ld, int64_t n, int degree, co
                            const float* partials, const uint32_t* stamps, uint32_t* gen,
                            const uint32_t* d_count, const uint8_t* frozen, float* d2sum, float* G,
                            int64_t gld, float* ema, float beta, float* grad2d_out, float* dstats, int opact,
-                           hipStream_t s) {
+                           const ShMask& sm, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     k_sum_partials<<<dim3((unsigned)((n + kSumRows - 1) / kSumRows), (unsigned)nv), block, 0, s>>>(
         rect, inst_off, stride, n, partials, stamps, gen, d_count, frozen, d2sum);
-#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats, gen, opact
+#define GSTA_BWD_ARGS P, ld, n, cams, nv, rect, stride, d2sum, frozen, G, gld, ema, beta, grad2d_out, dstats, gen, opact, sm
     switch (degree) {
         case 0: k_preprocess_bwd<0><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;
         case 1: k_preprocess_bwd<1><<<grid, block, 0, s>>>(GSTA_BWD_ARGS); break;

@@ -25,7 +25,8 @@ def dev(a):
 class GpuScene:
     """One parameter block + cameras rendered through libgsta."""
 
-    def __init__(self, params, degree, cams, bg=(0.0, 0.0, 0.0), capacity=1 << 22, ctx=None, opacity_act=0):
+    def __init__(self, params, degree, cams, bg=(0.0, 0.0, 0.0), capacity=1 << 22, ctx=None, opacity_act=0,
+                 sh_mask=None, sh_mask_threshold=0.0):
         import torch
         import paper_2504_06716_amd as G
         self.torch = torch
@@ -40,11 +41,16 @@ class GpuScene:
         self.carr = G.camera_array(cams)
         self.R = params.shape[0]
         self.opacity_act = opacity_act
+        # SH-band mask logits [3, n] (same row stride as the contiguous block)
+        self.M = None if sh_mask is None else dev(np.ascontiguousarray(sh_mask, np.float32))
+        self.thr = sh_mask_threshold
+        self.mask_grad = None
 
     def forward(self):
         t = self.torch
         img = t.empty((self.V, 3, self.H, self.W), dtype=t.float32, device="cuda")
-        self.ctx.render_forward(self.P, self.degree, self.carr, self.bg, img, 0, opacity_act=self.opacity_act)
+        self.ctx.render_forward(self.P, self.degree, self.carr, self.bg, img, 0, opacity_act=self.opacity_act,
+                                sh_mask=self.M, sh_mask_threshold=self.thr)
         t.cuda.synchronize()
         self.image = img
         return img.cpu().numpy()
@@ -63,9 +69,12 @@ class GpuScene:
         g2 = t.zeros((self.V, 9, self.n), dtype=t.float32, device="cuda")
         fz = None if frozen is None else dev(frozen.astype(np.uint8))
         em = None if ema is None else dev(ema.astype(np.float32))
+        mg = None if self.M is None else t.full((3, self.n), float("nan"), dtype=t.float32, device="cuda")
         self.ctx.render_backward(self.P, self.degree, self.carr, self.bg, 0, dev(dL.astype(np.float32)),
-                                 fz, grad, g2, em, beta, opacity_act=self.opacity_act)
+                                 fz, grad, g2, em, beta, opacity_act=self.opacity_act, sh_mask=self.M,
+                                 sh_mask_threshold=self.thr, sh_mask_grad=mg)
         t.cuda.synchronize()
+        self.mask_grad = None if mg is None else mg.cpu().numpy()
         return grad.cpu().numpy(), g2.cpu().numpy(), (None if em is None else em.cpu().numpy())
 
 

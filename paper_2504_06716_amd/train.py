@@ -61,6 +61,11 @@ class TrainConfig:
     fused_loss: bool = True              # L1 loss computed by the forward compositing (else a separate pass)
     lambda_ssim: float = 0.0             # eq. 3: L = (1 - lambda) L1 + lambda D-SSIM (the paper uses 0.2)
     abs_opacity_finetune: bool = False   # Section 4.1: opacity = |x| instead of sigmoid once the finetune starts
+    sh_mask_finetune: bool = False       # Section 3.3: learn hard SH-band masks during the finetune (+small variant)
+    sh_mask_threshold: float = 0.01      # gate: sigmoid(logit) > threshold
+    sh_mask_init: float = 2.0            # initial logits (every gate open)
+    sh_mask_lr: float = 0.01             # Adam learning rate of the logits
+    sh_mask_lambda: float = 5e-4         # weight of the masks' sparsity term (mean sigmoid)
 
 
 class Trainer:
@@ -119,6 +124,15 @@ class Trainer:
         self.sums = torch.zeros(2, dtype=torch.float64, device="cuda")
         self.ssim_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.opacity_act = 0                 # 1 after the finetune's switch to the absolute activation
+        # SH-band masks (logits, gradient, moments; [3, n] views of capacity-sized
+        # storage), allocated and switched on when the finetune starts
+        self.shm = None
+        self.shm_step = 0
+        self.shm_out = torch.zeros(4, dtype=torch.float64, device="cuda")
+        if cfg.sh_mask_finetune and cfg.graph:
+            raise ValueError("the SH-band masks' Adam takes a host step count: no graph capture with them")
+        if cfg.sh_mask_finetune and not (0.0 < cfg.sh_mask_threshold < 1.0):
+            raise ValueError("sh_mask_threshold must be in (0, 1)")
         self.step_count = 0
         self.k = 0
         self.psnrs: list[float] = []
@@ -178,6 +192,8 @@ class Trainer:
         if ds is None:
             return
         if ds.densify_now(k, self.stop_iter):
+            if self.shm is not None:
+                raise ValueError("densification after the SH-band masks started: the masks do not follow it")
             ex, er = ds.thresholds(k, ds.end(self.stop_iter))
             use_rgb = bool(self.dens_rng.random() < ds.rgb_prob)
             # the split children's normals are drawn in the kernel from Philox (seed, iteration, column)
@@ -312,16 +328,25 @@ class Trainer:
             torch.index_select(self.targets, 0, idx, out=self.tgt_batch)
             tgt = self.tgt_batch
         act = self.opacity_act
+        mk = {} if self.shm is None else dict(sh_mask=self.shm["x"], sh_mask_threshold=cfg.sh_mask_threshold)
         if cfg.fused_loss:
             self.ctx.render_forward_l1(self.P, self.degree, cam, cfg.bg, tgt, self.image, self.dL, self.sums, 0,
-                                       opacity_act=act)
+                                       opacity_act=act, **mk)
         else:
-            self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0, opacity_act=act)
+            self.ctx.render_forward(self.P, self.degree, cam, cfg.bg, self.image, 0, opacity_act=act, **mk)
             self.ctx.l1_loss(self.image, tgt, self.dL, self.sums)
         if cfg.lambda_ssim > 0.0:
             self.ctx.dssim_loss(self.image, tgt, cfg.lambda_ssim, self.dL, self.ssim_sum)
         self.ctx.render_backward(self.P, self.degree, cam, cfg.bg, 0, self.dL, frz, self.G, None, ema,
-                                 cfg.ema_beta, dstats=self.dstats, opacity_act=act)
+                                 cfg.ema_beta, dstats=self.dstats, opacity_act=act,
+                                 sh_mask_grad=None if self.shm is None else self.shm["g"], **mk)
+        if self.shm is not None:
+            # the masks' sparsity term adds its gradient; then their own Adam step
+            self.shm_step += 1
+            self.ctx.sh_mask_reg(self.shm["x"], cfg.sh_mask_threshold, cfg.sh_mask_lambda, self.shm_out,
+                                 frozen=frz, grad=self.shm["g"])
+            self.ctx.adam_rows(self.shm["x"], self.shm["g"], self.shm["m"], self.shm["v"], [cfg.sh_mask_lr] * 3,
+                               cfg.beta1, cfg.beta2, cfg.adam_eps, self.shm_step, frz)
         if self.use_sched:
             self.ctx.adam_masked_sched(self.P, self.G, self.M, self.Vm, self.degree, self.sched, frz)
         else:
@@ -339,6 +364,11 @@ class Trainer:
             self.ctx.opacity_to_absolute(self.P, self.M, self.Vm, self.degree)
             self.opacity_act = 1
             self._drop_graphs()                      # the captured calls carry the old activation
+        if cfg.sh_mask_finetune and self.shm is None and k >= self.window_close():
+            # the finetune starts: every Gaussian's three band masks, all open
+            # (the parameter block's row stride, which the library requires of them)
+            self.shm = {nm: _padded(3, self.cap)[:, :self.n] for nm in ("x", "g", "m", "v")}
+            self.shm["x"].fill_(cfg.sh_mask_init)
         if self.traj is not None:
             self.traj.maybe_push(k, self.ema)
         self._freeze_step(k)
@@ -428,8 +458,23 @@ class Trainer:
             for b in range(0, len(views), vmax):
                 vs = views[b:b + vmax]
                 self.ctx.render_forward(self.P, self.degree, [self.cams[v] for v in vs], self.cfg.bg,
-                                        out[b:b + len(vs)], 0, opacity_act=self.opacity_act)
+                                        out[b:b + len(vs)], 0, opacity_act=self.opacity_act,
+                                        **({} if self.shm is None else dict(
+                                            sh_mask=self.shm["x"], sh_mask_threshold=self.cfg.sh_mask_threshold)))
         return out
+
+    def sh_mask_stats(self) -> dict | None:
+        """The SH-band masks after the last step: the sparsity term, open
+        gates per band, and the SH coefficients a stored model keeps
+        (closed bands pruned) as a fraction of all of them."""
+        if self.shm is None:
+            return None
+        o = self.shm_out.cpu().numpy()
+        D = self.degree
+        kept = 3 * self.n + sum(3 * (2 * l + 1) * o[l] for l in range(1, D + 1))
+        total = 3 * self.n * (D + 1) ** 2
+        return {"loss": float(o[0]), "open": [int(o[l]) for l in range(1, 4)], "n": self.n,
+                "sh_coeff_kept": float(kept / total)}
 
     def evaluate(self, views=None) -> float:
         """Mean over views of the PSNR 10 log10(count / SSE), the squared

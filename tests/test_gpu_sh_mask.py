@@ -161,3 +161,52 @@ def test_mask_arguments_are_checked():
     out = torch.zeros(4, dtype=torch.float64, device="cuda")
     with pytest.raises(_lib.GstaError):
         g.ctx.sh_mask_reg(g.M, 0.0, 0.1, out)
+
+
+@pytest.mark.parametrize("lam,init", [(2000.0, -3.0), (0.0, 2.0)])
+def test_training_learns_band_masks_in_the_finetune(lam, init):
+    import torch
+    import paper_2504_06716_amd as G
+    from paper_2504_06716_amd.schedule import FreezeSchedule, LearningRates
+    from paper_2504_06716_amd.train import Trainer, TrainConfig, render_targets
+    n = 2000
+    p = S.make_scene(n, 3, seed=8)
+    p[3:6] += 0.4
+    cams = [S.look_at(-20.0 + 10 * k, 40.0 * k, 48, 40) for k in range(4)]
+    ctx = G.Context(n, 4, 40, 48, 1 << 20)
+    tgt = render_targets(ctx, S.perturb_scene(p, 3), 3, cams)
+    fs = FreezeSchedule(total_iters=100, warmup=10, every=5, reset_every=30, wait=5, window_end=40,
+                        eps_xyz0=1e-6, eps_rgb0=1e-7)
+    # a strong sparsity weight closes every gate within the 60 finetune iterations;
+    # without it the rendering loss alone keeps (nearly) all of them open
+    cfg = TrainConfig(iters=100, freeze=True, schedule=fs, lrs=LearningRates(decay_iters=100), finetune_iters=60,
+                      sh_mask_finetune=True, sh_mask_lr=0.2, sh_mask_lambda=lam, sh_mask_init=init)
+    tr = Trainer(p, 3, cams, tgt, cfg, S.view_order(4, 100), ctx=ctx)
+    tr.run(40)
+    assert tr.shm is None and tr.sh_mask_stats() is None
+    tr.step()                                         # iteration 40: the masks start, all open
+    assert tr.shm is not None
+    tr.run()
+    torch.cuda.synchronize()
+    assert tr.k == 100
+    st = tr.sh_mask_stats()
+    print("sh mask stats", st, flush=True)
+    assert all(0 <= o <= n for o in st["open"])
+    if lam > 0:
+        assert st["open"] == [0, 0, 0] and st["sh_coeff_kept"] == pytest.approx(1 / 16)
+    else:
+        assert st["sh_coeff_kept"] > 0.95
+    # the masked model renders as the stored model with its closed bands set to zero
+    x = tr.shm["x"].cpu().numpy()
+    gates = O.sh_band_gates(x, cfg.sh_mask_threshold)
+    pz = tr.P.clone()
+    for band in (1, 2, 3):
+        closed = torch.as_tensor(gates[band - 1] == 0, device="cuda")
+        for r in _sh_rows(band):
+            pz[r] = torch.where(closed, torch.zeros_like(pz[r]), pz[r])
+    img = torch.empty((1, 3, 40, 48), device="cuda")
+    ctx.render_forward(pz, 3, [cams[2]], (0, 0, 0), img, 0)
+    got = tr.render_views([2])
+    torch.cuda.synchronize()
+    assert torch.equal(img, got)
+    assert np.isfinite(tr.evaluate())

@@ -35,12 +35,14 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
 FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quadratic form, exp, o*G, min
 # Initial freeze thresholds of this workload, from the one-time calibration
-# rule of paper_2504_06716_amd/calibrate.py (`python bench.py --calibrate 0.4`):
+# rule of paper_2504_06716_amd/calibrate.py (`python bench.py --calibrate 0.35`):
 # the positive gradient-norm averages at the start of the freeze window of a
-# no-freeze run, quantile q = 0.4: the largest of 0.1, 0.2, 0.3, 0.4, 0.45,
-# 0.5 whose runs stay within 0.1 dB of the no-freeze PSNR for two view orders.
-C2_EPS0 = (1.0214666633002803e-06, 2.4916703086761885e-08)
+# no-freeze run, quantile q = 0.35: of 0.25, 0.3, 0.35 and 0.4, the largest
+# whose whole schedules on five view orders (2, 12, 22, 32, 42) all end within
+# 0.1 dB of the no-freeze PSNR (0.4 lost 0.157 dB on one of them).
+C2_EPS0 = (4.576265598045307e-07, 1.0948354737425498e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 0, 2, 64    # launch shape (the library defaults; forward 0 = per quarter)
+EXTRA_ORDERS = (12, 22, 32, 42)                 # view orders of the whole-schedule PSNR check besides the timed one
 COPY_PROBE_BYTES = 256 << 20   # plain device copy read and written once per call (--copy-probe)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "c2_compositing_pmc.md")
 FLOP_PER_GRAD_PAIR = 63        # backward gradient arithmetic of a pair that reaches the pixel (prefix, behind, dL/dalpha, 9 partials, T)
@@ -599,12 +601,12 @@ def main():
     if st != 0:
         raise RuntimeError(f"device flag raised during the benchmark (status {st})")
 
-    # whole schedules on two more view orders: the equal-iteration PSNR check
-    # over three orders, and the whole-schedule rates
+    # whole schedules on four more view orders: the equal-iteration PSNR check
+    # over five orders, and the whole-schedule rates
     import synthetic as S
     deltas = [psnr_f - psnr_n]
     whole = []
-    for seed in (12, 22):
+    for seed in EXTRA_ORDERS:
         order = S.view_order(len(w["cams"]), w["iters"], seed=seed)
         rf, df, _, _ = run_trainer(torch, w, True, w["iters"], order=order, finish=True)
         rn, dn, _, _ = run_trainer(torch, w, False, w["iters"], order=order, finish=True)
@@ -654,7 +656,7 @@ def main():
                       "phases_ms_per_iter": {k: round(v[0] / max(steps, 1), 5) for k, v in prof_n.items()}},
         "psnr_db": round(psnr_f, 4),
         "delta_psnr_db": round(psnr_f - psnr_n, 4),
-        "delta_psnr_db_view_orders": {"seeds": [2, 12, 22], "values": [round(d, 4) for d in deltas],
+        "delta_psnr_db_view_orders": {"seeds": [2, *EXTRA_ORDERS], "values": [round(d, 4) for d in deltas],
                                       "mean": round(sum(deltas) / len(deltas), 4),
                                       "min": round(min(deltas), 4), "max": round(max(deltas), 4)},
         "speedup_vs_no_freeze": round(dt_n / dt_f, 4),
@@ -663,7 +665,7 @@ def main():
         "frozen_fraction_peak": round(peak_frozen, 4),
         "frozen_fraction_mean": round(mean_frozen, 4),
         "whole_schedule_iters_per_s": {"gsta": [round(a, 1) for a, _ in whole],
-                                       "no_freeze": [round(b, 1) for _, b in whole], "seeds": [12, 22]},
+                                       "no_freeze": [round(b, 1) for _, b in whole], "seeds": list(EXTRA_ORDERS)},
         "roofline": {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
                      "unit": unit_r, "frac": round(achieved / peak, 5),
                      "traffic": measured_traffic(os.path.join(ROOT, "paper_2504_06716_amd", "csrc", "k_raster.hip"),

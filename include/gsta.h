@@ -124,9 +124,9 @@ typedef enum {
 
 /* Execution options (gsta_set_option).  They change speed, not what is
  * computed: images, states and forward decisions are bit-identical for every
- * setting, and so are gradients except across GSTA_OPT_BWD_WAVES, which
- * changes the order of the backward's float additions (agreement to
- * rounding). */
+ * setting, and so are gradients except across GSTA_OPT_BWD_WAVES and
+ * GSTA_OPT_BWD_VARIANT, which change the order of the backward's float
+ * additions (agreement to rounding). */
 typedef enum {
     GSTA_OPT_FWD_WAVES = 0,     /* forward compositing: 0 (default): one independent wave per 8x8
                                    quarter of each tile, each writing its quarter's backward
@@ -142,10 +142,17 @@ typedef enum {
                                    placement scratch was reserved for the call's views, else sorts;
                                    1 always expands and sorts the tile keys (LSD radix).  Both give
                                    the same lists (Section 3.1: splats per tile in depth order). */
-    GSTA_OPT_DEPTH_SORT = 4     /* the per-view depth sort: 0 (default) histogram / scan / scatter
+    GSTA_OPT_DEPTH_SORT = 4,    /* the per-view depth sort: 0 (default) histogram / scan / scatter
                                    kernels per 8-bit pass, 1 onesweep (a global digit histogram,
                                    then one kernel per pass with decoupled look-back).  Both are the
                                    same stable sort: identical order. */
+    GSTA_OPT_BWD_VARIANT = 5    /* backward compositing (Section 3.2.4): 0 (default) per pixel, lanes
+                                   are pixels and each splat's terms are summed across the wave (a
+                                   frozen splat skipped for all its pixels at once); 1 per splat, the
+                                   paper's parallelisation: lanes are the splats of a 64-splat span,
+                                   pixel state passed lane to lane, each lane summing its own splat.
+                                   Gradients agree to rounding (the order of a splat's additions
+                                   differs).  GSTA_OPT_BWD_WAVES applies to variant 0 only. */
 } gsta_option;
 
 /* ---- context ------------------------------------------------------------ */
@@ -594,19 +601,23 @@ typedef struct {
     int32_t candidates;     /* settings timed */
     float fwd_ms;           /* forward per call with the chosen forward shape */
     float step_ms;          /* forward + backward per call with the chosen options */
+    int32_t bwd_variant;    /* GSTA_OPT_BWD_VARIANT chosen (bwd_waves applies to variant 0) */
 } gsta_tuning;
 
 /* Times the execution options that do not change results on the caller's
- * own workload -- forward waves {0, 1, 2, 4} (forward calls), then backward
- * waves {1, 2, 4} x segment length {64, 128, 256, one item per tile}
- * (forward + backward calls) -- `repeats` calls each after one untimed call,
- * and sets the fastest on the context (profiling is suspended meanwhile).
- * Synchronises.  image [n_views][3][H][W], dL_dimage (same shape; any
- * values) and grad (shaped like g) are the caller's scratch; their contents
- * afterwards are unspecified.  out (host) may be NULL. */
+ * own workload -- forward waves {0, 1, 2, 4} (forward calls), then the
+ * backward: the per-pixel variant's waves {1, 2, 4} and the per-splat
+ * variant (Section 3.2.4), each x segment length {64, 128, 256, one item per
+ * tile} (forward + backward calls) -- `repeats` calls each after one untimed
+ * call, and sets the fastest on the context (profiling is suspended
+ * meanwhile).  Synchronises.  frozen [n] (device, or NULL): the freeze map
+ * the backward calls skip, as in training.  image [n_views][3][H][W],
+ * dL_dimage (same shape; any values) and grad (shaped like g) are the
+ * caller's scratch; their contents afterwards are unspecified.  out (host)
+ * may be NULL. */
 gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams, int32_t n_views,
-                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, int32_t repeats,
-                          gsta_tuning* out, hipStream_t stream);
+                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, const uint8_t* frozen,
+                          int32_t repeats, gsta_tuning* out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "HIP", 4: "OOM", 5: "NO
 
 (STATE_REC_GEO, STATE_REC_COL, STATE_REC_RGB, STATE_RECT, STATE_DEPTH_ORDER, STATE_INST_KEYS,
  STATE_INST_IDS, STATE_RANGES, STATE_T_FINAL, STATE_LAST, STATE_N_INSTANCES, STATE_INST_GID) = range(12)
-OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT, OPT_BINNING, OPT_DEPTH_SORT = 0, 1, 2, 3, 4
+OPT_FWD_WAVES, OPT_BWD_WAVES, OPT_BWD_SEGMENT, OPT_BINNING, OPT_DEPTH_SORT, OPT_BWD_VARIANT = 0, 1, 2, 3, 4, 5
 FREEZE_RULE_MINGRAD, FREEZE_RULE_RANDOM = 1, 2
 
 
@@ -59,7 +59,8 @@ class Columns(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fwd_waves", ctypes.c_int32), ("bwd_waves", ctypes.c_int32), ("bwd_segment", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("fwd_ms", ctypes.c_float), ("step_ms", ctypes.c_float)]
+                ("candidates", ctypes.c_int32), ("fwd_ms", ctypes.c_float), ("step_ms", ctypes.c_float),
+                ("bwd_variant", ctypes.c_int32)]
 
 
 class GstaError(RuntimeError):
@@ -117,7 +118,7 @@ def load(path: str = LIB_PATH):
     L.gsta_graph_launch.argtypes = [P, P]
     L.gsta_graph_destroy.argtypes = [P]
     L.gsta_graph_destroy.restype = None
-    L.gsta_autotune.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, P, PP, i32,
+    L.gsta_autotune.argtypes = [P, PP, ctypes.POINTER(Camera), i32, ctypes.POINTER(f32), P, P, PP, P, i32,
                                 ctypes.POINTER(Tuning), P]
     L.gsta_traj_push.argtypes = [P, P, i64, P, i32, P]
     L.gsta_mlp_feature_stats.argtypes = [P, P, i64, i32, P, P]

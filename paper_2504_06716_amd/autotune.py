@@ -2,7 +2,8 @@
 
 Two levels, both on the caller's own workload and neither changing results:
 the library's gsta_autotune times the compositing launch options (forward
-waves per tile, backward waves per tile, backward segment length) on the
+waves per tile, the backward variant -- per pixel with 1, 2 or 4 waves per
+tile, or per splat -- and the backward segment length) on the
 first views of the workload and keeps the fastest on the context; this
 module then times whole training iterations eagerly and replayed from HIP
 graphs and picks the faster.  Results are cached on disk, keyed by the
@@ -30,27 +31,30 @@ def workload_key(n, degree, height, width, views_per_step) -> str:
 
 def apply(ctx, choice: dict):
     ctx.set_waves(fwd=choice["fwd"], bwd=choice["bwd"])
+    ctx.set_option(_lib.OPT_BWD_VARIANT, choice.get("variant", 0))
     ctx.set_option(_lib.OPT_BWD_SEGMENT, choice["segment"])
 
 
-def tune_options(params0, degree, cams, ctx, views: int = 1, repeats: int = 3, bg=(0.0, 0.0, 0.0)) -> dict:
-    """gsta_autotune on the first `views` cameras: sets and returns the
-    fastest {fwd, bwd, segment} with their times."""
+def tune_options(params0, degree, cams, ctx, views: int = 1, repeats: int = 3, bg=(0.0, 0.0, 0.0),
+                 frozen=None) -> dict:
+    """gsta_autotune on the first `views` cameras (with the freeze map
+    `frozen`, a [n] uint8 device tensor, if given): sets and returns the
+    fastest {fwd, bwd, variant, segment} with their times."""
     P = torch.from_numpy(params0).float().cuda()
     H, W = cams[0].height, cams[0].width
     img = torch.empty((views, 3, H, W), device="cuda")
     dL = torch.full_like(img, 1.0 / img.numel())
     grad = torch.empty_like(P)
-    t = ctx.autotune(P, degree, camera_array(cams[:views]), bg, img, dL, grad, repeats)
-    return dict(fwd=t["fwd_waves"], bwd=t["bwd_waves"], segment=t["bwd_segment"], fwd_ms=t["fwd_ms"],
-                step_ms=t["step_ms"], candidates=t["candidates"])
+    t = ctx.autotune(P, degree, camera_array(cams[:views]), bg, img, dL, grad, repeats, frozen=frozen)
+    return dict(fwd=t["fwd_waves"], bwd=t["bwd_waves"], variant=t["bwd_variant"], segment=t["bwd_segment"],
+                fwd_ms=t["fwd_ms"], step_ms=t["step_ms"], candidates=t["candidates"])
 
 
 def tune(params0, degree, cams, targets, order, ctx, base_cfg: TrainConfig, iters: int = 30,
          cache_path: str | None = _DEFAULT_CACHE, log=None) -> dict:
     """Fastest launch options (gsta_autotune) and the faster of eager and
     graph-replayed training iterations for this workload: returns {fwd,
-    bwd, segment, graph} and leaves the options set on ctx."""
+    bwd, variant, segment, graph} and leaves the options set on ctx."""
     n = params0.shape[1]
     assert params0.shape[0] == n_rows(degree)
     key = workload_key(n, degree, cams[0].height, cams[0].width, base_cfg.views_per_step)
@@ -81,7 +85,7 @@ def tune(params0, degree, cams, targets, order, ctx, base_cfg: TrainConfig, iter
             log(f"autotune graph={graph}: {dt * 1e3:.3f} ms/iter")
         if dt < best_t:
             best, best_t = graph, dt
-    choice = dict(fwd=opts["fwd"], bwd=opts["bwd"], segment=opts["segment"], graph=best)
+    choice = dict(fwd=opts["fwd"], bwd=opts["bwd"], variant=opts["variant"], segment=opts["segment"], graph=best)
     apply(ctx, choice)
     if cache_path:
         cache[key] = choice

@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsta.so")
 MICRO_LIB = os.path.join(HERE, "libgsta_micro.so")
 MICRO_SRC = "micro.hip"
-SOURCES = ["gsta_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_optim.hip", "k_densify.hip", "k_mlp.hip", "gsta_noalloc.hip", "k_freeze_rules.hip", "k_ssim.hip"]
+SOURCES = ["gsta_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_raster_splat.hip", "k_optim.hip", "k_densify.hip", "k_mlp.hip", "gsta_noalloc.hip", "k_freeze_rules.hip", "k_ssim.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

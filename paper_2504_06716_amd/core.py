@@ -195,9 +195,10 @@ class Context:
         check(self.h, st)
         return Graph(self.L, out)
 
-    def autotune(self, params, degree, cams, bg, image, dL_dimage, grad, repeats=3, stream=None):
-        """Time the result-neutral launch options on this workload and keep
-        the fastest (gsta_autotune); returns the gsta_tuning fields."""
+    def autotune(self, params, degree, cams, bg, image, dL_dimage, grad, repeats=3, stream=None, frozen=None):
+        """Time the result-neutral launch options on this workload (with the
+        freeze map `frozen`, if given) and keep the fastest (gsta_autotune);
+        returns the gsta_tuning fields."""
         ps, gs = params_struct(params, degree), params_struct(grad, degree)
         ca = cams if isinstance(cams, ctypes.Array) else camera_array(cams)
         shape = (len(ca), 3, ca[0].height, ca[0].width)
@@ -205,6 +206,7 @@ class Context:
         check(self.h, self.L.gsta_autotune(self.h, ctypes.byref(ps), ca, len(ca), _f3(bg),
                                             _arr(image, shape, torch.float32, "image"),
                                             _arr(dL_dimage, shape, torch.float32, "dL_dimage"), ctypes.byref(gs),
+                                            _arr(frozen, (ps.n,), torch.uint8, "frozen"),
                                             int(repeats), ctypes.byref(t), _stream(stream)))
         self.segment = int(t.bwd_segment)
         return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}

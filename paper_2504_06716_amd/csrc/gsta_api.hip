@@ -92,6 +92,8 @@ struct gsta_ctx {
     uint32_t first_slots = 0;      // of which the tiles' first batches own the first ones
     uint32_t item_cap = 0;         // backward work items per state slot
     int cus = 1, bwd_blocks = 1;   // persistent backward grid
+    int bwd_variant = 0;           // 0 per pixel (lanes = pixels), 1 per splat (lanes = splats)
+    int bwd_splat_blocks = 1;      // persistent grid of the per-splat variant
     uint32_t* flags = nullptr;     // [0] instance overflow, [1] non-finite gradient, [2] densify overflow
     uint8_t* dens_code = nullptr;  // [max_gaussians] densify decisions
     uint32_t* dens_boff = nullptr; // [3][blocks] densify block counts / offsets
@@ -251,6 +253,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         ctx->cus = 1;
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
+    ctx->bwd_splat_blocks = ctx->cus * composite_bwd_splat_blocks_per_cu();
     if (hipMemset(ctx->flags, 0, 8 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->stamps, 0, (size_t)std::max<int64_t>(cap, 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMemcpy(ctx->gen, &kGen0, sizeof(kGen0), hipMemcpyHostToDevice) != hipSuccess ||
@@ -494,6 +497,10 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
         case GSTA_OPT_DEPTH_SORT:
             if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "depth sort must be 0 or 1");
             ctx->depth_sort = (int)value;
+            return GSTA_OK;
+        case GSTA_OPT_BWD_VARIANT:
+            if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "backward variant must be 0 or 1");
+            ctx->bwd_variant = (int)value;
             return GSTA_OK;
         default:
             return fail(ctx, GSTA_ERR_INVALID, "unknown option %d", option);
@@ -775,9 +782,15 @@ gsta_status gsta_render_backward(gsta_ctx* ctx, const gsta_params* g, const gsta
     const int nv = n_views;
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE_BWD, stream);
-        launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.gsort, s.geo, s.col,
-                             s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg, dL_dimage,
-                             ctx->tile_grads, s.n_count, seg_ckpt(ctx, s), pair_counter(ctx, 1), stream);
+        unsigned long long* pairs = pair_counter(ctx, 1);
+        if (ctx->bwd_variant == 1 && !pairs)   // (the pair counts come from the per-pixel variant)
+            launch_composite_bwd_splat(ctx->bwd_splat_blocks, s.ranges, s.ival[s.inst_buf], s.gsort, s.geo, s.col,
+                                       s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg,
+                                       dL_dimage, ctx->tile_grads, seg_ckpt(ctx, s), stream);
+        else
+            launch_composite_bwd(ctx->bwd_waves, ctx->bwd_blocks, s.ranges, s.ival[s.inst_buf], s.gsort, s.geo,
+                                 s.col, s.rgb, S, frozen, ca, nv, bg[0], bg[1], bg[2], s.T_final, s.last, s.cfg,
+                                 dL_dimage, ctx->tile_grads, s.n_count, seg_ckpt(ctx, s), pairs, stream);
     }
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS_BWD, stream);
@@ -1232,13 +1245,13 @@ void gsta_graph_destroy(gsta_graph* graph) {
 }
 
 gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera* cams, int32_t n_views,
-                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, int32_t repeats,
-                          gsta_tuning* out, hipStream_t stream) {
+                          const float* bg, float* image, float* dL_dimage, gsta_params* grad, const uint8_t* frozen,
+                          int32_t repeats, gsta_tuning* out, hipStream_t stream) {
     if (!ctx || ctx->allocs.empty()) return GSTA_ERR_INVALID;
     if (ctx->capturing) return fail(ctx, GSTA_ERR_INVALID, "the autotuner synchronises: not while a graph is captured");
     if (repeats < 1 || repeats > 1000) return fail(ctx, GSTA_ERR_INVALID, "repeats must be in [1, 1000]");
     if (!image || !dL_dimage || !grad) return fail(ctx, GSTA_ERR_INVALID, "NULL scratch argument");
-    const int fwd0 = ctx->fwd_waves, bwd0 = ctx->bwd_waves;
+    const int fwd0 = ctx->fwd_waves, bwd0 = ctx->bwd_waves, var0 = ctx->bwd_variant;
     const uint32_t seg0 = ctx->seg_shift;
     const uint32_t prof0 = ctx->profiling;
     ctx->profiling = 0;
@@ -1249,6 +1262,7 @@ gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera
         ctx->fwd_waves = fwd0;
         ctx->bwd_waves = bwd0;
         ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(bwd0);
+        ctx->bwd_variant = var0;
         ctx->seg_shift = seg0;
         ctx->profiling = prof0;
         if (e0) (void)hipEventDestroy(e0);
@@ -1274,7 +1288,7 @@ gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera
     auto step = [&]() {
         gsta_status s = gsta_render_forward(ctx, g, cams, n_views, bg, image, 0, stream);
         if (s == GSTA_OK)
-            s = gsta_render_backward(ctx, g, cams, n_views, bg, 0, dL_dimage, nullptr, grad, nullptr, nullptr, 0.9f,
+            s = gsta_render_backward(ctx, g, cams, n_views, bg, 0, dL_dimage, frozen, grad, nullptr, nullptr, 0.9f,
                                      nullptr, stream);
         return s;
     };
@@ -1295,22 +1309,25 @@ gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera
         }
     }
     ctx->fwd_waves = best.fwd_waves;
-    // then backward waves x segment length, timed as forward + backward
+    // then the backward: the per-pixel variant's waves x segment length and
+    // the per-splat variant x segment length, timed as forward + backward
     // (the segment length also sets the forward's checkpoints)
     float best_s = 3.0e38f;
-    const int bwd_c[3] = {1, 2, 4};
+    const int bwd_c[4] = {1, 2, 4, 0};   // 0: the per-splat variant
     const uint32_t seg_c[4] = {6, 7, 8, 31};
     for (int b : bwd_c)
         for (uint32_t sh : seg_c) {
-            ctx->bwd_waves = b;
-            ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(b);
+            ctx->bwd_variant = b == 0 ? 1 : 0;
+            ctx->bwd_waves = b == 0 ? bwd0 : b;
+            ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(ctx->bwd_waves);
             ctx->seg_shift = sh;
             float ms = 0.f;
             if ((st = timed(step, &ms)) != GSTA_OK) return restore(st);
             ++cands;
             if (ms < best_s) {
                 best_s = ms;
-                best.bwd_waves = b;
+                best.bwd_variant = ctx->bwd_variant;
+                best.bwd_waves = ctx->bwd_waves;
                 best.bwd_segment = sh >= 31 ? 0 : (1 << sh);
                 best.step_ms = ms;
             }
@@ -1319,6 +1336,7 @@ gsta_status gsta_autotune(gsta_ctx* ctx, const gsta_params* g, const gsta_camera
     restore(GSTA_OK);
     ctx->fwd_waves = best.fwd_waves;
     ctx->bwd_waves = best.bwd_waves;
+    ctx->bwd_variant = best.bwd_variant;
     ctx->bwd_blocks = ctx->cus * composite_bwd_blocks_per_cu(best.bwd_waves);
     ctx->seg_shift = best.bwd_segment == 0 ? 31u : (uint32_t)__builtin_ctz((unsigned)best.bwd_segment);
     if (out) *out = best;

@@ -280,6 +280,15 @@ void launch_composite_bwd(int waves, int blocks, const uint2* ranges, const uint
                           hipStream_t s);
 // Workgroups of the backward compositing that fit on one compute unit.
 int composite_bwd_blocks_per_cu(int waves);
+// The per-splat backward variant over the same work items (one 64-lane
+// workgroup per item, one splat per lane, pixel state passed lane to lane);
+// same outputs as launch_composite_bwd, equal to rounding.
+void launch_composite_bwd_splat(int blocks, const uint2* ranges, const uint32_t* ids, const uint32_t* gsort,
+                                const float4* geo, const float4* col, const float4* rgb, int64_t stride,
+                                const uint8_t* frozen, const CamArray& cams, int nv, float bg0, float bg1, float bg2,
+                                const float* T_final, const uint32_t* last, const double* cfg,
+                                const float* dL_dimage, float* partials, const SegCkpt& sc, hipStream_t s);
+int composite_bwd_splat_blocks_per_cu();
 void launch_adam(float* p, int64_t pld, const float* g, int64_t gld, float* m, int64_t mld, float* v,
                  int64_t vld, int64_t n, int rows, const LrArray& lr, float b1, float b2, float eps,
                  float bc1, float bc2, const uint8_t* frozen, uint32_t* flags, hipStream_t s);

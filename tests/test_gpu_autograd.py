@@ -131,6 +131,7 @@ def test_autotuner_picks_a_candidate(tmp_path):
     cache = str(tmp_path / "tune.json")
     best = tune(p, 3, cams, tgt, S.view_order(4, 200), ctx, cfg, iters=8, cache_path=cache)
     assert best["fwd"] in (0, 1, 2, 4) and best["bwd"] in (1, 2, 4) and best["segment"] in (0, 64, 128, 256)
+    assert best["variant"] in (0, 1)
     assert best["graph"] in (False, True)
     assert tune(p, 3, cams, tgt, S.view_order(4, 200), ctx, cfg, iters=8, cache_path=cache) == best
 

@@ -151,12 +151,14 @@ def test_autotune_sets_options_without_changing_results():
         return out.cpu().numpy(), g.cpu().numpy()
 
     a = run()
-    t = ctx.autotune(P, 3, carr, (0, 0, 0), img, dLs, grad, repeats=2)
-    assert t["candidates"] == 16
+    frozen = dev((rng.random(4000) < 0.5).astype(np.uint8))
+    t = ctx.autotune(P, 3, carr, (0, 0, 0), img, dLs, grad, repeats=2, frozen=frozen)
+    assert t["candidates"] == 20          # 4 forward shapes; (3 waves + the per-splat variant) x 4 segments
     assert t["fwd_waves"] in (0, 1, 2, 4) and t["bwd_waves"] in (1, 2, 4) and t["bwd_segment"] in (0, 64, 128, 256)
+    assert t["bwd_variant"] in (0, 1)
     assert 0 < t["fwd_ms"] < 1000 and 0 < t["step_ms"] < 1000
     b = run()
     assert np.array_equal(a[0], b[0])                   # images: bit-identical for every option
-    # gradients: the backward's waves per tile change the order of its float additions
+    # gradients: the backward's waves per tile and variant change the order of its float additions
     np.testing.assert_allclose(b[1], a[1], rtol=1e-4, atol=1e-6 * np.abs(a[1]).max())
     assert ctx.check()[0] == 0

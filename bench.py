@@ -511,6 +511,8 @@ def main():
     ap.add_argument("--c3", action="store_true",
                     help="time the c3 workload's graph-captured 4-view steps (1M Gaussians, 1080x1600) and exit")
     ap.add_argument("--peaks", action="store_true", help="run the peak microbenchmarks and exit")
+    ap.add_argument("--bwd-variant", type=int, default=0, choices=(0, 1),
+                    help="backward compositing: 0 per pixel (default), 1 per splat (GSTA_OPT_BWD_VARIANT)")
     ap.add_argument("--profile-window", type=int, default=None, metavar="K",
                     help="for counter collection: advance the c2 GSta run untimed to iteration 1000, run K "
                          "iterations, exit")
@@ -544,6 +546,9 @@ def main():
         return
     log("setting up the c2 workload")
     w = c2_setup(torch)
+    if args.bwd_variant:
+        from paper_2504_06716_amd import _lib
+        w["ctx"].set_option(_lib.OPT_BWD_VARIANT, args.bwd_variant)
     if args.profile_window is not None:
         from paper_2504_06716_amd.train import Trainer
         tr = Trainer(w["p0"], w["D"], w["cams"], w["targets"], w["cfg"](True), w["order"], ctx=w["ctx"])

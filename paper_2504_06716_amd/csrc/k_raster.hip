@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     // step reaching past the last staged record evaluates as non-members
     __shared__ float4 s_geo[B + kStep - 1];
     __shared__ float4 s_co[B + kStep - 1];
-    __shared__ float4 s_rgb[B + kStep - 1];
+    __shared__ double s_rgb[3][B + kStep - 1];   // colours, converted once when staged
     __shared__ unsigned int s_pairs;
     __shared__ uint32_t s_last;
     __shared__ uint32_t s_ckbase;      // pool slots of the current batch's segment boundaries
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     if (tid < kStep - 1) {
         s_geo[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         s_co[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_rgb[B + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_rgb[0][B + tid] = s_rgb[1][B + tid] = s_rgb[2][B + tid] = 0.0;
     }
     // checkpoints at list positions that are multiples of K (none in quadrant mode)
     const uint32_t kmask = sc.shift >= 31u ? 0xFFFFFFFFu : ((1u << sc.shift) - 1u);
@@ -240,26 +240,30 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             if (hit) {
                 s_geo[r] = cur.g;
                 s_co[r] = cur.co;
-                s_rgb[r] = cur.c;
+                s_rgb[0][r] = (double)cur.c.x;
+                s_rgb[1][r] = (double)cur.c.y;
+                s_rgb[2][r] = (double)cur.c.z;
                 s_pos[r] = (uint8_t)tid;
             }
             if (tid >= cnt && tid < cnt + kStep - 1) {   // zero-opacity records after the kept ones
                 s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_rgb[0][tid] = s_rgb[1][tid] = s_rgb[2][tid] = 0.0;
             }
         } else {
             cnt = (int)min((uint32_t)B, rg.y - base);
             if (base + tid < rg.y) {
                 s_geo[tid] = cur.g;
                 s_co[tid] = cur.co;
-                s_rgb[tid] = cur.c;
+                s_rgb[0][tid] = (double)cur.c.x;
+                s_rgb[1][tid] = (double)cur.c.y;
+                s_rgb[2][tid] = (double)cur.c.z;
             } else if (base + tid < rg.y + (uint32_t)(kStep - 1)) {
                 // zero-opacity records after the list's last splat: a step that
                 // reaches past the end evaluates them and they are never members
                 s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 s_co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_rgb[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_rgb[0][tid] = s_rgb[1][tid] = s_rgb[2][tid] = 0.0;
             }
         }
         if (ckpt && tid == 0) {
@@ -305,7 +309,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
             const int kend = min(cnt, kc + L);
             for (int k = kc; k < kend && !alldone; k += kStep) {
                 // offsets k .. k + kStep - 1 (past cnt: the zero-opacity records)
-                float4 g[kStep], rgb[kStep];
+                float4 g[kStep];
+                double rgb[kStep][3];
                 float2 o[kStep];
                 uint32_t pos[kStep];     // list positions (kept records: their batch offsets)
 #pragma unroll
@@ -313,7 +318,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                     g[i] = s_geo[k + i];
                     const float4 t = s_co[k + i];
                     o[i] = make_float2(t.x, t.y);
-                    rgb[i] = s_rgb[k + i];
+                    rgb[i][0] = s_rgb[0][k + i];
+                    rgb[i][1] = s_rgb[1][k + i];
+                    rgb[i][2] = s_rgb[2][k + i];
                     pos[i] = base - rg.x + (QUAD ? (uint32_t)s_pos[k + i] : (uint32_t)(k + i));
                 }
                 const int nreal = min(kStep, cnt - k);   // (counted by the counting variant only)
@@ -349,11 +356,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                             if (CNT) evals += (Tp[i] >= kTMin && i < nreal) ? 1u : 0u;   // a one-at-a-time walk's pairs
                             const bool ok = Tp[i + 1] >= kTMin;
                             const bool c = mem[i] && ok;                    // contributes
-                            const double wd = c ? (double)(e[i].alpha * Tp[i]) : 0.0;
+                            const double wd = (double)(c ? e[i].alpha * Tp[i] : 0.f);
                             // a zero weight leaves the colour unchanged
-                            C[p][0] = fma((double)rgb[i].x, wd, C[p][0]);
-                            C[p][1] = fma((double)rgb[i].y, wd, C[p][1]);
-                            C[p][2] = fma((double)rgb[i].z, wd, C[p][2]);
+                            C[p][0] = fma(rgb[i][0], wd, C[p][0]);
+                            C[p][1] = fma(rgb[i][1], wd, C[p][1]);
+                            C[p][2] = fma(rgb[i][2], wd, C[p][2]);
                             last[p] = c ? pos[i] + 1u : last[p];
                             Tc = ok ? Tp[i + 1] : Tc;
                         }

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
     __shared__ unsigned int s_pairs;
     __shared__ uint32_t s_last;
     __shared__ uint32_t s_ckbase;      // pool slots of the current batch's segment boundaries
-    __shared__ uint8_t s_pos[QUAD ? B + kStep - 1 : 1];   // quadrant mode: batch offset of each kept record
+    __shared__ uint32_t s_pos[QUAD ? B + kStep - 1 : 1];  // quadrant mode: list position + 1 of each kept record
     const int v = blockIdx.y;
     const DevCam& cm = cams.c[v];
     const int tiles = cm.ntx * cm.nty;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                 s_rgb[0][r] = (double)cur.c.x;
                 s_rgb[1][r] = (double)cur.c.y;
                 s_rgb[2][r] = (double)cur.c.z;
-                s_pos[r] = (uint8_t)tid;
+                s_pos[r] = base - rg.x + (uint32_t)tid + 1u;
             }
             if (tid >= cnt && tid < cnt + kStep - 1) {   // zero-opacity records after the kept ones
                 s_geo[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                 float4 g[kStep];
                 double rgb[kStep][3];
                 float2 o[kStep];
-                uint32_t pos[kStep];     // list positions (kept records: their batch offsets)
+                uint32_t pos1[kStep];    // list positions + 1 (the `last` a contributing record sets)
 #pragma unroll
                 for (int i = 0; i < kStep; ++i) {
                     g[i] = s_geo[k + i];
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                     rgb[i][0] = s_rgb[0][k + i];
                     rgb[i][1] = s_rgb[1][k + i];
                     rgb[i][2] = s_rgb[2][k + i];
-                    pos[i] = base - rg.x + (QUAD ? (uint32_t)s_pos[k + i] : (uint32_t)(k + i));
+                    pos1[i] = QUAD ? s_pos[k + i] : base - rg.x + (uint32_t)(k + i) + 1u;
                 }
                 const int nreal = min(kStep, cnt - k);   // (counted by the counting variant only)
                 bool all = true;
@@ -356,12 +356,15 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
                             if (CNT) evals += (Tp[i] >= kTMin && i < nreal) ? 1u : 0u;   // a one-at-a-time walk's pairs
                             const bool ok = Tp[i + 1] >= kTMin;
                             const bool c = mem[i] && ok;                    // contributes
-                            const double wd = (double)(c ? e[i].alpha * Tp[i] : 0.f);
+                            // the weight selected as float bits, then widened once
+                            const float wf = __builtin_bit_cast(
+                                float, c ? __builtin_bit_cast(uint32_t, e[i].alpha * Tp[i]) : 0u);
+                            const double wd = (double)wf;
                             // a zero weight leaves the colour unchanged
                             C[p][0] = fma(rgb[i][0], wd, C[p][0]);
                             C[p][1] = fma(rgb[i][1], wd, C[p][1]);
                             C[p][2] = fma(rgb[i][2], wd, C[p][2]);
-                            last[p] = c ? pos[i] + 1u : last[p];
+                            last[p] = c ? pos1[i] : last[p];
                             Tc = ok ? Tp[i + 1] : Tc;
                         }
                         const bool stop = Tp[kStep] < kTMin;

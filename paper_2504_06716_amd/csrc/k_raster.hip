@@ -741,10 +741,11 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             if (CNT) wred += 1u;
 #pragma unroll
                             for (int q = 0; q < 9; ++q) g9[q] = row_sum(g9[q]);
-                            if ((lane & 15) == 0) {
+                            // every lane of a row writes its row's total (the same value to
+                            // the same word): no lane mask, so the last DPP step of the row
+                            // sum stays one fused add
 #pragma unroll
-                                for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = g9[q];
-                            }
+                            for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = g9[q];
                         }
                     }
                 }

@@ -38,8 +38,8 @@ FLOP_PER_PAIR = 15             # one (pixel, splat) evaluation: dx, dy, the quad
 # rule of paper_2504_06716_amd/calibrate.py (`python bench.py --calibrate 0.35`):
 # the positive gradient-norm averages at the start of the freeze window of a
 # no-freeze run, quantile q = 0.35: of 0.25, 0.3, 0.35 and 0.4, the largest
-# whose whole schedules on five view orders (2, 12, 22, 32, 42) all end within
-# 0.1 dB of the no-freeze PSNR (0.4 lost 0.157 dB on one of them).
+# whose whole schedules on five view orders (2, 12, 22, 32, 42) all end no more
+# than 0.1 dB below the no-freeze PSNR (0.4 lost 0.157 dB on one of them).
 C2_EPS0 = (4.576265598045307e-07, 1.0948354737425498e-08)
 FWD_WAVES, BWD_WAVES, BWD_SEGMENT = 0, 2, 64    # launch shape (the library defaults; forward 0 = per quarter)
 EXTRA_ORDERS = (12, 22, 32, 42)                 # view orders of the whole-schedule PSNR check besides the timed one

@@ -142,10 +142,13 @@ typedef enum {
                                    placement scratch was reserved for the call's views, else sorts;
                                    1 always expands and sorts the tile keys (LSD radix).  Both give
                                    the same lists (Section 3.1: splats per tile in depth order). */
-    GSTA_OPT_DEPTH_SORT = 4,    /* the per-view depth sort: 0 (default) histogram / scan / scatter
-                                   kernels per 8-bit pass, 1 onesweep (a global digit histogram,
-                                   then one kernel per pass with decoupled look-back).  Both are the
-                                   same stable sort: identical order. */
+    GSTA_OPT_DEPTH_SORT = 4,    /* the per-view depth sort: 0 (default) one kernel per 8-bit pass
+                                   for views of at most 131072 Gaussians (4096 keys per workgroup,
+                                   each pass leaving the next its per-chunk digit counts), else as
+                                   2; 1 onesweep (a global digit histogram, then one kernel per
+                                   pass with decoupled look-back); 2 histogram / scan / scatter
+                                   kernels per pass.  All are the same stable sort: identical
+                                   order. */
     GSTA_OPT_BWD_VARIANT = 5    /* backward compositing (Section 3.2.4): 0 (default) per pixel, lanes
                                    are pixels and each splat's terms are summed across the wave (a
                                    frozen splat skipped for all its pixels at once); 1 per splat, the

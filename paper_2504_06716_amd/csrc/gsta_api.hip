@@ -81,6 +81,8 @@ struct gsta_ctx {
     uint32_t* os_tot = nullptr;      // onesweep depth sort: [V][4][256] digit totals
     uint32_t* os_status = nullptr;   // [V][4][chunks][256] look-back words
     uint32_t* os_tickets = nullptr;  // [V][4] chunk tickets
+    uint32_t* sort_cnt = nullptr;    // depth sort of short views: first-pass counts [V][64][256]
+    uint32_t* sort_pre[2] = {};      // ... and the prefix tables between passes
     float* tile_grads = nullptr;   // [cap][9] per (tile, splat) 2-D gradient of the backward
     uint32_t* stamps = nullptr;    // [cap] backward generation that wrote each slot
     uint32_t* gen = nullptr;       // [1] backward generation (starts at 1; stamps start at 0)
@@ -243,6 +245,9 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
          alloc(ctx, &ctx->mlp_stats, (int64_t)kMlpBlocks * 64) &&
          alloc(ctx, &ctx->os_tot, V * 4 * 256) && alloc(ctx, &ctx->os_tickets, V * 4) &&
          alloc(ctx, &ctx->os_status, V * 4 * onesweep_chunks(S) * 256) &&
+         alloc(ctx, &ctx->sort_cnt, small_sort_count_words(V)) &&
+         alloc(ctx, &ctx->sort_pre[0], small_sort_prefix_words(V)) &&
+         alloc(ctx, &ctx->sort_pre[1], small_sort_prefix_words(V)) &&
          alloc(ctx, &ctx->flags, 8) && alloc(ctx, &ctx->max_inst, 1) && alloc(ctx, &ctx->pairs, kCounters);
     if (!ok) {
         free_all(ctx);
@@ -258,6 +263,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
         hipMemset(ctx->stamps, 0, (size_t)std::max<int64_t>(cap, 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMemcpy(ctx->gen, &kGen0, sizeof(kGen0), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(ctx->max_inst, 0, sizeof(uint64_t)) != hipSuccess ||
+        hipMemset(ctx->sort_cnt, 0, small_sort_count_words(V) * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(ctx->pairs, 0, kCounters * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx);
@@ -495,7 +501,7 @@ gsta_status gsta_set_option(gsta_ctx* ctx, int32_t option, int64_t value) {
             ctx->binning = (int)value;
             return GSTA_OK;
         case GSTA_OPT_DEPTH_SORT:
-            if (value != 0 && value != 1) return fail(ctx, GSTA_ERR_INVALID, "depth sort must be 0 or 1");
+            if (value < 0 || value > 2) return fail(ctx, GSTA_ERR_INVALID, "depth sort must be 0, 1 or 2");
             ctx->depth_sort = (int)value;
             return GSTA_OK;
         case GSTA_OPT_BWD_VARIANT:
@@ -648,20 +654,27 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
     const int ntx = ca.c[0].ntx;
     const int64_t T = (int64_t)ca.c[0].ntx * ca.c[0].nty;
 
-    // onesweep depth sort (default), or the hist / scan / scatter passes, whose
-    // first-pass histograms the preprocess writes when its chunks are 256 keys
+    // depth sort: one kernel per pass for short views (default), onesweep, or
+    // the hist / scan / scatter passes; the preprocess provides the first
+    // pass's digit counts for the first (added to its zeroed count table) and
+    // (with chunks of 256 keys) the last
+    const bool small = ctx->depth_sort == 0 && n <= kSmallSortKeys;
     const bool onesweep = ctx->depth_sort == 1 && n < ((int64_t)1 << 30);
-    const bool hist_given = !onesweep && ctx->items_depth == 1;
+    const bool hist_given = small || (!onesweep && ctx->items_depth == 1);
+    uint32_t* hist0 = !hist_given ? nullptr : small ? ctx->sort_cnt : ctx->hist;
     if (n > 0) {
         PhaseTimer pt(ctx, GSTA_PHASE_PREPROCESS, stream);
         launch_preprocess_fwd(g->block, g->ld, n, g->sh_degree, ca, nv, s.geo, s.col, s.rgb, s.rect,
-                              s.dkey[0], s.dval[0], S, hist_given ? ctx->hist : nullptr, g->opacity_act,
+                              s.dkey[0], s.dval[0], S, hist0, small, g->opacity_act,
                               sh_mask_of(g, nullptr), stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_DEPTH_SORT, stream);
         if (n == 0) {
             s.depth_buf = 0;
+        } else if (small) {
+            s.depth_buf = radix_sort_small(s.dkey, s.dval, S, nv, (uint32_t)n, ctx->sort_cnt,
+                                           small_sort_count_words(ctx->lim.max_views), ctx->sort_pre, stream);
         } else if (onesweep) {
             OnesweepScratch os{ctx->os_tot, ctx->os_status, ctx->os_tickets};
             s.depth_buf = radix_sort_onesweep(s.dkey, s.dval, S, nv, (uint32_t)n, os, ctx->flags, stream);

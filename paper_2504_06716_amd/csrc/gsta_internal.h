@@ -100,9 +100,10 @@ __device__ __forceinline__ float wave_sum(float x) {
 // Host launchers (all asynchronous on `s`).
 // -------------------------------------------------------------------------
 
-// hist0 (optional, [nv][256][ceil(n/256)]): the depth sort's first-pass
-// chunk histograms (chunks of 256 keys), for radix_sort_pairs with
-// first_hist_given.
+// hist0 (optional): the depth sort's first-pass digit counts, of every block
+// of 256 keys as [nv][256][ceil(n/256)] for radix_sort_pairs with
+// first_hist_given, or with hist_chunks added to the per-chunk counts
+// [nv][kSmallSortChunks][256] of radix_sort_small (which must be zero).
 // SH-band masks of the finetune stage (Section 3.3): logits [3][ld] (same
 // ld as the parameters) or null, the gate threshold as a logit, and the
 // backward's output dL/dlogit ([3][gld], or null).
@@ -121,8 +122,8 @@ void launch_sh_mask_reg(const float* logits, int64_t n, int64_t ld, float thr_lo
 
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
-                           const ShMask& sm, hipStream_t s);
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, bool hist_chunks,
+                           int opact, const ShMask& sm, hipStream_t s);
 
 // Sums each active Gaussian's per-tile 2-D gradients (partials at its
 // expansion offsets inst_off[v][gid], in tile order, taking a slot only if
@@ -166,6 +167,21 @@ struct OnesweepScratch {
 int64_t onesweep_chunks(int64_t count);
 int radix_sort_onesweep(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, uint32_t count,
                         const OnesweepScratch& os, uint32_t* flags, hipStream_t s);
+
+// Depth sort of views of at most kSmallSortKeys keys: one kernel per 8-bit
+// pass (kSmallSortChunkKeys keys per workgroup).  cnt: the first pass's
+// per-chunk digit counts, [nseg][kSmallSortChunks][256], which the
+// preprocess adds to a zeroed table; the sort clears its cnt_words words
+// again.  pre: two prefix tables of small_sort_prefix_words(nseg) words that
+// carry each pass's counts to the next.  Returns the buffer holding the
+// result (0); does nothing for count 0 or above the limit.
+constexpr int kSmallSortChunks = 64;
+constexpr int kSmallSortChunkKeys = 2048;
+constexpr int64_t kSmallSortKeys = (int64_t)kSmallSortChunks * kSmallSortChunkKeys;
+int64_t small_sort_count_words(int64_t nseg);
+int64_t small_sort_prefix_words(int64_t nseg);
+int radix_sort_small(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, uint32_t count,
+                     uint32_t* cnt, int64_t cnt_words, uint32_t* pre[2], hipStream_t s);
 
 // Depth-ordered tile-instance expansion: counts per Gaussian in depth
 // order, exclusive scan, write (view*T + tile, gid) for every touched tile.

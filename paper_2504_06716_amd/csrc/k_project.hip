@@ -200,13 +200,15 @@ __device__ __forceinline__ constexpr int sh_band(int k) { return k < 1 ? 0 : (k 
 
 template <int D>
 // hist0 (optional): the depth sort's first-pass (low 8 bits) digit counts of
-// the block's keys -- its 256 Gaussians are the sort's first chunk --
-// written to hist0[v][digit][blockIdx.x] with row pitch hpitch.
+// the block's keys (its 256 Gaussians), at hist0[v * hv + digit * hd +
+// (blockIdx.x >> hshift) * hc]: stored when hshift is 0, else added (the
+// 2^hshift blocks of a chunk share its counters).
 __global__ __launch_bounds__(256) void k_preprocess_fwd(
     const float* __restrict__ P, int64_t ld, int64_t n, CamArray cams, int nv,
     float4* __restrict__ geo, float4* __restrict__ col, float4* __restrict__ rgbo,
     ushort4* __restrict__ rect, uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-    int64_t stride, uint32_t* __restrict__ hist0, int64_t hpitch, int opact, ShMask sm) {
+    int64_t stride, uint32_t* __restrict__ hist0, int64_t hv, int64_t hd, int64_t hc, int hshift, int opact,
+    ShMask sm) {
     constexpr int K = (D + 1) * (D + 1);
     __shared__ uint32_t s_h[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,7 +296,11 @@ __global__ __launch_bounds__(256) void k_preprocess_fwd(
         }
         if (hist0) {
             __syncthreads();
-            hist0[((int64_t)v * 256 + threadIdx.x) * hpitch + blockIdx.x] = s_h[threadIdx.x];
+            uint32_t* h = hist0 + (int64_t)v * hv + (int64_t)threadIdx.x * hd + (int64_t)(blockIdx.x >> hshift) * hc;
+            if (hshift == 0)
+                *h = s_h[threadIdx.x];
+            else if (s_h[threadIdx.x])
+                atomicAdd(h, s_h[threadIdx.x]);
             __syncthreads();
         }
     }
@@ -609,11 +615,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 void launch_preprocess_fwd(const float* P, int64_t ld, int64_t n, int degree, const CamArray& cams,
                            int nv, float4* geo, float4* col, float4* rgb, ushort4* rect,
-                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, int opact,
-                           const ShMask& sm, hipStream_t s) {
+                           uint32_t* dkey, uint32_t* dval, int64_t stride, uint32_t* hist0, bool hist_chunks,
+                           int opact, const ShMask& sm, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    const int64_t hp = (n + 255) / 256;
-#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hp, opact, sm
+    const int64_t hp = (n + 255) / 256;   // blocks of 256 keys
+    int hshift = 0;
+    while ((256 << hshift) < kSmallSortChunkKeys) ++hshift;
+    const int64_t hv = hist_chunks ? (int64_t)kSmallSortChunks * 256 : 256 * hp;
+    const int64_t hd = hist_chunks ? 1 : hp, hc = hist_chunks ? 256 : 1;
+    if (!hist_chunks) hshift = 0;
+#define GSTA_PRE_ARGS P, ld, n, cams, nv, geo, col, rgb, rect, dkey, dval, stride, hist0, hv, hd, hc, hshift, opact, sm
     switch (degree) {
         case 0: k_preprocess_fwd<0><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;
         case 1: k_preprocess_fwd<1><<<grid, block, 0, s>>>(GSTA_PRE_ARGS); break;

@@ -952,6 +952,254 @@ __global__ void k_keys_from_ranges(const uint2* __restrict__ ranges, int64_t nti
     }
 }
 
+// ---------------------------------------------------------------------------
+// Depth sort of short segments (at most kSmallSortChunks chunks of SM_CHUNK
+// keys per view): one kernel per 8-bit pass and nothing else.  A workgroup
+// of 512 threads sorts one chunk of 2048 keys per pass.  Where its keys go
+// needs, per digit, how many keys all chunks hold and how many the earlier
+// chunks hold:
+//   * the first pass reads per-chunk digit counts cnt[seg][chunk][digit],
+//     which the preprocess adds up from its blocks of 256 keys (the second
+//     pass clears them again for the next sort; the allocation starts them
+//     at zero);
+//   * every pass leaves the next one a table of prefixes: workgroup s, having
+//     placed its keys, writes for e = 0 .. nchunks
+//         pre[seg][s][e][d] = its keys whose new position lies in a chunk
+//                             before e and whose next digit is d
+//     (16-bit counts, two per word), so the next pass sums, over the source
+//     chunks s, entry e = c for the keys below its chunk c and e = nchunks
+//     for the totals -- plain stores and loads, no atomics and no clears.
+// ---------------------------------------------------------------------------
+constexpr int SM_THREADS = 512;
+constexpr int SM_WAVES = SM_THREADS / 64;
+constexpr int SM_ITEMS = 4;
+constexpr int SM_LOG_CHUNK = 11;
+constexpr int SM_CHUNK = 1 << SM_LOG_CHUNK;       // SM_THREADS * SM_ITEMS keys
+constexpr int SM_MAXCH = kSmallSortChunks;        // chunks per segment
+constexpr int SM_WSPAN = 64 * SM_ITEMS;           // keys of one wave in a chunk
+static_assert(SM_CHUNK == SM_THREADS * SM_ITEMS, "chunk = threads x items");
+static_assert(SM_CHUNK == kSmallSortChunkKeys, "chunk size shared with the preprocess");
+static_assert(2 * SM_WAVES * RS_BINS <= 2 * SM_CHUNK, "table sums fit the staging area");
+
+// Exclusive scan of one value per thread over a workgroup of NW waves.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_tmp, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_tmp[wid] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t t = s_tmp[w];
+        base += (w < wid) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return base + incl - x;
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_sort_small(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t seg_stride, uint32_t count, int shift, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ tin, uint32_t* __restrict__ tout, uint32_t* __restrict__ tzero,
+    int64_t zero_words) {
+    __shared__ uint32_t s_stage[2 * SM_CHUNK];            // keys | values; first the table sums
+    __shared__ uint32_t s_cnt[SM_WAVES][RS_BINS];         // per-wave digit counters
+    __shared__ uint32_t s_next[SM_MAXCH][RS_BINS / 2];    // placed keys per (new chunk, next digit): u16 pairs
+    __shared__ uint32_t s_gb[RS_BINS];                    // new position of staged key p: s_gb[d] + p
+    __shared__ uint32_t s_ls[RS_BINS];                    // chunk-local start of each digit
+    __shared__ uint32_t s_tmp[SM_WAVES];
+    const int seg = blockIdx.y, c = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nch = (int)((count + SM_CHUNK - 1) >> SM_LOG_CHUNK);
+    const uint32_t* ki = kin + seg * seg_stride;
+    const uint32_t* vi = vin + seg * seg_stride;
+    uint32_t* ko = kout + seg * seg_stride;
+    uint32_t* vo = vout + seg * seg_stride;
+    const int64_t base = (int64_t)c * SM_CHUNK;
+    const int n_valid = (int)min((int64_t)SM_CHUNK, (int64_t)count - base);
+
+    uint32_t key[SM_ITEMS], val[SM_ITEMS], rank[SM_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SM_ITEMS; ++it) {
+        const int j = wid * SM_WSPAN + it * 64 + lane;
+        const bool ok = j < n_valid;
+        key[it] = ok ? ki[base + j] : 0u;
+        val[it] = ok ? vi[base + j] : 0u;
+    }
+    if (cnt) {   // first pass: wave w sums the count rows w, w + 8, ..., each lane four digits
+        uint4 pre = make_uint4(0u, 0u, 0u, 0u), tot = make_uint4(0u, 0u, 0u, 0u);
+        const uint4* t4 = reinterpret_cast<const uint4*>(cnt + (int64_t)seg * SM_MAXCH * RS_BINS);
+        uint4 h[SM_MAXCH / SM_WAVES];
+#pragma unroll
+        for (int k = 0; k < SM_MAXCH / SM_WAVES; ++k)   // all loads issued at once (rows past the
+            h[k] = t4[min(wid + SM_WAVES * k, nch - 1) * (RS_BINS / 4) + lane];   // last are re-reads)
+#pragma unroll
+        for (int k = 0; k < SM_MAXCH / SM_WAVES; ++k) {
+            const int r = wid + SM_WAVES * k;
+            const uint32_t in = r < nch ? ~0u : 0u, below = r < c ? ~0u : 0u;
+            pre.x += h[k].x & below;
+            pre.y += h[k].y & below;
+            pre.z += h[k].z & below;
+            pre.w += h[k].w & below;
+            tot.x += h[k].x & in;
+            tot.y += h[k].y & in;
+            tot.z += h[k].z & in;
+            tot.w += h[k].w & in;
+        }
+        reinterpret_cast<uint4*>(s_stage)[wid * (RS_BINS / 4) + lane] = pre;
+        reinterpret_cast<uint4*>(s_stage + SM_CHUNK)[wid * (RS_BINS / 4) + lane] = tot;
+    } else {     // later passes: thread (w, j) sums, over the sources s = w, w + 8, ..., the j-th
+                 // 16-byte piece of rows e = c (j < 32) and e = nch (j >= 32): 8 digits each
+        const int j = lane;
+        const int e = j < 32 ? c : nch;
+        uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        uint4 h[SM_MAXCH / SM_WAVES];
+#pragma unroll
+        for (int k = 0; k < SM_MAXCH / SM_WAVES; ++k) {
+            const int src = min(wid + SM_WAVES * k, nch - 1);
+            const int64_t row = ((int64_t)seg * SM_MAXCH + src) * (SM_MAXCH + 1) + e;
+            h[k] = reinterpret_cast<const uint4*>(tin)[row * (RS_BINS / 8) + (j & 31)];
+        }
+#pragma unroll
+        for (int k = 0; k < SM_MAXCH / SM_WAVES; ++k) {
+            const uint32_t in = wid + SM_WAVES * k < nch ? ~0u : 0u;
+            const uint32_t x[4] = {h[k].x & in, h[k].y & in, h[k].z & in, h[k].w & in};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[2 * q] += x[q] & 0xFFFFu;
+                acc[2 * q + 1] += x[q] >> 16;
+            }
+        }
+        // s_stage as [wave][j][8]: digit d of row c at j = d / 8, of the totals at j = 32 + d / 8
+        uint4* o = reinterpret_cast<uint4*>(s_stage + (wid * 64 + j) * 8);
+        o[0] = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+        o[1] = make_uint4(acc[4], acc[5], acc[6], acc[7]);
+    }
+    {   // this pass's share of clearing the table the previous pass read
+        const int64_t nthr = (int64_t)gridDim.x * gridDim.y * SM_THREADS;
+        const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * SM_THREADS + tid;
+        uint4* z4 = reinterpret_cast<uint4*>(tzero);
+        for (int64_t i = t0; i < zero_words / 4; i += nthr) z4[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    for (int i = tid; i < SM_WAVES * RS_BINS / 4; i += SM_THREADS)
+        reinterpret_cast<uint4*>(&s_cnt[0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (tout)
+        for (int i = tid; i < nch * (RS_BINS / 8); i += SM_THREADS)
+            reinterpret_cast<uint4*>(&s_next[0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    {
+        uint32_t pre = 0, tot = 0;
+        if (tid < RS_BINS) {
+#pragma unroll
+            for (int w = 0; w < SM_WAVES; ++w) {
+                pre += cnt ? s_stage[w * RS_BINS + tid] : s_stage[w * 512 + tid];
+                tot += cnt ? s_stage[SM_CHUNK + w * RS_BINS + tid] : s_stage[w * 512 + 256 + tid];
+            }
+        }
+        uint32_t all;
+        const uint32_t start = block_excl_scan<SM_WAVES>(tot, s_tmp, all);   // first position of digit tid
+        if (tid < RS_BINS) s_gb[tid] = start + pre;                          // ... of this chunk's keys of it
+    }
+
+    // Stable ranks inside each wave, as in k_radix_scatter.
+    const uint32_t dmask = 0xFFu;
+#pragma unroll
+    for (int it = 0; it < SM_ITEMS; ++it) {
+        const int j = wid * SM_WSPAN + it * 64 + lane;
+        const bool ok = j < n_valid;
+        const uint32_t d = (key[it] >> shift) & dmask;
+        uint64_t match = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot(ok && ((d >> b) & 1u));
+            match &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(match >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)match, 0u));
+        const uint32_t before = ok ? s_cnt[wid][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == 0) s_cnt[wid][d] = before + (uint32_t)__popcll(match);
+        __builtin_amdgcn_wave_barrier();
+        rank[it] = before + below;
+    }
+    __syncthreads();
+    {   // per digit: offsets of the waves, then the chunk-local start
+        uint32_t dtot = 0;
+        if (tid < RS_BINS) {
+#pragma unroll
+            for (int w = 0; w < SM_WAVES; ++w) {
+                const uint32_t x = s_cnt[w][tid];
+                s_cnt[w][tid] = dtot;
+                dtot += x;
+            }
+        }
+        uint32_t all;
+        const uint32_t ls = block_excl_scan<SM_WAVES>(dtot, s_tmp, all);
+        if (tid < RS_BINS) {
+            s_ls[tid] = ls;
+            s_gb[tid] -= ls;
+        }
+    }
+    __syncthreads();
+    const int nshift = shift + 8;
+#pragma unroll
+    for (int it = 0; it < SM_ITEMS; ++it) {
+        const int j = wid * SM_WSPAN + it * 64 + lane;
+        if (j < n_valid) {
+            const uint32_t d = (key[it] >> shift) & dmask;
+            const uint32_t pos = s_ls[d] + s_cnt[wid][d] + rank[it];
+            if (pos < (uint32_t)SM_CHUNK) {
+                s_stage[pos] = key[it];
+                s_stage[SM_CHUNK + pos] = val[it];
+                if (tout) {   // at most SM_CHUNK per counter: the 16-bit halves never carry
+                    const uint32_t g = s_gb[d] + pos, dn = (key[it] >> nshift) & dmask;
+                    if (g < count) atomicAdd(&s_next[g >> SM_LOG_CHUNK][dn >> 1], 1u << (16 * (dn & 1u)));
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SM_ITEMS; ++it) {
+        const int p = it * SM_THREADS + tid;
+        if (p < n_valid) {
+            const uint32_t k = s_stage[p];
+            const uint32_t g = s_gb[(k >> shift) & dmask] + (uint32_t)p;
+            if (g < count) {
+                ko[g] = k;
+                vo[g] = s_stage[SM_CHUNK + p];
+            }
+        }
+    }
+    if (!tout) return;
+    // tout[seg][c][e] = prefix over e of the placed keys per next digit, e = 0 .. nch, as packed
+    // 16-bit pairs (a half never exceeds SM_CHUNK, so the words add without carries): thread
+    // (part, w) sums rows [16 part, 16 part + 16) of word column w, then writes its prefixes
+    // after adding the lower parts' sums (part 3 also writes e = 64).
+    const int w = tid & (RS_BINS / 2 - 1), part = tid >> 7;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sum += (16 * part + e < nch) ? s_next[16 * part + e][w] : 0u;
+    s_cnt[part][w] = sum;    // the digit counters are no longer needed
+    __syncthreads();
+    uint32_t run = 0;
+    for (int q = 0; q < part; ++q) run += s_cnt[q][w];
+    uint32_t* trow = tout + ((int64_t)seg * SM_MAXCH + c) * (SM_MAXCH + 1) * (RS_BINS / 2) + w;
+    const int e1 = min(nch + 1, part == 3 ? SM_MAXCH + 1 : 16 * part + 16);
+    for (int e = 16 * part; e < e1; ++e) {
+        trow[(int64_t)e * (RS_BINS / 2)] = run;
+        run += e < nch ? s_next[e][w] : 0u;
+    }
+}
+
 int grid_for(int64_t chunks) {
     int64_t g = chunks < 1 ? 1 : chunks;
     return (int)(g > 2048 ? 2048 : g);
@@ -1004,6 +1252,25 @@ int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
     if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 8) return radix_passes<8>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+}
+
+int64_t small_sort_count_words(int64_t nseg) { return nseg * SM_MAXCH * RS_BINS; }
+int64_t small_sort_prefix_words(int64_t nseg) { return nseg * SM_MAXCH * (SM_MAXCH + 1) * (RS_BINS / 2); }
+
+int radix_sort_small(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, int nseg, uint32_t count,
+                     uint32_t* cnt, int64_t cnt_words, uint32_t* pre[2], hipStream_t s) {
+    // 32-bit keys in 4 passes of 8 bits; the second pass clears the first pass's counts
+    const int nch = (int)((count + SM_CHUNK - 1) >> SM_LOG_CHUNK);
+    if (nch == 0 || nch > SM_MAXCH) return 0;
+    int cur = 0;
+    for (int p = 0; p < 4; ++p) {
+        k_sort_small<<<dim3((unsigned)nch, (unsigned)nseg), SM_THREADS, 0, s>>>(
+            keys[cur], vals[cur], keys[1 - cur], vals[1 - cur], seg_stride, count, 8 * p, p == 0 ? cnt : nullptr,
+            p == 0 ? nullptr : pre[(p - 1) & 1], p < 3 ? pre[p & 1] : nullptr, p == 1 ? cnt : nullptr,
+            p == 1 ? cnt_words : 0);
+        cur = 1 - cur;
+    }
+    return cur;
 }
 
 int64_t onesweep_chunks(int64_t count) { return (count + OS_CHUNK - 1) / OS_CHUNK; }

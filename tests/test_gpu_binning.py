@@ -117,14 +117,18 @@ def test_binning_option_is_checked():
     ctx = G.Context(100, 1, 32, 32, 1 << 16)
     with pytest.raises(L.GstaError):
         ctx.set_option(L.OPT_BINNING, 2)
+    with pytest.raises(L.GstaError):
+        ctx.set_option(L.OPT_DEPTH_SORT, 3)
 
 
-@pytest.mark.parametrize("n,views", [(1, 1), (2049, 1), (100_000, 1), (4097, 8), (300_001, 2)])
-def test_onesweep_depth_sort_equals_pass_sort(n, views):
-    """The onesweep depth sort (GSTA_OPT_DEPTH_SORT 1) and the histogram /
-    scan / scatter passes (0) give the same stable order, bit for bit, and
-    the same images (the default path's order against the oracle is in
-    test_gpu_parity)."""
+@pytest.mark.parametrize("n,views", [(1, 1), (2049, 1), (4096, 3), (4097, 8), (100_000, 1), (131_072, 2),
+                                     (131_073, 1), (300_001, 2)])
+def test_depth_sort_variants_agree(n, views):
+    """The three depth sorts (GSTA_OPT_DEPTH_SORT 0: one kernel per pass for
+    views of at most 131072 Gaussians, else as 2; 1: onesweep; 2: histogram /
+    scan / scatter passes) give the same stable order, bit for bit, and the
+    same images, on both sides of the 131072 limit and of the 4096-key chunks
+    (the default path's order against the oracle is in test_gpu_parity)."""
     import torch
     import paper_2504_06716_amd as G
     from paper_2504_06716_amd import _lib as L
@@ -132,7 +136,7 @@ def test_onesweep_depth_sort_equals_pass_sort(n, views):
     p = S.make_scene(n, 0, seed=n % 97)
     cams = [S.look_at(10.0 * v, 40.0 * v, 48, 32) for v in range(views)]
     out = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         ctx = G.Context(n, views, 32, 48, 1 << 22)
         ctx.set_option(L.OPT_DEPTH_SORT, mode)
         P = dev(p)
@@ -144,7 +148,8 @@ def test_onesweep_depth_sort_equals_pass_sort(n, views):
         torch.cuda.synchronize()
         assert ctx.check()[0] == 0
         out.append((order.cpu().numpy(), img.cpu().numpy()))
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0])
+        assert np.array_equal(out[0][1], out[k][1])
     for v in range(views):                       # a permutation of the Gaussians
         assert np.array_equal(np.sort(out[0][0][v]), np.arange(n, dtype=np.int32))

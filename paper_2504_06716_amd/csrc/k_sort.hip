@@ -1010,9 +1010,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_sort_small(
     uint32_t* __restrict__ vout, int64_t seg_stride, uint32_t count, int shift, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ tin, uint32_t* __restrict__ tout, uint32_t* __restrict__ tzero,
     int64_t zero_words) {
-    __shared__ uint32_t s_stage[2 * SM_CHUNK];            // keys | values; first the table sums
-    __shared__ uint32_t s_cnt[SM_WAVES][RS_BINS];         // per-wave digit counters
-    __shared__ uint32_t s_next[SM_MAXCH][RS_BINS / 2];    // placed keys per (new chunk, next digit): u16 pairs
+    __shared__ __align__(16) uint32_t s_stage[2 * SM_CHUNK];           // keys | values; first the table sums
+    __shared__ __align__(16) uint32_t s_cnt[SM_WAVES][RS_BINS];        // per-wave digit counters
+    __shared__ __align__(16) uint32_t s_next[SM_MAXCH][RS_BINS / 2];   // placed keys per (new chunk, next digit): u16 pairs
     __shared__ uint32_t s_gb[RS_BINS];                    // new position of staged key p: s_gb[d] + p
     __shared__ uint32_t s_ls[RS_BINS];                    // chunk-local start of each digit
     __shared__ uint32_t s_tmp[SM_WAVES];
@@ -1182,22 +1182,47 @@ __global__ __launch_bounds__(SM_THREADS) void k_sort_small(
     if (!tout) return;
     // tout[seg][c][e] = prefix over e of the placed keys per next digit, e = 0 .. nch, as packed
     // 16-bit pairs (a half never exceeds SM_CHUNK, so the words add without carries): thread
-    // (part, w) sums rows [16 part, 16 part + 16) of word column w, then writes its prefixes
-    // after adding the lower parts' sums (part 3 also writes e = 64).
-    const int w = tid & (RS_BINS / 2 - 1), part = tid >> 7;
-    uint32_t sum = 0;
+    // (part, q) sums rows [4 part, 4 part + 4) of the 16-byte column q, then writes its prefixes
+    // after adding the lower parts' sums (part 15 also writes e = 64).
+    constexpr int Q = RS_BINS / 8;                         // 16-byte columns per row
+    static_assert(SM_THREADS == Q * (SM_MAXCH / 4), "four rows per part");
+    const uint4* nx = reinterpret_cast<const uint4*>(&s_next[0][0]);
+    uint4* s_part = reinterpret_cast<uint4*>(&s_cnt[0][0]);   // [16][Q]; the digit counters are done
+    const int q = tid & (Q - 1), part = tid / Q;
+    uint4 sum = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sum += (16 * part + e < nch) ? s_next[16 * part + e][w] : 0u;
-    s_cnt[part][w] = sum;    // the digit counters are no longer needed
+    for (int e = 4 * part; e < 4 * part + 4; ++e)
+        if (e < nch) {
+            const uint4 x = nx[e * Q + q];
+            sum.x += x.x;
+            sum.y += x.y;
+            sum.z += x.z;
+            sum.w += x.w;
+        }
+    s_part[part * Q + q] = sum;
     __syncthreads();
-    uint32_t run = 0;
-    for (int q = 0; q < part; ++q) run += s_cnt[q][w];
-    uint32_t* trow = tout + ((int64_t)seg * SM_MAXCH + c) * (SM_MAXCH + 1) * (RS_BINS / 2) + w;
-    const int e1 = min(nch + 1, part == 3 ? SM_MAXCH + 1 : 16 * part + 16);
-    for (int e = 16 * part; e < e1; ++e) {
-        trow[(int64_t)e * (RS_BINS / 2)] = run;
-        run += e < nch ? s_next[e][w] : 0u;
+    uint4 run = make_uint4(0u, 0u, 0u, 0u);
+    for (int k = 0; k < part; ++k) {
+        const uint4 x = s_part[k * Q + q];
+        run.x += x.x;
+        run.y += x.y;
+        run.z += x.z;
+        run.w += x.w;
     }
+    uint4* trow = reinterpret_cast<uint4*>(tout) + ((int64_t)seg * SM_MAXCH + c) * (SM_MAXCH + 1) * Q + q;
+#pragma unroll
+    for (int e = 4 * part; e < 4 * part + 4; ++e)
+        if (e <= nch) {
+            trow[(int64_t)e * Q] = run;
+            if (e < nch) {
+                const uint4 x = nx[e * Q + q];
+                run.x += x.x;
+                run.y += x.y;
+                run.z += x.z;
+                run.w += x.w;
+            }
+        }
+    if (part == SM_MAXCH / 4 - 1 && nch == SM_MAXCH) trow[(int64_t)SM_MAXCH * Q] = run;
 }
 
 int grid_for(int64_t chunks) {

@@ -839,7 +839,8 @@ size_t place_write_lds(int T, int win) {
     return (size_t)T * 4 * sizeof(uint64_t) + (size_t)(2 * T + 1) * sizeof(uint32_t) + (size_t)win * sizeof(uint16_t);
 }
 
-__global__ __launch_bounds__(PL_THREADS) void k_place_write(
+// Kept to 76 SGPRs: above about 80 a CU holds one 1024-thread block instead of two.
+__global__ __launch_bounds__(PL_THREADS) __attribute__((amdgpu_num_sgpr(76))) void k_place_write(
     const ushort4* __restrict__ rect, const uint32_t* __restrict__ order, int64_t stride, int64_t n, int nb,
     int ntx, int T, int win, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ tile_tot,
     const uint64_t* __restrict__ partials, const uint64_t* __restrict__ d_total, uint32_t* __restrict__ ids,
@@ -854,28 +855,40 @@ __global__ __launch_bounds__(PL_THREADS) void k_place_write(
     __shared__ uint32_t s_gid[PL_GAUSS];
     __shared__ ushort4 s_rect[PL_GAUSS];
     const int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
-    const uint32_t tot = place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp);
-    const uint64_t base = partials[(int64_t)v * nb + b];   // expansion index of the block's first instance
-    const uint64_t vbase = partials[(int64_t)v * nb];      // ... and of the view's
-    const bool over = *d_total > capacity;
-    if (tid < PL_GAUSS && (int64_t)b * PL_GAUSS + tid < n)
-        inst_off[(int64_t)v * stride + s_gid[tid]] = (uint32_t)min(base + s_off[tid], capacity);
-    // tile starts: the view's first index + exclusive scan of its tile totals
+    // this thread's tiles [ta, tb): their totals and the block's counts, loaded before anything waits
+    constexpr int kPer = (kPlaceMaxTiles + PL_THREADS - 1) / PL_THREADS;
     const int per = (T + PL_THREADS - 1) / PL_THREADS;
     const int ta = min(T, tid * per), tb = min(T, ta + per);
     const uint32_t* tt = tile_tot + (int64_t)v * T;
     const uint32_t* crow = cnt + ((int64_t)v * nb + b) * T;
-    {
+    uint32_t rt[kPer], rc[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        rt[i] = ta + i < tb ? tt[ta + i] : 0u;
+        rc[i] = ta + i < tb ? crow[ta + i] : 0u;
+    }
+    const uint64_t base = partials[(int64_t)v * nb + b];   // expansion index of the block's first instance
+    const uint64_t vbase = partials[(int64_t)v * nb];      // ... and of the view's
+    const bool over = *d_total > capacity;
+    const uint32_t tot = place_load(rect, order, stride, n, v, b, s_rect, s_gid, s_off, s_tmp);
+    if (tid < PL_GAUSS && (int64_t)b * PL_GAUSS + tid < n)
+        inst_off[(int64_t)v * stride + s_gid[tid]] = (uint32_t)min(base + s_off[tid], capacity);
+    {   // tile starts: the view's first index + exclusive scan of its tile totals
         uint32_t loc = 0, all;
-        for (int t = ta; t < tb; ++t) loc += tt[t];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) loc += rt[i];
         uint64_t start = vbase + block_excl_scan_1024(loc, s_tmp, all);
-        for (int t = ta; t < tb; ++t) {
-            const uint32_t rt = tt[t];
-            s_base[t] = (uint32_t)(start + crow[t]);
-            if (b == 0)
-                ranges[(int64_t)v * T + t] = (over || rt == 0) ? make_uint2(0u, 0u)
-                                                                 : make_uint2((uint32_t)start, (uint32_t)(start + rt));
-            start += rt;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = ta + i;
+            if (t < tb) {
+                s_base[t] = (uint32_t)(start + rc[i]);
+                if (b == 0)
+                    ranges[(int64_t)v * T + t] = (over || rt[i] == 0)
+                                                     ? make_uint2(0u, 0u)
+                                                     : make_uint2((uint32_t)start, (uint32_t)(start + rt[i]));
+            }
+            start += rt[i];
         }
     }
     if (over) return;   // nothing placed; the overflow is reported

@@ -70,7 +70,9 @@ __device__ __forceinline__ void adam_columns(int row, float* __restrict__ p, int
         v[row * vld + i] = vk;
         p[row * pld + i] -= lrr * (mk * rbc1) / (sqrtf(vk * rbc2) + eps);
     }
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1u);
+    // the first lane with a bad gradient reports it (lanes that returned early had none)
+    const uint64_t bb = __ballot(bad);
+    if (bb != 0ull && (int)(threadIdx.x & 63) == __builtin_ctzll(bb)) atomicOr(&flags[1], 1u);
 }
 
 // Grid: x over columns, y over rows.

@@ -458,10 +458,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
 constexpr int kChunk = 32;
 
 // Items per tile: ceil(tile_last / K) (one if segments are off), scanned by
-// one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total);
-// item_tile[i] names the tile of item i.
+// one workgroup of 1024 threads into item_off[0..nt] (item_off[nt] = total),
+// two tiles per thread and round; item_tile[i] names the tile of item i.
 // With a fused L1 loss (sums set) it also adds the forward's nparts
-// per-workgroup loss sums in a fixed order.
+// per-workgroup loss sums in a fixed order (thread t: parts t, t + 1024, ...;
+// the first kSegPre of them loaded before the scan).
+constexpr int kSegPre = 8;
 __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__ tile_last, int nt, uint32_t shift,
                                                     uint32_t* __restrict__ item_off, uint32_t* __restrict__ item_tile,
                                                     uint32_t item_cap, const double2* __restrict__ lpart,
@@ -469,16 +471,27 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double2 pre[kSegPre];
+#pragma unroll
+    for (int k = 0; k < kSegPre; ++k) {
+        const int i = (int)threadIdx.x + 1024 * k;
+        pre[k] = (sums && i < nparts) ? lpart[i] : make_double2(0.0, 0.0);
+    }
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    for (int base = 0; base < nt; base += 1024) {
-        const int j = base + (int)threadIdx.x;
-        uint32_t x = 0;
-        if (j < nt) {
-            const uint32_t l = tile_last[j];
-            x = shift >= 31u ? (l ? 1u : 0u) : ((l + (1u << shift) - 1u) >> shift);
+    for (int base = 0; base < nt; base += 2048) {
+        const int j0 = base + 2 * (int)threadIdx.x;
+        uint32_t x[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            x[h] = 0;
+            if (j0 + h < nt) {
+                const uint32_t l = tile_last[j0 + h];
+                x[h] = shift >= 31u ? (l ? 1u : 0u) : ((l + (1u << shift) - 1u) >> shift);
+            }
         }
-        uint32_t incl = x;
+        const uint32_t xs = x[0] + x[1];
+        uint32_t incl = xs;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
@@ -488,11 +501,15 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
         __syncthreads();
         uint32_t wbase = s_carry;
         for (int k = 0; k < w; ++k) wbase += s_w[k];
-        if (j < nt) {
-            const uint32_t off = wbase + incl - x;
-            item_off[j] = off;
-            for (uint32_t i = 0; i < x; ++i)
-                if (off + i < item_cap) item_tile[off + i] = (uint32_t)j;
+        uint32_t off = wbase + incl - xs;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (j0 + h < nt) {
+                item_off[j0 + h] = off;
+                for (uint32_t i = 0; i < x[h]; ++i)
+                    if (off + i < item_cap) item_tile[off + i] = (uint32_t)(j0 + h);
+                off += x[h];
+            }
         }
         __syncthreads();
         if (threadIdx.x == 1023) s_carry = wbase + incl;
@@ -502,8 +519,13 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
     if (sums) {   // uniform
         __shared__ double s_a[16], s_b[16];
         double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSegPre; ++k) {
+            a += pre[k].x;
+            b += pre[k].y;
+        }
 #pragma unroll 4
-        for (int i = (int)threadIdx.x; i < nparts; i += 1024) {
+        for (int i = (int)threadIdx.x + 1024 * kSegPre; i < nparts; i += 1024) {
             a += lpart[i].x;
             b += lpart[i].y;
         }

@@ -137,8 +137,35 @@ __device__ __forceinline__ void fwd_checkpoint(const SegCkpt& sc, uint32_t gpos,
 // length is).
 constexpr int kStep = 4;
 
+// Whether a splat can be a member of a pixel of the box [x0, x1] x [y0, y1]
+// (pixel coordinates).  A member has power2 >= max(kPower2Floor,
+// -log2(255 o)) (the 3-sigma floor and alpha >= 1/255), i.e. the positive
+// form Q(d) = -power2(d) at most minus that bound; Q's minimum over the box is
+// 0 if the centre is inside, else on an edge, where it is the clamped
+// stationary point of a parabola.  The margin (0.1 in log2 units, plus a
+// relative 1e-4 of the form's size over the box) covers the float rounding of
+// this test and of the walk's own evaluation, so a false answer is certain.
+__device__ __forceinline__ bool splat_reaches_box(float u, float v, float A, float B, float C, float o, float x0,
+                                                  float x1, float y0, float y1) {
+    const float a = -A, b = -B, c = -C;   // Q = a dx^2 + b dx dy + c dy^2, d = (u, v) - pixel
+    const float dx0 = u - x1, dx1 = u - x0, dy0 = v - y1, dy1 = v - y0;
+    float qmin = 0.f;
+    if (!(dx0 <= 0.f && dx1 >= 0.f && dy0 <= 0.f && dy1 >= 0.f)) {
+        const float ry = 0.5f * b / c, rx = 0.5f * b / a;
+        const float ya = fminf(fmaxf(-ry * dx0, dy0), dy1), yb = fminf(fmaxf(-ry * dx1, dy0), dy1);
+        const float xa = fminf(fmaxf(-rx * dy0, dx0), dx1), xb = fminf(fmaxf(-rx * dy1, dx0), dx1);
+        const float qa = (a * dx0 + b * ya) * dx0 + c * ya * ya, qb = (a * dx1 + b * yb) * dx1 + c * yb * yb;
+        const float qc = (c * dy0 + b * xa) * dy0 + a * xa * xa, qd = (c * dy1 + b * xb) * dy1 + a * xb * xb;
+        qmin = fminf(fminf(qa, qb), fminf(qc, qd));
+    }
+    const float thr = fmaxf(kPower2Floor, -log2f(255.0f * o));
+    const float dxm = fmaxf(fabsf(dx0), fabsf(dx1)), dym = fmaxf(fabsf(dy0), fabsf(dy1));
+    const float size = a * dxm * dxm + c * dym * dym + fabsf(b) * dxm * dym;
+    return qmin <= -thr + 0.1f + 1e-4f * size;
+}
+
 template <int W, bool QUAD, bool CNT>
-__global__ __launch_bounds__(64 * W) void k_composite_fwd(
+__global__ __launch_bounds__(64 * W, QUAD ? 5 : 1) void k_composite_fwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ gsort,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, CamArray cams, float bg0, float bg1, float bg2, float* __restrict__ image,
@@ -228,11 +255,14 @@ __global__ __launch_bounds__(64 * W) void k_composite_fwd(
         int cnt;
         if (QUAD) {
             // Keep only the splats whose member extent (col.z, col.w: half-widths
-            // beyond which no pixel can be a member) reaches the quarter: the
-            // others are non-members of every pixel here and would leave T and
-            // the colour as they are.  The kept records stay in list order.
+            // beyond which no pixel can be a member) and member ellipse reach
+            // the quarter: the others are non-members of every pixel here and
+            // would leave T and the colour as they are.  The kept records stay
+            // in list order.
             const bool hit = base + tid < rg.y && cur.g.x + cur.co.z >= qx0 && cur.g.x - cur.co.z <= qx0 + 7.0f &&
-                             cur.g.y + cur.co.w >= qy0 && cur.g.y - cur.co.w <= qy0 + 7.0f;
+                             cur.g.y + cur.co.w >= qy0 && cur.g.y - cur.co.w <= qy0 + 7.0f &&
+                             splat_reaches_box(cur.g.x, cur.g.y, cur.g.z, cur.g.w, cur.co.x, cur.co.y, qx0,
+                                               qx0 + 7.0f, qy0, qy0 + 7.0f);
             const uint64_t hm = __ballot(hit);
             const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));

@@ -595,6 +595,8 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     __shared__ float4 s_rgb[B];
     __shared__ uint32_t s_idx[B];
     __shared__ uint32_t s_frz[B];
+    __shared__ uint32_t s_pos[B];      // list position (from the tile's start) of each kept record
+    __shared__ uint32_t s_wkept[W];
     // row totals; the chunk dimension is padded to kChunk + 1 words so that the
     // four row writers of a wave (rows 4 wid .. +3, stride 9 (kChunk + 1))
     // fall into different LDS banks
@@ -700,13 +702,31 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
             }
         }
         for (uint32_t base = beg; base < end; base += B) {
+            // Keep only the splats whose member ellipse reaches the tile (the
+            // others are non-members of all its pixels: they would change
+            // nothing and get no gradient), in list order.
+            const bool hit = base + tid < end && splat_reaches_box(cur.g.x, cur.g.y, cur.g.z, cur.g.w, cur.co.x,
+                                                                   cur.co.y, (float)tx0, (float)(tx0 + kTile - 1),
+                                                                   (float)ty0, (float)(ty0 + kTile - 1));
+            const uint64_t hm = __ballot(hit);
             __syncthreads();
-            if (base + tid < end) {
-                s_idx[tid] = idx_cur;
-                s_geo[tid] = cur.g;
-                s_co[tid] = cur.co;
-                s_rgb[tid] = cur.c;
-                s_frz[tid] = frz_cur;
+            if (lane == 0) s_wkept[wid] = (uint32_t)__popcll(hm);
+            __syncthreads();
+            int cnt = 0, woff = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                woff += w < wid ? (int)s_wkept[w] : 0;
+                cnt += (int)s_wkept[w];
+            }
+            if (hit) {
+                const int r = woff + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                s_idx[r] = idx_cur;
+                s_geo[r] = cur.g;
+                s_co[r] = cur.co;
+                s_rgb[r] = cur.c;
+                s_frz[r] = frz_cur;
+                s_pos[r] = base - rg.x + (uint32_t)tid;
             }
             __syncthreads();
             {
@@ -721,11 +741,10 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                     gid_nxt = gsort[jn + B];
                 }
             }
-            const int cnt = (int)min((uint32_t)B, end - base);
             for (int c0 = 0; c0 < cnt; c0 += kChunk) {
                 const int c1 = min(cnt, c0 + kChunk);
                 for (int k = c0; k < c1; ++k) {
-                    const uint32_t pos = base - rg.x + (uint32_t)k;
+                    const uint32_t pos = s_pos[k];
                     const float4 g = s_geo[k];
                     const float2 co = make_float2(s_co[k].x, s_co[k].y);
                     // uniform over the wave: a scalar branch

@@ -27,7 +27,8 @@ constexpr float kFltMax = 3.402823466e+38f;
 __global__ void k_zero_count(unsigned long long* p) { *p = 0ull; }
 
 // freeze map update with condition `cond` (mode 0: OR, 1: reset, 2: replace)
-// and the frozen count by ballot
+// and the frozen count by ballot, one atomic per 256-thread workgroup (every
+// thread calls this; same-address atomics serialise)
 __device__ __forceinline__ void apply_and_count(bool in, int64_t i, bool cond, int mode, uint8_t* frozen,
                                                 unsigned long long* n_frozen) {
     bool f = false;
@@ -36,8 +37,14 @@ __device__ __forceinline__ void apply_and_count(bool in, int64_t i, bool cond, i
         frozen[i] = f ? 1 : 0;
     }
     if (n_frozen) {
+        __shared__ uint32_t s_c[4];
         const uint64_t b = __ballot(f);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_frozen, (unsigned long long)__popcll(b));
+        if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t c = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+            if (c) atomicAdd(n_frozen, (unsigned long long)c);
+        }
     }
 }
 

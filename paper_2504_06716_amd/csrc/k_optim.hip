@@ -130,9 +130,15 @@ __global__ __launch_bounds__(256) void k_freeze(const float* __restrict__ sx, co
         f = (mode == 0) ? ((frozen[i] != 0) || cond) : (mode == 1 ? false : cond);
         frozen[i] = f ? 1 : 0;
     }
-    if (n_frozen) {
-        const uint64_t b = __ballot(f);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_frozen, (unsigned long long)__popcll(b));
+    if (n_frozen) {   // uniform; one atomic per workgroup (same-address atomics serialise)
+        __shared__ uint32_t s_w[4];
+        const uint64_t bal = __ballot(f);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t c = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+            if (c) atomicAdd(n_frozen, (unsigned long long)c);
+        }
     }
 }
 

@@ -143,7 +143,7 @@ typedef enum {
                                    1 always expands and sorts the tile keys (LSD radix).  Both give
                                    the same lists (Section 3.1: splats per tile in depth order). */
     GSTA_OPT_DEPTH_SORT = 4,    /* the per-view depth sort: 0 (default) one kernel per 8-bit pass
-                                   for views of at most 131072 Gaussians (4096 keys per workgroup,
+                                   for views of at most 131072 Gaussians (2048 keys per workgroup,
                                    each pass leaving the next its per-chunk digit counts), else as
                                    2; 1 onesweep (a global digit histogram, then one kernel per
                                    pass with decoupled look-back); 2 histogram / scan / scatter

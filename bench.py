@@ -285,7 +285,7 @@ def c3_throughput(torch, steps, vb=4):
     cams = S.config_cameras("c3")
     log("c3: sizing the instance capacity, rendering targets")
     from paper_2504_06716_amd.train import required_capacity
-    ctx = Context(n, vb, H, W, instance_capacity=(1 << 28), n_slots=1)
+    ctx = Context(n, vb, H, W, instance_capacity=(1 << 22), n_slots=1)   # sized below from the count
     pt = S.perturb_scene(p0, D)
     need = max(required_capacity(ctx, p0, D, cams), required_capacity(ctx, pt, D, cams))
     ctx.reserve(instance_capacity=min(int(need * 1.5) + 4096, (1 << 32) - 1))

@@ -18,6 +18,7 @@ namespace {
 constexpr int kCounters = 6;   // profiling counters, see gsta_read_profile
 constexpr int64_t kPlaceBytes = (int64_t)1 << 29;   // placement count scratch limit
 const uint32_t kGen0 = 1u;      // first backward generation (stamps start at 0)
+const int64_t kPoolBudgetSlots = (int64_t)1 << 22;   // checkpoint slots sized for full walks: 8 GiB
 
 struct Slot {
     float4* geo = nullptr;
@@ -191,14 +192,23 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
     ctx->slots.assign((size_t)l->n_slots, Slot());
     // checkpoint slots: the forward reserves, per tile and walked batch of up
     // to 256 list positions, one slot per 64-pixel group and boundary (up to
-    // 4 boundaries at the shortest segment, 64), and one batch ahead.  Room
-    // for two batches of every tile of every view plus one slot per 256
-    // instances of capacity for longer walks; running out is reported.
+    // 4 boundaries at the shortest segment, 64), and one batch ahead.  The
+    // tiles' first batches own their slots; the counter hands out the rest:
+    // at most one per group and 64 walked positions -- (cap >> 6) per group
+    // when every list is walked to its end (transmittance never reaching its
+    // floor) -- plus each tile's one batch reserved ahead.  The pool holds
+    // that many (2 KiB per slot: 128 bytes per instance of capacity) where
+    // they fit kPoolBudgetSlots, so no walk can run out; past it, the larger
+    // of the budget and one slot per 256 instances, and running out is
+    // reported.
     static_assert(kBatchSlotsMax == (uint32_t)kCkptGroups * (256u >> kMinSegShift), "batch slot bound");
     const int64_t per_batch = kBatchSlotsMax;
     ctx->first_slots = (uint32_t)(V * ctx->tiles_max * per_batch);
+    const int64_t ahead = 2 * V * ctx->tiles_max * per_batch;
+    const int64_t full = kCkptGroups * ((cap >> kMinSegShift) + 1) + ahead;
     const int64_t pool_cap = std::min<int64_t>(
-        std::max<int64_t>(4096, cap / 256 + 2 * V * ctx->tiles_max * per_batch), (int64_t)1 << 30);
+        std::max<int64_t>(4096, std::min<int64_t>(full, std::max<int64_t>(cap / 256 + ahead, kPoolBudgetSlots))),
+        (int64_t)1 << 30);
     ctx->pool_cap = (uint32_t)pool_cap;
     // work items of the backward: ceil(tile_last / K) per tile, K >= 2^kMinSegShift,
     // and the tiles' walks add up to at most the instance capacity

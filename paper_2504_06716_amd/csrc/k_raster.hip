@@ -31,20 +31,36 @@
 namespace gsta {
 namespace {
 
-// Sum over each row of 16 lanes with DPP: pairs, quads, then the mirror
-// within each half-row (lane i and 7 - i) and within the row (i and 15 - i),
-// permutations under which every lane has a source.  Every lane of a row
-// holds its row's total, (q0 + q1) + (q2 + q3) over its quads.
-__device__ __forceinline__ float row_sum(float v) {
-    int x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
-    x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
-    x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));
-    x = __builtin_bit_cast(int, v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, true));
-    return v;
+// The row totals of nine values at once, transposing as it sums: at each of
+// the four exchanges (lane ^ 1, lane ^ 2 within quads, then the row rotated
+// by 4 and by 8, whose partners share the lower lane bits) a lane keeps the
+// half of its values that its bit of the lane index selects and adds its
+// partner's copy of them, so the pairs of values halve each time: 13 + 7 + 4
+// + 2 adds and selects instead of 36 adds.  Lane l of a row ends with the
+// row total of value l & 7 (out) and of value 8 (out8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ float keep_add(float a, float b, bool hi) {
+    const float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp_row<CTRL>(send);
+}
+__device__ __forceinline__ void row_sum9(const float (&g)[9], int lane, float& out, float& out8) {
+    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
+    const float p0 = keep_add<0xB1>(g[0], g[1], b0), p1 = keep_add<0xB1>(g[2], g[3], b0);
+    const float p2 = keep_add<0xB1>(g[4], g[5], b0), p3 = keep_add<0xB1>(g[6], g[7], b0);
+    float v8 = g[8] + dpp_row<0xB1>(g[8]);
+    const float r0 = keep_add<0x4E>(p0, p1, b1), r1 = keep_add<0x4E>(p2, p3, b1);
+    v8 += dpp_row<0x4E>(v8);
+    float s0 = keep_add<0x124>(r0, r1, b2);   // row_ror:4
+    v8 += dpp_row<0x124>(v8);
+    s0 += dpp_row<0x128>(s0);                 // row_ror:8
+    v8 += dpp_row<0x128>(v8);
+    out = s0;
+    out8 = v8;
 }
 
 // One splat record as staged in LDS: mean + scaled conic (A, B), scaled
@@ -597,9 +613,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
     __shared__ uint32_t s_frz[B];
     __shared__ uint32_t s_pos[B];      // list position (from the tile's start) of each kept record
     __shared__ uint32_t s_wkept[W];
-    // row totals; the chunk dimension is padded to kChunk + 1 words so that the
-    // four row writers of a wave (rows 4 wid .. +3, stride 9 (kChunk + 1))
-    // fall into different LDS banks
+    // row totals; the chunk dimension is padded to kChunk + 1 words so that
+    // the 36 words one write of a wave fills (rows 4 wid .. +3, values 0-8)
+    // fall into nearly distinct LDS banks
     __shared__ float s_part[4 * W][9][kChunk + 1];
     __shared__ unsigned int s_pairs, s_grad;
 
@@ -810,13 +826,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                         }
                         if (!frz && __ballot(contrib) != 0ull) {
                             if (CNT) wred += 1u;
-#pragma unroll
-                            for (int q = 0; q < 9; ++q) g9[q] = row_sum(g9[q]);
-                            // every lane of a row writes its row's total (the same value to
-                            // the same word): no lane mask, so the last DPP step of the row
-                            // sum stays one fused add
-#pragma unroll
-                            for (int q = 0; q < 9; ++q) s_part[4 * wid + (lane >> 4)][q][k - c0] = g9[q];
+                            float t, t8;
+                            row_sum9(g9, lane, t, t8);
+                            // one write per lane, no lane mask: lanes 0-7 of a row write
+                            // values 0-7, lanes 8-15 all value 8 (the same word and value)
+                            const bool hi8 = (lane & 8) != 0;
+                            s_part[4 * wid + (lane >> 4)][hi8 ? 8 : (lane & 7)][k - c0] = hi8 ? t8 : t;
                         }
                     }
                 }

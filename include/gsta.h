@@ -124,9 +124,9 @@ typedef enum {
 
 /* Execution options (gsta_set_option).  They change speed, not what is
  * computed: images, states and forward decisions are bit-identical for every
- * setting, and so are gradients except across GSTA_OPT_BWD_WAVES and
- * GSTA_OPT_BWD_VARIANT, which change the order of the backward's float
- * additions (agreement to rounding). */
+ * setting, and so are gradients except across GSTA_OPT_BWD_WAVES,
+ * GSTA_OPT_BWD_VARIANT and GSTA_OPT_BWD_SEGMENT, which change the order of
+ * the backward's float additions (agreement to rounding). */
 typedef enum {
     GSTA_OPT_FWD_WAVES = 0,     /* forward compositing: 0 (default): one independent wave per 8x8
                                    quarter of each tile, each writing its quarter's backward
@@ -136,7 +136,7 @@ typedef enum {
                                    two in [64, 65536] (default 64).  The forward checkpoints every
                                    pixel's transmittance and colour prefix at each multiple of it, so
                                    the backward of a long tile list is spread over several
-                                   workgroups; the result does not depend on it. */
+                                   workgroups; gradients depend on it only through rounding. */
     GSTA_OPT_BINNING = 3,       /* how the per-tile lists are built: 0 (default) places every tile
                                    instance directly where views have at most 1408 tiles and the
                                    placement scratch was reserved for the call's views, else sorts;

@@ -649,10 +649,12 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
         const uint32_t p1 = seg ? min(tl, (sgi + 1u) << sc.shift) : tl;          // one past its last
 
         float fpx[P], fpy[P], dC[P][3], T[P];
-        // FB: the pixel's final colour, background term included (the
-        // forward's double colour + T_final bg); FB - A is then what lies
-        // behind the current splat
-        double FB[P][3], A[P][3];
+        // Db = sum over channels of dL/dC (FB - A): FB the pixel's final
+        // colour, background term included (the forward's double colour +
+        // T_final bg), A the colour of the splats walked so far, so FB - A is
+        // what lies behind the current splat.  A splat of colour c and weight
+        // w takes w (dL/dC . c) off it.  dCd: dL/dC in double.
+        double Db[P], dCd[P][3];
         uint32_t last[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -661,9 +663,9 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
             fpx[p] = (float)px;
             fpy[p] = (float)py;
             T[p] = 1.0f;
-            A[p][0] = A[p][1] = A[p][2] = 0.0;
             dC[p][0] = dC[p][1] = dC[p][2] = 0.f;
-            FB[p][0] = FB[p][1] = FB[p][2] = 0.0;
+            dCd[p][0] = dCd[p][1] = dCd[p][2] = 0.0;
+            Db[p] = 0.0;
             last[p] = 0;
             if (px < cm.width && py < cm.height) {
                 const int64_t o = (int64_t)py * cm.width + px;
@@ -673,11 +675,13 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                     dC[p][0] = dl[0];
                     dC[p][1] = dl[HW];
                     dC[p][2] = dl[2 * HW];
+                    dCd[p][0] = (double)dC[p][0];
+                    dCd[p][1] = (double)dC[p][1];
+                    dCd[p][2] = (double)dC[p][2];
                     const float tf = T_final[(int64_t)v * HW + o];
                     const double* cf = cfg + (int64_t)v * 3 * HW + o;
-                    FB[p][0] = cf[0] + (double)(tf * bg0);
-                    FB[p][1] = cf[HW] + (double)(tf * bg1);
-                    FB[p][2] = cf[2 * HW] + (double)(tf * bg2);
+                    Db[p] = dCd[p][0] * (cf[0] + (double)(tf * bg0)) + dCd[p][1] * (cf[HW] + (double)(tf * bg1)) +
+                            dCd[p][2] * (cf[2 * HW] + (double)(tf * bg2));
                 }
             }
         }
@@ -694,9 +698,7 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                 }
                 const double* d = sc.pool + (size_t)slot * 256;
                 T[p] = (float)d[lane];
-                A[p][0] = d[64 + lane];
-                A[p][1] = d[128 + lane];
-                A[p][2] = d[192 + lane];
+                Db[p] -= dCd[p][0] * d[64 + lane] + dCd[p][1] * d[128 + lane] + dCd[p][2] * d[192 + lane];
             }
         }
         const uint32_t beg = rg.x + p0, end = rg.x + p1;
@@ -793,19 +795,14 @@ __global__ __launch_bounds__(64 * W) void k_composite_bwd(
                             const bool m = mem[p] && (e[p].alpha >= kAlphaMin);
                             const float w = m ? e[p].alpha * T[p] : 0.f;
                             const double wd = (double)w;
-                            A[p][0] = fma(cx, wd, A[p][0]);
-                            A[p][1] = fma(cy, wd, A[p][1]);
-                            A[p][2] = fma(cz, wd, A[p][2]);
+                            const double dcc = fma(dCd[p][2], cz, fma(dCd[p][1], cy, dCd[p][0] * cx));
+                            Db[p] = fma(-wd, dcc, Db[p]);
                             if (!frz) {   // uniform
                                 contrib = contrib || m;
                                 if (CNT) ngrad += m ? 1u : 0u;
                                 const float inv1m = __builtin_amdgcn_rcpf(1.0f - e[p].alpha);
-                                const float b0 = (float)(FB[p][0] - A[p][0]);
-                                const float b1 = (float)(FB[p][1] - A[p][1]);
-                                const float b2 = (float)(FB[p][2] - A[p][2]);
-                                const float da = dC[p][0] * (c.x * T[p] - b0 * inv1m) +
-                                                 dC[p][1] * (c.y * T[p] - b1 * inv1m) +
-                                                 dC[p][2] * (c.z * T[p] - b2 * inv1m);
+                                // sum over channels of dL/dC (c T - behind / (1 - alpha))
+                                const float da = fmaf(T[p], (float)dcc, -((float)Db[p] * inv1m));
                                 g9[6] += dC[p][0] * w;
                                 g9[7] += dC[p][1] * w;
                                 g9[8] += dC[p][2] * w;

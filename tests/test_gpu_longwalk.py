@@ -3,11 +3,12 @@ only near a splat's centre) whose pixels never reach the transmittance
 floor, so every quarter walks its tile's whole list (~12000 splats) and the
 forward writes a checkpoint at every multiple of the segment length.  The
 checkpoint pool holds a slot per 64-pixel group and 64 instances of capacity
-(where that fits 8 GiB, as here), so such walks cannot run out of it: the call succeeds (no capacity flag), and
-the images, final transmittance, last members and gradients equal, bit for
-bit, those of the walk with no segments (one backward item per tile, no
-checkpoints).  (The pool once held one slot per 256 instances: this scene
-needs ~6800 slots, at most 4096 were there.)"""
+(where that fits 8 GiB, as here), so such walks cannot run out of it: the
+call succeeds (no capacity flag), the images, final transmittance and last
+members equal, bit for bit, those of the walk with no segments (one backward
+item per tile, no checkpoints), and the gradients agree with it to rounding.
+(The pool once held one slot per 256 instances: this scene needs ~6800
+slots, at most 4096 were there.)"""
 import numpy as np
 import pytest
 import torch
@@ -47,8 +48,10 @@ def test_long_walks_fit_the_checkpoint_pool(fwd):
     p, D, cams = _faint_scene(30000, 48, 7)
     seg = _run(p, D, cams, fwd, 64)
     whole = _run(p, D, cams, fwd, 0)
-    for k in ("img", "tf", "last", "grad", "g2"):
+    for k in ("img", "tf", "last"):
         assert np.array_equal(seg[k], whole[k]), k
+    for k in ("grad", "g2"):
+        np.testing.assert_allclose(seg[k], whole[k], rtol=1e-4, atol=1e-6 * np.abs(whole[k]).max(), err_msg=k)
     # walks past thousands of list positions, nowhere near the floor
     assert seg["last"].max() > 6000
     assert seg["tf"].min() > 1e-3

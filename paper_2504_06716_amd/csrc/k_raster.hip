@@ -597,8 +597,10 @@ __global__ __launch_bounds__(1024) void k_seg_items(const uint32_t* __restrict__
     }
 }
 
+// Two waves per tile (the default): at most 96 VGPRs, five waves per SIMD, so
+// that nine of these workgroups (the LDS bound) fit a CU instead of eight.
 template <int W, bool CNT>
-__global__ __launch_bounds__(64 * W) void k_composite_bwd(
+__global__ __launch_bounds__(64 * W, W == 2 ? 5 : 1) void k_composite_bwd(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ gsort,
     const float4* __restrict__ geo, const float4* __restrict__ col, const float4* __restrict__ rgbv,
     int64_t stride, const uint8_t* __restrict__ frozen, CamArray cams, int nv, float bg0, float bg1, float bg2,

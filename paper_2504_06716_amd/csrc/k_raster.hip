@@ -812,14 +812,18 @@ __global__ __launch_bounds__(64 * W, W == 2 ? 5 : 1) void k_composite_bwd(
                                 const float dalpha = (m && e[p].oG <= kAlphaMax) ? da : 0.f;
                                 // d power / d(u, v) = -(a dx + b dy, b dx + c dy)
                                 //                   = ln 2 (2 A dx + B dy, B dx + 2 C dy)
+                                // The splat's conic is the same for all its pixels: the
+                                // pixels accumulate the moments of dpow = dalpha alpha,
+                                // sum dpow (dx, dy, dx^2, dx dy, dy^2), and the flush
+                                // forms the 2-D gradient from them.
                                 const float dpow = dalpha * e[p].alpha;
-                                const float dpl = dpow * kLn2;
                                 g9[5] += dalpha * e[p].G;
-                                g9[0] += dpl * (2.0f * g.z * e[p].dx + g.w * e[p].dy);
-                                g9[1] += dpl * (g.w * e[p].dx + 2.0f * co.x * e[p].dy);
-                                g9[2] -= 0.5f * dpow * e[p].dx * e[p].dx;
-                                g9[3] -= dpow * e[p].dx * e[p].dy;
-                                g9[4] -= 0.5f * dpow * e[p].dy * e[p].dy;
+                                const float tx = dpow * e[p].dx, ty = dpow * e[p].dy;
+                                g9[0] += tx;
+                                g9[1] += ty;
+                                g9[2] = fmaf(tx, e[p].dx, g9[2]);
+                                g9[3] = fmaf(tx, e[p].dy, g9[3]);
+                                g9[4] = fmaf(ty, e[p].dy, g9[4]);
                             }
                             T[p] = m ? next_T(T[p], e[p].alpha) : T[p];
                         }
@@ -855,6 +859,17 @@ __global__ __launch_bounds__(64 * W, W == 2 ? 5 : 1) void k_composite_bwd(
                                 nz = nz || (acc != 0.f);
                             }
                             if (nz) {   // a slot counts only with this call's stamp
+                                // from the moments (sums of dpow dx, dpow dy, dpow dx^2,
+                                // dpow dx dy, dpow dy^2) to the gradient of the mean,
+                                // d power / d(u, v) = ln 2 (2 A dx + B dy, B dx + 2 C dy),
+                                // and of the conic entries (-dx^2 / 2, -dx dy, -dy^2 / 2)
+                                const float A = s_geo[k].z, B = s_geo[k].w, C = s_co[k].x;
+                                const float X = sum[0], Y = sum[1];
+                                sum[0] = kLn2 * fmaf(2.0f * A, X, B * Y);
+                                sum[1] = kLn2 * fmaf(B, X, 2.0f * C * Y);
+                                sum[2] = -0.5f * sum[2];
+                                sum[3] = -sum[3];
+                                sum[4] = -0.5f * sum[4];
                                 float* dst = partials + (int64_t)s_idx[k] * 9;
 #pragma unroll
                                 for (int q = 0; q < 9; ++q) dst[q] = sum[q];

@@ -17,12 +17,15 @@
 // segment up to its last member and recomputes the transmittance with the
 // same instructions as the forward (shared eval_splat / next_T), so every
 // membership and termination decision is identical.  The colour behind a
-// member is the forward colour minus the recomputed prefix (both double).
+// member enters dL/dalpha only through its dot product with dL/dC, which
+// each pixel carries as one double: the forward colour's (at a segment start
+// minus the checkpointed prefix's), less w (dL/dC . c) per walked splat.
 // Frozen splats still attenuate the pixels behind them but get no gradient
-// work.  Per splat, a thread sums its pixels' 9 partial derivatives, each
-// row of 16 lanes sums them with DPP operations, the rows' totals (4 per
-// wave) are added through LDS in a fixed order every kChunk splats, and the
-// tile's total is written to the splat's own
+// work.  Per splat, a thread sums its pixels' 9 terms (dL/d opacity, colour,
+// and the moments of dalpha alpha over dx, dy), each row of 16 lanes sums
+// them with DPP operations, the rows' totals (4 per wave) are added through
+// LDS in a fixed order every kChunk splats, the splat's conic turns the
+// moments into its 2-D gradient, and the tile's total is written to the splat's own
 // slot (its position in the depth-ordered expansion) -- no atomics, so the
 // backward is deterministic.  The per-Gaussian sum over tiles happens in the
 // preprocess backward, in a fixed order too.

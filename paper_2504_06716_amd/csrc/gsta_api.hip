@@ -29,7 +29,8 @@ struct Slot {
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* ikey[2] = {nullptr, nullptr};
     uint32_t* ival[2] = {nullptr, nullptr};
-    uint32_t* inst_gid = nullptr;   // [cap] gid of each expansion index (sorted path)
+    uint32_t* inst_gid = nullptr;   // [cap] gid of each expansion index (written for the state export)
+    uint4* rank_tab = nullptr;      // [V][S] gid, first instance, rectangle of each depth rank (sorted path)
     uint32_t* gsort = nullptr;      // [cap] gid at each tile-list position
     uint32_t* inst_off = nullptr;   // [V][S] first expansion index of each Gaussian
     uint2* ranges = nullptr;
@@ -221,6 +222,7 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.dval[0], V * S) && alloc(ctx, &s.dval[1], V * S) && alloc(ctx, &s.ikey[0], cap) &&
              alloc(ctx, &s.ikey[1], cap) && alloc(ctx, &s.ival[0], cap) && alloc(ctx, &s.ival[1], cap) &&
              alloc(ctx, &s.inst_gid, cap) && alloc(ctx, &s.gsort, cap) && alloc(ctx, &s.inst_off, V * S) &&
+             alloc(ctx, &s.rank_tab, V * S) &&
              alloc(ctx, &s.ranges, V * ctx->tiles_max) && alloc(ctx, &s.T_final, V * HW) &&
              alloc(ctx, &s.last, V * HW) && alloc(ctx, &s.cfg, 3 * V * HW) && alloc(ctx, &s.n_total, 1) &&
              alloc(ctx, &s.n_count, 1) && alloc(ctx, &s.ck_idx, ((cap >> kMinSegShift) + 2) * kCkptGroups) &&
@@ -627,9 +629,10 @@ gsta_status gsta_get_state(gsta_ctx* ctx, int32_t slot, int32_t field, void* dst
         if (st != GSTA_OK) return st;
         src = s.ikey[0];
     }
-    if (field == GSTA_STATE_INST_GID && s.placed) {
-        // placed lists are built without the per-expansion-index gids
-        launch_gid_by_index(s.ival[0], s.gsort, s.n_count, ctx->lim.instance_capacity, s.inst_gid, stream);
+    if (field == GSTA_STATE_INST_GID) {
+        // the lists are built without the per-expansion-index gids
+        launch_gid_by_index(s.ival[s.inst_buf], s.gsort, s.n_count, ctx->lim.instance_capacity, s.inst_gid,
+                            stream);
         gsta_status st = hip_check(ctx, hipGetLastError(), "gids by index");
         if (st != GSTA_OK) return st;
     }
@@ -717,14 +720,14 @@ gsta_status render_forward(gsta_ctx* ctx, const gsta_params* g, const gsta_camer
             cl.ptr[2] = s.ck_ctr;
             cl.count[2] = 1;
             launch_expand(s.rect, s.dval[s.depth_buf], S, n, nv, ntx, (int)T, ctx->partials, s.n_total,
-                          s.n_count, s.ikey[0], s.ival[0], s.inst_gid, s.inst_off,
+                          s.n_count, s.ikey[0], s.ival[0], s.rank_tab, s.inst_off,
                           (uint64_t)ctx->lim.instance_capacity, ctx->flags, ctx->max_inst, cl, stream);
         }
         PhaseTimer pt(ctx, GSTA_PHASE_TILE_SORT, stream);
         RadixScratch ri{ctx->hist, ctx->digit_tot, ctx->chunks_inst, ctx->items_inst};
         s.inst_buf = radix_sort_pairs(s.ikey, s.ival, 0, 1, s.n_count, 0u, key_bits(T * nv), ri, stream);
-        launch_ranges(s.ikey[s.inst_buf], s.ival[s.inst_buf], s.inst_gid, s.n_count, ctx->lim.instance_capacity,
-                      s.ranges, s.gsort, stream);
+        launch_ranges(s.ikey[s.inst_buf], s.ival[s.inst_buf], s.rank_tab, S, (int)T, ntx, s.n_count,
+                      ctx->lim.instance_capacity, s.ranges, s.gsort, stream);
     }
     {
         PhaseTimer pt(ctx, GSTA_PHASE_COMPOSITE, stream);

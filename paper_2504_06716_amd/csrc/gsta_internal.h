@@ -184,10 +184,11 @@ int radix_sort_small(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
                      uint32_t* cnt, int64_t cnt_words, uint32_t* pre[2], hipStream_t s);
 
 // Depth-ordered tile-instance expansion: counts per Gaussian in depth
-// order, exclusive scan, write (view*T + tile, gid) for every touched tile.
-// Writes keys[j] = view*T + tile, vals[j] = j, inst_gid[j] = gid for every
-// instance j of the expansion, and inst_off[v][gid] = the first j of each
-// Gaussian (its instances are contiguous, in row-major tile order).
+// order, exclusive scan, a key per touched tile.  Writes keys[j] =
+// view*T + tile and vals[j] = the Gaussian's depth rank in its view for
+// every instance j of the expansion, inst_off[v][gid] = the first j of each
+// Gaussian (its instances are contiguous, in row-major tile order), and
+// rank_tab[v][rank] = (gid, first j, rectangle x0 | x1 << 16, y0 | y1 << 16).
 // Its first kernel also zeroes the buffers named in `cl`.
 struct Clears {
     static constexpr int kMax = 3;
@@ -196,7 +197,7 @@ struct Clears {
 };
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
-                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint4* rank_tab,
                    uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, const Clears& cl,
                    hipStream_t s);
 int64_t expand_blocks(int64_t elements);
@@ -216,16 +217,22 @@ void launch_place(const ushort4* rect, const uint32_t* order, int64_t stride, in
                   uint32_t* cnt, uint32_t* tile_tot, uint64_t* partials, uint64_t* d_total, uint32_t* d_count,
                   uint32_t* ids, uint32_t* gsort, uint32_t* inst_off, uint2* ranges, uint64_t capacity,
                   uint32_t* flags, uint64_t* max_inst, const Clears& cl, hipStream_t s);
-// inst_gid[ids[i]] = gsort[i] for the d_count positions of placed lists.
+// inst_gid[ids[i]] = gsort[i] for the d_count list positions (the state
+// export of the gid of each expansion index, for either way of building
+// the lists).
 void launch_gid_by_index(const uint32_t* ids, const uint32_t* gsort, const uint32_t* d_count, int64_t capacity,
                          uint32_t* inst_gid, hipStream_t s);
 // keys[i] = tile index of list position i, from the ranges of ntiles tiles.
 void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys, hipStream_t s);
 
-// Tile ranges of the sorted keys (`ranges` must hold zeros beforehand), and
-// gsort[i] = inst_gid[ids[i]], the gid at each list position.
-void launch_ranges(const uint32_t* keys, const uint32_t* ids, const uint32_t* inst_gid, const uint32_t* d_count,
-                   int64_t capacity, uint2* ranges, uint32_t* gsort, hipStream_t s);
+// Tile ranges of the sorted keys (`ranges` must hold zeros beforehand),
+// gsort[i] = the gid at each list position, and ids[i] turned from the
+// depth rank the sort carried into the instance's expansion index, both
+// from rank_tab [views][stride] (gid, first instance, rectangle of each
+// depth rank, written by launch_expand).
+void launch_ranges(const uint32_t* keys, uint32_t* ids, const uint4* rank_tab, int64_t stride, int tiles_per_view,
+                   int ntx, const uint32_t* d_count, int64_t capacity, uint2* ranges, uint32_t* gsort,
+                   hipStream_t s);
 
 // Splat-segment checkpoints of the forward compositing, read by the
 // backward.  Every tile's depth-ordered list is cut into segments of K

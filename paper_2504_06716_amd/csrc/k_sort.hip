@@ -508,7 +508,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
                                                        const uint64_t* __restrict__ partials,
                                                        uint32_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals,
-                                                       uint32_t* __restrict__ inst_gid,
+                                                       uint4* __restrict__ rank_tab,
                                                        uint32_t* __restrict__ inst_off, uint64_t capacity) {
     __shared__ uint32_t s_tmp[RS_WAVES];
     __shared__ uint32_t s_off[EX_THREADS + 1];
@@ -537,7 +537,13 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
     const uint64_t base = partials[blockIdx.x];
     if (e < total_el) {
         const uint64_t first = base + ex;
-        inst_off[(int64_t)s_view[tid] * stride + s_gid[tid]] = (uint32_t)(first < capacity ? first : capacity);
+        const uint32_t f32 = (uint32_t)(first < capacity ? first : capacity);
+        const int64_t v = s_view[tid];
+        inst_off[v * stride + s_gid[tid]] = f32;
+        // what the ranges pass needs of this depth rank: gid, first instance, rectangle
+        const ushort4 r = s_rect[tid];
+        rank_tab[v * stride + (e - v * n)] =
+            make_uint4(s_gid[tid], f32, (uint32_t)r.x | ((uint32_t)r.y << 16), (uint32_t)r.z | ((uint32_t)r.w << 16));
     }
     // Every instance of this block's Gaussians, one per thread in turn, in
     // windows of kExWin instances: each Gaussian first marks its instances of
@@ -559,22 +565,34 @@ __global__ __launch_bounds__(EX_THREADS) void k_expand(const ushort4* __restrict
             const uint64_t dst = base + j;
             if (dst < capacity) {
                 keys[dst] = s_view[lo] * (uint32_t)tiles_per_view + ty * (uint32_t)ntx + tx;
-                vals[dst] = (uint32_t)dst;
-                inst_gid[dst] = s_gid[lo];
+                // the Gaussian's depth rank in its view (the sort is stable, so ranks
+                // stay increasing within each tile)
+                vals[dst] = (uint32_t)((int64_t)blockIdx.x * EX_THREADS + lo - (int64_t)s_view[lo] * n);
             }
         }
         __syncthreads();
     }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ids,
-                         const uint32_t* __restrict__ inst_gid, const uint32_t* d_count,
-                         uint2* __restrict__ ranges, uint32_t* __restrict__ gsort) {
+// From the sorted (tile key, depth rank) pairs: the tile ranges, the gid at
+// each list position and, in place of the rank, the instance's expansion
+// index (its Gaussian's first instance + its tile's place in the rectangle).
+// One 16-byte read per position from the rank table, whose entries of a
+// tile's list are in increasing rank order.
+__global__ void k_ranges(const uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                         const uint4* __restrict__ rank_tab, int64_t stride, uint32_t tiles_per_view,
+                         uint32_t ntx, const uint32_t* d_count, uint2* __restrict__ ranges,
+                         uint32_t* __restrict__ gsort) {
     const uint32_t count = *d_count;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        gsort[i] = inst_gid[ids[i]];
         const uint32_t k = keys[i];
+        const uint32_t v = k / tiles_per_view, t = k - v * tiles_per_view;
+        const uint4 rt = rank_tab[(int64_t)v * stride + ids[i]];
+        const uint32_t ty = t / ntx, tx = t - ty * ntx;
+        const uint32_t x0 = rt.z & 0xFFFFu, x1 = rt.z >> 16, y0 = rt.w & 0xFFFFu;
+        gsort[i] = rt.x;
+        ids[i] = rt.y + (ty - y0) * (x1 - x0) + (tx - x0);
         if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
         if (i + 1 == count || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
     }
@@ -1337,7 +1355,7 @@ int64_t expand_blocks(int64_t elements) { return (elements + EX_THREADS - 1) / E
 
 void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, int64_t n, int nv,
                    int ntx, int tiles_per_view, uint64_t* partials, uint64_t* d_total,
-                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint32_t* inst_gid,
+                   uint32_t* d_count, uint32_t* keys, uint32_t* vals, uint4* rank_tab,
                    uint32_t* inst_off, uint64_t capacity, uint32_t* flags, uint64_t* max_inst, const Clears& cl,
                    hipStream_t s) {
     const int64_t total_el = n * nv;
@@ -1346,7 +1364,7 @@ void launch_expand(const ushort4* rect, const uint32_t* order, int64_t stride, i
     k_scan_partials<<<1, 1024, 0, s>>>(partials, nb, d_total, d_count, capacity, flags, max_inst);
     if (nb > 0)
         k_expand<<<(unsigned)nb, EX_THREADS, 0, s>>>(rect, order, stride, n, total_el, ntx, tiles_per_view,
-                                                    partials, keys, vals, inst_gid, inst_off, capacity);
+                                                    partials, keys, vals, rank_tab, inst_off, capacity);
 }
 
 int64_t place_blocks(int64_t n) { return n > 0 ? (n + PL_GAUSS - 1) / PL_GAUSS : 1; }
@@ -1376,12 +1394,14 @@ void launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, uint32_t* keys
     k_keys_from_ranges<<<(unsigned)g, 256, 0, s>>>(ranges, ntiles, keys);
 }
 
-void launch_ranges(const uint32_t* keys, const uint32_t* ids, const uint32_t* inst_gid, const uint32_t* d_count,
-                   int64_t capacity, uint2* ranges, uint32_t* gsort, hipStream_t s) {
+void launch_ranges(const uint32_t* keys, uint32_t* ids, const uint4* rank_tab, int64_t stride, int tiles_per_view,
+                   int ntx, const uint32_t* d_count, int64_t capacity, uint2* ranges, uint32_t* gsort,
+                   hipStream_t s) {
     int64_t blocks = (capacity + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_ranges<<<(unsigned)blocks, 256, 0, s>>>(keys, ids, inst_gid, d_count, ranges, gsort);
+    k_ranges<<<(unsigned)blocks, 256, 0, s>>>(keys, ids, rank_tab, stride, (uint32_t)tiles_per_view, (uint32_t)ntx,
+                                              d_count, ranges, gsort);
 }
 
 // inst_gid[ids[i]] = gsort[i] for the d_count list positions (state export

@@ -231,7 +231,9 @@ gsta_status allocate(gsta_ctx* ctx, const gsta_limits* l) {
              alloc(ctx, &s.item_tile, item_cap);
     }
     ctx->items_depth = S <= (1 << 20) ? 1 : 16;
-    ctx->items_inst = cap <= (1 << 20) ? 4 : 8;
+    // tile-key sort: 1024, 2048 or 4096 keys per chunk; the larger chunks of
+    // large sorts give each digit longer runs of consecutive writes
+    ctx->items_inst = cap <= (1 << 20) ? 4 : (cap <= (1 << 24) ? 8 : 32);
     ctx->chunks_depth = radix_chunks(S, ctx->items_depth);
     ctx->chunks_inst = radix_chunks(cap, ctx->items_inst);
     const int64_t hist_words = std::max(V * 256 * ctx->chunks_depth, 256 * ctx->chunks_inst);

@@ -1307,7 +1307,8 @@ int radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t seg_stride, i
     if (rs.items == 1) return radix_passes<1>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 4) return radix_passes<4>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
     if (rs.items == 8) return radix_passes<8>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
-    return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+    if (rs.items == 16) return radix_passes<16>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
+    return radix_passes<32>(keys, vals, seg_stride, nseg, d_count, h_count, bits, rs, s);
 }
 
 int64_t small_sort_count_words(int64_t nseg) { return nseg * SM_MAXCH * RS_BINS; }

@@ -95,6 +95,18 @@ def test_placement_equals_sorted_lists(kind):
     _same(placed, sorted_)
 
 
+@pytest.mark.parametrize("kind", ["c2view", "tiles1440"])
+def test_large_capacity_sort_equals_placement(kind):
+    """Contexts of more than 2^24 instances of capacity sort the tile keys in
+    chunks of 8192 keys (32 per thread): the same lists, bit for bit."""
+    p, D, cams = _case(kind)
+    print(f"binning {kind}, capacity 2^25", flush=True)
+    placed = _run(p, D, cams, 0)
+    sorted_ = _run(p, D, cams, 1, capacity=1 << 25)
+    assert placed["status"] == 0 and sorted_["status"] == 0 and placed["ninst"] > 0
+    _same(placed, sorted_)
+
+
 def test_placement_overflow_is_reported_and_renders_nothing():
     p, D, cams = _case("ragged")
     full = _run(p, D, cams, 0, backward=False)
